@@ -1,0 +1,103 @@
+"""Seeded synthetic inputs shared by the GPU path's tests, the benchmark and the
+oracle checks.
+
+This module holds only random draws and the left-hand-side bands of each
+synthetic PDE workload.  It contains none of the solver's arithmetic, imports
+nothing from the GPU library or from the oracle, and is the only code both
+sides of a parity check have in common.
+
+Array convention: a batch is an (n, m) float64 array, element i of system k at
+[i, k] -- the interleaved layout (batch index fastest) of Section 2 of
+Carroll et al., arXiv:2107.05395.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+SEED_BASE = 2107053950
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(seed)
+
+
+def uniform_batch(n: int, m: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """i.i.d. uniform[lo, hi) entries, shape (n, m)."""
+    return rng(seed).uniform(lo, hi, size=(n, m))
+
+
+def sine_mode_batch(n: int, m: int, seed: int, modes: int = 8) -> np.ndarray:
+    """Random-phase sum of `modes` Dirichlet sine modes per system:
+    b[i, k] = sum_j A[j,k] sin(j pi x_i + phi[j,k]), x_i = (i+1)/(n+1),
+    A ~ N(0, 1), phi ~ U[0, 2 pi), independent per system."""
+    g = rng(seed)
+    amp = g.standard_normal((modes, m))
+    phase = g.uniform(0.0, 2.0 * math.pi, size=(modes, m))
+    x = (np.arange(n, dtype=np.float64) + 1.0) / (n + 1.0)
+    out = np.zeros((n, m))
+    for j in range(modes):
+        out += amp[j][None, :] * np.sin((j + 1) * math.pi * x[:, None] + phase[j][None, :])
+    return out
+
+
+# ---------------------------------------------------------------- LHS bands
+
+def diffusion_tri_bands(n: int, r: float):
+    """Implicit-Euler diffusion, zero Dirichlet: rows (-r, 1 + 2r, -r)."""
+    return np.full(n, -r), np.full(n, 1.0 + 2.0 * r), np.full(n, -r)
+
+
+def hyperdiffusion_penta_bands(n: int, r: float):
+    """Implicit-Euler hyperdiffusion, bands (r, -4r, 1 + 6r, -4r, r) on every row."""
+    return (np.full(n, r), np.full(n, -4.0 * r), np.full(n, 1.0 + 6.0 * r),
+            np.full(n, -4.0 * r), np.full(n, r))
+
+
+def ch_penta_bands(n: int, sigma: float):
+    """Periodic Cahn-Hilliard LHS: a = e = sigma, b = d = -4 sigma, c = 1 + 6 sigma
+    (Section 5.1); the same five values wrap around the corners."""
+    return hyperdiffusion_penta_bands(n, sigma)
+
+
+def variable_diffusion_bands(D: np.ndarray, r: float):
+    """A(D) = I + r diag(D) T2, T2 = tridiag(-1, 2, -1): rows (-r D_i, 1 + 2 r D_i, -r D_i)."""
+    D = np.asarray(D, dtype=np.float64)
+    return -r * D, 1.0 + 2.0 * r * D, -r * D
+
+
+def random_dominant_tri(n: int, seed: int, margin: float = 1.0):
+    """Random row-dependent bands with |b_i| >= |a_i| + |c_i| + margin."""
+    g = rng(seed)
+    a, c = g.uniform(-1, 1, n), g.uniform(-1, 1, n)
+    b = (np.abs(a) + np.abs(c) + margin) * g.choice([-1.0, 1.0], n)
+    return a, b, c
+
+
+def random_dominant_penta(n: int, seed: int, margin: float = 1.0):
+    g = rng(seed)
+    a, b, d, e = (g.uniform(-1, 1, n) for _ in range(4))
+    c = (np.abs(a) + np.abs(b) + np.abs(d) + np.abs(e) + margin) * g.choice([-1.0, 1.0], n)
+    return a, b, c, d, e
+
+
+# ---------------------------------------------------------------- workloads
+
+def ch_parameters(n: int = 256, length: float = 2.0 * math.pi, gamma: float = 0.01,
+                  dt: float = 1e-3):
+    """sigma = gamma dt / dx^4, alpha = dt / dx^2 with dx = L / n (Section 5.1)."""
+    dx = length / n
+    return gamma * dt / dx ** 4, dt / dx ** 2
+
+
+WORKLOADS = {
+    # name: description; seeds are SEED_BASE + index
+    "diffusion_n256_m1024": dict(kind="tri", n=256, m=1024, r=0.5, seed=SEED_BASE + 0),
+    "diffusion_n512_m1048576": dict(kind="tri", n=512, m=1 << 20, r=1.0, seed=SEED_BASE + 1),
+    "hyperdiffusion_n1024_m262144": dict(kind="penta", n=1024, m=1 << 18, r=0.25, seed=SEED_BASE + 2),
+    "cahn_hilliard_n256_m1048576": dict(kind="ch", n=256, m=1 << 20, gamma=0.01, dt=1e-3,
+                                        steps=5000, seed=SEED_BASE + 3),
+    "adjoint_diffusion_n1024_m65536": dict(kind="adjoint", n=1024, m=1 << 16, r=0.5, steps=100,
+                                           checkpoint=10, seed=SEED_BASE + 4),
+}

@@ -1,0 +1,59 @@
+"""Pins for the oracle's semi-implicit Cahn-Hilliard step (Section 5.1)."""
+import math
+
+import numpy as np
+
+from paper_2107_05395_amd import inputs
+from tests.dense import penta_dense, rel_err
+
+
+def test_ch_step_vs_dense(oracle):
+    """RHS built here by array slicing, LHS solved densely with LAPACK."""
+    n, m = 24, 5
+    sigma, alpha = inputs.ch_parameters(n=n, length=2 * math.pi, gamma=0.01, dt=1e-3)
+    c0 = inputs.uniform_batch(n, m, seed=1, lo=-0.9, hi=0.9)
+    nl = c0 ** 3 - c0
+    f = c0 + alpha * (np.roll(nl, 1, axis=0) - 2 * nl + np.roll(nl, -1, axis=0))
+    A = penta_dense(*inputs.ch_penta_bands(n, sigma), cyclic=True)
+    ref = np.linalg.solve(A, f)
+    assert rel_err(oracle.ch_step(c0, sigma, alpha), ref) < 1e-13
+
+
+def test_ch_mass_conserved(oracle):
+    """Periodic boundaries conserve the mean (Section 5): the column sums of the
+    LHS are all 1 and the second difference sums to zero."""
+    n, m = 256, 64
+    sigma, alpha = inputs.ch_parameters()
+    c = inputs.uniform_batch(n, m, seed=inputs.SEED_BASE + 3, lo=-0.1, hi=0.1)
+    mass0 = c.sum(axis=0)
+    c = oracle.ch_step(c, sigma, alpha, steps=50)
+    assert np.max(np.abs(c.sum(axis=0) - mass0)) < 1e-12
+
+
+def test_ch_single_mode_linear_growth(oracle):
+    """For C = eps cos(k x), eps = 1e-6, the cubic term is O(eps^3) and each step
+    multiplies the mode by G = (1 + alpha s_k) / (1 + sigma s_k^2),
+    s_k = 2 - 2 cos(k dx)."""
+    n = 256
+    dx = 2 * math.pi / n
+    sigma, alpha = inputs.ch_parameters()
+    x = np.arange(n) * dx
+    eps, steps = 1e-6, 200
+    for k in (1, 5, 8, 20):
+        c = (eps * np.cos(k * x))[:, None]
+        s = 2 - 2 * math.cos(k * dx)
+        G = (1 + alpha * s) / (1 + sigma * s * s)
+        out = oracle.ch_step(c, sigma, alpha, steps=steps)
+        ref = eps * G ** steps * np.cos(k * x)
+        if G > 1:   # growing (spinodal) mode: the neglected cubic term is O(amplitude^2)
+            amp = eps * G ** steps
+            assert rel_err(out[:, 0], ref) < max(1e-11, 10.0 * amp * amp), k
+        else:       # decaying mode: what is left is rounding noise of size eps * 1e-12
+            assert G ** steps < 1e-6 and np.max(np.abs(out[:, 0])) < 1e-12 * eps, k
+
+
+def test_ch_constant_state_stays(oracle):
+    n = 64
+    sigma, alpha = inputs.ch_parameters(n=n)
+    c = np.full((n, 3), 0.3)
+    assert np.max(np.abs(oracle.ch_step(c, sigma, alpha, steps=5) - 0.3)) < 1e-14
