@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched shared-matrix solve on one MI355X.
+
+Default workload: implicit-Euler diffusion, tridiagonal shared LHS (-r, 1+2r, -r),
+r = 1.0, n = 512 unknowns, m = 2^20 interleaved right-hand sides drawn
+uniform[-1, 1) from a fixed seed; one "step" is one batched FP64 solve of all
+m systems (factorisation on the host, once, outside the timed region, as in
+Carroll et al. arXiv:2107.05395, Section 3).  The FP32-sweep + FP64-residual
+refinement form, the paper's thread-per-system design and the FP64 oracle on
+the host cores are measured alongside and reported in the same JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("sweep.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2107_05395_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, precision: str):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
+    when they were taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    entry = rec.get("%s/%s" % (workload, precision))
+    if not entry or entry.get("source_hash") != kernel_source_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def rel_err_cols(x, ref):
+    num = np.linalg.norm(x - ref, axis=0)
+    den = np.linalg.norm(ref, axis=0)
+    return float(np.max(num / np.where(den == 0, 1.0, den)))
+
+
+def time_launches(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(stop) / 1e3, wall
+
+
+def cpu_baseline_tri(bands, n, seed, budget_s):
+    """The oracle as it stands on the host cores, on a bounded sample."""
+    import oracle
+    from paper_2107_05395_amd import inputs
+    m_s = 1 << 15
+    rhs = inputs.uniform_batch(n, m_s, seed=seed)
+    calls, t0 = 0, time.perf_counter()
+    while True:
+        oracle.tri_solve(*bands, rhs)
+        calls += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": calls * m_s / el, "unit": "systems/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d x oracle.tri_solve on %d systems of the same workload (n=%d), %.1f s"
+                      % (calls, m_s, n, el)}
+
+
+def bench_tri(args, torch):
+    from paper_2107_05395_amd import Factor, inputs
+    spec = dict(inputs.WORKLOADS[args.workload])
+    n, m, r, seed = spec["n"], spec["m"], spec["r"], spec["seed"]
+    bands = inputs.diffusion_tri_bands(n, r)
+    f = Factor.tri(*bands)
+    f.upload()
+    rhs_host = inputs.uniform_batch(n, m, seed=seed)
+    rhs = torch.from_numpy(rhs_host).cuda()
+    x = torch.empty_like(rhs)
+    algo_bytes = 16.0 * n * m          # read b, write x (double)
+
+    results = {}
+    for prec in ("f64", "f32r"):
+        t, wall = time_launches(lambda: f.solve(rhs, out=x, precision=prec), args.steps,
+                                args.warmup, torch)
+        cols = np.unique(np.r_[np.linspace(0, m - 1, 254).astype(np.int64), 0, m - 1])
+        import oracle
+        ref = oracle.tri_solve(*bands, rhs_host[:, cols])
+        err = rel_err_cols(x[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref)
+        results[prec] = dict(seconds=t, wall=wall, err=err)
+    # the paper's own mapping: one thread per system, intermediate through HBM
+    pt, _ = time_launches(lambda: f.solve_thread_per_system(rhs, out=x), max(3, args.steps // 10),
+                          1, torch)
+    pt /= max(3, args.steps // 10)
+
+    k = args.steps
+    t64 = results["f64"]["seconds"]
+    per_launch = t64 / k
+    traffic = measured_traffic(args.workload, "f64")
+    line = {
+        "metric": "systems solved/s", "value": m * k / t64, "unit": "systems/s",
+        "n_gpus": 1, "steps": k, "warmup": args.warmup, "ms_per_step": 1e3 * per_launch,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded uniform[-1,1) right-hand sides)",
+        "config": {"workload": args.workload, "n": n, "m": m, "r": r,
+                   "matrix": "tridiagonal (-r, 1+2r, -r), zero Dirichlet", "parallelism": "none"},
+        "rel_err_vs_oracle": results["f64"]["err"],
+        "hbm_gbs_algorithmic": algo_bytes / per_launch / 1e9,
+        "f32r": {"value": m * k / results["f32r"]["seconds"], "unit": "systems/s",
+                 "ms_per_step": 1e3 * results["f32r"]["seconds"] / k,
+                 "rel_err_vs_oracle": results["f32r"]["err"],
+                 "hbm_gbs_algorithmic": algo_bytes * k / results["f32r"]["seconds"] / 1e9},
+        "thread_per_system_design": {"ms_per_step": 1e3 * pt, "value": m / pt,
+                                     "hbm_gbs_algorithmic": algo_bytes / pt / 1e9},
+        "roofline": {"bound": "hbm", "achieved": algo_bytes / per_launch / 1e9,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": algo_bytes / per_launch / 1e9 / PEAK_HBM_GBS,
+                     "traffic": traffic,
+                     "kernel": "sweep_kernel<double,1,%d,false,full>" % f.chunk(),
+                     "algorithmic_bytes_per_launch": algo_bytes},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_tri(bands, n, seed + 100, args.cpu_seconds)
+    return line
+
+
+def bench_penta(args, torch):
+    from paper_2107_05395_amd import Factor, inputs
+    spec = dict(inputs.WORKLOADS[args.workload])
+    n, m, r, seed = spec["n"], spec["m"], spec["r"], spec["seed"]
+    bands = inputs.hyperdiffusion_penta_bands(n, r)
+    f = Factor.penta(*bands)
+    f.upload()
+    rhs_host = inputs.sine_mode_batch(n, m, seed=seed)
+    rhs = torch.from_numpy(rhs_host).cuda()
+    x = torch.empty_like(rhs)
+    algo_bytes = 16.0 * n * m
+    out = {}
+    import oracle
+    cols = np.unique(np.r_[np.linspace(0, m - 1, 254).astype(np.int64), 0, m - 1])
+    ref = oracle.penta_solve(*bands, rhs_host[:, cols])
+    for prec in ("f64", "f32r"):
+        t, _ = time_launches(lambda: f.solve(rhs, out=x, precision=prec), args.steps, args.warmup, torch)
+        err = rel_err_cols(x[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref)
+        out[prec] = (t, err)
+    k = args.steps
+    per = out["f64"][0] / k
+    return {
+        "metric": "systems solved/s", "value": m * k / out["f64"][0], "unit": "systems/s",
+        "n_gpus": 1, "steps": k, "warmup": args.warmup, "ms_per_step": 1e3 * per,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (random-phase sums of 8 sine modes)",
+        "config": {"workload": args.workload, "n": n, "m": m, "r": r},
+        "rel_err_vs_oracle": out["f64"][1],
+        "f32r": {"value": m * k / out["f32r"][0], "rel_err_vs_oracle": out["f32r"][1],
+                 "ms_per_step": 1e3 * out["f32r"][0] / k},
+        "roofline": {"bound": "hbm", "achieved": algo_bytes / per / 1e9, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": algo_bytes / per / 1e9 / PEAK_HBM_GBS,
+                     "traffic": measured_traffic(args.workload, "f64")},
+    }
+
+
+def bench_ch(args, torch):
+    from paper_2107_05395_amd import Factor, inputs
+    spec = dict(inputs.WORKLOADS[args.workload])
+    n, m, seed = spec["n"], spec["m"], spec["seed"]
+    sigma, alpha = inputs.ch_parameters(n=n, gamma=spec["gamma"], dt=spec["dt"])
+    f = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
+    f.upload()
+    c_host = inputs.uniform_batch(n, m, seed=seed, lo=-0.1, hi=0.1)
+    c = torch.from_numpy(c_host).cuda()
+    out = torch.empty_like(c)
+    steps_per_launch = args.ch_fuse
+    launches = max(1, args.steps // steps_per_launch)
+    t, _ = time_launches(lambda: f.ch_step(c, alpha, steps=steps_per_launch, out=out), launches,
+                         args.warmup, torch)
+    total_steps = launches * steps_per_launch
+    per_step = t / total_steps
+    algo_bytes_per_step = 16.0 * n * m
+    import oracle
+    cols = np.arange(0, m, m // 64)
+    ref = oracle.ch_step(c_host[:, cols], sigma, alpha, steps=steps_per_launch)
+    err = rel_err_cols(out[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref)
+    return {
+        "metric": "system-steps/s", "value": m * total_steps / t, "unit": "system-steps/s",
+        "n_gpus": 1, "steps": total_steps, "warmup": args.warmup, "ms_per_step": 1e3 * per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded uniform[-0.1,0.1) initial states)",
+        "config": {"workload": args.workload, "n": n, "m": m, "steps_per_launch": steps_per_launch},
+        "rel_err_vs_oracle": err,
+        "hbm_equivalent_gbs": algo_bytes_per_step / per_step / 1e9,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="diffusion_n512_m1048576")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--ch-fuse", type=int, default=1, help="CH steps per kernel launch")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs every system of a batch on a "
+              "single MI355X and has no multi-GPU path (requested --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        print(json.dumps({"error": "single-GPU benchmark; --gpus %d not supported" % args.gpus}))
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        sys.exit("bench.py needs a GPU")
+    from paper_2107_05395_amd import inputs
+    kind = inputs.WORKLOADS[args.workload]["kind"]
+    if kind == "tri":
+        line = bench_tri(args, torch)
+    elif kind == "penta":
+        line = bench_penta(args, torch)
+    elif kind == "ch":
+        line = bench_ch(args, torch)
+    else:
+        sys.exit("workload %s is not a bench workload" % args.workload)
+    line["device"] = torch.cuda.get_device_name(0)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * bandbatch.h -- C ABI of libbandbatch: batched solution of many tridiagonal or
+ * pentadiagonal systems A x_k = b_k, k = 0..m-1, that all share one
+ * left-hand-side matrix A, on an AMD Instinct MI355X (gfx950).
+ *
+ * Method: Carroll, Gloster, Bustamante, O Naraigh, "A Batched GPU Methodology
+ * for Numerical Solutions of Partial Differential Equations", arXiv:2107.05395.
+ *   - A is factorised once on the host (Section 3.1 Thomas pre-factorisation,
+ *     Section 4.1 LR factorisation; Appendix A and B pre-factorisation steps)
+ *     and one copy of the factor is kept in device memory (Section 2).
+ *   - The right-hand sides are interleaved, batch index fastest (Section 2):
+ *     element i of system k lives at [i*ld + k], 0 <= i < n, 0 <= k < m <= ld.
+ *   - Every system is swept forward then backward (Section 3.1, 4.1; Appendix A
+ *     and B batched sweeps).  Periodic matrices take a Sherman-Morrison
+ *     correction (Section 3.3) or its rank-2 Woodbury analogue (Section 5.1
+ *     matrix).
+ *
+ * Conventions for every entry point
+ *   - Every call returns a bb_status; no C++ exception crosses the ABI.
+ *   - Argument, pivot and capacitance checks run synchronously on the host
+ *     before anything is enqueued; on error nothing is enqueued and
+ *     bb_last_error_message() (thread-local) says what was wrong.
+ *   - Device work is enqueued on `stream` (a hipStream_t; NULL = the default
+ *     stream) and the call returns without waiting.  A fault in device code is
+ *     reported as BB_ERR_HIP by a later call or by the caller's stream sync.
+ *   - Pointers named rhs, x, g, lam, c_in, c_out, grad_bands and workspace are
+ *     DEVICE pointers owned by the caller.  Band pointers given to the factor
+ *     constructors are HOST pointers, read during the call and not kept.
+ *   - In place is allowed wherever input and output have the same type and
+ *     layout (x == rhs, lam == g, c_out == c_in); partial overlap is not.
+ *   - A bb_factor is immutable after construction and may be used from several
+ *     host threads and streams at once.  It owns its host and device memory,
+ *     released by bb_factor_destroy().
+ */
+#ifndef BANDBATCH_H
+#define BANDBATCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BB_OK = 0,
+    BB_ERR_ARG = -1,                  /* bad size, pointer, precision or factor kind */
+    BB_ERR_ZERO_PIVOT = -2,           /* a pivot (b^_i or alpha_i) is 0 or not finite; the method does not pivot */
+    BB_ERR_SINGULAR_CAPACITANCE = -3, /* 1 + V.z (or I + V^T Z) of a periodic correction is singular */
+    BB_ERR_HIP = -4,                  /* a HIP runtime call failed */
+    BB_ERR_OOM = -5,                  /* host or device allocation failed */
+    BB_ERR_UNSUPPORTED = -6           /* size outside what the kernels are built for (see bb_max_n) */
+} bb_status;
+
+typedef enum {
+    BB_F64 = 0,        /* rhs, x and all arithmetic in double */
+    BB_F32_REFINE = 1, /* double rhs and x; sweeps in float with the factor rounded to float, then one
+                          residual r = b - A x0 in double with the original bands and a float correction
+                          sweep: x = x0 + A^{-1} r.  Relative error ~ (kappa eps32)^2 + kappa eps64. */
+    BB_F32 = 2         /* float rhs and x, float sweeps; no refinement */
+} bb_precision;
+
+typedef struct bb_factor_s *bb_factor;
+
+/* ---------------------------------------------------------------- factors
+ * Factorise a shared matrix once, on the host, in double (Section 3.1
+ * pre-factorisation; Section 4.1 steps 1-14; Appendix A/B).  The device copy
+ * is made lazily on the first solve, or by bb_factor_upload().
+ *
+ * Tridiagonal row i:   a[i] x[i-1] + b[i] x[i] + c[i] x[i+1] = rhs[i].
+ *   Non-cyclic: a[0] and c[n-1] are ignored.
+ *   Cyclic (indices mod n): a[0] is A[0][n-1], c[n-1] is A[n-1][0] (Section 3.3).
+ * Pentadiagonal row i: a[i] x[i-2] + b[i] x[i-1] + c[i] x[i] + d[i] x[i+1] + e[i] x[i+2].
+ *   Non-cyclic: a[0], a[1], b[0], d[n-1], e[n-2], e[n-1] are ignored.
+ *   Cyclic (indices mod n): those six are the corners (Section 5.1 matrix).
+ *
+ * Sizes: 1 <= n <= bb_max_n() non-cyclic; 3 <= n (tri) or 5 <= n (penta) cyclic.
+ * Errors: BB_ERR_ARG (null pointer, n out of range), BB_ERR_ZERO_PIVOT,
+ *         BB_ERR_SINGULAR_CAPACITANCE (cyclic), BB_ERR_OOM.  *out is set only on BB_OK. */
+bb_status bb_factor_shared_tri(const double *a, const double *b, const double *c, int64_t n,
+                               bb_factor *out);
+bb_status bb_factor_shared_tri_cyclic(const double *a, const double *b, const double *c, int64_t n,
+                                      bb_factor *out);
+bb_status bb_factor_shared_penta(const double *a, const double *b, const double *c, const double *d,
+                                 const double *e, int64_t n, bb_factor *out);
+bb_status bb_factor_shared_penta_cyclic(const double *a, const double *b, const double *c,
+                                        const double *d, const double *e, int64_t n, bb_factor *out);
+
+/* Release a factor and its device copies.  NULL is accepted.  The caller must
+ * make sure no enqueued work still uses it (synchronise the streams first). */
+bb_status bb_factor_destroy(bb_factor f);
+
+/* Copy the factor's coefficient tables to the current device now, ordered on
+ * `stream`, instead of on the first solve. */
+bb_status bb_factor_upload(bb_factor f, void *stream);
+
+/* Matrix size, kind (0 tri, 1 tri cyclic, 2 penta, 3 penta cyclic) and the
+ * number of unknowns per lane ("chunk") the sweeps use for this n.  Any out
+ * pointer may be NULL. */
+bb_status bb_factor_info(bb_factor f, int64_t *n, int32_t *kind, int32_t *chunk);
+
+/* Largest n the sweep kernels are built for (2048: the shared coefficient
+ * tables are staged in LDS). */
+int64_t bb_max_n(void);
+
+/* ---------------------------------------------------------------- solves
+ * x[:,k] = A^{-1} rhs[:,k] for 0 <= k < m (Appendix A/B batched sweeps, with
+ * the periodic correction of Section 3.3 when the factor is cyclic).
+ * rhs, x: device, interleaved [i*ld + k]; double for BB_F64 and BB_F32_REFINE,
+ * float for BB_F32.  m >= 0 (m == 0 enqueues nothing), ld >= max(m, 1).
+ * The tri entry point requires a tri factor (cyclic or not), the penta one a
+ * penta factor; the _cyclic names additionally require a cyclic factor.
+ * Errors: BB_ERR_ARG (wrong factor kind, null pointer, m or ld out of range,
+ * unknown precision), BB_ERR_HIP, BB_ERR_OOM (first upload). */
+bb_status bb_solve_batch_tri(bb_factor f, const void *rhs, void *x, int64_t m, int64_t ld,
+                             bb_precision p, void *stream);
+bb_status bb_solve_batch_penta(bb_factor f, const void *rhs, void *x, int64_t m, int64_t ld,
+                               bb_precision p, void *stream);
+bb_status bb_solve_batch_tri_cyclic(bb_factor f, const void *rhs, void *x, int64_t m, int64_t ld,
+                                    bb_precision p, void *stream);
+bb_status bb_solve_batch_penta_cyclic(bb_factor f, const void *rhs, void *x, int64_t m, int64_t ld,
+                                      bb_precision p, void *stream);
+
+/* Adjoint (transposed) solve lam[:,k] = A^{-T} g[:,k] with the same shared
+ * factor: A = L U gives A^T = U^T L^T, so the sweeps run with the factor's
+ * transposed coefficients (for periodic factors the Sherman-Morrison /
+ * Woodbury correction is transposed as well).  This is the backward pass of a
+ * batched solve: for x = A^{-1} b and a loss L, dL/db = A^{-T} dL/dx.
+ * Same layouts, sizes, precisions and errors as the solves. */
+bb_status bb_solve_batch_tri_adjoint(bb_factor f, const void *g, void *lam, int64_t m, int64_t ld,
+                                     bb_precision p, void *stream);
+bb_status bb_solve_batch_penta_adjoint(bb_factor f, const void *g, void *lam, int64_t m,
+                                       int64_t ld, bb_precision p, void *stream);
+
+/* The paper's own work mapping, kept as a measured baseline design (Appendix A
+ * batched sweep): one thread per system walks all n rows, writing the forward
+ * intermediate to x and reading it back in the backward sweep.  Non-cyclic
+ * tridiagonal factor, double only; same layouts and errors as the solves.
+ * Moves twice the bytes of bb_solve_batch_tri, which keeps every system's
+ * intermediate on chip. */
+bb_status bb_solve_batch_tri_thread_per_system(bb_factor f, const double *rhs, double *x,
+                                               int64_t m, int64_t ld, void *stream);
+
+/* Band gradients of a batched solve: for x = A^{-1} b and lam = A^{-T} dL/dx,
+ * dL/dA_ij = -sum_k lam[i,k] x[j,k].  For each band (a..c for tri, a..e for
+ * penta, in that order) and row i:
+ *     grad_bands[band*n + i] += -sum_k lam[i,k] * x[i + band - nb/2, k]
+ * where nb = 3 or 5; entries outside the matrix receive nothing unless the
+ * factor is cyclic, where column indices wrap mod n.  Accumulates (+=) into
+ * grad_bands (device, nb*n doubles), so calls for several time steps sum.
+ * The batch sum runs in a fixed order: results are bitwise reproducible.
+ * workspace: device scratch of at least bb_band_grad_workspace_bytes(f, m)
+ * bytes, caller-owned; it may be NULL when that size is 0.
+ * Errors: BB_ERR_ARG, BB_ERR_HIP. */
+size_t bb_band_grad_workspace_bytes(bb_factor f, int64_t m);
+bb_status bb_band_grad(bb_factor f, const double *lam, const double *x, int64_t m, int64_t ld,
+                       double *grad_bands, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------- Cahn-Hilliard
+ * `steps` semi-implicit Cahn-Hilliard steps (Section 5.1) of m periodic
+ * systems:  C^{n+1} + dt gamma d4 C^{n+1} = C^n + dt d2 (C^3 - C)^n, i.e.
+ * C^{n+1} = A^{-1} f with f_i = C_i + alpha (N_{i-1} - 2 N_i + N_{i+1}),
+ * N = C^3 - C, alpha = dt/dx^2, indices mod n.  `f` must be the cyclic penta
+ * factor of the LHS (a = e = sigma, b = d = -4 sigma, c = 1 + 6 sigma,
+ * sigma = gamma dt / dx^4).  All `steps` steps of a system run inside one
+ * kernel with the state held on chip, reading c_in once and writing c_out once.
+ * c_in, c_out: device double, interleaved, same ld.  steps >= 1.
+ * Errors: BB_ERR_ARG (not a cyclic penta factor, sizes), BB_ERR_HIP. */
+bb_status bb_ch_step(bb_factor f, const double *c_in, double *c_out, int64_t m, int64_t ld,
+                     double alpha, int64_t steps, void *stream);
+
+/* ---------------------------------------------------------------- loss
+ * Mean-squared-error loss of a batch against a target and its gradient:
+ *   grad[i,k] = 2 (u[i,k] - target[i,k]) / (n m),
+ *   partial sums of (u - target)^2 are written to workspace and folded in a
+ *   fixed order into *loss_dev = sum (u - target)^2 / (n m)   (device double).
+ * grad may alias u.  workspace: bb_mse_workspace_bytes(n, m) bytes.
+ * Errors: BB_ERR_ARG, BB_ERR_HIP. */
+size_t bb_mse_workspace_bytes(int64_t n, int64_t m);
+bb_status bb_mse_loss_grad(const double *u, const double *target, double *grad, double *loss_dev,
+                           int64_t n, int64_t m, int64_t ld, void *workspace,
+                           size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------- errors */
+const char *bb_status_string(bb_status s);
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char *bb_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BANDBATCH_H */

@@ -1,0 +1,114 @@
+"""Differentiable batched solves.
+
+The backward pass of x = A^{-1} b is one transposed solve with the same
+shared factor, lam = A^{-T} dL/dx (so dL/db = lam), plus the band gradients
+dL/dA_ij = -sum_k lam_i x_j reduced over the batch into the shared bands.
+Both run in libbandbatch's kernels; torch only sees the results.
+
+``banded_rollout`` differentiates T implicit steps u_t = A^{-1} u_{t-1}
+with activation checkpointing: the forward pass keeps every
+``checkpoint_every``-th state, and the backward pass recomputes each segment
+from its checkpoint before walking it backwards.
+"""
+from __future__ import annotations
+
+import torch
+
+from .solver import Factor, mse_loss_grad
+
+
+def _factor_from(bands, kind: str, cyclic: bool) -> Factor:
+    host = [b.detach().to("cpu", torch.float64).numpy() for b in bands]
+    return Factor.tri(*host, cyclic=cyclic) if kind == "tri" else Factor.penta(*host, cyclic=cyclic)
+
+
+def _kind(nb: int) -> str:
+    if nb not in (3, 5):
+        raise ValueError("need 3 (tri) or 5 (penta) bands")
+    return "tri" if nb == 3 else "penta"
+
+
+class BandedSolve(torch.autograd.Function):
+    """x = A(bands)^{-1} rhs, differentiable in rhs and in every band."""
+
+    @staticmethod
+    def forward(ctx, rhs, cyclic, precision, *bands):
+        f = _factor_from(bands, _kind(len(bands)), cyclic)
+        x = f.solve(rhs.contiguous(), precision=precision)
+        ctx.factor, ctx.precision = f, precision
+        ctx.save_for_backward(x)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (x,) = ctx.saved_tensors
+        f = ctx.factor
+        lam = f.adjoint(gx.contiguous(), precision=ctx.precision)
+        gb = f.band_grad(lam, x)
+        return (lam, None, None, *[gb[q] for q in range(f.nbands)])
+
+
+def banded_solve(rhs, bands, cyclic: bool = False, precision: str = "f64"):
+    return BandedSolve.apply(rhs, cyclic, precision, *bands)
+
+
+class BandedRollout(torch.autograd.Function):
+    """u_T after `steps` solves u_t = A(bands)^{-1} u_{t-1}, checkpointed."""
+
+    @staticmethod
+    def forward(ctx, u0, steps, checkpoint_every, precision, *bands):
+        if steps < 1 or checkpoint_every < 1:
+            raise ValueError("steps and checkpoint_every must be >= 1")
+        f = _factor_from(bands, _kind(len(bands)), False)
+        u = u0.detach().contiguous()
+        checkpoints = [u]
+        for t in range(1, steps + 1):
+            u = f.solve(u, precision=precision)
+            if t % checkpoint_every == 0 and t < steps:
+                checkpoints.append(u)
+        ctx.factor, ctx.steps, ctx.every, ctx.precision = f, steps, checkpoint_every, precision
+        ctx.checkpoints = checkpoints
+        return u
+
+    @staticmethod
+    def backward(ctx, g_out):
+        f, steps, every, prec = ctx.factor, ctx.steps, ctx.every, ctx.precision
+        g = g_out.contiguous()
+        gb = torch.zeros(f.nbands, f.n, dtype=torch.float64, device=g.device)
+        # segments [s, e): states u_s .. u_e; checkpoint i holds u_{i*every}
+        for i in reversed(range(len(ctx.checkpoints))):
+            s = i * every
+            e = min(s + every, steps)
+            states = [ctx.checkpoints[i]]
+            for _ in range(s, e):
+                states.append(f.solve(states[-1], precision=prec))
+            for t in range(e, s, -1):          # u_t = A^{-1} u_{t-1}
+                lam = f.adjoint(g, precision=prec)
+                f.band_grad(lam, states[t - s], gb)
+                g = lam
+            del states
+        ctx.checkpoints = None
+        return (g, None, None, None, *[gb[q] for q in range(f.nbands)])
+
+
+def banded_rollout(u0, bands, steps: int, checkpoint_every: int = 10, precision: str = "f64"):
+    return BandedRollout.apply(u0, steps, checkpoint_every, precision, *bands)
+
+
+class MSELoss(torch.autograd.Function):
+    """mean((u - target)^2) over every entry, gradient from the same kernel."""
+
+    @staticmethod
+    def forward(ctx, u, target):
+        loss, grad = mse_loss_grad(u.contiguous(), target.contiguous())
+        ctx.save_for_backward(grad)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gl):
+        (grad,) = ctx.saved_tensors
+        return grad * gl, None
+
+
+def mse_loss(u, target):
+    return MSELoss.apply(u, target)

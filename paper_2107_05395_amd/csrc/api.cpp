@@ -1,0 +1,436 @@
+// api.cpp -- the extern "C" boundary of libbandbatch (declared in
+// include/bandbatch.h): argument checks, choice of the sweep decomposition,
+// lazy upload of the factor's coefficient tables, kernel dispatch.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/bandbatch.h"
+#include "factor.h"
+
+struct bb_factor_s {
+    bb::Factor f;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bb_status fail(bb_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+bb_status from_internal(int st, const std::string &err)
+{
+    switch (st) {
+    case bb::kOk: return BB_OK;
+    case bb::kErrPivot: return fail(BB_ERR_ZERO_PIVOT, err);
+    case bb::kErrCapacitance: return fail(BB_ERR_SINGULAR_CAPACITANCE, err);
+    default: return fail(BB_ERR_ARG, err);
+    }
+}
+
+bb_status hip_fail(hipError_t e, const char *where)
+{
+    return fail(BB_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Upper bound on rows per lane.  The sweeps hold C rows of the right-hand side
+// per lane in registers; the refinement kernel holds the double input, the
+// float first solution and the float correction at once, so it gets half.
+// BANDBATCH_MAX_CHUNK overrides the solve bound (tuning).
+int max_chunk(bb_precision p)
+{
+    int c = bb::kChunkMax;
+    if (const char *env = std::getenv("BANDBATCH_MAX_CHUNK")) {
+        const int v = std::atoi(env);
+        if (v >= bb::kChunkMin && v <= bb::kChunkMax && (v & (v - 1)) == 0) c = v;
+    }
+    if (p == BB_F32_REFINE && c > 32) c = 32;
+    return c;
+}
+
+bb_status make(int kind, const double *a, const double *b, const double *c, const double *d,
+               const double *e, int64_t n, bb_factor *out)
+{
+    if (!out) return fail(BB_ERR_ARG, "out is NULL");
+    const bool penta = (kind == bb::kPenta || kind == bb::kPentaCyclic);
+    if (!a || !b || !c || (penta && (!d || !e))) return fail(BB_ERR_ARG, "band pointer is NULL");
+    const int64_t nmin = kind == bb::kTriCyclic ? 3 : kind == bb::kPentaCyclic ? 5 : 1;
+    if (n < nmin) return fail(BB_ERR_ARG, "n = " + std::to_string(n) + " is below the minimum " + std::to_string(nmin));
+    if (n > bb::kMaxN) return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(n) + " exceeds bb_max_n()");
+    bb_factor f = new (std::nothrow) bb_factor_s;
+    if (!f) return fail(BB_ERR_OOM, "host allocation");
+    const double *bands[5] = {a, b, c, d, e};
+    std::string err;
+    int st;
+    try {
+        st = bb::make_factor(kind, bands, n, f->f, err);
+    } catch (const std::bad_alloc &) {
+        delete f;
+        return fail(BB_ERR_OOM, "host allocation");
+    }
+    if (st != bb::kOk) {
+        delete f;
+        return from_internal(st, err);
+    }
+    *out = f;
+    g_last_error.clear();
+    return BB_OK;
+}
+
+bb_status current_device(int *dev)
+{
+    hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    return BB_OK;
+}
+
+// Device copy of a host table, created on first use per (device, key).
+template <typename Key, typename Build>
+bb_status device_table(bb::Factor &f, std::map<Key, bb::DeviceTable> &cache, const Key &key,
+                       bool as_float, Build build, bb::DeviceTable *out)
+{
+    std::lock_guard<std::mutex> lock(f.mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) { *out = it->second; return BB_OK; }
+    std::vector<double> host = build();
+    bb::DeviceTable t;
+    t.elems = (int64_t)host.size();
+    const size_t bytes = host.size() * (as_float ? sizeof(float) : sizeof(double));
+    hipError_t e = hipMalloc(&t.ptr, bytes ? bytes : 8);
+    if (e != hipSuccess) { (void)hipGetLastError(); return fail(BB_ERR_OOM, "hipMalloc of the coefficient table"); }
+    if (as_float) {
+        std::vector<float> hf(host.begin(), host.end());
+        e = hipMemcpy(t.ptr, hf.data(), bytes, hipMemcpyHostToDevice);
+    } else {
+        e = hipMemcpy(t.ptr, host.data(), bytes, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) { (void)hipFree(t.ptr); return hip_fail(e, "hipMemcpy of the coefficient table"); }
+    cache[key] = t;
+    *out = t;
+    return BB_OK;
+}
+
+bb_status check_batch(bb_factor f, const void *in, const void *out, int64_t m, int64_t ld)
+{
+    if (!f) return fail(BB_ERR_ARG, "factor is NULL");
+    if (m < 0) return fail(BB_ERR_ARG, "m < 0");
+    if (ld < (m > 1 ? m : 1)) return fail(BB_ERR_ARG, "ld < max(m, 1)");
+    if (m > 0 && (!in || !out)) return fail(BB_ERR_ARG, "device pointer is NULL");
+    if (ld > (int64_t(1) << 40)) return fail(BB_ERR_ARG, "ld too large");
+    return BB_OK;
+}
+
+bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, bb_precision p,
+                void *stream, bool adjoint, int want_k, int want_cyclic)
+{
+    bb_status st = check_batch(fh, in, out, m, ld);
+    if (st != BB_OK) return st;
+    bb::Factor &f = fh->f;
+    if (f.K != want_k) return fail(BB_ERR_ARG, want_k == 1 ? "not a tridiagonal factor" : "not a pentadiagonal factor");
+    if (want_cyclic == 1 && !f.cyclic) return fail(BB_ERR_ARG, "not a cyclic factor");
+    if (p != BB_F64 && p != BB_F32_REFINE && p != BB_F32) return fail(BB_ERR_ARG, "unknown precision");
+    if (m == 0) { g_last_error.clear(); return BB_OK; }
+    int dev;
+    if ((st = current_device(&dev)) != BB_OK) return st;
+
+    const int C = bb::choose_chunk(f.n, max_chunk(p));
+    const int P = bb::lanes_for(f.n, C);
+    int log2P = 0;
+    while ((1 << log2P) < P) ++log2P;
+    const bool f32 = (p != BB_F64);
+    const bb::Direction &dir = adjoint ? f.adjoint : f.primal;
+    bb::DeviceTable tab, band;
+    st = device_table(f, f.dev, std::make_tuple(dev, (int)adjoint, (int)f32, C, 0), f32,
+                      [&] { return bb::build_table(dir, f.K, f.cyclic, f.n, C, P); }, &tab);
+    if (st != BB_OK) return st;
+    bb::Corners corners = f.corners;
+    bb::Op op = bb::Op::Solve;
+    if (p == BB_F32_REFINE) {
+        op = bb::Op::Refine;
+        if (adjoint) {
+            // residual of the transposed system: bands and corners of A^T
+            st = device_table(f, f.dev, std::make_tuple(dev, 1, 0, C, 1), false,
+                              [&] {
+                                  bb::Factor t;
+                                  t.n = f.n;
+                                  t.K = f.K;
+                                  const int nb = 2 * f.K + 1;
+                                  for (int q = 0; q < nb; ++q) {
+                                      t.band[q].assign(f.n, 0.0);
+                                      const int off = q - f.K;
+                                      // A^T[i][i+off] = A[i+off][i] = band[K-off][i+off]
+                                      for (int64_t i = 0; i < f.n; ++i)
+                                          if (i + off >= 0 && i + off < f.n)
+                                              t.band[q][i] = f.band[2 * f.K - q][i + off];
+                                  }
+                                  return bb::build_band_table(t, C, P);
+                              },
+                              &band);
+            for (int r = 0; r < 2; ++r)
+                for (int q = 0; q < 2; ++q) {
+                    // A^T top-right block = (A bottom-left block)^T, and vice versa
+                    corners.top[r][q] = f.corners.bot[q][r];
+                    corners.bot[r][q] = f.corners.top[q][r];
+                }
+            if (f.K == 1) {
+                corners = bb::Corners{};
+                corners.top[0][1] = f.corners.bot[1][0];
+                corners.bot[1][0] = f.corners.top[0][1];
+            }
+        } else {
+            st = device_table(f, f.dev, std::make_tuple(dev, 0, 0, C, 1), false,
+                              [&] { return bb::build_band_table(f, C, P); }, &band);
+        }
+        if (st != BB_OK) return st;
+    }
+    bb::SweepGeom g;
+    g.n = (int)f.n;
+    g.C = C;
+    g.log2P = log2P;
+    g.exact = (f.n % C) == 0;
+    g.m = m;
+    g.ld = ld;
+    const int S = bb::kWave / P;
+    g.groups = (m + S - 1) / S;
+    hipError_t e = bb::launch_sweep(f.K, f.cyclic, op, f32 && p == BB_F32, tab.ptr, tab.elems,
+                                    (const double *)band.ptr, band.elems, dir.cor.q, corners, g,
+                                    in, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    g_last_error.clear();
+    return BB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bb_status bb_factor_shared_tri(const double *a, const double *b, const double *c, int64_t n,
+                               bb_factor *out)
+{
+    return make(bb::kTri, a, b, c, nullptr, nullptr, n, out);
+}
+
+bb_status bb_factor_shared_tri_cyclic(const double *a, const double *b, const double *c, int64_t n,
+                                      bb_factor *out)
+{
+    return make(bb::kTriCyclic, a, b, c, nullptr, nullptr, n, out);
+}
+
+bb_status bb_factor_shared_penta(const double *a, const double *b, const double *c, const double *d,
+                                 const double *e, int64_t n, bb_factor *out)
+{
+    return make(bb::kPenta, a, b, c, d, e, n, out);
+}
+
+bb_status bb_factor_shared_penta_cyclic(const double *a, const double *b, const double *c,
+                                        const double *d, const double *e, int64_t n,
+                                        bb_factor *out)
+{
+    return make(bb::kPentaCyclic, a, b, c, d, e, n, out);
+}
+
+bb_status bb_factor_destroy(bb_factor f)
+{
+    delete f;
+    return BB_OK;
+}
+
+bb_status bb_factor_upload(bb_factor fh, void *stream)
+{
+    (void)stream;   // the upload is a blocking copy; it is complete when this returns
+    if (!fh) return fail(BB_ERR_ARG, "factor is NULL");
+    bb::Factor &f = fh->f;
+    int dev;
+    bb_status st = current_device(&dev);
+    if (st != BB_OK) return st;
+    for (bb_precision p : {BB_F64, BB_F32_REFINE}) {
+        const int C = bb::choose_chunk(f.n, max_chunk(p));
+        const int P = bb::lanes_for(f.n, C);
+        const int f32 = p != BB_F64;
+        for (int adj = 0; adj < 2; ++adj) {
+            const bb::Direction &dir = adj ? f.adjoint : f.primal;
+            bb::DeviceTable t;
+            st = device_table(f, f.dev, std::make_tuple(dev, adj, f32, C, 0), f32 != 0,
+                              [&] { return bb::build_table(dir, f.K, f.cyclic, f.n, C, P); }, &t);
+            if (st != BB_OK) return st;
+        }
+    }
+    g_last_error.clear();
+    return BB_OK;
+}
+
+bb_status bb_factor_info(bb_factor fh, int64_t *n, int32_t *kind, int32_t *chunk)
+{
+    if (!fh) return fail(BB_ERR_ARG, "factor is NULL");
+    if (n) *n = fh->f.n;
+    if (kind) *kind = fh->f.kind;
+    if (chunk) *chunk = bb::choose_chunk(fh->f.n, max_chunk(BB_F64));
+    return BB_OK;
+}
+
+int64_t bb_max_n(void) { return bb::kMaxN; }
+
+bb_status bb_solve_batch_tri(bb_factor f, const void *rhs, void *x, int64_t m, int64_t ld,
+                             bb_precision p, void *stream)
+{
+    return solve(f, rhs, x, m, ld, p, stream, false, 1, -1);
+}
+
+bb_status bb_solve_batch_penta(bb_factor f, const void *rhs, void *x, int64_t m, int64_t ld,
+                               bb_precision p, void *stream)
+{
+    return solve(f, rhs, x, m, ld, p, stream, false, 2, -1);
+}
+
+bb_status bb_solve_batch_tri_cyclic(bb_factor f, const void *rhs, void *x, int64_t m, int64_t ld,
+                                    bb_precision p, void *stream)
+{
+    return solve(f, rhs, x, m, ld, p, stream, false, 1, 1);
+}
+
+bb_status bb_solve_batch_penta_cyclic(bb_factor f, const void *rhs, void *x, int64_t m, int64_t ld,
+                                      bb_precision p, void *stream)
+{
+    return solve(f, rhs, x, m, ld, p, stream, false, 2, 1);
+}
+
+bb_status bb_solve_batch_tri_adjoint(bb_factor f, const void *g, void *lam, int64_t m, int64_t ld,
+                                     bb_precision p, void *stream)
+{
+    return solve(f, g, lam, m, ld, p, stream, true, 1, -1);
+}
+
+bb_status bb_solve_batch_penta_adjoint(bb_factor f, const void *g, void *lam, int64_t m,
+                                       int64_t ld, bb_precision p, void *stream)
+{
+    return solve(f, g, lam, m, ld, p, stream, true, 2, -1);
+}
+
+bb_status bb_solve_batch_tri_thread_per_system(bb_factor fh, const double *rhs, double *x,
+                                               int64_t m, int64_t ld, void *stream)
+{
+    bb_status st = check_batch(fh, rhs, x, m, ld);
+    if (st != BB_OK) return st;
+    bb::Factor &f = fh->f;
+    if (f.kind != bb::kTri) return fail(BB_ERR_ARG, "needs a non-cyclic tridiagonal factor");
+    if (m == 0) return BB_OK;
+    int dev;
+    if ((st = current_device(&dev)) != BB_OK) return st;
+    bb::DeviceTable t;
+    st = device_table(f, f.dev_paper, dev, false,
+                      [&] {
+                          std::vector<double> h(f.rhat);
+                          h.insert(h.end(), f.aprime.begin(), f.aprime.end());
+                          h.insert(h.end(), f.chat.begin(), f.chat.end());
+                          return h;
+                      },
+                      &t);
+    if (st != BB_OK) return st;
+    const double *base = (const double *)t.ptr;
+    hipError_t e = bb::launch_tri_thread_per_system(base, base + f.n, base + 2 * f.n, (int)f.n, m,
+                                                    ld, rhs, x, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "thread-per-system launch");
+    return BB_OK;
+}
+
+size_t bb_band_grad_workspace_bytes(bb_factor f, int64_t m)
+{
+    if (!f || m <= 0) return 0;
+    return bb::band_grad_workspace(2 * f->f.K + 1, (int)f->f.n, m);
+}
+
+bb_status bb_band_grad(bb_factor fh, const double *lam, const double *x, int64_t m, int64_t ld,
+                       double *grad_bands, void *workspace, size_t workspace_bytes, void *stream)
+{
+    bb_status st = check_batch(fh, lam, x, m, ld);
+    if (st != BB_OK) return st;
+    if (!grad_bands) return fail(BB_ERR_ARG, "grad_bands is NULL");
+    if (m == 0) return BB_OK;
+    const bb::Factor &f = fh->f;
+    const int nb = 2 * f.K + 1;
+    const size_t need = bb::band_grad_workspace(nb, (int)f.n, m);
+    if (workspace_bytes < need || (need && !workspace))
+        return fail(BB_ERR_ARG, "workspace smaller than bb_band_grad_workspace_bytes()");
+    hipError_t e = bb::launch_band_grad(nb, f.cyclic, (int)f.n, m, ld, lam, x, grad_bands,
+                                        workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "band-gradient launch");
+    return BB_OK;
+}
+
+bb_status bb_ch_step(bb_factor fh, const double *c_in, double *c_out, int64_t m, int64_t ld,
+                     double alpha, int64_t steps, void *stream)
+{
+    bb_status st = check_batch(fh, c_in, c_out, m, ld);
+    if (st != BB_OK) return st;
+    bb::Factor &f = fh->f;
+    if (f.kind != bb::kPentaCyclic) return fail(BB_ERR_ARG, "needs a cyclic pentadiagonal factor");
+    if (steps < 1) return fail(BB_ERR_ARG, "steps < 1");
+    if (!std::isfinite(alpha)) return fail(BB_ERR_ARG, "alpha is not finite");
+    if (m == 0) return BB_OK;
+    int dev;
+    if ((st = current_device(&dev)) != BB_OK) return st;
+    const int C = bb::choose_chunk(f.n, max_chunk(BB_F64));
+    const int P = bb::lanes_for(f.n, C);
+    int log2P = 0;
+    while ((1 << log2P) < P) ++log2P;
+    bb::DeviceTable tab;
+    st = device_table(f, f.dev, std::make_tuple(dev, 0, 0, C, 0), false,
+                      [&] { return bb::build_table(f.primal, 2, true, f.n, C, P); }, &tab);
+    if (st != BB_OK) return st;
+    bb::SweepGeom g;
+    g.n = (int)f.n;
+    g.C = C;
+    g.log2P = log2P;
+    g.exact = (f.n % C) == 0;
+    g.m = m;
+    g.ld = ld;
+    g.groups = (m + bb::kWave / P - 1) / (bb::kWave / P);
+    hipError_t e = bb::launch_ch((const double *)tab.ptr, tab.elems, f.primal.cor.q, g, alpha, steps,
+                                 c_in, c_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "Cahn-Hilliard launch");
+    return BB_OK;
+}
+
+size_t bb_mse_workspace_bytes(int64_t n, int64_t m)
+{
+    if (n <= 0 || m <= 0) return 0;
+    return bb::mse_workspace(n, m);
+}
+
+bb_status bb_mse_loss_grad(const double *u, const double *target, double *grad, double *loss_dev,
+                           int64_t n, int64_t m, int64_t ld, void *workspace,
+                           size_t workspace_bytes, void *stream)
+{
+    if (n < 1 || n > bb::kMaxN || m < 1 || ld < m) return fail(BB_ERR_ARG, "bad n, m or ld");
+    if (!u || !target || !grad || !loss_dev) return fail(BB_ERR_ARG, "device pointer is NULL");
+    const size_t need = bb::mse_workspace(n, m);
+    if (workspace_bytes < need || !workspace) return fail(BB_ERR_ARG, "workspace too small");
+    hipError_t e = bb::launch_mse(u, target, grad, loss_dev, (int)n, m, ld, workspace,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mse launch");
+    return BB_OK;
+}
+
+const char *bb_status_string(bb_status s)
+{
+    switch (s) {
+    case BB_OK: return "success";
+    case BB_ERR_ARG: return "invalid argument";
+    case BB_ERR_ZERO_PIVOT: return "zero or non-finite pivot";
+    case BB_ERR_SINGULAR_CAPACITANCE: return "singular periodic-correction capacitance";
+    case BB_ERR_HIP: return "HIP runtime error";
+    case BB_ERR_OOM: return "out of memory";
+    case BB_ERR_UNSUPPORTED: return "unsupported size";
+    }
+    return "unknown status";
+}
+
+const char *bb_last_error_message(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

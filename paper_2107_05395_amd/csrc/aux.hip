@@ -1,0 +1,225 @@
+// aux.hip -- the remaining gfx950 kernels of libbandbatch:
+//   * band gradients of a batched solve, reduced over the batch in a fixed order
+//   * mean-squared-error loss and gradient
+//   * the paper's thread-per-system tridiagonal sweep (Appendix A batched
+//     sweep), kept as the measured baseline design
+#include "internal.h"
+
+namespace bb {
+namespace {
+
+constexpr int kGradR = 4;          // systems per lane in the band-gradient kernel
+constexpr int kGradRows = 32;      // rows per wave strip
+constexpr int kGradSys = kWave * kGradR;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// One wave: rows [i0, i0 + kGradRows) x systems [kb * kGradSys, (kb+1) * kGradSys).
+// part[kb][band][i] = -sum over the wave's systems of lam[i,k] x[i+off,k].
+template <int NB>
+__global__ __launch_bounds__(256) void band_grad_partial(int n, int cyclic, int64_t m, int64_t ld,
+                                                         const double *__restrict__ lam,
+                                                         const double *__restrict__ x,
+                                                         double *__restrict__ part)
+{
+    constexpr int H = NB / 2;
+    const int lane = threadIdx.x % kWave;
+    const int strip = blockIdx.y * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int i0 = strip * kGradRows;
+    if (i0 >= n) return;
+    const int i1 = i0 + kGradRows < n ? i0 + kGradRows : n;
+    const int64_t kb = blockIdx.x;
+    int64_t ks[kGradR];
+    bool kv[kGradR];
+#pragma unroll
+    for (int r = 0; r < kGradR; ++r) {
+        ks[r] = kb * kGradSys + r * kWave + lane;
+        kv[r] = ks[r] < m;
+    }
+    auto load_x = [&](int row, int r) -> double {
+        if (row < 0 || row >= n) {
+            if (!cyclic) return 0.0;
+            row = (row % n + n) % n;
+        }
+        return kv[r] ? x[(int64_t)row * ld + ks[r]] : 0.0;
+    };
+    // sliding window of x rows i-H .. i+H
+    double win[NB][kGradR];
+#pragma unroll
+    for (int w = 0; w < NB - 1; ++w)
+#pragma unroll
+        for (int r = 0; r < kGradR; ++r) win[w + 1][r] = load_x(i0 - H + w, r);
+    double *dst = part + (int64_t)kb * NB * n;
+    for (int i = i0; i < i1; ++i) {
+#pragma unroll
+        for (int w = 0; w < NB - 1; ++w)
+#pragma unroll
+            for (int r = 0; r < kGradR; ++r) win[w][r] = win[w + 1][r];
+#pragma unroll
+        for (int r = 0; r < kGradR; ++r) win[NB - 1][r] = load_x(i + H, r);
+        double acc[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) acc[q] = 0.0;
+#pragma unroll
+        for (int r = 0; r < kGradR; ++r) {
+            const double l = kv[r] ? lam[(int64_t)i * ld + ks[r]] : 0.0;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) acc[q] = fma(l, win[q][r], acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const double s = wave_sum(acc[q]);
+            // entries outside a non-cyclic matrix have no gradient
+            const bool inside = cyclic || (i + q - H >= 0 && i + q - H < n);
+            if (lane == 0) dst[(int64_t)q * n + i] = inside ? -s : 0.0;
+        }
+    }
+}
+
+// grad[q*n + i] += sum over k-blocks (ascending) of part[kb][q][i]
+__global__ __launch_bounds__(256) void band_grad_fold(int64_t total, int64_t kblocks,
+                                                      const double *__restrict__ part,
+                                                      double *__restrict__ grad)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    double s = 0.0;
+    for (int64_t kb = 0; kb < kblocks; ++kb) s += part[kb * total + e];
+    grad[e] += s;
+}
+
+// ---------------------------------------------------------------- MSE
+constexpr int kMseCols = 1024;   // systems per block (4 per thread)
+
+__global__ __launch_bounds__(256) void mse_partial(int n, int64_t m, int64_t ld, double scale,
+                                                   const double *u,
+                                                   const double *__restrict__ y,
+                                                   double *grad,
+                                                   double *__restrict__ part)
+{
+    __shared__ double red[256 / kWave];
+    const int row = blockIdx.y;
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < kMseCols / 256; ++r) {
+        const int64_t k = (int64_t)blockIdx.x * kMseCols + r * 256 + threadIdx.x;
+        if (k < m) {
+            const int64_t idx = (int64_t)row * ld + k;
+            const double d = u[idx] - y[idx];
+            grad[idx] = 2.0 * scale * d;
+            acc = fma(d, d, acc);
+        }
+    }
+    acc = wave_sum(acc);
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < 256 / kWave; ++w) s += red[w];
+        part[(int64_t)row * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void mse_fold(int64_t parts, double scale,
+                                                const double *__restrict__ part,
+                                                double *__restrict__ loss)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t e = threadIdx.x; e < parts; e += 256) s += part[e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = red[0] * scale;
+}
+
+// ---------------------------------------------------------------- baseline
+// One thread per system walks all n rows: forward sweep into x, backward
+// sweep reading x back (the forward intermediate goes through memory).
+// Coefficients are wave-uniform (scalar loads).
+__global__ __launch_bounds__(256) void tri_thread_per_system(const double *__restrict__ rhat,
+                                                             const double *__restrict__ aprime,
+                                                             const double *__restrict__ chat,
+                                                             int n, int64_t m, int64_t ld,
+                                                             const double *rhs, double *x)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    double prev = rhs[k] * rhat[0];
+    x[k] = prev;
+    for (int i = 1; i < n; ++i) {
+        prev = fma(-aprime[i], prev, rhs[(int64_t)i * ld + k] * rhat[i]);
+        x[(int64_t)i * ld + k] = prev;
+    }
+    for (int i = n - 2; i >= 0; --i) {
+        prev = fma(-chat[i], prev, x[(int64_t)i * ld + k]);
+        x[(int64_t)i * ld + k] = prev;
+    }
+}
+
+}  // namespace
+
+size_t band_grad_workspace(int nb, int n, int64_t m)
+{
+    const int64_t kblocks = (m + kGradSys - 1) / kGradSys;
+    return (size_t)kblocks * nb * n * sizeof(double);
+}
+
+hipError_t launch_band_grad(int nb, bool cyclic, int n, int64_t m, int64_t ld, const double *lam,
+                            const double *x, double *grad, void *ws, hipStream_t s)
+{
+    const int64_t kblocks = (m + kGradSys - 1) / kGradSys;
+    const int strips = (n + kGradRows - 1) / kGradRows;
+    const int waves = 256 / kWave;
+    dim3 grid((unsigned)kblocks, (unsigned)((strips + waves - 1) / waves));
+    double *part = (double *)ws;
+    if (nb == 3)
+        hipLaunchKernelGGL(band_grad_partial<3>, grid, dim3(256), 0, s, n, (int)cyclic, m, ld, lam, x, part);
+    else
+        hipLaunchKernelGGL(band_grad_partial<5>, grid, dim3(256), 0, s, n, (int)cyclic, m, ld, lam, x, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t total = (int64_t)nb * n;
+    hipLaunchKernelGGL(band_grad_fold, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, total,
+                       kblocks, (const double *)part, grad);
+    return hipGetLastError();
+}
+
+size_t mse_workspace(int64_t n, int64_t m)
+{
+    return (size_t)n * (size_t)((m + kMseCols - 1) / kMseCols) * sizeof(double);
+}
+
+hipError_t launch_mse(const double *u, const double *target, double *grad, double *loss, int n,
+                      int64_t m, int64_t ld, void *ws, hipStream_t s)
+{
+    const int64_t cols = (m + kMseCols - 1) / kMseCols;
+    const double scale = 1.0 / ((double)n * (double)m);
+    hipLaunchKernelGGL(mse_partial, dim3((unsigned)cols, (unsigned)n), dim3(256), 0, s, n, m, ld,
+                       scale, u, target, grad, (double *)ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mse_fold, dim3(1), dim3(256), 0, s, (int64_t)n * cols, scale,
+                       (const double *)ws, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_tri_thread_per_system(const double *rhat, const double *aprime,
+                                        const double *chat, int n, int64_t m, int64_t ld,
+                                        const double *rhs, double *x, hipStream_t s)
+{
+    const int64_t blocks = (m + 255) / 256;
+    hipLaunchKernelGGL(tri_thread_per_system, dim3((unsigned)blocks), dim3(256), 0, s, rhat,
+                       aprime, chat, n, m, ld, rhs, x);
+    return hipGetLastError();
+}
+
+}  // namespace bb

@@ -1,0 +1,124 @@
+// internal.h -- layouts and launch interfaces shared by the host side
+// (factor.cpp, api.cpp) and the gfx950 kernels (*.hip) of libbandbatch.
+//
+// Work decomposition ("chunked sweep")
+// ------------------------------------
+// The paper gives every system one GPU thread that walks all n rows forward
+// and back (Section 2; Appendix A/B batched sweeps), keeping the forward
+// intermediate in global memory.  Here a system is split into P contiguous
+// chunks of C rows and each chunk is owned by one lane that holds its rows in
+// registers, so the right-hand side is read once and the solution written
+// once.  A wave of 64 lanes holds S = 64/P systems: lane = chunk * S + sys.
+//
+// Both sweeps of a banded LU are order-K linear recurrences (K = 1 tri,
+// K = 2 penta).  The lanes of one system couple only through K numbers at
+// each chunk boundary:
+//   forward  y_i = s_i f_i - l1_i y_{i-1} - l2_i y_{i-2}
+//   backward x_i = y_i - u1_i x_{i+1} - u2_i x_{i+2}
+// Each lane first runs its forward recurrence from a zero history to get its
+// chunk-end state E_j, the lanes combine E_j with the shared KxK chunk
+// transfer matrices Mf_j (prefix scan over chunks), and every lane re-runs its
+// chunk from the true history.  The backward sweep does the same from the
+// right with Mb_j.  The matrices depend only on A, so the host computes them
+// once with the factor.
+//
+// Coefficient table (one per direction, precision and chunk size)
+// ----------------------------------------------------------------
+// NA arrays, each L = P*(C+1) elements long; row r = j*C + t of array q is
+// element [q*L + j*(C+1) + t] (one pad element per chunk keeps the P chunks of
+// a wave in different LDS banks).  Array order:
+//   s, -l1, [-l2], -u1, [-u2], [-z0, [-z1]]  (bracketed: K = 2 / cyclic only)
+// (all but s stored negated, so each recurrence step is a single fma)
+// followed by Mf[P][K][K] and Mb[P][K][K] (row-major KxK).
+//   Mf_j[r][c]: response of y_{end_j - r} to the history component c
+//               (history = (y_{end_{j-1}}, y_{end_{j-1}-1}));
+//   Mb_j[r][c]: response of x_{start_j + r} to the future component c
+//               (future = (x_{start_{j+1}}, x_{start_{j+1}+1})).
+// Rows r >= n are padding: every coefficient 0, so they hold 0 and couple to
+// nothing.  Periodic systems: A = A' + U V^T; the table describes A' and the
+// correction x = y - Z s, s = Q (y_0..y_{K-1}, y_{n-K}..y_{n-1}) uses the
+// per-row z arrays and the K x 2K matrix Q passed by value.
+//
+// Residual table (refinement only, double): the 2K+1 bands of the original
+// matrix in the same padded layout (entries outside the matrix 0; periodic
+// corners are passed separately as 'corner').
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace bb {
+
+constexpr int kWave = 64;
+constexpr int kBlockThreads = 256;   // 4 waves per workgroup for the sweep kernels
+
+// chunk sizes the sweep kernels are instantiated for
+constexpr int kChunkMin = 4;
+constexpr int kChunkMax = 64;
+// Largest system size.  The coefficient tables of a workgroup live in LDS
+// (160 KB per CU); at n = 2048 the largest one (periodic pentadiagonal with
+// FP32 sweeps plus the double residual bands) takes 143 KB.
+constexpr int64_t kMaxN = 2048;
+
+inline int num_arrays(int K, bool cyclic) { return (K == 1 ? 3 : 5) + (cyclic ? K : 0); }
+
+inline int64_t table_len(int K, bool cyclic, int C, int P)
+{
+    return (int64_t)num_arrays(K, cyclic) * P * (C + 1) + 2LL * P * K * K;
+}
+
+// Uniform arguments of a sweep launch.
+struct SweepGeom {
+    int n;          // rows per system
+    int C;          // rows per lane (template parameter of the kernel, repeated for checks)
+    int log2P;      // lanes per system = 1 << log2P
+    int exact;      // n == (number of non-padding chunks) * C
+    int64_t m;      // systems
+    int64_t ld;     // leading dimension (elements) of the interleaved arrays
+    int64_t groups; // ceil(m / S): wave-sized groups of systems
+};
+
+struct CyclicQ {
+    double q[2][4];  // K x 2K, uses q[0][0..1] for K = 1
+};
+
+struct Corners {      // periodic corner entries of the original matrix (refinement residual)
+    double top[2][2];  // K = 2: A[0][n-2], A[0][n-1]; A[1][n-2], A[1][n-1].  K = 1: top[0][1] = A[0][n-1]
+    double bot[2][2];  // K = 2: A[n-2][0], A[n-2][1]; A[n-1][0], A[n-1][1].  K = 1: bot[1][0] = A[n-1][0]
+};
+
+enum class Op : int { Solve = 0, Refine = 1 };
+
+// Launch the chunked sweep kernel.
+//   T_io / T_sweep: double/double (FP64), float/float (FP32), double/float (refine)
+//   table:          device coefficient table in T_sweep (layout above)
+//   band_table:     device residual table (double) -- refine only, else nullptr
+hipError_t launch_sweep(int K, bool cyclic, Op op, bool f32, const void *table,
+                        int64_t table_elems, const double *band_table, int64_t band_elems,
+                        const CyclicQ &q, const Corners &corners, const SweepGeom &g,
+                        const void *in, void *out, hipStream_t stream);
+
+// Cahn-Hilliard steps with the state resident on chip (cyclic penta, double).
+hipError_t launch_ch(const double *table, int64_t table_elems, const CyclicQ &q,
+                     const SweepGeom &g, double alpha, int64_t steps, const double *in,
+                     double *out, hipStream_t stream);
+
+// The paper's thread-per-system mapping (Appendix A), kept as a measured
+// baseline design: forward intermediate written to and re-read from `x`.
+hipError_t launch_tri_thread_per_system(const double *rhat, const double *aprime,
+                                        const double *chat, int n, int64_t m, int64_t ld,
+                                        const double *rhs, double *x, hipStream_t stream);
+
+// Batch-reduced band gradients: partial sums per (k-block, band, row), then a
+// fixed-order fold into grad (+=).
+size_t band_grad_workspace(int nb, int n, int64_t m);
+hipError_t launch_band_grad(int nb, bool cyclic, int n, int64_t m, int64_t ld, const double *lam,
+                            const double *x, double *grad, void *ws, hipStream_t stream);
+
+size_t mse_workspace(int64_t n, int64_t m);
+hipError_t launch_mse(const double *u, const double *target, double *grad, double *loss, int n,
+                      int64_t m, int64_t ld, void *ws, hipStream_t stream);
+
+}  // namespace bb

@@ -1,0 +1,673 @@
+// sweep.hip -- gfx950 kernels for batched banded solves with one shared LHS.
+//
+// Forward elimination + back substitution of the Thomas algorithm (Section
+// 3.1; Appendix A batched sweep) and of the pentadiagonal LR solve (Section
+// 4.1; Appendix B), on right-hand sides interleaved with the batch index
+// fastest (Section 2).  The decomposition of a system over P lanes, the
+// coefficient table and its LDS layout are described in internal.h.
+//
+// Per lane: load the C rows of its chunk (one coalesced wave-wide load per
+// row), run the two recurrences in registers with the chunk-boundary scans,
+// apply the periodic correction if any, store once.  HBM traffic is one read
+// of the right-hand side and one write of the solution; coefficients come
+// from LDS, where each workgroup stages the shared table once.
+#include "internal.h"
+
+namespace bb {
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T shfl(T v, int src)
+{
+    return __shfl(v, src, kWave);
+}
+
+// Opaque copies of loop-invariant values.  The persistent loops below would
+// otherwise let the compiler hoist every per-row LDS coefficient read and
+// every per-row address offset out of the loop and keep them all live in
+// registers; re-reading them each iteration is what the design wants.
+__device__ __forceinline__ int opaque_v(int x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+__device__ __forceinline__ int64_t opaque_s(int64_t x)
+{
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
+// Scheduling fence: nothing moves across it.  Placed every few rows and
+// between passes so coefficient reads are issued a short distance ahead of
+// their use instead of all at once.
+constexpr int kFenceRows = 8;
+__device__ __forceinline__ void fence_rows(int t)
+{
+    if (t % kFenceRows == kFenceRows - 1) __builtin_amdgcn_sched_barrier(0);
+}
+
+// runtime-indexed read of a register array without spilling it: C selects
+template <typename T, int C>
+__device__ __forceinline__ T pick(const T (&v)[C], int t)
+{
+    T r = T(0);
+#pragma unroll
+    for (int q = 0; q < C; ++q) r = (q == t) ? v[q] : r;
+    return r;
+}
+
+// Where this lane sits: chunk j of system slot sl in a wave of S systems.
+struct LaneGeom {
+    int j, sl, S, P;
+};
+
+// This lane's view of a coefficient table staged in LDS.
+template <typename T, int K, bool CYC>
+struct LaneTable {
+    const T *s, *l1, *l2, *u1, *u2, *z0, *z1;
+    const T *Mf, *Mb;
+};
+
+template <typename T, int K, int C, bool CYC>
+__device__ __forceinline__ LaneTable<T, K, CYC> lane_table(const T *lds, int P, int j)
+{
+    const int L = P * (C + 1);
+    const int off = j * (C + 1);
+    LaneTable<T, K, CYC> tb;
+    int q = 0;
+    tb.s = lds + (q++) * L + off;
+    tb.l1 = lds + (q++) * L + off;
+    tb.l2 = (K == 2) ? lds + (q++) * L + off : nullptr;
+    tb.u1 = lds + (q++) * L + off;
+    tb.u2 = (K == 2) ? lds + (q++) * L + off : nullptr;
+    tb.z0 = CYC ? lds + (q++) * L + off : nullptr;
+    tb.z1 = (CYC && K == 2) ? lds + (q++) * L + off : nullptr;
+    tb.Mf = lds + q * L;
+    tb.Mb = tb.Mf + P * K * K;
+    return tb;
+}
+
+// Gather rows 0, 1, n-2, n-1 of the system this lane works on (every lane of
+// the system gets the same four values).  Row n-1 / n-2 sit at a compile-time
+// position when the chunks tile n exactly, else they are picked at run time.
+template <typename T, int K, int C>
+__device__ __forceinline__ void gather_ends(const T (&v)[C], const LaneGeom &lg, int n, int exact,
+                                            T &r0, T &r1, T &rn2, T &rn1)
+{
+    r0 = shfl(v[0], lg.sl);
+    r1 = (K == 2) ? shfl(v[1], lg.sl) : T(0);
+    if (exact) {
+        const int src = (n / C - 1) * lg.S + lg.sl;
+        rn1 = shfl(v[C - 1], src);
+        rn2 = (K == 2) ? shfl(v[C - 2], src) : T(0);
+    } else {
+        rn1 = shfl(pick(v, (n - 1) % C), ((n - 1) / C) * lg.S + lg.sl);
+        rn2 = (K == 2) ? shfl(pick(v, (n - 2) % C), ((n - 2) / C) * lg.S + lg.sl) : T(0);
+    }
+}
+
+// Solve this lane's chunk in place: v holds the right-hand side rows on entry
+// and the solution rows on exit.  All 64 lanes of the wave must call it
+// together (the scans shuffle across the wave).  The table stores the
+// off-diagonal recurrence coefficients and z negated, so every step is one
+// fma.  Each pass re-derives its LDS pointers from an opaque base so the
+// compiler re-reads the coefficients instead of keeping C of them live.
+template <typename T, int K, int C, bool CYC>
+__device__ __forceinline__ void chunk_solve(T (&v)[C], const T *lds, const LaneGeom &lg, int n,
+                                            int exact, const CyclicQ &cq)
+{
+    __builtin_amdgcn_sched_barrier(0);
+    // pass 1: v <- s f in place, forward recurrence from a zero history
+    T y1 = T(0), y2 = T(0);
+    {
+        const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
+#pragma unroll
+        for (int t = 0; t < C; ++t) {
+            v[t] *= tb.s[t];
+            T y = v[t];
+            if constexpr (K == 2) y = fma(tb.l2[t], y2, y);
+            y = fma(tb.l1[t], y1, y);
+            y2 = y1;
+            y1 = y;
+            fence_rows(t);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // scan over the chunks before this one: true history (y_{start-1}, y_{start-2})
+    T h1 = T(0), h2 = T(0);
+    {
+        const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
+        for (int i = 0; i < lg.P; ++i) {
+            const int src = i * lg.S + lg.sl;
+            const T e1 = shfl(y1, src);
+            const T e2 = (K == 2) ? shfl(y2, src) : T(0);
+            if (i < lg.j) {
+                const T *M = tb.Mf + i * K * K;
+                if constexpr (K == 1) {
+                    h1 = fma(M[0], h1, e1);
+                } else {
+                    const T n1 = fma(M[1], h2, fma(M[0], h1, e1));
+                    const T n2 = fma(M[3], h2, fma(M[2], h1, e2));
+                    h1 = n1;
+                    h2 = n2;
+                }
+            }
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // pass 2: forward recurrence again, from the true history
+    {
+        const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
+        y1 = h1;
+        y2 = h2;
+#pragma unroll
+        for (int t = 0; t < C; ++t) {
+            T y = v[t];
+            if constexpr (K == 2) y = fma(tb.l2[t], y2, y);
+            y = fma(tb.l1[t], y1, y);
+            v[t] = y;
+            y2 = y1;
+            y1 = y;
+            fence_rows(t);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // pass 3: backward recurrence from a zero future: chunk-start state
+    T x1 = T(0), x2 = T(0);
+    {
+        const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
+#pragma unroll
+        for (int t = C - 1; t >= 0; --t) {
+            T x = v[t];
+            if constexpr (K == 2) x = fma(tb.u2[t], x2, x);
+            x = fma(tb.u1[t], x1, x);
+            x2 = x1;
+            x1 = x;
+            fence_rows(C - 1 - t);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // scan over the chunks after this one: true future (x_{end+1}, x_{end+2})
+    T f1 = T(0), f2 = T(0);
+    {
+        const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
+        for (int i = lg.P - 1; i >= 0; --i) {
+            const int src = i * lg.S + lg.sl;
+            const T s1 = shfl(x1, src);
+            const T s2 = (K == 2) ? shfl(x2, src) : T(0);
+            if (i > lg.j) {
+                const T *M = tb.Mb + i * K * K;
+                if constexpr (K == 1) {
+                    f1 = fma(M[0], f1, s1);
+                } else {
+                    const T n1 = fma(M[1], f2, fma(M[0], f1, s1));
+                    const T n2 = fma(M[3], f2, fma(M[2], f1, s2));
+                    f1 = n1;
+                    f2 = n2;
+                }
+            }
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // pass 4: backward recurrence again, from the true future
+    {
+        const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
+        x1 = f1;
+        x2 = f2;
+#pragma unroll
+        for (int t = C - 1; t >= 0; --t) {
+            T x = v[t];
+            if constexpr (K == 2) x = fma(tb.u2[t], x2, x);
+            x = fma(tb.u1[t], x1, x);
+            v[t] = x;
+            x2 = x1;
+            x1 = x;
+            fence_rows(C - 1 - t);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (CYC) {
+        // x = y - Z s,  s = Q (y_0 .. y_{K-1}, y_{n-K} .. y_{n-1})
+        T r0, r1, rn2, rn1;
+        gather_ends<T, K, C>(v, lg, n, exact, r0, r1, rn2, rn1);
+        T s0, s1 = T(0);
+        if constexpr (K == 1) {
+            s0 = T(cq.q[0][0]) * r0 + T(cq.q[0][1]) * rn1;
+        } else {
+            s0 = T(cq.q[0][0]) * r0 + T(cq.q[0][1]) * r1 + T(cq.q[0][2]) * rn2 + T(cq.q[0][3]) * rn1;
+            s1 = T(cq.q[1][0]) * r0 + T(cq.q[1][1]) * r1 + T(cq.q[1][2]) * rn2 + T(cq.q[1][3]) * rn1;
+        }
+        const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
+#pragma unroll
+        for (int t = 0; t < C; ++t) {
+            T x = fma(tb.z0[t], s0, v[t]);
+            if constexpr (K == 2) x = fma(tb.z1[t], s1, x);
+            v[t] = x;
+            fence_rows(t);
+        }
+    }
+}
+
+// Workgroup -> group-of-systems mapping.  Workgroups are dealt round-robin to
+// the 8 XCDs; give each XCD a contiguous range of groups so that the partly
+// used cache lines at group boundaries are shared inside one L2.
+struct GroupRange {
+    int64_t first, end, stride;
+};
+
+__device__ __forceinline__ GroupRange group_range(int64_t groups)
+{
+    constexpr int kXcd = 8;
+    const int waves_per_block = blockDim.x / kWave;
+    const int wave = threadIdx.x / kWave;
+    const int xcd = blockIdx.x % kXcd;
+    const int64_t blocks_per_xcd = gridDim.x / kXcd;   // host launches a multiple of 8
+    const int64_t local_block = blockIdx.x / kXcd;
+    const int64_t per_xcd = (groups + kXcd - 1) / kXcd;
+    GroupRange r;
+    const int64_t base = (int64_t)xcd * per_xcd;
+    r.first = base + local_block * waves_per_block + wave;
+    r.end = base + per_xcd < groups ? base + per_xcd : groups;
+    r.stride = blocks_per_xcd * waves_per_block;
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_table(T *lds, const T *__restrict__ table, int64_t elems)
+{
+    for (int64_t e = threadIdx.x; e < elems; e += blockDim.x) lds[e] = table[e];
+}
+
+// Load the C rows of this lane's chunk; column k must be in bounds.
+// FULL: every row of every chunk is a real row, no predicates at all.
+// Ragged: the row pointer stops at row n-1 (in bounds) and rows past n read 0.
+// The stride is laundered once per call so the C row offsets are recomputed
+// here rather than hoisted out of the persistent loop and kept live.
+template <typename T, int C, bool FULL>
+__device__ __forceinline__ void load_chunk(T (&v)[C], const T *base, int row0, int64_t k,
+                                           int64_t ld, int n)
+{
+    ld = opaque_s(ld);
+    if constexpr (FULL) {
+        const T *p = base + (int64_t)row0 * ld + k;
+#pragma unroll
+        for (int t = 0; t < C; ++t) v[t] = p[(int64_t)t * ld];
+    } else {
+        const int nv = opaque_v(n - row0);   // rows of this chunk that are real
+        const T *p = base + (int64_t)(row0 < n ? row0 : n - 1) * ld + k;
+#pragma unroll
+        for (int t = 0; t < C; ++t) {
+            const T x = *p;
+            v[t] = t < nv ? x : T(0);
+            p += (t + 1 < nv) ? ld : 0;
+        }
+    }
+}
+
+// Store the chunk; the caller masks out lanes whose column is past m.  Ragged:
+// the pointer stops at row n-1 and the rows past n rewrite row n-1 with its
+// own value, so no store is predicated per row.
+template <typename T, int C, bool FULL>
+__device__ __forceinline__ void store_chunk(const T (&v)[C], T *base, int row0, int64_t k,
+                                            int64_t ld, int n)
+{
+    ld = opaque_s(ld);
+    if constexpr (FULL) {
+        T *p = base + (int64_t)row0 * ld + k;
+#pragma unroll
+        for (int t = 0; t < C; ++t) p[(int64_t)t * ld] = v[t];
+    } else if (row0 < n) {
+        const int nv = opaque_v(n - row0);
+        T *p = base + (int64_t)row0 * ld + k;
+        T keep = v[0];
+#pragma unroll
+        for (int t = 0; t < C; ++t) {
+            keep = t < nv ? v[t] : keep;
+            *p = keep;
+            p += (t + 1 < nv) ? ld : 0;
+        }
+    }
+}
+
+// Lane coordinates inside a wave of S = 64/P systems: lane = chunk * S + slot.
+__device__ __forceinline__ LaneGeom lane_geom(int log2P)
+{
+    LaneGeom lg;
+    lg.P = 1 << log2P;
+    lg.S = kWave >> log2P;
+    const int lane = threadIdx.x % kWave;
+    lg.j = lane >> (6 - log2P);
+    lg.sl = lane & (lg.S - 1);
+    return lg;
+}
+
+// ---------------------------------------------------------------- solve
+template <typename T, int K, int C, bool CYC, bool FULL>
+__global__ __launch_bounds__(kBlockThreads) void sweep_kernel(const T *__restrict__ table,
+                                                              int64_t table_elems, CyclicQ cq,
+                                                              SweepGeom g, const T *in, T *out)
+{
+    extern __shared__ double smem_d[];
+    T *lds = reinterpret_cast<T *>(smem_d);
+    stage_table(lds, table, table_elems);
+    __syncthreads();
+
+    const LaneGeom lg = lane_geom(g.log2P);
+    const int row0 = lg.j * C;
+    const GroupRange gr = group_range(g.groups);
+    for (int64_t grp = gr.first; grp < gr.end; grp += gr.stride) {
+        const int64_t k = grp * lg.S + lg.sl;
+        const bool kval = k < g.m;
+        T v[C];
+        load_chunk<T, C, FULL>(v, in, row0, kval ? k : g.m - 1, g.ld, g.n);
+        chunk_solve<T, K, C, CYC>(v, lds, lg, g.n, FULL || g.exact, cq);
+        if (kval) store_chunk<T, C, FULL>(v, out, row0, k, g.ld, g.n);
+    }
+}
+
+// ---------------------------------------------------------------- refine
+// x0 = solve_f32(b); r = b - A x0 in double with the original bands;
+// x = x0 + solve_f32(r), stored as double.
+template <int K, int C, bool CYC, bool FULL>
+__global__ __launch_bounds__(kBlockThreads) void refine_kernel(
+    const float *__restrict__ table, int64_t table_elems, const double *__restrict__ band_table,
+    int64_t band_elems, CyclicQ cq, Corners cn, SweepGeom g, const double *in, double *out)
+{
+    extern __shared__ double smem_d[];
+    double *lds_band = smem_d;
+    float *lds = reinterpret_cast<float *>(smem_d + band_elems);
+    stage_table(lds_band, band_table, band_elems);
+    stage_table(lds, table, table_elems);
+    __syncthreads();
+
+    const LaneGeom lg = lane_geom(g.log2P);
+    const int lane = threadIdx.x % kWave;
+    const int L = lg.P * (C + 1);
+    const int row0 = lg.j * C;
+    const bool has_left = lg.j > 0, has_right = lg.j < lg.P - 1;
+    const int left = has_left ? lane - lg.S : lane;
+    const int right = has_right ? lane + lg.S : lane;
+    const int exact = FULL || g.exact;
+    const GroupRange gr = group_range(g.groups);
+
+    for (int64_t grp = gr.first; grp < gr.end; grp += gr.stride) {
+        const int64_t k = grp * lg.S + lg.sl;
+        const bool kval = k < g.m;
+        double b[C];
+        load_chunk<double, C, FULL>(b, in, row0, kval ? k : g.m - 1, g.ld, g.n);
+        float x0[C];
+#pragma unroll
+        for (int t = 0; t < C; ++t) x0[t] = (float)b[t];
+        chunk_solve<float, K, C, CYC>(x0, lds, lg, g.n, exact, cq);
+        __builtin_amdgcn_sched_barrier(0);
+
+        // neighbours across the chunk boundaries (zero outside the matrix)
+        float xl1 = shfl(x0[C - 1], left), xl2 = shfl(x0[C - 2], left);
+        float xr1 = shfl(x0[0], right), xr2 = shfl(x0[1], right);
+        if (!has_left) xl1 = xl2 = 0.f;
+        if (!has_right) xr1 = xr2 = 0.f;
+        double ctop0 = 0.0, ctop1 = 0.0, cbot2 = 0.0, cbot1 = 0.0;
+        if constexpr (CYC) {
+            float r0, r1, rn2, rn1;
+            gather_ends<float, K, C>(x0, lg, g.n, exact, r0, r1, rn2, rn1);
+            if constexpr (K == 1) {
+                ctop0 = cn.top[0][1] * (double)rn1;
+                cbot1 = cn.bot[1][0] * (double)r0;
+            } else {
+                ctop0 = cn.top[0][0] * (double)rn2 + cn.top[0][1] * (double)rn1;
+                ctop1 = cn.top[1][0] * (double)rn2 + cn.top[1][1] * (double)rn1;
+                cbot2 = cn.bot[0][0] * (double)r0 + cn.bot[0][1] * (double)r1;
+                cbot1 = cn.bot[1][0] * (double)r0 + cn.bot[1][1] * (double)r1;
+            }
+        }
+        const int nrow = opaque_v(g.n - row0);   // this chunk's row index of row n (may be <= 0 or > C)
+        const double *band[5];
+        {
+            const int off = opaque_v(lg.j * (C + 1));
+#pragma unroll
+            for (int q = 0; q < 2 * K + 1; ++q) band[q] = lds_band + q * L + off;
+        }
+        float dx[C];
+#pragma unroll
+        for (int t = 0; t < C; ++t) {
+            const double xm1 = t >= 1 ? (double)x0[t - 1] : (double)xl1;
+            const double xp1 = t + 1 < C ? (double)x0[t + 1] : (double)xr1;
+            double ax = band[K][t] * (double)x0[t];
+            ax = fma(band[K - 1][t], xm1, ax);
+            ax = fma(band[K + 1][t], xp1, ax);
+            if constexpr (K == 2) {
+                const double xm2 = t >= 2 ? (double)x0[t - 2] : (t == 1 ? (double)xl1 : (double)xl2);
+                const double xp2 = t + 2 < C ? (double)x0[t + 2]
+                                             : (t + 1 < C ? (double)xr1 : (double)xr2);
+                ax = fma(band[0][t], xm2, ax);
+                ax = fma(band[4][t], xp2, ax);
+            }
+            double r = b[t] - ax;
+            if constexpr (CYC) {
+                // corner terms of the periodic matrix: rows 0, 1 (chunk 0) and n-2, n-1
+                if (t == 0) r -= (lg.j == 0) ? ctop0 : 0.0;
+                if constexpr (K == 2) {
+                    if (t == 1) r -= (lg.j == 0) ? ctop1 : 0.0;
+                    r -= (t == nrow - 2) ? cbot2 : 0.0;
+                }
+                r -= (t == nrow - 1) ? cbot1 : 0.0;
+            }
+            if constexpr (!FULL) r = t < nrow ? r : 0.0;
+            dx[t] = (float)r;
+            fence_rows(t);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        chunk_solve<float, K, C, CYC>(dx, lds, lg, g.n, exact, cq);
+        double xo[C];
+#pragma unroll
+        for (int t = 0; t < C; ++t) xo[t] = (double)x0[t] + (double)dx[t];
+        if (kval) store_chunk<double, C, FULL>(xo, out, row0, k, g.ld, g.n);
+    }
+}
+
+// ---------------------------------------------------------------- Cahn-Hilliard
+// `steps` steps of C <- A^{-1} (C + alpha d2(C^3 - C)), periodic, state in registers.
+__device__ __forceinline__ double ch_nl(double c) { return fma(c * c, c, -c); }
+
+template <int C, bool FULL>
+__global__ __launch_bounds__(kBlockThreads) void ch_kernel(const double *__restrict__ table,
+                                                           int64_t table_elems, CyclicQ cq,
+                                                           SweepGeom g, double alpha,
+                                                           int64_t steps, const double *in,
+                                                           double *out)
+{
+    extern __shared__ double smem_d[];
+    stage_table(smem_d, table, table_elems);
+    __syncthreads();
+
+    const LaneGeom lg = lane_geom(g.log2P);
+    const int lane = threadIdx.x % kWave;
+    const int row0 = lg.j * C;
+    const bool has_left = lg.j > 0, has_right = lg.j < lg.P - 1;
+    const int left = has_left ? lane - lg.S : lane;
+    const int right = has_right ? lane + lg.S : lane;
+    const int exact = FULL || g.exact;
+    const GroupRange gr = group_range(g.groups);
+
+    for (int64_t grp = gr.first; grp < gr.end; grp += gr.stride) {
+        const int64_t k = grp * lg.S + lg.sl;
+        const bool kval = k < g.m;
+        double c[C];
+        load_chunk<double, C, FULL>(c, in, row0, kval ? k : g.m - 1, g.ld, g.n);
+
+        for (int64_t step = 0; step < steps; ++step) {
+            double cl = shfl(c[C - 1], left), cr = shfl(c[0], right);
+            if (!has_left) cl = 0.0;
+            if (!has_right) cr = 0.0;
+            double r0, r1, rn2, rn1;
+            gather_ends<double, 2, C>(c, lg, g.n, exact, r0, r1, rn2, rn1);
+            const double wrap_first = alpha * ch_nl(rn1);   // row 0 sees row n-1 on its left
+            const double wrap_last = alpha * ch_nl(r0);     // row n-1 sees row 0 on its right
+            const int nrow = opaque_v(g.n - row0);
+            double nprev = ch_nl(cl), ncur = ch_nl(c[0]);
+#pragma unroll
+            for (int t = 0; t < C; ++t) {
+                const double nnext = ch_nl(t + 1 < C ? c[t + 1] : cr);
+                double f = fma(alpha, nprev - 2.0 * ncur + nnext, c[t]);
+                if (t == 0) f += (lg.j == 0) ? wrap_first : 0.0;
+                f += (t == nrow - 1) ? wrap_last : 0.0;
+                if constexpr (!FULL) f = t < nrow ? f : 0.0;
+                c[t] = f;
+                nprev = ncur;
+                ncur = nnext;
+                fence_rows(t);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            chunk_solve<double, 2, C, true>(c, smem_d, lg, g.n, exact, cq);
+        }
+        if (kval) store_chunk<double, C, FULL>(c, out, row0, k, g.ld, g.n);
+    }
+}
+
+// ---------------------------------------------------------------- launch helpers
+int cu_count()
+{
+    static int cached = 0;
+    if (!cached) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            cus > 0)
+            cached = cus;
+        else
+            return 256;
+    }
+    return cached;
+}
+
+// Persistent-style launch: as many workgroups as can be resident at once
+// (rounded to a multiple of the 8 XCDs), each looping over groups of systems.
+template <typename... KArgs, typename... Args>
+hipError_t launch_grid(void (*kern)(KArgs...), size_t lds, int64_t groups, hipStream_t s,
+                       Args... args)
+{
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlockThreads, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    const int waves_per_block = kBlockThreads / kWave;
+    int64_t need = (groups + waves_per_block - 1) / waves_per_block;
+    int64_t cap = (int64_t)cu_count() * per_cu;
+    int64_t blocks = need < cap ? need : cap;
+    blocks = ((blocks + 7) / 8) * 8;   // multiple of the XCD count, see group_range
+    if (blocks < 8) blocks = 8;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kBlockThreads), lds, s, args...);
+    return hipGetLastError();
+}
+
+bool is_full(const SweepGeom &g) { return ((int64_t)g.C << g.log2P) == g.n; }
+
+template <typename T, int K, bool CYC, int C>
+hipError_t sweep_c(const void *table, int64_t table_elems, const CyclicQ &q, const SweepGeom &g,
+                   const void *in, void *out, hipStream_t stream)
+{
+    const size_t lds = (size_t)table_elems * sizeof(T);
+    if (is_full(g))
+        return launch_grid(sweep_kernel<T, K, C, CYC, true>, lds, g.groups, stream,
+                           (const T *)table, table_elems, q, g, (const T *)in, (T *)out);
+    return launch_grid(sweep_kernel<T, K, C, CYC, false>, lds, g.groups, stream, (const T *)table,
+                       table_elems, q, g, (const T *)in, (T *)out);
+}
+
+template <int K, bool CYC, int C>
+hipError_t refine_c(const void *table, int64_t table_elems, const double *band,
+                    int64_t band_elems, const CyclicQ &q, const Corners &cn, const SweepGeom &g,
+                    const void *in, void *out, hipStream_t stream)
+{
+    const size_t lds = (size_t)band_elems * sizeof(double) + (size_t)table_elems * sizeof(float);
+    if (is_full(g))
+        return launch_grid(refine_kernel<K, C, CYC, true>, lds, g.groups, stream,
+                           (const float *)table, table_elems, band, band_elems, q, cn, g,
+                           (const double *)in, (double *)out);
+    return launch_grid(refine_kernel<K, C, CYC, false>, lds, g.groups, stream, (const float *)table,
+                       table_elems, band, band_elems, q, cn, g, (const double *)in, (double *)out);
+}
+
+template <typename T, int K, bool CYC>
+hipError_t sweep_dispatch(const void *table, int64_t te, const CyclicQ &q, const SweepGeom &g,
+                          const void *in, void *out, hipStream_t s)
+{
+    switch (g.C) {
+    case 4: return sweep_c<T, K, CYC, 4>(table, te, q, g, in, out, s);
+    case 8: return sweep_c<T, K, CYC, 8>(table, te, q, g, in, out, s);
+    case 16: return sweep_c<T, K, CYC, 16>(table, te, q, g, in, out, s);
+    case 32: return sweep_c<T, K, CYC, 32>(table, te, q, g, in, out, s);
+    case 64: return sweep_c<T, K, CYC, 64>(table, te, q, g, in, out, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int K, bool CYC>
+hipError_t refine_dispatch(const void *table, int64_t te, const double *band, int64_t be,
+                           const CyclicQ &q, const Corners &cn, const SweepGeom &g,
+                           const void *in, void *out, hipStream_t s)
+{
+    switch (g.C) {
+    case 4: return refine_c<K, CYC, 4>(table, te, band, be, q, cn, g, in, out, s);
+    case 8: return refine_c<K, CYC, 8>(table, te, band, be, q, cn, g, in, out, s);
+    case 16: return refine_c<K, CYC, 16>(table, te, band, be, q, cn, g, in, out, s);
+    case 32: return refine_c<K, CYC, 32>(table, te, band, be, q, cn, g, in, out, s);
+    case 64: return refine_c<K, CYC, 64>(table, te, band, be, q, cn, g, in, out, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_sweep(int K, bool cyclic, Op op, bool f32, const void *table,
+                        int64_t table_elems, const double *band_table, int64_t band_elems,
+                        const CyclicQ &q, const Corners &cn, const SweepGeom &g, const void *in,
+                        void *out, hipStream_t s)
+{
+    if (op == Op::Refine) {
+        if (K == 1) return cyclic ? refine_dispatch<1, true>(table, table_elems, band_table, band_elems, q, cn, g, in, out, s)
+                                  : refine_dispatch<1, false>(table, table_elems, band_table, band_elems, q, cn, g, in, out, s);
+        return cyclic ? refine_dispatch<2, true>(table, table_elems, band_table, band_elems, q, cn, g, in, out, s)
+                      : refine_dispatch<2, false>(table, table_elems, band_table, band_elems, q, cn, g, in, out, s);
+    }
+    if (f32) {
+        if (K == 1) return cyclic ? sweep_dispatch<float, 1, true>(table, table_elems, q, g, in, out, s)
+                                  : sweep_dispatch<float, 1, false>(table, table_elems, q, g, in, out, s);
+        return cyclic ? sweep_dispatch<float, 2, true>(table, table_elems, q, g, in, out, s)
+                      : sweep_dispatch<float, 2, false>(table, table_elems, q, g, in, out, s);
+    }
+    if (K == 1) return cyclic ? sweep_dispatch<double, 1, true>(table, table_elems, q, g, in, out, s)
+                              : sweep_dispatch<double, 1, false>(table, table_elems, q, g, in, out, s);
+    return cyclic ? sweep_dispatch<double, 2, true>(table, table_elems, q, g, in, out, s)
+                  : sweep_dispatch<double, 2, false>(table, table_elems, q, g, in, out, s);
+}
+
+hipError_t launch_ch(const double *table, int64_t table_elems, const CyclicQ &q,
+                     const SweepGeom &g, double alpha, int64_t steps, const double *in,
+                     double *out, hipStream_t s)
+{
+    const size_t lds = (size_t)table_elems * sizeof(double);
+#define BB_CH(CC)                                                                              \
+    case CC:                                                                                   \
+        return is_full(g) ? launch_grid(ch_kernel<CC, true>, lds, g.groups, s, table,           \
+                                        table_elems, q, g, alpha, steps, in, out)               \
+                          : launch_grid(ch_kernel<CC, false>, lds, g.groups, s, table,          \
+                                        table_elems, q, g, alpha, steps, in, out);
+    switch (g.C) {
+        BB_CH(4)
+        BB_CH(8)
+        BB_CH(16)
+        BB_CH(32)
+        BB_CH(64)
+    default: return hipErrorInvalidValue;
+    }
+#undef BB_CH
+}
+
+}  // namespace bb

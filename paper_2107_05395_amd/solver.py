@@ -1,0 +1,195 @@
+"""Python face of libbandbatch: shared-matrix factors and batched solves on
+torch device tensors.  Argument marshalling only -- every operation on a
+batch runs in the library's HIP kernels.
+
+A batch of m systems of size n is an (n, m) tensor, or an (n, m) view with
+strides (ld, 1) into a wider array: element i of system k at [i, k], the
+interleaved layout of Carroll et al. (arXiv:2107.05395), Section 2.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BandBatchError, check, dptr, lib
+
+KINDS = ("tri", "tri_cyclic", "penta", "penta_cyclic")
+
+
+def _stream_ptr(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _batch_view(t: torch.Tensor, n: int, dtype: torch.dtype, what: str):
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % what)
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (what, dtype, t.dtype))
+    if t.dim() != 2 or t.shape[0] != n:
+        raise ValueError("%s must have shape (n=%d, m), got %s" % (what, n, tuple(t.shape)))
+    m = t.shape[1]
+    if m > 1 and t.stride(1) != 1:
+        raise ValueError("%s must have unit stride along the batch" % what)
+    ld = t.stride(0) if n > 1 else max(m, 1)
+    if ld < max(m, 1):
+        raise ValueError("%s: leading dimension %d < m = %d" % (what, ld, m))
+    return m, ld
+
+
+class Factor:
+    """One shared left-hand-side matrix, factorised once on the host.
+
+    Bands are host sequences of length n (see include/bandbatch.h for which
+    entries are ignored or are periodic corners)."""
+
+    def __init__(self, kind: str, bands, n: int, handle):
+        self.kind = kind
+        self.n = n
+        self.nbands = 3 if kind.startswith("tri") else 5
+        self.cyclic = kind.endswith("cyclic")
+        self._handle = handle
+        self._bands = bands   # float64 numpy copies, kept for reference
+
+    @classmethod
+    def _make(cls, kind: str, bands, cyclic: bool):
+        arrs = [np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(-1)) for b in bands]
+        n = arrs[0].shape[0]
+        if any(a.shape[0] != n for a in arrs):
+            raise ValueError("all bands must have the same length")
+        full = kind + ("_cyclic" if cyclic else "")
+        h = ctypes.c_void_p()
+        fn = getattr(lib(), "bb_factor_shared_" + full)
+        check(fn(*(dptr(a) for a in arrs), n, ctypes.byref(h)))
+        return cls(full, arrs, n, h)
+
+    @classmethod
+    def tri(cls, a, b, c, cyclic: bool = False) -> "Factor":
+        return cls._make("tri", (a, b, c), cyclic)
+
+    @classmethod
+    def penta(cls, a, b, c, d, e, cyclic: bool = False) -> "Factor":
+        return cls._make("penta", (a, b, c, d, e), cyclic)
+
+    def __del__(self):
+        h = getattr(self, "_handle", None)
+        if h is not None and h.value:
+            try:
+                lib().bb_factor_destroy(h)
+            except Exception:
+                pass
+            self._handle = None
+
+    @property
+    def handle(self):
+        return self._handle
+
+    def chunk(self) -> int:
+        c = ctypes.c_int32()
+        check(lib().bb_factor_info(self._handle, None, None, ctypes.byref(c)))
+        return c.value
+
+    def upload(self, device=None) -> None:
+        with torch.cuda.device(device if device is not None else torch.cuda.current_device()):
+            check(lib().bb_factor_upload(self._handle, None))
+
+    # ------------------------------------------------------------ solves
+    def _run(self, fname: str, rhs: torch.Tensor, out, precision: str):
+        if precision not in _lib.PRECISION:
+            raise ValueError("precision must be one of %s" % list(_lib.PRECISION))
+        dtype = torch.float32 if precision == "f32" else torch.float64
+        m, ld = _batch_view(rhs, self.n, dtype, "rhs")
+        if out is None:
+            out = torch.empty_like(rhs)
+        m2, ld2 = _batch_view(out, self.n, dtype, "out")
+        if (m2, ld2) != (m, ld) or out.device != rhs.device:
+            raise ValueError("out must match rhs in shape, strides and device")
+        with torch.cuda.device(rhs.device):
+            check(getattr(lib(), fname)(self._handle, ctypes.c_void_p(rhs.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), m, ld,
+                                        _lib.PRECISION[precision], _stream_ptr(rhs)))
+        return out
+
+    def solve(self, rhs: torch.Tensor, out: torch.Tensor | None = None,
+              precision: str = "f64") -> torch.Tensor:
+        """x = A^{-1} rhs for every column (out may be rhs: in place)."""
+        return self._run("bb_solve_batch_" + self.kind.replace("_cyclic", ""), rhs, out, precision)
+
+    def adjoint(self, g: torch.Tensor, out: torch.Tensor | None = None,
+                precision: str = "f64") -> torch.Tensor:
+        """lam = A^{-T} g for every column."""
+        return self._run("bb_solve_batch_" + self.kind.replace("_cyclic", "") + "_adjoint", g, out,
+                         precision)
+
+    def solve_thread_per_system(self, rhs: torch.Tensor, out: torch.Tensor | None = None):
+        """The paper's one-thread-per-system sweep (baseline design; tri, double)."""
+        m, ld = _batch_view(rhs, self.n, torch.float64, "rhs")
+        if out is None:
+            out = torch.empty_like(rhs)
+        with torch.cuda.device(rhs.device):
+            check(lib().bb_solve_batch_tri_thread_per_system(
+                self._handle, ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                m, ld, _stream_ptr(rhs)))
+        return out
+
+    def band_grad(self, lam: torch.Tensor, x: torch.Tensor,
+                  grad: torch.Tensor | None = None) -> torch.Tensor:
+        """grad[band, i] += -sum_k lam[i,k] x[i+band-nb/2, k]  ->  (nbands, n) float64."""
+        m, ld = _batch_view(lam, self.n, torch.float64, "lam")
+        if _batch_view(x, self.n, torch.float64, "x") != (m, ld):
+            raise ValueError("x must match lam in shape and strides")
+        if grad is None:
+            grad = torch.zeros(self.nbands, self.n, dtype=torch.float64, device=lam.device)
+        if grad.shape != (self.nbands, self.n) or grad.dtype != torch.float64 or not grad.is_contiguous():
+            raise ValueError("grad must be a contiguous (nbands, n) float64 tensor")
+        nbytes = lib().bb_band_grad_workspace_bytes(self._handle, m)
+        ws = torch.empty(max(nbytes, 8), dtype=torch.uint8, device=lam.device)
+        with torch.cuda.device(lam.device):
+            check(lib().bb_band_grad(self._handle, ctypes.c_void_p(lam.data_ptr()),
+                                     ctypes.c_void_p(x.data_ptr()), m, ld,
+                                     ctypes.c_void_p(grad.data_ptr()),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(lam)))
+        return grad
+
+    def ch_step(self, c: torch.Tensor, alpha: float, steps: int = 1,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+        """`steps` semi-implicit Cahn-Hilliard steps (cyclic penta factor of the LHS)."""
+        m, ld = _batch_view(c, self.n, torch.float64, "c")
+        if out is None:
+            out = torch.empty_like(c)
+        if _batch_view(out, self.n, torch.float64, "out") != (m, ld):
+            raise ValueError("out must match c in shape and strides")
+        with torch.cuda.device(c.device):
+            check(lib().bb_ch_step(self._handle, ctypes.c_void_p(c.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr()), m, ld, float(alpha),
+                                   int(steps), _stream_ptr(c)))
+        return out
+
+
+def mse_loss_grad(u: torch.Tensor, target: torch.Tensor, grad: torch.Tensor | None = None):
+    """(loss as a 0-d device tensor, dloss/du) for loss = mean((u - target)^2)."""
+    n = u.shape[0]
+    m, ld = _batch_view(u, n, torch.float64, "u")
+    if _batch_view(target, n, torch.float64, "target") != (m, ld):
+        raise ValueError("target must match u in shape and strides")
+    if grad is None:
+        grad = torch.empty_like(u)
+    loss = torch.empty((), dtype=torch.float64, device=u.device)
+    nbytes = lib().bb_mse_workspace_bytes(n, m)
+    ws = torch.empty(max(nbytes, 8), dtype=torch.uint8, device=u.device)
+    with torch.cuda.device(u.device):
+        check(lib().bb_mse_loss_grad(ctypes.c_void_p(u.data_ptr()),
+                                     ctypes.c_void_p(target.data_ptr()),
+                                     ctypes.c_void_p(grad.data_ptr()),
+                                     ctypes.c_void_p(loss.data_ptr()), n, m, ld,
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(u)))
+    return loss, grad
+
+
+def max_n() -> int:
+    return int(lib().bb_max_n())
+
+
+__all__ = ["Factor", "BandBatchError", "mse_loss_grad", "max_n", "KINDS"]

@@ -1,0 +1,139 @@
+"""CPU-only checks of the C ABI: the library loads, exports every function
+include/bandbatch.h declares, and its host-side validation (factorisation,
+pivots, capacitance, argument checks, error strings) behaves as documented.
+No call here touches a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2107_05395_amd import _lib, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bandbatch.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2107_05395_amd import build
+        build.build(verbose=False)
+    return _lib.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bb_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for must in ["bb_factor_shared_tri", "bb_factor_shared_penta", "bb_factor_shared_tri_cyclic",
+                 "bb_factor_shared_penta_cyclic", "bb_solve_batch_tri", "bb_solve_batch_penta",
+                 "bb_solve_batch_tri_adjoint", "bb_solve_batch_penta_adjoint", "bb_band_grad",
+                 "bb_ch_step", "bb_status_string", "bb_last_error_message"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(declared_functions()) == set(_lib.SIGNATURES)
+
+
+def _factor(L, kind, bands, n):
+    h = ctypes.c_void_p()
+    arrs = [np.ascontiguousarray(b, dtype=np.float64) for b in bands]
+    st = getattr(L, "bb_factor_shared_" + kind)(*(_lib.dptr(a) for a in arrs), n, ctypes.byref(h))
+    return st, h
+
+
+def test_factor_ok_and_info(L):
+    n = 512
+    st, h = _factor(L, "tri", inputs.diffusion_tri_bands(n, 1.0), n)
+    assert st == 0 and h.value
+    nn, kind, chunk = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    assert L.bb_factor_info(h, ctypes.byref(nn), ctypes.byref(kind), ctypes.byref(chunk)) == 0
+    assert (nn.value, kind.value) == (n, 0)
+    assert chunk.value in (4, 8, 16, 32, 64) and chunk.value * 64 >= n
+    assert L.bb_factor_destroy(h) == 0
+    assert L.bb_factor_destroy(None) == 0
+
+
+def test_zero_pivot_rejected(L):
+    n = 3
+    st, h = _factor(L, "tri", ([0, 1, 1], [0, 1, 1], [1, 1, 0]), n)
+    assert st == -2 and not h.value
+    assert b"pivot" in L.bb_last_error_message()
+    # nonsingular, but the leading 2x2 minor is singular: the method does not pivot
+    st, _ = _factor(L, "tri", ([0, 1, 1], [1, 1, 2], [1, 1, 0]), n)
+    assert st == -2
+    st, _ = _factor(L, "penta", ([0] * 5, [0] * 5, [0, 1, 1, 1, 1], [0] * 5, [0] * 5), 5)
+    assert st == -2
+    st, _ = _factor(L, "tri", ([0, -1, -1], [1, np.nan, 1], [-1, -1, 0]), n)
+    assert st == -2
+
+
+def test_singular_capacitance_rejected(L):
+    # periodic tri with b = a + c everywhere: A has the constant vector in its null space
+    n = 6
+    st, _ = _factor(L, "tri_cyclic", (np.full(n, -1.0), np.full(n, 2.0), np.full(n, -1.0)), n)
+    assert st in (-2, -3)
+    assert L.bb_last_error_message()
+
+
+def test_size_limits(L):
+    st, _ = _factor(L, "tri", ([1.0], [2.0], [1.0]), 1)
+    assert st == 0
+    st, _ = _factor(L, "tri", ([], [], []), 0)
+    assert st == -1
+    st, _ = _factor(L, "tri_cyclic", ([1.0] * 2, [4.0] * 2, [1.0] * 2), 2)
+    assert st == -1
+    st, _ = _factor(L, "penta_cyclic", *([[[1.0] * 4] * 5, 4]))
+    assert st == -1
+    big = L.bb_max_n() + 1
+    st, _ = _factor(L, "tri", (np.ones(big), np.full(big, 3.0), np.ones(big)), big)
+    assert st == -6
+    h = ctypes.c_void_p()
+    assert L.bb_factor_shared_tri(None, None, None, 4, ctypes.byref(h)) == -1
+    one = np.ones(4)
+    assert L.bb_factor_shared_tri(_lib.dptr(one), _lib.dptr(one), _lib.dptr(one), 4, None) == -1
+
+
+def test_solve_argument_checks_need_no_gpu(L):
+    n = 16
+    _, h = _factor(L, "tri", inputs.diffusion_tri_bands(n, 0.5), n)
+    _, hp = _factor(L, "penta", inputs.hyperdiffusion_penta_bands(n, 0.25), n)
+    fake = ctypes.c_void_p(0x1000)
+    assert L.bb_solve_batch_tri(None, fake, fake, 4, 4, 0, None) == -1
+    assert L.bb_solve_batch_tri(h, fake, fake, -1, 4, 0, None) == -1
+    assert L.bb_solve_batch_tri(h, fake, fake, 8, 4, 0, None) == -1        # ld < m
+    assert L.bb_solve_batch_tri(h, None, fake, 4, 4, 0, None) == -1
+    assert L.bb_solve_batch_tri(h, fake, fake, 4, 4, 7, None) == -1        # bad precision
+    assert L.bb_solve_batch_penta(h, fake, fake, 4, 4, 0, None) == -1      # wrong kind
+    assert L.bb_solve_batch_tri(hp, fake, fake, 4, 4, 0, None) == -1
+    assert L.bb_solve_batch_tri_cyclic(h, fake, fake, 4, 4, 0, None) == -1  # not cyclic
+    assert L.bb_ch_step(h, fake, fake, 4, 4, 1.0, 1, None) == -1           # not cyclic penta
+    assert L.bb_solve_batch_tri(h, None, None, 0, 1, 0, None) == 0         # m = 0: nothing to do
+    assert L.bb_band_grad(h, fake, fake, 4, 4, None, None, 0, None) == -1
+    assert L.bb_solve_batch_tri_thread_per_system(hp, fake, fake, 4, 4, None) == -1
+    L.bb_factor_destroy(h)
+    L.bb_factor_destroy(hp)
+
+
+def test_status_strings(L):
+    for s in _lib.STATUS:
+        assert L.bb_status_string(s)
+    assert L.bb_status_string(12345) == b"unknown status"
+
+
+def test_workspace_sizes(L):
+    n = 64
+    _, h = _factor(L, "tri", inputs.diffusion_tri_bands(n, 0.5), n)
+    assert L.bb_band_grad_workspace_bytes(h, 0) == 0
+    assert L.bb_band_grad_workspace_bytes(h, 1000) >= 3 * n * 8
+    assert L.bb_mse_workspace_bytes(n, 1000) >= 8
+    L.bb_factor_destroy(h)

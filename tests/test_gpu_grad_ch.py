@@ -1,0 +1,150 @@
+"""GPU parity of the differentiable path (band gradients, MSE loss, autograd
+solve, checkpointed rollout) and of the fused Cahn-Hilliard steps, against
+the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2107_05395_amd import inputs
+from tests.gpu_util import dev, host, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib_loaded():
+    from paper_2107_05395_amd import solver  # noqa: F401
+    oracle.build()
+
+
+def _bands(kind, n, seed):
+    return inputs.random_dominant_tri(n, seed) if kind == "tri" else inputs.random_dominant_penta(n, seed)
+
+
+@pytest.mark.parametrize("kind,cyclic,n,m", [("tri", False, 64, 300), ("tri", True, 65, 1000),
+                                             ("tri", False, 1024, 2048), ("penta", False, 100, 257),
+                                             ("penta", True, 256, 1500), ("tri", False, 3, 5)])
+def test_band_grad(kind, cyclic, n, m):
+    from paper_2107_05395_amd import Factor
+    say("band grad", kind, cyclic, n, m)
+    bands = _bands(kind, n, n)
+    f = Factor.tri(*bands, cyclic=cyclic) if kind == "tri" else Factor.penta(*bands, cyclic=cyclic)
+    lam = inputs.uniform_batch(n, m, seed=1)
+    x = inputs.uniform_batch(n, m, seed=2)
+    nb = 3 if kind == "tri" else 5
+    ref = oracle.band_grad(lam, x, nb, cyclic=cyclic)
+    g = f.band_grad(dev(lam), dev(x))
+    scale = np.max(np.abs(lam)) * np.max(np.abs(x)) * m
+    assert np.max(np.abs(host(g) - ref)) < 1e-13 * scale
+    g2 = f.band_grad(dev(lam), dev(x), g)             # accumulates
+    assert np.max(np.abs(host(g2) - 2 * ref)) < 2e-13 * scale
+
+
+def test_mse_loss_grad():
+    from paper_2107_05395_amd import mse_loss_grad
+    n, m = 333, 1234
+    u = inputs.uniform_batch(n, m, seed=3)
+    y = inputs.uniform_batch(n, m, seed=4)
+    loss, grad = mse_loss_grad(dev(u), dev(y))
+    assert abs(loss.item() - np.mean((u - y) ** 2)) < 1e-14
+    assert np.max(np.abs(host(grad) - 2 * (u - y) / (n * m))) < 1e-18
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32r", 1e-10)])
+def test_autograd_solve_matches_oracle(precision, tol):
+    from paper_2107_05395_amd import banded_solve
+    n, m = 200, 64
+    bands = _bands("penta", n, 5)
+    rhs = inputs.uniform_batch(n, m, seed=6)
+    w = inputs.uniform_batch(n, m, seed=7)
+    tb = [torch.tensor(b, dtype=torch.float64, requires_grad=True) for b in bands]
+    trhs = dev(rhs).requires_grad_(True)
+    x = banded_solve(trhs, tb, precision=precision)
+    (x * dev(w)).sum().backward()
+    lam = oracle.penta_adjoint(*bands, w)
+    xs = oracle.penta_solve(*bands, rhs)
+    gb = oracle.band_grad(lam, xs, 5)
+    assert rel_err(host(trhs.grad), lam) < tol
+    for q in range(5):
+        assert np.max(np.abs(tb[q].grad.numpy() - gb[q])) < tol * max(1.0, np.max(np.abs(gb)))
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32r", 1e-10)])
+def test_rollout_gradients_match_oracle(precision, tol):
+    from paper_2107_05395_amd import banded_rollout, mse_loss
+    n, m, steps, r = 128, 96, 23, 0.5
+    D0 = inputs.rng(8).uniform(0.5, 1.5, n)
+    u0 = inputs.uniform_batch(n, m, seed=9)
+    y = inputs.uniform_batch(n, m, seed=10)
+    loss_ref, dD_ref, du0_ref = oracle.diffusion_loss_and_grads(D0, r, u0, y, steps)
+    D = torch.tensor(D0, requires_grad=True)
+    tu0 = dev(u0).requires_grad_(True)
+    a, b, c = -r * D, 1 + 2 * r * D, -r * D
+    uT = banded_rollout(tu0, (a, b, c), steps=steps, checkpoint_every=5, precision=precision)
+    loss = mse_loss(uT, dev(y))
+    loss.backward()
+    say("rollout", precision, loss.item(), loss_ref)
+    assert abs(loss.item() - loss_ref) < tol * loss_ref
+    assert np.max(np.abs(D.grad.numpy() - dD_ref)) < tol * np.max(np.abs(dD_ref))
+    assert rel_err(host(tu0.grad), du0_ref) < tol
+
+
+def test_checkpointing_is_bitwise_neutral():
+    from paper_2107_05395_amd import banded_rollout, mse_loss
+    n, m, steps = 256, 200, 30
+    D0 = inputs.rng(11).uniform(0.5, 1.5, n)
+    u0 = inputs.uniform_batch(n, m, seed=12)
+    y = inputs.uniform_batch(n, m, seed=13)
+    grads = []
+    for every in (1, 7, 30):
+        D = torch.tensor(D0, requires_grad=True)
+        tu0 = dev(u0).requires_grad_(True)
+        bands = (-0.5 * D, 1 + D, -0.5 * D)
+        mse_loss(banded_rollout(tu0, bands, steps, every), dev(y)).backward()
+        grads.append((D.grad.numpy().copy(), host(tu0.grad)))
+    for gD, gu in grads[1:]:
+        assert np.array_equal(gD, grads[0][0]) and np.array_equal(gu, grads[0][1])
+
+
+# ---------------------------------------------------------------- Cahn-Hilliard
+
+def _ch(n):
+    from paper_2107_05395_amd import Factor
+    sigma, alpha = inputs.ch_parameters(n=n)
+    return Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True), sigma, alpha
+
+
+@pytest.mark.parametrize("n,m", [(256, 1000), (64, 130), (200, 77), (5, 9)])
+def test_ch_single_step(n, m):
+    say("ch step", n, m)
+    f, sigma, alpha = _ch(n)
+    c0 = inputs.uniform_batch(n, m, seed=n, lo=-0.1, hi=0.1)
+    ref = oracle.ch_step(c0, sigma, alpha)
+    assert rel_err(host(f.ch_step(dev(c0), alpha)), ref) < 1e-12
+
+
+def test_ch_many_steps_and_mass():
+    n, m, steps = 256, 512, 200
+    f, sigma, alpha = _ch(n)
+    c0 = inputs.uniform_batch(n, m, seed=21, lo=-0.1, hi=0.1)
+    ref = oracle.ch_step(c0, sigma, alpha, steps=steps)
+    out = host(f.ch_step(dev(c0), alpha, steps=steps))
+    err = rel_err(out, ref)
+    say("ch 200 steps rel err", err)
+    assert err < 1e-10
+    assert np.max(np.abs(out.sum(axis=0) - c0.sum(axis=0))) < 1e-11
+    # fused steps equal the same number of single steps
+    t = dev(c0)
+    for _ in range(10):
+        t = f.ch_step(t, alpha)
+    assert rel_err(host(t), host(f.ch_step(dev(c0), alpha, steps=10))) < 1e-14
+
+
+def test_ch_in_place():
+    n, m = 256, 300
+    f, sigma, alpha = _ch(n)
+    c0 = inputs.uniform_batch(n, m, seed=22, lo=-0.1, hi=0.1)
+    t = dev(c0)
+    f.ch_step(t, alpha, steps=3, out=t)
+    assert rel_err(host(t), oracle.ch_step(c0, sigma, alpha, steps=3)) < 1e-12

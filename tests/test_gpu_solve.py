@@ -1,0 +1,184 @@
+"""GPU parity: every solve path of libbandbatch against the FP64 oracle, element
+by element on the same seeded inputs, at sizes that span several chunks, a
+ragged last chunk, a ragged batch tail and the degenerate sizes.
+
+Bars: FP64 1e-12, FP32 sweeps + one FP64-residual refinement 1e-10 (per-system
+relative 2-norm error, max over systems); unrefined FP32 only as a sanity check."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2107_05395_amd import inputs
+from tests.gpu_util import dev, host, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32R_TOL = 1e-10
+F32_TOL = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib_loaded():
+    from paper_2107_05395_amd import solver  # noqa: F401  (fails loudly if not built)
+    oracle.build()
+    torch.cuda.synchronize()
+
+
+def make(kind, n, seed, cyclic=False, dominant=True):
+    from paper_2107_05395_amd import Factor
+    if kind == "tri":
+        bands = inputs.random_dominant_tri(n, seed) if dominant else inputs.diffusion_tri_bands(n, 0.5)
+        return Factor.tri(*bands, cyclic=cyclic), bands
+    bands = inputs.random_dominant_penta(n, seed) if dominant else inputs.hyperdiffusion_penta_bands(n, 0.25)
+    return Factor.penta(*bands, cyclic=cyclic), bands
+
+
+def oracle_solve(kind, bands, rhs, cyclic):
+    if kind == "tri":
+        return oracle.tri_solve(*bands, rhs, cyclic=cyclic)
+    return oracle.penta_solve(*bands, rhs, cyclic=cyclic)
+
+
+def oracle_adjoint(kind, bands, g, cyclic):
+    if kind == "tri":
+        return oracle.tri_adjoint(*bands, g, cyclic=cyclic)
+    return oracle.penta_adjoint(*bands, g, cyclic=cyclic)
+
+
+SHAPES_TRI = [(1, 5), (2, 3), (3, 64), (5, 65), (8, 1), (63, 130), (64, 64), (100, 77),
+              (256, 1024), (257, 300), (512, 200), (1000, 129), (1024, 64), (1025, 40), (2048, 33)]
+SHAPES_PENTA = [(1, 3), (2, 4), (3, 9), (4, 64), (5, 70), (9, 33), (64, 100), (130, 65),
+                (256, 128), (1024, 96), (1030, 50), (2048, 20)]
+
+
+@pytest.mark.parametrize("n,m", SHAPES_TRI)
+def test_tri_f64(n, m):
+    say("tri f64", n, m)
+    f, bands = make("tri", n, seed=n)
+    rhs = inputs.uniform_batch(n, m, seed=1000 + n)
+    x = host(f.solve(dev(rhs)))
+    assert rel_err(x, oracle.tri_solve(*bands, rhs)) < F64_TOL
+
+
+@pytest.mark.parametrize("n,m", SHAPES_PENTA)
+def test_penta_f64(n, m):
+    say("penta f64", n, m)
+    f, bands = make("penta", n, seed=n)
+    rhs = inputs.uniform_batch(n, m, seed=2000 + n)
+    x = host(f.solve(dev(rhs)))
+    assert rel_err(x, oracle.penta_solve(*bands, rhs)) < F64_TOL
+
+
+@pytest.mark.parametrize("kind,n,m", [("tri", 3, 10), ("tri", 4, 64), ("tri", 97, 130),
+                                      ("tri", 256, 256), ("tri", 1000, 70), ("tri", 2048, 17),
+                                      ("penta", 5, 10), ("penta", 6, 64), ("penta", 77, 100),
+                                      ("penta", 256, 256), ("penta", 1000, 40),
+                                      ("penta", 2048, 12)])
+def test_cyclic_f64(kind, n, m):
+    say("cyclic f64", kind, n, m)
+    f, bands = make(kind, n, seed=3 * n, cyclic=True)
+    rhs = inputs.uniform_batch(n, m, seed=3000 + n)
+    x = host(f.solve(dev(rhs)))
+    assert rel_err(x, oracle_solve(kind, bands, rhs, True)) < F64_TOL
+
+
+@pytest.mark.parametrize("kind", ["tri", "penta"])
+@pytest.mark.parametrize("cyclic", [False, True])
+@pytest.mark.parametrize("n", [64, 300, 1024])
+def test_refine_f32r(kind, cyclic, n):
+    say("f32r", kind, cyclic, n)
+    f, bands = make(kind, n, seed=7 * n, cyclic=cyclic, dominant=False)
+    rhs = inputs.uniform_batch(n, 200, seed=4000 + n)
+    x = host(f.solve(dev(rhs), precision="f32r"))
+    err = rel_err(x, oracle_solve(kind, bands, rhs, cyclic))
+    say("  rel err", err)
+    assert err < F32R_TOL
+
+
+@pytest.mark.parametrize("kind", ["tri", "penta"])
+@pytest.mark.parametrize("cyclic", [False, True])
+def test_plain_f32(kind, cyclic):
+    n = 512
+    f, bands = make(kind, n, seed=11, cyclic=cyclic, dominant=False)
+    rhs = inputs.uniform_batch(n, 100, seed=12)
+    x = host(f.solve(dev(rhs, torch.float32), precision="f32"))
+    assert rel_err(x, oracle_solve(kind, bands, rhs, cyclic)) < F32_TOL
+
+
+@pytest.mark.parametrize("kind", ["tri", "penta"])
+@pytest.mark.parametrize("cyclic", [False, True])
+@pytest.mark.parametrize("n", [5, 64, 257, 1024])
+def test_adjoint(kind, cyclic, n):
+    say("adjoint", kind, cyclic, n)
+    f, bands = make(kind, n, seed=13 * n, cyclic=cyclic)
+    g = inputs.uniform_batch(n, 90, seed=5000 + n)
+    ref = oracle_adjoint(kind, bands, g, cyclic)
+    assert rel_err(host(f.adjoint(dev(g))), ref) < F64_TOL
+    assert rel_err(host(f.adjoint(dev(g), precision="f32r")), ref) < F32R_TOL
+
+
+def test_in_place_and_strided():
+    n, m, ld = 300, 100, 160
+    f, bands = make("penta", n, seed=1)
+    big = inputs.uniform_batch(n, ld, seed=6)
+    t = dev(big)
+    view = t[:, :m]
+    f.solve(view, out=view)                      # in place on a strided view
+    out = host(t)
+    assert rel_err(out[:, :m], oracle.penta_solve(*bands, big[:, :m])) < F64_TOL
+    assert np.array_equal(out[:, m:], big[:, m:])  # columns past m untouched
+
+
+def test_out_of_place_leaves_input():
+    n, m = 256, 500
+    f, _ = make("tri", n, seed=2)
+    rhs = inputs.uniform_batch(n, m, seed=7)
+    t = dev(rhs)
+    f.solve(t)
+    assert np.array_equal(host(t), rhs)
+
+
+def test_empty_batch_is_noop():
+    f, _ = make("tri", 64, seed=3)
+    t = torch.zeros(64, 0, dtype=torch.float64, device="cuda")
+    f.solve(t)
+    torch.cuda.synchronize()
+
+
+def test_thread_per_system_baseline():
+    n, m = 512, 3000
+    f, bands = make("tri", n, seed=4)
+    rhs = inputs.uniform_batch(n, m, seed=8)
+    assert rel_err(host(f.solve_thread_per_system(dev(rhs))), oracle.tri_solve(*bands, rhs)) < F64_TOL
+    t = dev(rhs)
+    f.solve_thread_per_system(t, out=t)          # the paper's in-place form
+    assert rel_err(host(t), oracle.tri_solve(*bands, rhs)) < F64_TOL
+
+
+def test_bitwise_deterministic():
+    n, m = 1024, 4096
+    f, _ = make("penta", n, seed=5, cyclic=True)
+    t = dev(inputs.uniform_batch(n, m, seed=9))
+    a = host(f.solve(t))
+    b = host(f.solve(t))
+    assert np.array_equal(a, b)
+
+
+def test_factor_on_the_oracle_matrices_of_every_config():
+    """The LHS of each configured workload, small batch, against the oracle."""
+    for kind, n, bands, cyc in [
+        ("tri", 256, inputs.diffusion_tri_bands(256, 0.5), False),
+        ("tri", 512, inputs.diffusion_tri_bands(512, 1.0), False),
+        ("penta", 1024, inputs.hyperdiffusion_penta_bands(1024, 0.25), False),
+        ("penta", 256, inputs.ch_penta_bands(256, inputs.ch_parameters()[0]), True),
+        ("tri", 1024, inputs.variable_diffusion_bands(inputs.rng(1).uniform(0.5, 1.5, 1024), 0.5), False),
+    ]:
+        from paper_2107_05395_amd import Factor
+        f = Factor.tri(*bands, cyclic=cyc) if kind == "tri" else Factor.penta(*bands, cyclic=cyc)
+        rhs = inputs.uniform_batch(n, 256, seed=n)
+        ref = oracle_solve(kind, bands, rhs, cyc)
+        say("config matrix", kind, n, cyc)
+        assert rel_err(host(f.solve(dev(rhs))), ref) < F64_TOL
+        assert rel_err(host(f.solve(dev(rhs), precision="f32r")), ref) < F32R_TOL
