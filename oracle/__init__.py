@@ -186,7 +186,7 @@ def ch_bands(n: int, sigma: float):
 
 
 def ch_step(c, sigma: float, alpha: float, steps: int = 1) -> np.ndarray:
-    c = _f64(c)
+    c = np.array(c, dtype=np.float64, order="C", copy=True)   # never write into the caller's array
     n, m = c.shape
     out = np.empty_like(c)
     for _ in range(steps):

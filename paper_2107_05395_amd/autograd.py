@@ -36,6 +36,7 @@ class BandedSolve(torch.autograd.Function):
         f = _factor_from(bands, _kind(len(bands)), cyclic)
         x = f.solve(rhs.contiguous(), precision=precision)
         ctx.factor, ctx.precision = f, precision
+        ctx.band_devices = [b.device for b in bands]
         ctx.save_for_backward(x)
         return x
 
@@ -45,7 +46,7 @@ class BandedSolve(torch.autograd.Function):
         f = ctx.factor
         lam = f.adjoint(gx.contiguous(), precision=ctx.precision)
         gb = f.band_grad(lam, x)
-        return (lam, None, None, *[gb[q] for q in range(f.nbands)])
+        return (lam, None, None, *[gb[q].to(d) for q, d in enumerate(ctx.band_devices)])
 
 
 def banded_solve(rhs, bands, cyclic: bool = False, precision: str = "f64"):
@@ -67,6 +68,7 @@ class BandedRollout(torch.autograd.Function):
             if t % checkpoint_every == 0 and t < steps:
                 checkpoints.append(u)
         ctx.factor, ctx.steps, ctx.every, ctx.precision = f, steps, checkpoint_every, precision
+        ctx.band_devices = [b.device for b in bands]
         ctx.checkpoints = checkpoints
         return u
 
@@ -88,7 +90,7 @@ class BandedRollout(torch.autograd.Function):
                 g = lam
             del states
         ctx.checkpoints = None
-        return (g, None, None, None, *[gb[q] for q in range(f.nbands)])
+        return (g, None, None, None, *[gb[q].to(d) for q, d in enumerate(ctx.band_devices)])
 
 
 def banded_rollout(u0, bands, steps: int, checkpoint_every: int = 10, precision: str = "f64"):

@@ -57,3 +57,12 @@ def test_ch_constant_state_stays(oracle):
     sigma, alpha = inputs.ch_parameters(n=n)
     c = np.full((n, 3), 0.3)
     assert np.max(np.abs(oracle.ch_step(c, sigma, alpha, steps=5) - 0.3)) < 1e-14
+
+
+def test_ch_step_leaves_its_input_alone(oracle):
+    n = 32
+    sigma, alpha = inputs.ch_parameters(n=n)
+    c = inputs.uniform_batch(n, 4, seed=5, lo=-0.1, hi=0.1)
+    keep = c.copy()
+    oracle.ch_step(c, sigma, alpha, steps=3)
+    assert np.array_equal(c, keep)
