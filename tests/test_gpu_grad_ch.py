@@ -133,7 +133,10 @@ def test_ch_many_steps_and_mass():
     err = rel_err(out, ref)
     say("ch 200 steps rel err", err)
     assert err < 1e-10
-    assert np.max(np.abs(out.sum(axis=0) - c0.sum(axis=0))) < 1e-11
+    # exact in exact arithmetic; in double each step may move a 256-term sum by ~n eps |c|
+    bound = 4 * steps * n * np.finfo(float).eps * np.max(np.abs(out))
+    assert np.max(np.abs(out.sum(axis=0) - c0.sum(axis=0))) < bound
+    assert np.max(np.abs(ref.sum(axis=0) - c0.sum(axis=0))) < bound
     # fused steps equal the same number of single steps
     t = dev(c0)
     for _ in range(10):
