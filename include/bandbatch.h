@@ -74,7 +74,8 @@ typedef struct bb_factor_s *bb_factor;
  *   Non-cyclic: a[0], a[1], b[0], d[n-1], e[n-2], e[n-1] are ignored.
  *   Cyclic (indices mod n): those six are the corners (Section 5.1 matrix).
  *
- * Sizes: 1 <= n <= bb_max_n() non-cyclic; 3 <= n (tri) or 5 <= n (penta) cyclic.
+ * Sizes: 1 <= n <= bb_max_n() (tri) or 1024 (penta, whose larger coefficient tables
+ * must also fit LDS); cyclic needs 3 <= n (tri) or 5 <= n (penta).
  * Errors: BB_ERR_ARG (null pointer, n out of range), BB_ERR_ZERO_PIVOT,
  *         BB_ERR_SINGULAR_CAPACITANCE (cyclic), BB_ERR_OOM.  *out is set only on BB_OK. */
 bb_status bb_factor_shared_tri(const double *a, const double *b, const double *c, int64_t n,

@@ -42,7 +42,7 @@ bb_status hip_fail(hipError_t e, const char *where)
 // Upper bound on rows per lane.  The sweeps hold C rows of the right-hand side
 // per lane in registers; the refinement kernel holds the double input, the
 // float first solution and the float correction at once, so it gets half.
-// BANDBATCH_MAX_CHUNK overrides the solve bound (tuning).
+// BANDBATCH_MAX_CHUNK lowers the bound (tuning).
 int max_chunk(bb_precision p)
 {
     int c = bb::kChunkMax;
@@ -50,7 +50,7 @@ int max_chunk(bb_precision p)
         const int v = std::atoi(env);
         if (v >= bb::kChunkMin && v <= bb::kChunkMax && (v & (v - 1)) == 0) c = v;
     }
-    if (p == BB_F32_REFINE && c > 32) c = 32;
+    if (p == BB_F32_REFINE && c > bb::kChunkMaxRefine) c = bb::kChunkMaxRefine;
     return c;
 }
 
@@ -63,6 +63,9 @@ bb_status make(int kind, const double *a, const double *b, const double *c, cons
     const int64_t nmin = kind == bb::kTriCyclic ? 3 : kind == bb::kPentaCyclic ? 5 : 1;
     if (n < nmin) return fail(BB_ERR_ARG, "n = " + std::to_string(n) + " is below the minimum " + std::to_string(nmin));
     if (n > bb::kMaxN) return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(n) + " exceeds bb_max_n()");
+    if (penta && n > bb::kMaxNPenta)
+        return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(n) + " exceeds the pentadiagonal limit " +
+                                            std::to_string(bb::kMaxNPenta));
     bb_factor f = new (std::nothrow) bb_factor_s;
     if (!f) return fail(BB_ERR_OOM, "host allocation");
     const double *bands[5] = {a, b, c, d, e};

@@ -137,7 +137,20 @@ Factor::~Factor()
     for (auto &kv : dev_paper) if (kv.second.ptr) (void)hipFree(kv.second.ptr);
 }
 
+int make_factor_impl(int kind, const double *const bands[5], int64_t n, Factor &f, std::string &err);
+
 int make_factor(int kind, const double *const bands[5], int64_t n, Factor &f, std::string &err)
+{
+    const int st = make_factor_impl(kind, bands, n, f, err);
+    if (st == kOk && f.n >= 2) {
+        // -u1 of row n-2 of each direction (the table stores u1 negated)
+        f.primal.cor.q.u1_nm2 = -f.primal.rec.u1[f.n - 2];
+        f.adjoint.cor.q.u1_nm2 = -f.adjoint.rec.u1[f.n - 2];
+    }
+    return st;
+}
+
+int make_factor_impl(int kind, const double *const bands[5], int64_t n, Factor &f, std::string &err)
 {
     f.kind = kind;
     f.K = (kind == kTri || kind == kTriCyclic) ? 1 : 2;
@@ -299,52 +312,82 @@ std::vector<double> build_table(const Direction &d, int K, bool cyclic, int64_t 
     const int na = num_arrays(K, cyclic);
     std::vector<double> tab((size_t)table_len(K, cyclic, C, P), 0.0);
     const Recurrence &r = d.rec;
-    std::vector<const std::vector<double> *> arrays = {&r.s, &r.l1};
-    if (K == 2) arrays.push_back(&r.l2);
-    arrays.push_back(&r.u1);
-    if (K == 2) arrays.push_back(&r.u2);
-    if (cyclic) {
-        arrays.push_back(&d.cor.z0);
-        if (K == 2) arrays.push_back(&d.cor.z1);
-    }
-    // every array but s is stored negated: the kernels compute each step as one fma
-    for (int q = 0; q < na; ++q) {
-        const double sign = q == 0 ? 1.0 : -1.0;
-        for (int j = 0; j < P; ++j)
-            for (int t = 0; t < C; ++t) {
-                const int64_t row = (int64_t)j * C + t;
-                if (row < n) tab[(size_t)(q * L + (int64_t)j * (C + 1) + t)] = sign * (*arrays[q])[row];
-            }
-    }
-    // chunk transfer matrices from homogeneous runs of the recurrences
+    auto coef = [&](const std::vector<double> &v, int64_t row) {
+        return row < n && !v.empty() ? v[row] : 0.0;
+    };
+    auto at = [&](int q, int j, int t) -> double & {
+        return tab[(size_t)(q * L + (int64_t)j * (C + 1) + t)];
+    };
+    // array indices of the layout in internal.h
+    const int qE = 0, qS = K, qs = 2 * K, ql = 2 * K + 1, qu = 3 * K + 1, qz = 4 * K + 1;
     double *Mf = tab.data() + na * L;
     double *Mb = Mf + (int64_t)P * K * K;
-    auto coef = [&](const std::vector<double> &v, int64_t row) { return row < n && !v.empty() ? v[row] : 0.0; };
+    double *G = Mb + (int64_t)P * K * K;
+
+    std::vector<double> y(C), x(C);
     for (int j = 0; j < P; ++j) {
         const int64_t r0 = (int64_t)j * C;
-        for (int comp = 0; comp < K; ++comp) {
-            // forward: history (y_{r0-1}, y_{r0-2}) = unit vector comp
-            double y1 = comp == 0 ? 1.0 : 0.0, y2 = comp == 1 ? 1.0 : 0.0;
+        // forward recurrence over the chunk for right-hand side f (C values) and
+        // history (h1, h2); backward recurrence for input y and future (g1, g2)
+        auto forward = [&](const double *f, double h1, double h2) {
             for (int t = 0; t < C; ++t) {
                 const int64_t row = r0 + t;
-                double y = -coef(r.l1, row) * y1;
-                if (K == 2) y -= coef(r.l2, row) * y2;
-                y2 = y1;
-                y1 = y;
+                double v = (f ? coef(r.s, row) * f[t] : 0.0) - coef(r.l1, row) * h1;
+                if (K == 2) v -= coef(r.l2, row) * h2;
+                y[t] = v;
+                h2 = h1;
+                h1 = v;
             }
-            Mf[j * K * K + 0 * K + comp] = y1;               // y_end
-            if (K == 2) Mf[j * K * K + 1 * K + comp] = y2;   // y_end-1
-            // backward: future (x_{r0+C}, x_{r0+C+1}) = unit vector comp
-            double x1 = comp == 0 ? 1.0 : 0.0, x2 = comp == 1 ? 1.0 : 0.0;
+        };
+        auto backward = [&](const std::vector<double> &in, double g1, double g2) {
             for (int t = C - 1; t >= 0; --t) {
                 const int64_t row = r0 + t;
-                double x = -coef(r.u1, row) * x1;
-                if (K == 2) x -= coef(r.u2, row) * x2;
-                x2 = x1;
-                x1 = x;
+                double v = in[t] - coef(r.u1, row) * g1;
+                if (K == 2) v -= coef(r.u2, row) * g2;
+                x[t] = v;
+                g2 = g1;
+                g1 = v;
             }
-            Mb[j * K * K + 0 * K + comp] = x1;               // x_start
-            if (K == 2) Mb[j * K * K + 1 * K + comp] = x2;   // x_start+1
+        };
+        // weights of e and o: responses to a unit right-hand side at each row
+        std::vector<double> unit(C, 0.0);
+        for (int tau = 0; tau < C; ++tau) {
+            unit.assign(C, 0.0);
+            unit[tau] = 1.0;
+            forward(unit.data(), 0.0, 0.0);
+            at(qE, j, tau) = y[C - 1];
+            if (K == 2) at(qE + 1, j, tau) = y[C - 2];
+            backward(y, 0.0, 0.0);
+            at(qS, j, tau) = x[0];
+            if (K == 2) at(qS + 1, j, tau) = x[1];
+        }
+        for (int comp = 0; comp < K; ++comp) {
+            // history unit vector: end state (Mf) and backward start state (G)
+            forward(nullptr, comp == 0 ? 1.0 : 0.0, comp == 1 ? 1.0 : 0.0);
+            Mf[j * K * K + 0 * K + comp] = y[C - 1];
+            if (K == 2) Mf[j * K * K + 1 * K + comp] = y[C - 2];
+            backward(y, 0.0, 0.0);
+            G[j * K * K + 0 * K + comp] = x[0];
+            if (K == 2) G[j * K * K + 1 * K + comp] = x[1];
+            // future unit vector: start state (Mb)
+            std::vector<double> zero(C, 0.0);
+            backward(zero, comp == 0 ? 1.0 : 0.0, comp == 1 ? 1.0 : 0.0);
+            Mb[j * K * K + 0 * K + comp] = x[0];
+            if (K == 2) Mb[j * K * K + 1 * K + comp] = x[1];
+        }
+        // recurrence coefficients (off-diagonal ones and z negated: one fma per step)
+        for (int t = 0; t < C; ++t) {
+            const int64_t row = r0 + t;
+            if (row >= n) continue;
+            at(qs, j, t) = r.s[row];
+            at(ql, j, t) = -r.l1[row];
+            if (K == 2) at(ql + 1, j, t) = -r.l2[row];
+            at(qu, j, t) = -r.u1[row];
+            if (K == 2) at(qu + 1, j, t) = -r.u2[row];
+            if (cyclic) {
+                at(qz, j, t) = -d.cor.z0[row];
+                if (K == 2) at(qz + 1, j, t) = -d.cor.z1[row];
+            }
         }
     }
     return tab;

@@ -11,29 +11,37 @@
 // once.  A wave of 64 lanes holds S = 64/P systems: lane = chunk * S + sys.
 //
 // Both sweeps of a banded LU are order-K linear recurrences (K = 1 tri,
-// K = 2 penta).  The lanes of one system couple only through K numbers at
-// each chunk boundary:
+// K = 2 penta):
 //   forward  y_i = s_i f_i - l1_i y_{i-1} - l2_i y_{i-2}
 //   backward x_i = y_i - u1_i x_{i+1} - u2_i x_{i+2}
-// Each lane first runs its forward recurrence from a zero history to get its
-// chunk-end state E_j, the lanes combine E_j with the shared KxK chunk
-// transfer matrices Mf_j (prefix scan over chunks), and every lane re-runs its
-// chunk from the true history.  The backward sweep does the same from the
-// right with Mb_j.  The matrices depend only on A, so the host computes them
-// once with the factor.
+// The lanes of one system couple only through K numbers at each chunk
+// boundary.  Because the matrix is shared, everything about that coupling
+// that depends only on A is precomputed once on the host:
+//   * the zero-history forward end state e_j and the zero-future backward
+//     start state o_j of a chunk are linear in its right-hand side, so each
+//     lane gets them as dot products with weight vectors;
+//   * chunk transfer matrices Mf_j, Mb_j (KxK) carry a history forward / a
+//     future backward across a chunk, and G_j carries the history into the
+//     backward start state;
+// so a solve is: one dot-product pass, two scans over the P chunks of a
+// system (shuffles inside the wave), one forward and one backward pass.
 //
 // Coefficient table (one per direction, precision and chunk size)
 // ----------------------------------------------------------------
 // NA arrays, each L = P*(C+1) elements long; row r = j*C + t of array q is
 // element [q*L + j*(C+1) + t] (one pad element per chunk keeps the P chunks of
-// a wave in different LDS banks).  Array order:
-//   s, -l1, [-l2], -u1, [-u2], [-z0, [-z1]]  (bracketed: K = 2 / cyclic only)
-// (all but s stored negated, so each recurrence step is a single fma)
-// followed by Mf[P][K][K] and Mb[P][K][K] (row-major KxK).
+// a wave in different LDS banks).  Array order (bracketed: K = 2 / cyclic):
+//   wE1, [wE2]   weights of e: e_r = sum_t wE_r[t] f_t   (e = (y_end, y_end-1))
+//   wS1, [wS2]   weights of o: o_r = sum_t wS_r[t] f_t   (o = (x_start, x_start+1))
+//   s, -l1, [-l2], -u1, [-u2], [-z0, [-z1]]
+// (off-diagonal coefficients and z stored negated: every step is one fma)
+// followed by Mf[P][K][K], Mb[P][K][K], G[P][K][K] (row-major KxK):
 //   Mf_j[r][c]: response of y_{end_j - r} to the history component c
 //               (history = (y_{end_{j-1}}, y_{end_{j-1}-1}));
 //   Mb_j[r][c]: response of x_{start_j + r} to the future component c
-//               (future = (x_{start_{j+1}}, x_{start_{j+1}+1})).
+//               (future = (x_{start_{j+1}}, x_{start_{j+1}+1}));
+//   G_j[r][c]:  response of the zero-future backward start state o_r of the
+//               chunk to the forward history component c.
 // Rows r >= n are padding: every coefficient 0, so they hold 0 and couple to
 // nothing.  Periodic systems: A = A' + U V^T; the table describes A' and the
 // correction x = y - Z s, s = Q (y_0..y_{K-1}, y_{n-K}..y_{n-1}) uses the
@@ -56,17 +64,20 @@ constexpr int kBlockThreads = 256;   // 4 waves per workgroup for the sweep kern
 
 // chunk sizes the sweep kernels are instantiated for
 constexpr int kChunkMin = 4;
-constexpr int kChunkMax = 64;
-// Largest system size.  The coefficient tables of a workgroup live in LDS
-// (160 KB per CU); at n = 2048 the largest one (periodic pentadiagonal with
-// FP32 sweeps plus the double residual bands) takes 143 KB.
+constexpr int kChunkMax = 128;
+constexpr int kChunkMaxRefine = 64;   // the refinement kernel holds 4 words per row
+// Largest system sizes.  The coefficient tables of a workgroup live in LDS
+// (160 KB per CU): a tridiagonal table has up to 6 arrays of n (+pad) values,
+// a pentadiagonal one up to 11; at these limits the largest tables (periodic,
+// double) take 100 KB (tri, n = 2048) and 92 KB (penta, n = 1024).
 constexpr int64_t kMaxN = 2048;
+constexpr int64_t kMaxNPenta = 1024;
 
-inline int num_arrays(int K, bool cyclic) { return (K == 1 ? 3 : 5) + (cyclic ? K : 0); }
+inline int num_arrays(int K, bool cyclic) { return 4 * K + 1 + (cyclic ? K : 0); }
 
 inline int64_t table_len(int K, bool cyclic, int C, int P)
 {
-    return (int64_t)num_arrays(K, cyclic) * P * (C + 1) + 2LL * P * K * K;
+    return (int64_t)num_arrays(K, cyclic) * P * (C + 1) + 3LL * P * K * K;
 }
 
 // Uniform arguments of a sweep launch.
@@ -81,7 +92,8 @@ struct SweepGeom {
 };
 
 struct CyclicQ {
-    double q[2][4];  // K x 2K, uses q[0][0..1] for K = 1
+    double q[2][4];   // K x 2K, uses q[0][0..1] for K = 1
+    double u1_nm2;    // -u1 of row n-2 (x_{n-2} = y_{n-2} - u1 y_{n-1} at the last chunk)
 };
 
 struct Corners {      // periodic corner entries of the original matrix (refinement residual)

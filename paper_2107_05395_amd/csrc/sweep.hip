@@ -38,13 +38,45 @@ __device__ __forceinline__ int64_t opaque_s(int64_t x)
     return x;
 }
 
-// Scheduling fence: nothing moves across it.  Placed every few rows and
-// between passes so coefficient reads are issued a short distance ahead of
-// their use instead of all at once.
+// A branch the compiler cannot fold (always taken, on a uniform value it
+// cannot see).  Each pass runs in blocks of kFenceRows rows, each block inside
+// such a branch: a separate basic block, so the coefficient reads of one block
+// are not hoisted above the work of the previous one and only a few rows of
+// coefficients are live at a time.
 constexpr int kFenceRows = 8;
-__device__ __forceinline__ void fence_rows(int t)
+__device__ __forceinline__ bool opaque_true()
 {
-    if (t % kFenceRows == kFenceRows - 1) __builtin_amdgcn_sched_barrier(0);
+    int x = 1;
+    asm volatile("" : "+s"(x));
+    return x != 0;
+}
+
+// body(t) for t = 0 .. C-1 (rows_up) or C-1 .. 0 (rows_down), fully
+// unrolled, in fenced blocks of kFenceRows rows.
+template <int C, typename F>
+__device__ __forceinline__ void rows_up(F &&body)
+{
+    constexpr int B = C < kFenceRows ? C : kFenceRows;
+#pragma unroll
+    for (int t0 = 0; t0 < C; t0 += B) {
+        if (opaque_true()) {
+#pragma unroll
+            for (int tt = 0; tt < B; ++tt) body(t0 + tt);
+        }
+    }
+}
+
+template <int C, typename F>
+__device__ __forceinline__ void rows_down(F &&body)
+{
+    constexpr int B = C < kFenceRows ? C : kFenceRows;
+#pragma unroll
+    for (int t0 = C - B; t0 >= 0; t0 -= B) {
+        if (opaque_true()) {
+#pragma unroll
+            for (int tt = B - 1; tt >= 0; --tt) body(t0 + tt);
+        }
+    }
 }
 
 // runtime-indexed read of a register array without spilling it: C selects
@@ -62,11 +94,14 @@ struct LaneGeom {
     int j, sl, S, P;
 };
 
-// This lane's view of a coefficient table staged in LDS.
+// This lane's view of a coefficient table staged in LDS (layout in internal.h).
 template <typename T, int K, bool CYC>
 struct LaneTable {
-    const T *s, *l1, *l2, *u1, *u2, *z0, *z1;
-    const T *Mf, *Mb;
+    const T *wE1, *wE2, *wS1, *wS2;   // boundary-state weights (pass 1)
+    const T *s, *l1, *l2;             // forward recurrence (pass 2), l stored negated
+    const T *u1, *u2;                 // backward recurrence (pass 3), stored negated
+    const T *z0, *z1;                 // periodic correction, stored negated
+    const T *Mf, *Mb, *G;             // per-chunk KxK matrices
 };
 
 template <typename T, int K, int C, bool CYC>
@@ -76,6 +111,10 @@ __device__ __forceinline__ LaneTable<T, K, CYC> lane_table(const T *lds, int P, 
     const int off = j * (C + 1);
     LaneTable<T, K, CYC> tb;
     int q = 0;
+    tb.wE1 = lds + (q++) * L + off;
+    tb.wE2 = (K == 2) ? lds + (q++) * L + off : nullptr;
+    tb.wS1 = lds + (q++) * L + off;
+    tb.wS2 = (K == 2) ? lds + (q++) * L + off : nullptr;
     tb.s = lds + (q++) * L + off;
     tb.l1 = lds + (q++) * L + off;
     tb.l2 = (K == 2) ? lds + (q++) * L + off : nullptr;
@@ -85,6 +124,7 @@ __device__ __forceinline__ LaneTable<T, K, CYC> lane_table(const T *lds, int P, 
     tb.z1 = (CYC && K == 2) ? lds + (q++) * L + off : nullptr;
     tb.Mf = lds + q * L;
     tb.Mb = tb.Mf + P * K * K;
+    tb.G = tb.Mb + P * K * K;
     return tb;
 }
 
@@ -107,144 +147,159 @@ __device__ __forceinline__ void gather_ends(const T (&v)[C], const LaneGeom &lg,
     }
 }
 
+// y <- M y + e for a KxK matrix M (row-major) and K-vectors
+template <typename T, int K>
+__device__ __forceinline__ void affine(const T *M, T &y1, T &y2, T e1, T e2)
+{
+    if constexpr (K == 1) {
+        y1 = fma(M[0], y1, e1);
+    } else {
+        const T n1 = fma(M[1], y2, fma(M[0], y1, e1));
+        const T n2 = fma(M[3], y2, fma(M[2], y1, e2));
+        y1 = n1;
+        y2 = n2;
+    }
+}
+
 // Solve this lane's chunk in place: v holds the right-hand side rows on entry
 // and the solution rows on exit.  All 64 lanes of the wave must call it
-// together (the scans shuffle across the wave).  The table stores the
-// off-diagonal recurrence coefficients and z negated, so every step is one
-// fma.  Each pass re-derives its LDS pointers from an opaque base so the
-// compiler re-reads the coefficients instead of keeping C of them live.
+// together (the scans shuffle across the wave).
+//
+//   pass 1: the chunk's zero-history forward end state e and the zero-future
+//           backward start state o of that forward solution, both linear in
+//           the right-hand side: dot products with precomputed weights (no
+//           dependency chain, nothing written);
+//   scans:  history H_j (prefix over chunks, H_{i+1} = e_i + Mf_i H_i), then
+//           S_j = o_j + G_j H_j and the future F_j (suffix, F_{i-1} = S_i + Mb_i F_i);
+//   pass 2: forward recurrence from H_j, writing y;
+//   pass 3: backward recurrence from F_j, writing x (periodic correction fused
+//           when the chunks tile n exactly, else applied afterwards).
+// Each pass re-derives its LDS pointers from an opaque base so the compiler
+// re-reads coefficients instead of keeping C of them live across passes.
 template <typename T, int K, int C, bool CYC>
 __device__ __forceinline__ void chunk_solve(T (&v)[C], const T *lds, const LaneGeom &lg, int n,
                                             int exact, const CyclicQ &cq)
 {
-    __builtin_amdgcn_sched_barrier(0);
-    // pass 1: v <- s f in place, forward recurrence from a zero history
-    T y1 = T(0), y2 = T(0);
+    T e1 = T(0), e2 = T(0), o1 = T(0), o2 = T(0);
     {
         const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
-#pragma unroll
-        for (int t = 0; t < C; ++t) {
-            v[t] *= tb.s[t];
-            T y = v[t];
-            if constexpr (K == 2) y = fma(tb.l2[t], y2, y);
-            y = fma(tb.l1[t], y1, y);
-            y2 = y1;
-            y1 = y;
-            fence_rows(t);
-        }
+        rows_up<C>([&](int t) {
+            e1 = fma(tb.wE1[t], v[t], e1);
+            o1 = fma(tb.wS1[t], v[t], o1);
+            if constexpr (K == 2) {
+                e2 = fma(tb.wE2[t], v[t], e2);
+                o2 = fma(tb.wS2[t], v[t], o2);
+            }
+        });
     }
     __builtin_amdgcn_sched_barrier(0);
-    // scan over the chunks before this one: true history (y_{start-1}, y_{start-2})
+    // history of this chunk: H_j = true (y_{start-1}, y_{start-2})
+    const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
     T h1 = T(0), h2 = T(0);
+    for (int i = 0; i < lg.P; ++i) {
+        const int src = i * lg.S + lg.sl;
+        const T a1 = shfl(e1, src);
+        const T a2 = (K == 2) ? shfl(e2, src) : T(0);
+        if (i < lg.j) affine<T, K>(tb.Mf + i * K * K, h1, h2, a1, a2);
+    }
+    // zero-future start state of the true forward solution of this chunk
+    T s1 = o1, s2 = o2;
     {
-        const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
-        for (int i = 0; i < lg.P; ++i) {
-            const int src = i * lg.S + lg.sl;
-            const T e1 = shfl(y1, src);
-            const T e2 = (K == 2) ? shfl(y2, src) : T(0);
-            if (i < lg.j) {
-                const T *M = tb.Mf + i * K * K;
-                if constexpr (K == 1) {
-                    h1 = fma(M[0], h1, e1);
-                } else {
-                    const T n1 = fma(M[1], h2, fma(M[0], h1, e1));
-                    const T n2 = fma(M[3], h2, fma(M[2], h1, e2));
-                    h1 = n1;
-                    h2 = n2;
-                }
+        const T *Gm = tb.G + lg.j * K * K;
+        if constexpr (K == 1) {
+            s1 = fma(Gm[0], h1, o1);
+        } else {
+            s1 = fma(Gm[1], h2, fma(Gm[0], h1, o1));
+            s2 = fma(Gm[3], h2, fma(Gm[2], h1, o2));
+        }
+    }
+    // future of this chunk: F_j = true (x_{end+1}, x_{end+2})
+    T f1 = T(0), f2 = T(0);
+    for (int i = lg.P - 1; i >= 0; --i) {
+        const int src = i * lg.S + lg.sl;
+        const T a1 = shfl(s1, src);
+        const T a2 = (K == 2) ? shfl(s2, src) : T(0);
+        if (i > lg.j) affine<T, K>(tb.Mb + i * K * K, f1, f2, a1, a2);
+    }
+    // periodic correction x = y - Z s, s = Q (y_0..y_{K-1}, y_{n-K}..y_{n-1}), from
+    // the scan results when the chunks tile n exactly
+    T c0 = T(0), c1 = T(0);
+    if constexpr (CYC) {
+        if (exact) {
+            // rows 0, 1: start state of chunk 0 = S_0 + Mb_0 F_0
+            T x0 = s1, x1 = s2;
+            {
+                T g1 = f1, g2 = f2;
+                affine<T, K>(tb.Mb + lg.j * K * K, g1, g2, s1, s2);
+                x0 = g1;
+                x1 = g2;
+            }
+            // rows n-1, n-2: the last real chunk's true forward end state (its
+            // future is zero, so x_{n-1} = y_{n-1}, x_{n-2} = y_{n-2} - u1 y_{n-1})
+            T y1 = h1, y2 = h2;
+            affine<T, K>(tb.Mf + lg.j * K * K, y1, y2, e1, e2);
+            const int last = (n / C - 1) * lg.S + lg.sl;
+            const T r0 = shfl(x0, lg.sl);
+            const T r1 = (K == 2) ? shfl(x1, lg.sl) : T(0);
+            const T rn1 = shfl(y1, last);
+            const T rn2 = (K == 2) ? fma(T(cq.u1_nm2), rn1, shfl(y2, last)) : T(0);
+            if constexpr (K == 1) {
+                c0 = T(cq.q[0][0]) * r0 + T(cq.q[0][1]) * rn1;
+            } else {
+                c0 = T(cq.q[0][0]) * r0 + T(cq.q[0][1]) * r1 + T(cq.q[0][2]) * rn2 + T(cq.q[0][3]) * rn1;
+                c1 = T(cq.q[1][0]) * r0 + T(cq.q[1][1]) * r1 + T(cq.q[1][2]) * rn2 + T(cq.q[1][3]) * rn1;
             }
         }
     }
     __builtin_amdgcn_sched_barrier(0);
-    // pass 2: forward recurrence again, from the true history
+    // pass 2: forward recurrence from the true history
     {
-        const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
-        y1 = h1;
-        y2 = h2;
-#pragma unroll
-        for (int t = 0; t < C; ++t) {
-            T y = v[t];
-            if constexpr (K == 2) y = fma(tb.l2[t], y2, y);
-            y = fma(tb.l1[t], y1, y);
+        const auto tp = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
+        T y1 = h1, y2 = h2;
+        rows_up<C>([&](int t) {
+            T y = tp.s[t] * v[t];
+            if constexpr (K == 2) y = fma(tp.l2[t], y2, y);
+            y = fma(tp.l1[t], y1, y);
             v[t] = y;
             y2 = y1;
             y1 = y;
-            fence_rows(t);
-        }
+        });
     }
     __builtin_amdgcn_sched_barrier(0);
-    // pass 3: backward recurrence from a zero future: chunk-start state
-    T x1 = T(0), x2 = T(0);
+    // pass 3: backward recurrence from the true future (+ fused periodic correction)
     {
-        const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
-#pragma unroll
-        for (int t = C - 1; t >= 0; --t) {
+        const auto tp = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
+        T x1 = f1, x2 = f2;
+        rows_down<C>([&](int t) {
             T x = v[t];
-            if constexpr (K == 2) x = fma(tb.u2[t], x2, x);
-            x = fma(tb.u1[t], x1, x);
+            if constexpr (K == 2) x = fma(tp.u2[t], x2, x);
+            x = fma(tp.u1[t], x1, x);
             x2 = x1;
             x1 = x;
-            fence_rows(C - 1 - t);
-        }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    // scan over the chunks after this one: true future (x_{end+1}, x_{end+2})
-    T f1 = T(0), f2 = T(0);
-    {
-        const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
-        for (int i = lg.P - 1; i >= 0; --i) {
-            const int src = i * lg.S + lg.sl;
-            const T s1 = shfl(x1, src);
-            const T s2 = (K == 2) ? shfl(x2, src) : T(0);
-            if (i > lg.j) {
-                const T *M = tb.Mb + i * K * K;
-                if constexpr (K == 1) {
-                    f1 = fma(M[0], f1, s1);
-                } else {
-                    const T n1 = fma(M[1], f2, fma(M[0], f1, s1));
-                    const T n2 = fma(M[3], f2, fma(M[2], f1, s2));
-                    f1 = n1;
-                    f2 = n2;
-                }
+            if constexpr (CYC) {
+                x = fma(tp.z0[t], c0, x);
+                if constexpr (K == 2) x = fma(tp.z1[t], c1, x);
             }
-        }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    // pass 4: backward recurrence again, from the true future
-    {
-        const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
-        x1 = f1;
-        x2 = f2;
-#pragma unroll
-        for (int t = C - 1; t >= 0; --t) {
-            T x = v[t];
-            if constexpr (K == 2) x = fma(tb.u2[t], x2, x);
-            x = fma(tb.u1[t], x1, x);
             v[t] = x;
-            x2 = x1;
-            x1 = x;
-            fence_rows(C - 1 - t);
-        }
+        });
     }
-    __builtin_amdgcn_sched_barrier(0);
     if constexpr (CYC) {
-        // x = y - Z s,  s = Q (y_0 .. y_{K-1}, y_{n-K} .. y_{n-1})
-        T r0, r1, rn2, rn1;
-        gather_ends<T, K, C>(v, lg, n, exact, r0, r1, rn2, rn1);
-        T s0, s1 = T(0);
-        if constexpr (K == 1) {
-            s0 = T(cq.q[0][0]) * r0 + T(cq.q[0][1]) * rn1;
-        } else {
-            s0 = T(cq.q[0][0]) * r0 + T(cq.q[0][1]) * r1 + T(cq.q[0][2]) * rn2 + T(cq.q[0][3]) * rn1;
-            s1 = T(cq.q[1][0]) * r0 + T(cq.q[1][1]) * r1 + T(cq.q[1][2]) * rn2 + T(cq.q[1][3]) * rn1;
-        }
-        const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
-#pragma unroll
-        for (int t = 0; t < C; ++t) {
-            T x = fma(tb.z0[t], s0, v[t]);
-            if constexpr (K == 2) x = fma(tb.z1[t], s1, x);
-            v[t] = x;
-            fence_rows(t);
+        if (!exact) {
+            __builtin_amdgcn_sched_barrier(0);
+            T r0, r1, rn2, rn1;
+            gather_ends<T, K, C>(v, lg, n, exact, r0, r1, rn2, rn1);
+            if constexpr (K == 1) {
+                c0 = T(cq.q[0][0]) * r0 + T(cq.q[0][1]) * rn1;
+            } else {
+                c0 = T(cq.q[0][0]) * r0 + T(cq.q[0][1]) * r1 + T(cq.q[0][2]) * rn2 + T(cq.q[0][3]) * rn1;
+                c1 = T(cq.q[1][0]) * r0 + T(cq.q[1][1]) * r1 + T(cq.q[1][2]) * rn2 + T(cq.q[1][3]) * rn1;
+            }
+            const auto tp = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
+            rows_up<C>([&](int t) {
+                T x = fma(tp.z0[t], c0, v[t]);
+                if constexpr (K == 2) x = fma(tp.z1[t], c1, x);
+                v[t] = x;
+            });
         }
     }
 }
@@ -273,10 +328,20 @@ __device__ __forceinline__ GroupRange group_range(int64_t groups)
     return r;
 }
 
+// Copy the shared table into LDS: four loads in flight per thread per round.
 template <typename T>
 __device__ __forceinline__ void stage_table(T *lds, const T *__restrict__ table, int64_t elems)
 {
-    for (int64_t e = threadIdx.x; e < elems; e += blockDim.x) lds[e] = table[e];
+    const int64_t stride = blockDim.x;
+    int64_t e = threadIdx.x;
+    for (; e + 3 * stride < elems; e += 4 * stride) {
+        const T a = table[e], b = table[e + stride], c = table[e + 2 * stride], d = table[e + 3 * stride];
+        lds[e] = a;
+        lds[e + stride] = b;
+        lds[e + 2 * stride] = c;
+        lds[e + 3 * stride] = d;
+    }
+    for (; e < elems; e += stride) lds[e] = table[e];
 }
 
 // Load the C rows of this lane's chunk; column k must be in bounds.
@@ -429,8 +494,7 @@ __global__ __launch_bounds__(kBlockThreads) void refine_kernel(
             for (int q = 0; q < 2 * K + 1; ++q) band[q] = lds_band + q * L + off;
         }
         float dx[C];
-#pragma unroll
-        for (int t = 0; t < C; ++t) {
+        rows_up<C>([&](int t) {
             const double xm1 = t >= 1 ? (double)x0[t - 1] : (double)xl1;
             const double xp1 = t + 1 < C ? (double)x0[t + 1] : (double)xr1;
             double ax = band[K][t] * (double)x0[t];
@@ -455,8 +519,7 @@ __global__ __launch_bounds__(kBlockThreads) void refine_kernel(
             }
             if constexpr (!FULL) r = t < nrow ? r : 0.0;
             dx[t] = (float)r;
-            fence_rows(t);
-        }
+        });
         __builtin_amdgcn_sched_barrier(0);
         chunk_solve<float, K, C, CYC>(dx, lds, lg, g.n, exact, cq);
         double xo[C];
@@ -506,8 +569,7 @@ __global__ __launch_bounds__(kBlockThreads) void ch_kernel(const double *__restr
             const double wrap_last = alpha * ch_nl(r0);     // row n-1 sees row 0 on its right
             const int nrow = opaque_v(g.n - row0);
             double nprev = ch_nl(cl), ncur = ch_nl(c[0]);
-#pragma unroll
-            for (int t = 0; t < C; ++t) {
+            rows_up<C>([&](int t) {
                 const double nnext = ch_nl(t + 1 < C ? c[t + 1] : cr);
                 double f = fma(alpha, nprev - 2.0 * ncur + nnext, c[t]);
                 if (t == 0) f += (lg.j == 0) ? wrap_first : 0.0;
@@ -516,8 +578,7 @@ __global__ __launch_bounds__(kBlockThreads) void ch_kernel(const double *__restr
                 c[t] = f;
                 nprev = ncur;
                 ncur = nnext;
-                fence_rows(t);
-            }
+            });
             __builtin_amdgcn_sched_barrier(0);
             chunk_solve<double, 2, C, true>(c, smem_d, lg, g.n, exact, cq);
         }
@@ -604,6 +665,7 @@ hipError_t sweep_dispatch(const void *table, int64_t te, const CyclicQ &q, const
     case 16: return sweep_c<T, K, CYC, 16>(table, te, q, g, in, out, s);
     case 32: return sweep_c<T, K, CYC, 32>(table, te, q, g, in, out, s);
     case 64: return sweep_c<T, K, CYC, 64>(table, te, q, g, in, out, s);
+    case 128: return sweep_c<T, K, CYC, 128>(table, te, q, g, in, out, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -665,6 +727,7 @@ hipError_t launch_ch(const double *table, int64_t table_elems, const CyclicQ &q,
         BB_CH(16)
         BB_CH(32)
         BB_CH(64)
+        BB_CH(128)
     default: return hipErrorInvalidValue;
     }
 #undef BB_CH

@@ -1,0 +1,124 @@
+// chunk_emu.cpp -- CPU model of the GPU sweep's dataflow, for tests only.
+//
+// Builds the library's host factor and coefficient table (factor.cpp, the
+// product code) and replays, lane by lane in double, exactly what one wave
+// does for one system: the boundary-state dot products, the two scans over
+// chunks, the forward and backward passes and the periodic correction.  A
+// CPU test compares the result with the oracle, so the table construction
+// and the decomposition are checked without a GPU.
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../paper_2107_05395_amd/csrc/factor.h"
+
+extern "C" int emu_solve(int kind, const double *a, const double *b, const double *c,
+                         const double *d, const double *e, int64_t n, int adjoint, int C,
+                         const double *f, double *x)
+{
+    bb::Factor F;
+    std::string err;
+    const double *bands[5] = {a, b, c, d, e};
+    int st = bb::make_factor(kind, bands, n, F, err);
+    if (st) return st;
+    const int K = F.K;
+    const int P = bb::lanes_for(n, C);
+    if ((int64_t)P * C < n) return -100;
+    const bb::Direction &dir = adjoint ? F.adjoint : F.primal;
+    const std::vector<double> tab = bb::build_table(dir, K, F.cyclic, n, C, P);
+    const int64_t L = (int64_t)P * (C + 1);
+    const int na = bb::num_arrays(K, F.cyclic);
+    auto arr = [&](int q, int j, int t) { return tab[(size_t)(q * L + (int64_t)j * (C + 1) + t)]; };
+    const double *Mf = tab.data() + na * L, *Mb = Mf + P * K * K, *G = Mb + P * K * K;
+    const int qE = 0, qS = K, qs = 2 * K, ql = 2 * K + 1, qu = 3 * K + 1, qz = 4 * K + 1;
+
+    std::vector<std::vector<double>> v(P, std::vector<double>(C, 0.0));
+    for (int j = 0; j < P; ++j)
+        for (int t = 0; t < C; ++t) v[j][t] = j * C + t < n ? f[j * C + t] : 0.0;
+    // pass 1
+    std::vector<double> e1(P, 0), e2(P, 0), o1(P, 0), o2(P, 0);
+    for (int j = 0; j < P; ++j)
+        for (int t = 0; t < C; ++t) {
+            e1[j] += arr(qE, j, t) * v[j][t];
+            o1[j] += arr(qS, j, t) * v[j][t];
+            if (K == 2) {
+                e2[j] += arr(qE + 1, j, t) * v[j][t];
+                o2[j] += arr(qS + 1, j, t) * v[j][t];
+            }
+        }
+    auto affine = [&](const double *M, double &y1, double &y2, double a1, double a2) {
+        if (K == 1) {
+            y1 = M[0] * y1 + a1;
+        } else {
+            const double n1 = M[0] * y1 + M[1] * y2 + a1, n2 = M[2] * y1 + M[3] * y2 + a2;
+            y1 = n1;
+            y2 = n2;
+        }
+    };
+    std::vector<double> h1(P, 0), h2(P, 0), s1(P), s2(P), f1(P, 0), f2(P, 0);
+    for (int j = 0; j < P; ++j)
+        for (int i = 0; i < j; ++i) affine(Mf + i * K * K, h1[j], h2[j], e1[i], e2[i]);
+    for (int j = 0; j < P; ++j) {
+        const double *g = G + j * K * K;
+        s1[j] = o1[j] + g[0] * h1[j] + (K == 2 ? g[1] * h2[j] : 0.0);
+        s2[j] = K == 2 ? o2[j] + g[2] * h1[j] + g[3] * h2[j] : 0.0;
+    }
+    for (int j = 0; j < P; ++j)
+        for (int i = P - 1; i > j; --i) affine(Mb + i * K * K, f1[j], f2[j], s1[i], s2[i]);
+    // pass 2 and pass 3 (correction applied afterwards, from the solution ends)
+    for (int j = 0; j < P; ++j) {
+        double y1 = h1[j], y2 = h2[j];
+        for (int t = 0; t < C; ++t) {
+            double y = arr(qs, j, t) * v[j][t];
+            if (K == 2) y += arr(ql + 1, j, t) * y2;
+            y += arr(ql, j, t) * y1;
+            v[j][t] = y;
+            y2 = y1;
+            y1 = y;
+        }
+        double x1 = f1[j], x2 = f2[j];
+        for (int t = C - 1; t >= 0; --t) {
+            double xx = v[j][t];
+            if (K == 2) xx += arr(qu + 1, j, t) * x2;
+            xx += arr(qu, j, t) * x1;
+            v[j][t] = xx;
+            x2 = x1;
+            x1 = xx;
+        }
+    }
+    if (F.cyclic) {
+        const bb::CyclicQ &q = dir.cor.q;
+        auto at = [&](int64_t row) { return v[row / C][row % C]; };
+        double c0, c1 = 0.0;
+        if (K == 1) {
+            c0 = q.q[0][0] * at(0) + q.q[0][1] * at(n - 1);
+        } else {
+            const double r[4] = {at(0), at(1), at(n - 2), at(n - 1)};
+            c0 = q.q[0][0] * r[0] + q.q[0][1] * r[1] + q.q[0][2] * r[2] + q.q[0][3] * r[3];
+            c1 = q.q[1][0] * r[0] + q.q[1][1] * r[1] + q.q[1][2] * r[2] + q.q[1][3] * r[3];
+        }
+        // cross-check the fused form the kernel uses when chunks tile n exactly
+        if (n % C == 0) {
+            const int jl = (int)(n / C) - 1;
+            double x0 = f1[0], x1v = f2[0];
+            affine(Mb, x0, x1v, s1[0], s2[0]);
+            double y1 = h1[jl], y2 = h2[jl];
+            affine(Mf + jl * K * K, y1, y2, e1[jl], e2[jl]);
+            const double rn1 = y1, rn2 = K == 2 ? q.u1_nm2 * rn1 + y2 : 0.0;
+            double d0, d1 = 0.0;
+            if (K == 1) {
+                d0 = q.q[0][0] * x0 + q.q[0][1] * rn1;
+            } else {
+                d0 = q.q[0][0] * x0 + q.q[0][1] * x1v + q.q[0][2] * rn2 + q.q[0][3] * rn1;
+                d1 = q.q[1][0] * x0 + q.q[1][1] * x1v + q.q[1][2] * rn2 + q.q[1][3] * rn1;
+            }
+            const double tol = 1e-9 * (1.0 + std::abs(c0) + std::abs(c1));
+            if (std::abs(d0 - c0) > tol || std::abs(d1 - c1) > tol) return -101;
+        }
+        for (int j = 0; j < P; ++j)
+            for (int t = 0; t < C; ++t)
+                v[j][t] += arr(qz, j, t) * c0 + (K == 2 ? arr(qz + 1, j, t) * c1 : 0.0);
+    }
+    for (int64_t i = 0; i < n; ++i) x[i] = v[i / C][i % C];
+    return 0;
+}

@@ -58,7 +58,7 @@ def test_factor_ok_and_info(L):
     nn, kind, chunk = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
     assert L.bb_factor_info(h, ctypes.byref(nn), ctypes.byref(kind), ctypes.byref(chunk)) == 0
     assert (nn.value, kind.value) == (n, 0)
-    assert chunk.value in (4, 8, 16, 32, 64) and chunk.value * 64 >= n
+    assert chunk.value in (4, 8, 16, 32, 64, 128) and chunk.value * 64 >= n
     assert L.bb_factor_destroy(h) == 0
     assert L.bb_factor_destroy(None) == 0
 
@@ -97,6 +97,12 @@ def test_size_limits(L):
     big = L.bb_max_n() + 1
     st, _ = _factor(L, "tri", (np.ones(big), np.full(big, 3.0), np.ones(big)), big)
     assert st == -6
+    # pentadiagonal tables are larger: n is limited to 1024
+    st, _ = _factor(L, "penta", [np.ones(1025)] * 2 + [np.full(1025, 9.0)] + [np.ones(1025)] * 2, 1025)
+    assert st == -6 and b"1024" in L.bb_last_error_message()
+    st, h = _factor(L, "penta", [np.ones(1024)] * 2 + [np.full(1024, 9.0)] + [np.ones(1024)] * 2, 1024)
+    assert st == 0
+    L.bb_factor_destroy(h)
     h = ctypes.c_void_p()
     assert L.bb_factor_shared_tri(None, None, None, 4, ctypes.byref(h)) == -1
     one = np.ones(4)

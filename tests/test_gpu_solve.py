@@ -50,7 +50,7 @@ def oracle_adjoint(kind, bands, g, cyclic):
 SHAPES_TRI = [(1, 5), (2, 3), (3, 64), (5, 65), (8, 1), (63, 130), (64, 64), (100, 77),
               (256, 1024), (257, 300), (512, 200), (1000, 129), (1024, 64), (1025, 40), (2048, 33)]
 SHAPES_PENTA = [(1, 3), (2, 4), (3, 9), (4, 64), (5, 70), (9, 33), (64, 100), (130, 65),
-                (256, 128), (1024, 96), (1030, 50), (2048, 20)]
+                (256, 128), (1000, 50), (1024, 96)]
 
 
 @pytest.mark.parametrize("n,m", SHAPES_TRI)
@@ -75,7 +75,7 @@ def test_penta_f64(n, m):
                                       ("tri", 256, 256), ("tri", 1000, 70), ("tri", 2048, 17),
                                       ("penta", 5, 10), ("penta", 6, 64), ("penta", 77, 100),
                                       ("penta", 256, 256), ("penta", 1000, 40),
-                                      ("penta", 2048, 12)])
+                                      ("penta", 1024, 12)])
 def test_cyclic_f64(kind, n, m):
     say("cyclic f64", kind, n, m)
     f, bands = make(kind, n, seed=3 * n, cyclic=True)
