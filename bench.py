@@ -216,6 +216,33 @@ def bench_ch(args, torch):
     }
 
 
+def probe(torch):
+    """One dispatch of each kernel of interest, for rocprofv3 counter runs:
+    a plain copy of known size (4 GiB read + 4 GiB written), the FP64 and
+    FP32+refine sweeps and the thread-per-system design on the bench workload,
+    and the FP64 pentadiagonal sweep on the hyperdiffusion workload."""
+    from paper_2107_05395_amd import Factor, inputs
+    n, m = 512, 1 << 20
+    rhs = torch.rand(n, m, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(rhs)
+    x.copy_(rhs)
+    torch.cuda.synchronize()
+    f = Factor.tri(*inputs.diffusion_tri_bands(n, 1.0))
+    for prec in ("f64", "f32r"):
+        f.solve(rhs, out=x, precision=prec)
+        torch.cuda.synchronize()
+    f.solve_thread_per_system(rhs, out=x)
+    torch.cuda.synchronize()
+    del rhs, x
+    n, m = 1024, 1 << 18
+    rhs = torch.rand(n, m, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(rhs)
+    g = Factor.penta(*inputs.hyperdiffusion_penta_bands(n, 0.25))
+    g.solve(rhs, out=x)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "done"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,6 +252,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--ch-fuse", type=int, default=1, help="CH steps per kernel launch")
+    ap.add_argument("--probe", action="store_true",
+                    help="one dispatch of each kernel (for rocprofv3 counter runs); no timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs every system of a batch on a "
@@ -236,6 +265,9 @@ def main():
     import torch
     if not torch.cuda.is_available():
         sys.exit("bench.py needs a GPU")
+    if args.probe:
+        probe(torch)
+        return
     from paper_2107_05395_amd import inputs
     kind = inputs.WORKLOADS[args.workload]["kind"]
     if kind == "tri":

@@ -60,7 +60,7 @@
 namespace bb {
 
 constexpr int kWave = 64;
-constexpr int kBlockThreads = 256;   // 4 waves per workgroup for the sweep kernels
+constexpr int kBlockThreads = 128;   // 2 waves per workgroup for the sweep kernels (measured best)
 
 // chunk sizes the sweep kernels are instantiated for
 constexpr int kChunkMin = 4;
@@ -89,6 +89,7 @@ struct SweepGeom {
     int64_t m;      // systems
     int64_t ld;     // leading dimension (elements) of the interleaved arrays
     int64_t groups; // ceil(m / S): wave-sized groups of systems
+    int lockstep;   // workgroup barrier at the start of every persistent-loop iteration
 };
 
 struct CyclicQ {

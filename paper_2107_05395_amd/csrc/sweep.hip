@@ -11,6 +11,8 @@
 // apply the periodic correction if any, store once.  HBM traffic is one read
 // of the right-hand side and one write of the solution; coefficients come
 // from LDS, where each workgroup stages the shared table once.
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace bb {
@@ -304,28 +306,41 @@ __device__ __forceinline__ void chunk_solve(T (&v)[C], const T *lds, const LaneG
     }
 }
 
-// Workgroup -> group-of-systems mapping.  Workgroups are dealt round-robin to
-// the 8 XCDs; give each XCD a contiguous range of groups so that the partly
-// used cache lines at group boundaries are shared inside one L2.
+// Workgroup -> group-of-systems mapping.  A workgroup of W waves works on
+// W consecutive groups at a time (one per wave); workgroups are dealt
+// round-robin to the 8 XCDs, and each XCD gets a contiguous range of these
+// blocks of groups, so segments that share 128 B lines are read inside one L2.
+// The trip count of the loop over blocks is uniform across the workgroup, so a
+// workgroup barrier inside it is reached by every wave the same number of times.
 struct GroupRange {
-    int64_t first, end, stride;
+    int64_t first, end, stride;   // blocks of W groups
+    int W, wave;
 };
 
 __device__ __forceinline__ GroupRange group_range(int64_t groups)
 {
     constexpr int kXcd = 8;
-    const int waves_per_block = blockDim.x / kWave;
-    const int wave = threadIdx.x / kWave;
-    const int xcd = blockIdx.x % kXcd;
-    const int64_t blocks_per_xcd = gridDim.x / kXcd;   // host launches a multiple of 8
-    const int64_t local_block = blockIdx.x / kXcd;
-    const int64_t per_xcd = (groups + kXcd - 1) / kXcd;
     GroupRange r;
+    r.W = blockDim.x / kWave;
+    r.wave = threadIdx.x / kWave;
+    const int64_t blocks = (groups + r.W - 1) / r.W;
+    const int xcd = blockIdx.x % kXcd;
+    const int64_t per_xcd = (blocks + kXcd - 1) / kXcd;
     const int64_t base = (int64_t)xcd * per_xcd;
-    r.first = base + local_block * waves_per_block + wave;
-    r.end = base + per_xcd < groups ? base + per_xcd : groups;
-    r.stride = blocks_per_xcd * waves_per_block;
+    r.first = base + blockIdx.x / kXcd;
+    r.end = base + per_xcd < blocks ? base + per_xcd : blocks;
+    r.stride = gridDim.x / kXcd;   // host launches a multiple of 8
     return r;
+}
+
+// Start of one iteration of the persistent loop.  With `lockstep`, the waves
+// of a workgroup start their loads together, so the two halves of a 128 B
+// line that two waves read (64 B segments) are requested close in time and
+// the second request hits in L2 instead of refetching the line.
+__device__ __forceinline__ int64_t begin_block(const GroupRange &r, int64_t b, int lockstep)
+{
+    if (lockstep) __syncthreads();
+    return b * r.W + r.wave;
 }
 
 // Copy the shared table into LDS: four loads in flight per thread per round.
@@ -421,7 +436,9 @@ __global__ __launch_bounds__(kBlockThreads) void sweep_kernel(const T *__restric
     const LaneGeom lg = lane_geom(g.log2P);
     const int row0 = lg.j * C;
     const GroupRange gr = group_range(g.groups);
-    for (int64_t grp = gr.first; grp < gr.end; grp += gr.stride) {
+    for (int64_t b = gr.first; b < gr.end; b += gr.stride) {
+        const int64_t grp = begin_block(gr, b, g.lockstep);
+        if (grp >= g.groups) continue;
         const int64_t k = grp * lg.S + lg.sl;
         const bool kval = k < g.m;
         T v[C];
@@ -456,7 +473,9 @@ __global__ __launch_bounds__(kBlockThreads) void refine_kernel(
     const int exact = FULL || g.exact;
     const GroupRange gr = group_range(g.groups);
 
-    for (int64_t grp = gr.first; grp < gr.end; grp += gr.stride) {
+    for (int64_t blk = gr.first; blk < gr.end; blk += gr.stride) {
+        const int64_t grp = begin_block(gr, blk, g.lockstep);
+        if (grp >= g.groups) continue;
         const int64_t k = grp * lg.S + lg.sl;
         const bool kval = k < g.m;
         double b[C];
@@ -553,7 +572,9 @@ __global__ __launch_bounds__(kBlockThreads) void ch_kernel(const double *__restr
     const int exact = FULL || g.exact;
     const GroupRange gr = group_range(g.groups);
 
-    for (int64_t grp = gr.first; grp < gr.end; grp += gr.stride) {
+    for (int64_t blk = gr.first; blk < gr.end; blk += gr.stride) {
+        const int64_t grp = begin_block(gr, blk, g.lockstep);
+        if (grp >= g.groups) continue;
         const int64_t k = grp * lg.S + lg.sl;
         const bool kval = k < g.m;
         double c[C];
@@ -613,17 +634,24 @@ hipError_t launch_grid(void (*kern)(KArgs...), size_t lds, int64_t groups, hipSt
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
+    // waves per workgroup: the workgroup is the unit that moves in step (see
+    // begin_block); BANDBATCH_WAVES_PER_BLOCK (1, 2 or 4) overrides (tuning)
+    int waves_per_block = kBlockThreads / kWave;
+    if (const char *env = std::getenv("BANDBATCH_WAVES_PER_BLOCK")) {
+        const int w = std::atoi(env);
+        if (w == 1 || w == 2 || w == 4) waves_per_block = w;
+    }
+    const int threads = waves_per_block * kWave;
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlockThreads, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
-    const int waves_per_block = kBlockThreads / kWave;
     int64_t need = (groups + waves_per_block - 1) / waves_per_block;
     int64_t cap = (int64_t)cu_count() * per_cu;
     int64_t blocks = need < cap ? need : cap;
     blocks = ((blocks + 7) / 8) * 8;   // multiple of the XCD count, see group_range
     if (blocks < 8) blocks = 8;
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kBlockThreads), lds, s, args...);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), lds, s, args...);
     return hipGetLastError();
 }
 
