@@ -60,7 +60,8 @@
 namespace bb {
 
 constexpr int kWave = 64;
-constexpr int kBlockThreads = 128;   // 2 waves per workgroup for the sweep kernels (measured best)
+constexpr int kBlockThreads = 128;      // 2 waves per workgroup for the sweep kernels (measured best)
+constexpr int kMaxBlockThreads = 256;   // launch bound: up to 4 waves per workgroup (tuning)
 
 // chunk sizes the sweep kernels are instantiated for
 constexpr int kChunkMin = 4;

@@ -424,7 +424,7 @@ __device__ __forceinline__ LaneGeom lane_geom(int log2P)
 
 // ---------------------------------------------------------------- solve
 template <typename T, int K, int C, bool CYC, bool FULL>
-__global__ __launch_bounds__(kBlockThreads) void sweep_kernel(const T *__restrict__ table,
+__global__ __launch_bounds__(kMaxBlockThreads) void sweep_kernel(const T *__restrict__ table,
                                                               int64_t table_elems, CyclicQ cq,
                                                               SweepGeom g, const T *in, T *out)
 {
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(kBlockThreads) void sweep_kernel(const T *__restric
 // x0 = solve_f32(b); r = b - A x0 in double with the original bands;
 // x = x0 + solve_f32(r), stored as double.
 template <int K, int C, bool CYC, bool FULL>
-__global__ __launch_bounds__(kBlockThreads) void refine_kernel(
+__global__ __launch_bounds__(kMaxBlockThreads) void refine_kernel(
     const float *__restrict__ table, int64_t table_elems, const double *__restrict__ band_table,
     int64_t band_elems, CyclicQ cq, Corners cn, SweepGeom g, const double *in, double *out)
 {
@@ -553,7 +553,7 @@ __global__ __launch_bounds__(kBlockThreads) void refine_kernel(
 __device__ __forceinline__ double ch_nl(double c) { return fma(c * c, c, -c); }
 
 template <int C, bool FULL>
-__global__ __launch_bounds__(kBlockThreads) void ch_kernel(const double *__restrict__ table,
+__global__ __launch_bounds__(kMaxBlockThreads) void ch_kernel(const double *__restrict__ table,
                                                            int64_t table_elems, CyclicQ cq,
                                                            SweepGeom g, double alpha,
                                                            int64_t steps, const double *in,
