@@ -216,11 +216,59 @@ def bench_ch(args, torch):
     }
 
 
+def bench_adjoint(args, torch):
+    """One step = forward rollout of T implicit steps (checkpoint every c), the
+    mean-squared-error loss, and the backward pass: adjoint solves with the
+    same factor, band-gradient reductions and recomputation between
+    checkpoints, through torch.autograd."""
+    from paper_2107_05395_amd import banded_rollout, mse_loss, inputs
+    spec = dict(inputs.WORKLOADS[args.workload])
+    n, m, r, T, every, seed = (spec[k] for k in ("n", "m", "r", "steps", "checkpoint", "seed"))
+    D0 = inputs.rng(seed).uniform(0.5, 1.5, n)
+    u0_host = inputs.uniform_batch(n, m, seed=seed + 1)
+    y_host = inputs.uniform_batch(n, m, seed=seed + 2)
+    u0, y = torch.from_numpy(u0_host).cuda(), torch.from_numpy(y_host).cuda()
+    grads = {}
+
+    def step(prec):
+        D = torch.tensor(D0, requires_grad=True)
+        u = u0.detach().requires_grad_(True)
+        uT = banded_rollout(u, (-r * D, 1 + 2 * r * D, -r * D), steps=T, checkpoint_every=every,
+                            precision=prec)
+        mse_loss(uT, y).backward()
+        grads[prec] = u.grad
+
+    out = {}
+    import oracle
+    cols = np.unique(np.r_[np.linspace(0, m - 1, 62).astype(np.int64), 0, m - 1])
+    _, _, du0_ref = oracle.diffusion_loss_and_grads(D0, r, u0_host[:, cols], y_host[:, cols], T)
+    du0_ref *= len(cols) / m          # the loss is a mean over all n*m entries
+    for prec in ("f64", "f32r"):
+        t, _ = time_launches(lambda: step(prec), args.steps, args.warmup, torch)
+        du0 = grads[prec][:, torch.from_numpy(cols).cuda()].cpu().numpy()
+        out[prec] = (t, rel_err_cols(du0, du0_ref))
+    k = args.steps
+    t64 = out["f64"][0]
+    return {
+        "metric": "system-steps/s (forward + backward)", "value": m * T * k / t64,
+        "unit": "system-steps/s", "n_gpus": 1, "steps": k, "warmup": args.warmup,
+        "ms_per_step": 1e3 * t64 / k, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded uniform[-1,1) initial states and targets, D ~ U[0.5,1.5))",
+        "config": {"workload": args.workload, "n": n, "m": m, "r": r, "T": T,
+                   "checkpoint_every": every},
+        "du0_rel_err_vs_oracle": out["f64"][1],
+        "f32r": {"value": m * T * k / out["f32r"][0], "ms_per_step": 1e3 * out["f32r"][0] / k,
+                 "du0_rel_err_vs_oracle": out["f32r"][1]},
+    }
+
+
 def probe(torch):
     """One dispatch of each kernel of interest, for rocprofv3 counter runs:
     a plain copy of known size (4 GiB read + 4 GiB written), the FP64 and
     FP32+refine sweeps and the thread-per-system design on the bench workload,
-    and the FP64 pentadiagonal sweep on the hyperdiffusion workload."""
+    the FP64 pentadiagonal sweep on the hyperdiffusion workload, and one
+    launch of 10 fused Cahn-Hilliard steps on the n=256, m=2^20 ensemble."""
     from paper_2107_05395_amd import Factor, inputs
     n, m = 512, 1 << 20
     rhs = torch.rand(n, m, dtype=torch.float64, device="cuda")
@@ -239,6 +287,13 @@ def probe(torch):
     x = torch.empty_like(rhs)
     g = Factor.penta(*inputs.hyperdiffusion_penta_bands(n, 0.25))
     g.solve(rhs, out=x)
+    torch.cuda.synchronize()
+    del rhs, x
+    n, m = 256, 1 << 20
+    sigma, alpha = inputs.ch_parameters(n=n)
+    c = torch.rand(n, m, dtype=torch.float64, device="cuda").mul_(0.2).sub_(0.1)
+    h = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
+    h.ch_step(c, alpha, steps=10)
     torch.cuda.synchronize()
     print(json.dumps({"probe": "done"}), flush=True)
 
@@ -276,6 +331,8 @@ def main():
         line = bench_penta(args, torch)
     elif kind == "ch":
         line = bench_ch(args, torch)
+    elif kind == "adjoint":
+        line = bench_adjoint(args, torch)
     else:
         sys.exit("workload %s is not a bench workload" % args.workload)
     line["device"] = torch.cuda.get_device_name(0)

@@ -36,10 +36,9 @@ def sine_mode_batch(n: int, m: int, seed: int, modes: int = 8) -> np.ndarray:
     amp = g.standard_normal((modes, m))
     phase = g.uniform(0.0, 2.0 * math.pi, size=(modes, m))
     x = (np.arange(n, dtype=np.float64) + 1.0) / (n + 1.0)
-    out = np.zeros((n, m))
-    for j in range(modes):
-        out += amp[j][None, :] * np.sin((j + 1) * math.pi * x[:, None] + phase[j][None, :])
-    return out
+    # sin(a + p) = sin(a) cos(p) + cos(a) sin(p): two (n x modes) @ (modes x m) products
+    arg = np.pi * np.outer(x, np.arange(1, modes + 1))
+    return np.sin(arg) @ (amp * np.cos(phase)) + np.cos(arg) @ (amp * np.sin(phase))
 
 
 # ---------------------------------------------------------------- LHS bands
