@@ -68,6 +68,24 @@ int lockstep_for(int S, size_t elem_bytes)
     return 1;
 }
 
+// Waves per system group (log2).  A full decomposition with many chunks per
+// system spreads each group over 2 or 4 waves so that a wave's load covers
+// at least 16 systems (128 B per row in double) -- see internal.h.
+// BANDBATCH_WAVES_PER_SYSTEM = 1, 2 or 4 forces the group size where it is
+// valid (tuning); anything else keeps the automatic choice.
+int split_log2(int log2P, int C, int n)
+{
+    if (C < 64 || ((int64_t)C << log2P) != n) return 0;
+    int l = 0;
+    while (log2P - l > 2 && l < bb::kMaxLog2Q) ++l;
+    if (const char *env = std::getenv("BANDBATCH_WAVES_PER_SYSTEM")) {
+        const int q = std::atoi(env);
+        const int fl = q == 1 ? 0 : q == 2 ? 1 : q == 4 ? 2 : -1;
+        if (fl >= 0 && fl <= log2P) l = fl;
+    }
+    return l;
+}
+
 bb_status make(int kind, const double *a, const double *b, const double *c, const double *d,
                const double *e, int64_t n, bb_factor *out)
 {
@@ -213,7 +231,8 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
     g.exact = (f.n % C) == 0;
     g.m = m;
     g.ld = ld;
-    const int S = bb::kWave / P;
+    g.log2Q = split_log2(log2P, C, (int)f.n);
+    const int S = (bb::kWave << g.log2Q) / P;
     g.groups = (m + S - 1) / S;
     g.lockstep = lockstep_for(S, p == BB_F32 ? sizeof(float) : sizeof(double));
     hipError_t e = bb::launch_sweep(f.K, f.cyclic, op, f32 && p == BB_F32, tab.ptr, tab.elems,
@@ -410,6 +429,7 @@ bb_status bb_ch_step(bb_factor fh, const double *c_in, double *c_out, int64_t m,
     g.ld = ld;
     g.groups = (m + bb::kWave / P - 1) / (bb::kWave / P);
     g.lockstep = lockstep_for(bb::kWave / P, sizeof(double));
+    g.log2Q = 0;
     hipError_t e = bb::launch_ch((const double *)tab.ptr, tab.elems, f.primal.cor.q, g, alpha, steps,
                                  c_in, c_out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "Cahn-Hilliard launch");

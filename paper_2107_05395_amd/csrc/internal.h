@@ -26,6 +26,14 @@
 // so a solve is: one dot-product pass, two scans over the P chunks of a
 // system (shuffles inside the wave), one forward and one backward pass.
 //
+// Split groups: when P is large, S = 64/P systems per wave make short row
+// segments (S*8 bytes per load instruction).  A system group can instead span
+// Q = 2^log2Q waves of one workgroup: each wave holds P/Q chunks of
+// S = 64Q/P systems, and the scans read the other waves' boundary states
+// through a small LDS exchange area (barriers instead of shuffles).  Only
+// full decompositions (P*C == n) with C >= 64 of the solve and refinement
+// kernels are split; the Cahn-Hilliard kernel is not.
+//
 // Coefficient table (one per direction, precision and chunk size)
 // ----------------------------------------------------------------
 // NA arrays, each L = P*(C+1) elements long; row r = j*C + t of array q is
@@ -89,9 +97,16 @@ struct SweepGeom {
     int exact;      // n == (number of non-padding chunks) * C
     int64_t m;      // systems
     int64_t ld;     // leading dimension (elements) of the interleaved arrays
-    int64_t groups; // ceil(m / S): wave-sized groups of systems
+    int64_t groups; // ceil(m / S): groups of S systems (one wave each, or 2^log2Q waves when split)
     int lockstep;   // workgroup barrier at the start of every persistent-loop iteration
+    int log2Q;      // waves per system group (0: a group is one wave)
 };
+
+constexpr int kMaxLog2Q = 2;   // split groups of up to 4 waves
+
+// LDS elements of the exchange area of one split group: three phases
+// (forward scan: 2 per lane, backward scan: 2, periodic end values: 4).
+inline int64_t split_exchange_len(int log2Q) { return 8LL * kWave << log2Q; }
 
 struct CyclicQ {
     double q[2][4];   // K x 2K, uses q[0][0..1] for K = 1

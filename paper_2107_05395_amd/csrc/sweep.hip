@@ -91,7 +91,7 @@ __device__ __forceinline__ T pick(const T (&v)[C], int t)
     return r;
 }
 
-// Where this lane sits: chunk j of system slot sl in a wave of S systems.
+// Where this lane sits: chunk j (of P) of system slot sl (of S) in its group.
 struct LaneGeom {
     int j, sl, S, P;
 };
@@ -178,9 +178,14 @@ __device__ __forceinline__ void affine(const T *M, T &y1, T &y2, T e1, T e2)
 //           when the chunks tile n exactly, else applied afterwards).
 // Each pass re-derives its LDS pointers from an opaque base so the compiler
 // re-reads coefficients instead of keeping C of them live across passes.
-template <typename T, int K, int C, bool CYC>
+//
+// SPLIT: the group spans several waves of the workgroup; boundary states go
+// through the exchange area xch (split_exchange_len elements) with workgroup
+// barriers, so every wave of the workgroup must call it the same number of
+// times.  Split groups are always full decompositions (exact).
+template <typename T, int K, int C, bool CYC, bool SPLIT = false>
 __device__ __forceinline__ void chunk_solve(T (&v)[C], const T *lds, const LaneGeom &lg, int n,
-                                            int exact, const CyclicQ &cq)
+                                            int exact, const CyclicQ &cq, T *xch = nullptr)
 {
     T e1 = T(0), e2 = T(0), o1 = T(0), o2 = T(0);
     {
@@ -198,11 +203,23 @@ __device__ __forceinline__ void chunk_solve(T (&v)[C], const T *lds, const LaneG
     // history of this chunk: H_j = true (y_{start-1}, y_{start-2})
     const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
     T h1 = T(0), h2 = T(0);
-    for (int i = 0; i < lg.P; ++i) {
-        const int src = i * lg.S + lg.sl;
-        const T a1 = shfl(e1, src);
-        const T a2 = (K == 2) ? shfl(e2, src) : T(0);
-        if (i < lg.j) affine<T, K>(tb.Mf + i * K * K, h1, h2, a1, a2);
+    const int me = lg.j * lg.S + lg.sl;   // (chunk, slot) index in the exchange area
+    if constexpr (SPLIT) {
+        T *xa = xch;
+        xa[2 * me] = e1;
+        xa[2 * me + 1] = e2;
+        __syncthreads();
+        for (int i = 0; i < lg.j; ++i) {
+            const int src = 2 * (i * lg.S + lg.sl);
+            affine<T, K>(tb.Mf + i * K * K, h1, h2, xa[src], xa[src + 1]);
+        }
+    } else {
+        for (int i = 0; i < lg.P; ++i) {
+            const int src = i * lg.S + lg.sl;
+            const T a1 = shfl(e1, src);
+            const T a2 = (K == 2) ? shfl(e2, src) : T(0);
+            if (i < lg.j) affine<T, K>(tb.Mf + i * K * K, h1, h2, a1, a2);
+        }
     }
     // zero-future start state of the true forward solution of this chunk
     T s1 = o1, s2 = o2;
@@ -217,11 +234,22 @@ __device__ __forceinline__ void chunk_solve(T (&v)[C], const T *lds, const LaneG
     }
     // future of this chunk: F_j = true (x_{end+1}, x_{end+2})
     T f1 = T(0), f2 = T(0);
-    for (int i = lg.P - 1; i >= 0; --i) {
-        const int src = i * lg.S + lg.sl;
-        const T a1 = shfl(s1, src);
-        const T a2 = (K == 2) ? shfl(s2, src) : T(0);
-        if (i > lg.j) affine<T, K>(tb.Mb + i * K * K, f1, f2, a1, a2);
+    if constexpr (SPLIT) {
+        T *xb = xch + 2 * lg.P * lg.S;
+        xb[2 * me] = s1;
+        xb[2 * me + 1] = s2;
+        __syncthreads();
+        for (int i = lg.P - 1; i > lg.j; --i) {
+            const int src = 2 * (i * lg.S + lg.sl);
+            affine<T, K>(tb.Mb + i * K * K, f1, f2, xb[src], xb[src + 1]);
+        }
+    } else {
+        for (int i = lg.P - 1; i >= 0; --i) {
+            const int src = i * lg.S + lg.sl;
+            const T a1 = shfl(s1, src);
+            const T a2 = (K == 2) ? shfl(s2, src) : T(0);
+            if (i > lg.j) affine<T, K>(tb.Mb + i * K * K, f1, f2, a1, a2);
+        }
     }
     // periodic correction x = y - Z s, s = Q (y_0..y_{K-1}, y_{n-K}..y_{n-1}), from
     // the scan results when the chunks tile n exactly
@@ -241,10 +269,24 @@ __device__ __forceinline__ void chunk_solve(T (&v)[C], const T *lds, const LaneG
             T y1 = h1, y2 = h2;
             affine<T, K>(tb.Mf + lg.j * K * K, y1, y2, e1, e2);
             const int last = (n / C - 1) * lg.S + lg.sl;
-            const T r0 = shfl(x0, lg.sl);
-            const T r1 = (K == 2) ? shfl(x1, lg.sl) : T(0);
-            const T rn1 = shfl(y1, last);
-            const T rn2 = (K == 2) ? fma(T(cq.u1_nm2), rn1, shfl(y2, last)) : T(0);
+            T r0, r1, rn1, rn2;
+            if constexpr (SPLIT) {
+                T *xc = xch + 4 * lg.P * lg.S;
+                xc[4 * me] = x0;
+                xc[4 * me + 1] = x1;
+                xc[4 * me + 2] = y1;
+                xc[4 * me + 3] = y2;
+                __syncthreads();
+                r0 = xc[4 * lg.sl];
+                r1 = xc[4 * lg.sl + 1];
+                rn1 = xc[4 * last + 2];
+                rn2 = (K == 2) ? fma(T(cq.u1_nm2), rn1, xc[4 * last + 3]) : T(0);
+            } else {
+                r0 = shfl(x0, lg.sl);
+                r1 = (K == 2) ? shfl(x1, lg.sl) : T(0);
+                rn1 = shfl(y1, last);
+                rn2 = (K == 2) ? fma(T(cq.u1_nm2), rn1, shfl(y2, last)) : T(0);
+            }
             if constexpr (K == 1) {
                 c0 = T(cq.q[0][0]) * r0 + T(cq.q[0][1]) * rn1;
             } else {
@@ -285,7 +327,7 @@ __device__ __forceinline__ void chunk_solve(T (&v)[C], const T *lds, const LaneG
             v[t] = x;
         });
     }
-    if constexpr (CYC) {
+    if constexpr (CYC && !SPLIT) {
         if (!exact) {
             __builtin_amdgcn_sched_barrier(0);
             T r0, r1, rn2, rn1;
@@ -317,12 +359,12 @@ struct GroupRange {
     int W, wave;
 };
 
-__device__ __forceinline__ GroupRange group_range(int64_t groups)
+__device__ __forceinline__ GroupRange group_range(int64_t groups, int log2Q = 0)
 {
     constexpr int kXcd = 8;
     GroupRange r;
-    r.W = blockDim.x / kWave;
-    r.wave = threadIdx.x / kWave;
+    r.W = (blockDim.x / kWave) >> log2Q;     // groups per workgroup
+    r.wave = (threadIdx.x / kWave) >> log2Q; // this wave's group in the workgroup
     const int64_t blocks = (groups + r.W - 1) / r.W;
     const int xcd = blockIdx.x % kXcd;
     const int64_t per_xcd = (blocks + kXcd - 1) / kXcd;
@@ -410,32 +452,41 @@ __device__ __forceinline__ void store_chunk(const T (&v)[C], T *base, int row0, 
     }
 }
 
-// Lane coordinates inside a wave of S = 64/P systems: lane = chunk * S + slot.
-__device__ __forceinline__ LaneGeom lane_geom(int log2P)
+// Lane coordinates: a wave holds P/Q chunks of S = 64Q/P systems,
+// lane = (chunk within the wave) * S + slot; wave q of a split group holds
+// chunks q*P/Q .. (q+1)*P/Q - 1.
+__device__ __forceinline__ LaneGeom lane_geom(int log2P, int log2Q = 0)
 {
     LaneGeom lg;
+    const int lw = log2P - log2Q;   // log2 of chunks per wave
     lg.P = 1 << log2P;
-    lg.S = kWave >> log2P;
+    lg.S = kWave >> lw;
     const int lane = threadIdx.x % kWave;
-    lg.j = lane >> (6 - log2P);
+    const int q = (threadIdx.x / kWave) & ((1 << log2Q) - 1);
+    lg.j = (q << lw) + (lane >> (6 - lw));
     lg.sl = lane & (lg.S - 1);
     return lg;
 }
 
 // ---------------------------------------------------------------- solve
-template <typename T, int K, int C, bool CYC, bool FULL>
+// QL = log2 of the waves per system group (0: one wave per group).  With
+// QL > 0 the workgroup is exactly one group (2^QL waves): every wave of it has
+// the same group index, so the exchange barriers are reached uniformly.
+template <typename T, int K, int C, bool CYC, bool FULL, int QL>
 __global__ __launch_bounds__(kMaxBlockThreads) void sweep_kernel(const T *__restrict__ table,
                                                               int64_t table_elems, CyclicQ cq,
                                                               SweepGeom g, const T *in, T *out)
 {
+    static_assert(QL == 0 || FULL, "split groups are full decompositions");
     extern __shared__ double smem_d[];
     T *lds = reinterpret_cast<T *>(smem_d);
     stage_table(lds, table, table_elems);
     __syncthreads();
+    T *xch = lds + table_elems;   // exchange area of the split group (QL > 0)
 
-    const LaneGeom lg = lane_geom(g.log2P);
+    const LaneGeom lg = lane_geom(g.log2P, QL);
     const int row0 = lg.j * C;
-    const GroupRange gr = group_range(g.groups);
+    const GroupRange gr = group_range(g.groups, QL);
     for (int64_t b = gr.first; b < gr.end; b += gr.stride) {
         const int64_t grp = begin_block(gr, b, g.lockstep);
         if (grp >= g.groups) continue;
@@ -443,7 +494,7 @@ __global__ __launch_bounds__(kMaxBlockThreads) void sweep_kernel(const T *__rest
         const bool kval = k < g.m;
         T v[C];
         load_chunk<T, C, FULL>(v, in, row0, kval ? k : g.m - 1, g.ld, g.n);
-        chunk_solve<T, K, C, CYC>(v, lds, lg, g.n, FULL || g.exact, cq);
+        chunk_solve<T, K, C, CYC, (QL > 0)>(v, lds, lg, g.n, FULL || g.exact, cq, xch);
         if (kval) store_chunk<T, C, FULL>(v, out, row0, k, g.ld, g.n);
     }
 }
@@ -451,19 +502,23 @@ __global__ __launch_bounds__(kMaxBlockThreads) void sweep_kernel(const T *__rest
 // ---------------------------------------------------------------- refine
 // x0 = solve_f32(b); r = b - A x0 in double with the original bands;
 // x = x0 + solve_f32(r), stored as double.
-template <int K, int C, bool CYC, bool FULL>
+// QL > 0: split groups as in sweep_kernel; the exchange area holds the three
+// phases of chunk_solve followed by rows 0, 1, C-2, C-1 of every chunk.
+template <int K, int C, bool CYC, bool FULL, int QL>
 __global__ __launch_bounds__(kMaxBlockThreads) void refine_kernel(
     const float *__restrict__ table, int64_t table_elems, const double *__restrict__ band_table,
     int64_t band_elems, CyclicQ cq, Corners cn, SweepGeom g, const double *in, double *out)
 {
+    static_assert(QL == 0 || (FULL && C >= 2), "split groups are full decompositions");
     extern __shared__ double smem_d[];
     double *lds_band = smem_d;
     float *lds = reinterpret_cast<float *>(smem_d + band_elems);
     stage_table(lds_band, band_table, band_elems);
     stage_table(lds, table, table_elems);
     __syncthreads();
+    float *xch = lds + table_elems;
 
-    const LaneGeom lg = lane_geom(g.log2P);
+    const LaneGeom lg = lane_geom(g.log2P, QL);
     const int lane = threadIdx.x % kWave;
     const int L = lg.P * (C + 1);
     const int row0 = lg.j * C;
@@ -471,7 +526,7 @@ __global__ __launch_bounds__(kMaxBlockThreads) void refine_kernel(
     const int left = has_left ? lane - lg.S : lane;
     const int right = has_right ? lane + lg.S : lane;
     const int exact = FULL || g.exact;
-    const GroupRange gr = group_range(g.groups);
+    const GroupRange gr = group_range(g.groups, QL);
 
     for (int64_t blk = gr.first; blk < gr.end; blk += gr.stride) {
         const int64_t grp = begin_block(gr, blk, g.lockstep);
@@ -483,18 +538,44 @@ __global__ __launch_bounds__(kMaxBlockThreads) void refine_kernel(
         float x0[C];
 #pragma unroll
         for (int t = 0; t < C; ++t) x0[t] = (float)b[t];
-        chunk_solve<float, K, C, CYC>(x0, lds, lg, g.n, exact, cq);
+        chunk_solve<float, K, C, CYC, (QL > 0)>(x0, lds, lg, g.n, exact, cq, xch);
         __builtin_amdgcn_sched_barrier(0);
 
-        // neighbours across the chunk boundaries (zero outside the matrix)
-        float xl1 = shfl(x0[C - 1], left), xl2 = shfl(x0[C - 2], left);
-        float xr1 = shfl(x0[0], right), xr2 = shfl(x0[1], right);
-        if (!has_left) xl1 = xl2 = 0.f;
-        if (!has_right) xr1 = xr2 = 0.f;
+        // neighbours across the chunk boundaries (zero outside the matrix) and,
+        // periodic, rows 0, 1, n-2, n-1 of the system
+        float xl1, xl2, xr1, xr2, r0 = 0.f, r1 = 0.f, rn2 = 0.f, rn1 = 0.f;
+        if constexpr (QL > 0) {
+            float *xd = xch + 8 * lg.P * lg.S;
+            const int me = 4 * (lg.j * lg.S + lg.sl);
+            xd[me] = x0[0];
+            xd[me + 1] = x0[1];
+            xd[me + 2] = x0[C - 2];
+            xd[me + 3] = x0[C - 1];
+            __syncthreads();
+            const int lft = 4 * ((has_left ? lg.j - 1 : lg.j) * lg.S + lg.sl);
+            const int rgt = 4 * ((has_right ? lg.j + 1 : lg.j) * lg.S + lg.sl);
+            xl1 = has_left ? xd[lft + 3] : 0.f;
+            xl2 = has_left ? xd[lft + 2] : 0.f;
+            xr1 = has_right ? xd[rgt] : 0.f;
+            xr2 = has_right ? xd[rgt + 1] : 0.f;
+            if constexpr (CYC) {
+                const int first = 4 * lg.sl, last = 4 * ((lg.P - 1) * lg.S + lg.sl);
+                r0 = xd[first];
+                r1 = xd[first + 1];
+                rn2 = xd[last + 2];
+                rn1 = xd[last + 3];
+            }
+        } else {
+            xl1 = shfl(x0[C - 1], left);
+            xl2 = shfl(x0[C - 2], left);
+            xr1 = shfl(x0[0], right);
+            xr2 = shfl(x0[1], right);
+            if (!has_left) xl1 = xl2 = 0.f;
+            if (!has_right) xr1 = xr2 = 0.f;
+            if constexpr (CYC) gather_ends<float, K, C>(x0, lg, g.n, exact, r0, r1, rn2, rn1);
+        }
         double ctop0 = 0.0, ctop1 = 0.0, cbot2 = 0.0, cbot1 = 0.0;
         if constexpr (CYC) {
-            float r0, r1, rn2, rn1;
-            gather_ends<float, K, C>(x0, lg, g.n, exact, r0, r1, rn2, rn1);
             if constexpr (K == 1) {
                 ctop0 = cn.top[0][1] * (double)rn1;
                 cbot1 = cn.bot[1][0] * (double)r0;
@@ -540,7 +621,7 @@ __global__ __launch_bounds__(kMaxBlockThreads) void refine_kernel(
             dx[t] = (float)r;
         });
         __builtin_amdgcn_sched_barrier(0);
-        chunk_solve<float, K, C, CYC>(dx, lds, lg, g.n, exact, cq);
+        chunk_solve<float, K, C, CYC, (QL > 0)>(dx, lds, lg, g.n, exact, cq, xch);
         double xo[C];
 #pragma unroll
         for (int t = 0; t < C; ++t) xo[t] = (double)x0[t] + (double)dx[t];
@@ -625,9 +706,10 @@ int cu_count()
 
 // Persistent-style launch: as many workgroups as can be resident at once
 // (rounded to a multiple of the 8 XCDs), each looping over groups of systems.
+// split_waves > 0: a split group of that many waves is the whole workgroup.
 template <typename... KArgs, typename... Args>
-hipError_t launch_grid(void (*kern)(KArgs...), size_t lds, int64_t groups, hipStream_t s,
-                       Args... args)
+hipError_t launch_grid_split(void (*kern)(KArgs...), size_t lds, int64_t groups, int split_waves,
+                             hipStream_t s, Args... args)
 {
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,
@@ -641,12 +723,17 @@ hipError_t launch_grid(void (*kern)(KArgs...), size_t lds, int64_t groups, hipSt
         const int w = std::atoi(env);
         if (w == 1 || w == 2 || w == 4) waves_per_block = w;
     }
+    int groups_per_block = waves_per_block;
+    if (split_waves > 0) {
+        waves_per_block = split_waves;
+        groups_per_block = 1;
+    }
     const int threads = waves_per_block * kWave;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
-    int64_t need = (groups + waves_per_block - 1) / waves_per_block;
+    int64_t need = (groups + groups_per_block - 1) / groups_per_block;
     int64_t cap = (int64_t)cu_count() * per_cu;
     int64_t blocks = need < cap ? need : cap;
     blocks = ((blocks + 7) / 8) * 8;   // multiple of the XCD count, see group_range
@@ -655,18 +742,43 @@ hipError_t launch_grid(void (*kern)(KArgs...), size_t lds, int64_t groups, hipSt
     return hipGetLastError();
 }
 
+template <typename... KArgs, typename... Args>
+hipError_t launch_grid(void (*kern)(KArgs...), size_t lds, int64_t groups, hipStream_t s,
+                       Args... args)
+{
+    return launch_grid_split(kern, lds, groups, 0, s, args...);
+}
+
 bool is_full(const SweepGeom &g) { return ((int64_t)g.C << g.log2P) == g.n; }
+
+template <typename T, int K, bool CYC, int C, int QL>
+hipError_t sweep_split(const void *table, int64_t table_elems, const CyclicQ &q,
+                       const SweepGeom &g, const void *in, void *out, hipStream_t stream)
+{
+    const size_t lds = (size_t)(table_elems + split_exchange_len(QL)) * sizeof(T);
+    return launch_grid_split(sweep_kernel<T, K, C, CYC, true, QL>, lds, g.groups, 1 << QL, stream,
+                             (const T *)table, table_elems, q, g, (const T *)in, (T *)out);
+}
 
 template <typename T, int K, bool CYC, int C>
 hipError_t sweep_c(const void *table, int64_t table_elems, const CyclicQ &q, const SweepGeom &g,
                    const void *in, void *out, hipStream_t stream)
 {
+    if (g.log2Q > 0) {
+        // split groups: full decompositions with 64 or 128 rows per lane only
+        if constexpr (C >= 64) {
+            if (!is_full(g) || g.log2Q > kMaxLog2Q || g.log2Q > g.log2P) return hipErrorInvalidValue;
+            if (g.log2Q == 1) return sweep_split<T, K, CYC, C, 1>(table, table_elems, q, g, in, out, stream);
+            return sweep_split<T, K, CYC, C, 2>(table, table_elems, q, g, in, out, stream);
+        }
+        return hipErrorInvalidValue;
+    }
     const size_t lds = (size_t)table_elems * sizeof(T);
     if (is_full(g))
-        return launch_grid(sweep_kernel<T, K, C, CYC, true>, lds, g.groups, stream,
+        return launch_grid(sweep_kernel<T, K, C, CYC, true, 0>, lds, g.groups, stream,
                            (const T *)table, table_elems, q, g, (const T *)in, (T *)out);
-    return launch_grid(sweep_kernel<T, K, C, CYC, false>, lds, g.groups, stream, (const T *)table,
-                       table_elems, q, g, (const T *)in, (T *)out);
+    return launch_grid(sweep_kernel<T, K, C, CYC, false, 0>, lds, g.groups, stream,
+                       (const T *)table, table_elems, q, g, (const T *)in, (T *)out);
 }
 
 template <int K, bool CYC, int C>
@@ -675,12 +787,27 @@ hipError_t refine_c(const void *table, int64_t table_elems, const double *band,
                     const void *in, void *out, hipStream_t stream)
 {
     const size_t lds = (size_t)band_elems * sizeof(double) + (size_t)table_elems * sizeof(float);
+    if (g.log2Q > 0) {
+        if constexpr (C >= 64) {
+            if (!is_full(g) || g.log2Q > kMaxLog2Q || g.log2Q > g.log2P) return hipErrorInvalidValue;
+            const size_t xl = (size_t)(split_exchange_len(g.log2Q) + (4LL * kWave << g.log2Q)) * sizeof(float);
+            if (g.log2Q == 1)
+                return launch_grid_split(refine_kernel<K, C, CYC, true, 1>, lds + xl, g.groups, 2,
+                                         stream, (const float *)table, table_elems, band,
+                                         band_elems, q, cn, g, (const double *)in, (double *)out);
+            return launch_grid_split(refine_kernel<K, C, CYC, true, 2>, lds + xl, g.groups, 4,
+                                     stream, (const float *)table, table_elems, band, band_elems,
+                                     q, cn, g, (const double *)in, (double *)out);
+        }
+        return hipErrorInvalidValue;
+    }
     if (is_full(g))
-        return launch_grid(refine_kernel<K, C, CYC, true>, lds, g.groups, stream,
+        return launch_grid(refine_kernel<K, C, CYC, true, 0>, lds, g.groups, stream,
                            (const float *)table, table_elems, band, band_elems, q, cn, g,
                            (const double *)in, (double *)out);
-    return launch_grid(refine_kernel<K, C, CYC, false>, lds, g.groups, stream, (const float *)table,
-                       table_elems, band, band_elems, q, cn, g, (const double *)in, (double *)out);
+    return launch_grid(refine_kernel<K, C, CYC, false, 0>, lds, g.groups, stream,
+                       (const float *)table, table_elems, band, band_elems, q, cn, g,
+                       (const double *)in, (double *)out);
 }
 
 template <typename T, int K, bool CYC>

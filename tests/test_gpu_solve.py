@@ -182,3 +182,33 @@ def test_factor_on_the_oracle_matrices_of_every_config():
         say("config matrix", kind, n, cyc)
         assert rel_err(host(f.solve(dev(rhs))), ref) < F64_TOL
         assert rel_err(host(f.solve(dev(rhs), precision="f32r")), ref) < F32R_TOL
+
+
+@pytest.mark.parametrize("kind,n,cyclic", [("tri", 512, False), ("tri", 1024, True),
+                                           ("tri", 2048, False), ("penta", 512, True),
+                                           ("penta", 1024, False), ("penta", 1024, True)])
+def test_split_groups_match_single_wave_groups(kind, n, cyclic, monkeypatch):
+    """A system group spread over 2 or 4 waves (boundary states exchanged
+    through LDS) computes exactly what a one-wave group computes: same
+    operations in the same order, so the results are bitwise equal.  Solve,
+    adjoint, plain FP32 and FP32 + refinement."""
+    f, bands = make(kind, n, seed=17 * n, cyclic=cyclic)
+    m = 1000                                   # not a multiple of any group width
+    rhs = inputs.uniform_batch(n, m, seed=6000 + n)
+    ref = oracle_solve(kind, bands, rhs, cyclic)
+    t = dev(rhs)
+    got = {}
+    for q in (1, 2, 4):
+        monkeypatch.setenv("BANDBATCH_WAVES_PER_SYSTEM", str(q))
+        say("split", kind, n, cyclic, "waves per system", q)
+        got[q] = host(f.solve(t))
+        assert rel_err(got[q], ref) < F64_TOL
+        lam = host(f.adjoint(t))
+        assert rel_err(lam, oracle_adjoint(kind, bands, rhs, cyclic)) < F64_TOL
+        x32 = host(f.solve(dev(rhs, torch.float32), precision="f32"))
+        assert rel_err(x32, ref) < F32_TOL
+        got[("r", q)] = host(f.solve(t, precision="f32r"))
+        assert rel_err(got[("r", q)], ref) < F32R_TOL
+    assert np.array_equal(got[1], got[2]) and np.array_equal(got[1], got[4])
+    assert np.array_equal(got[("r", 1)], got[("r", 2)])
+    assert np.array_equal(got[("r", 1)], got[("r", 4)])
