@@ -21,12 +21,16 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // One wave: rows [i0, i0 + kGradRows) x systems [kb * kGradSys, (kb+1) * kGradSys).
 // part[kb][band][i] = -sum over the wave's systems of lam[i,k] x[i+off,k].
+// The loads of row i+1 are issued before row i is reduced (one row in flight
+// ahead); lane i - i0 keeps row i's sums and the strip is stored at the end
+// as one coalesced store per band.
 template <int NB>
 __global__ __launch_bounds__(256) void band_grad_partial(int n, int cyclic, int64_t m, int64_t ld,
                                                          const double *__restrict__ lam,
                                                          const double *__restrict__ x,
                                                          double *__restrict__ part)
 {
+    static_assert(kGradRows <= kWave, "one row per lane at the store");
     constexpr int H = NB / 2;
     const int lane = threadIdx.x % kWave;
     const int strip = blockIdx.y * (blockDim.x / kWave) + threadIdx.x / kWave;
@@ -48,36 +52,58 @@ __global__ __launch_bounds__(256) void band_grad_partial(int n, int cyclic, int6
         }
         return kv[r] ? x[(int64_t)row * ld + ks[r]] : 0.0;
     };
-    // sliding window of x rows i-H .. i+H
-    double win[NB][kGradR];
+    auto load_l = [&](int row, int r) -> double {
+        return (kv[r] && row < n) ? lam[(int64_t)row * ld + ks[r]] : 0.0;
+    };
+    // sliding window of x rows i-H .. i+H, and the next row's operands
+    double win[NB][kGradR], xn[kGradR], ln[kGradR];
 #pragma unroll
     for (int w = 0; w < NB - 1; ++w)
 #pragma unroll
         for (int r = 0; r < kGradR; ++r) win[w + 1][r] = load_x(i0 - H + w, r);
-    double *dst = part + (int64_t)kb * NB * n;
+#pragma unroll
+    for (int r = 0; r < kGradR; ++r) {
+        xn[r] = load_x(i0 + H, r);
+        ln[r] = load_l(i0, r);
+    }
+    double keep[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) keep[q] = 0.0;
     for (int i = i0; i < i1; ++i) {
+        double l[kGradR];
 #pragma unroll
-        for (int w = 0; w < NB - 1; ++w)
+        for (int r = 0; r < kGradR; ++r) {
 #pragma unroll
-            for (int r = 0; r < kGradR; ++r) win[w][r] = win[w + 1][r];
+            for (int w = 0; w < NB - 1; ++w) win[w][r] = win[w + 1][r];
+            win[NB - 1][r] = xn[r];
+            l[r] = ln[r];
+        }
+        if (i + 1 < i1) {
 #pragma unroll
-        for (int r = 0; r < kGradR; ++r) win[NB - 1][r] = load_x(i + H, r);
+            for (int r = 0; r < kGradR; ++r) {
+                xn[r] = load_x(i + 1 + H, r);
+                ln[r] = load_l(i + 1, r);
+            }
+        }
         double acc[NB];
 #pragma unroll
         for (int q = 0; q < NB; ++q) acc[q] = 0.0;
 #pragma unroll
-        for (int r = 0; r < kGradR; ++r) {
-            const double l = kv[r] ? lam[(int64_t)i * ld + ks[r]] : 0.0;
+        for (int r = 0; r < kGradR; ++r)
 #pragma unroll
-            for (int q = 0; q < NB; ++q) acc[q] = fma(l, win[q][r], acc[q]);
-        }
+            for (int q = 0; q < NB; ++q) acc[q] = fma(l[r], win[q][r], acc[q]);
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const double s = wave_sum(acc[q]);
             // entries outside a non-cyclic matrix have no gradient
             const bool inside = cyclic || (i + q - H >= 0 && i + q - H < n);
-            if (lane == 0) dst[(int64_t)q * n + i] = inside ? -s : 0.0;
+            if (lane == i - i0) keep[q] = inside ? -s : 0.0;
         }
+    }
+    double *dst = part + (int64_t)kb * NB * n;
+    if (lane < i1 - i0) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) dst[(int64_t)q * n + i0 + lane] = keep[q];
     }
 }
 

@@ -163,6 +163,21 @@ __device__ __forceinline__ void affine(const T *M, T &y1, T &y2, T e1, T e2)
     }
 }
 
+// s = Q (r0, r1, rn2, rn1): the periodic correction scalars, with every
+// product-sum written as an explicit fma chain so the rounding does not
+// depend on how the compiler contracts a particular kernel.
+template <typename T, int K>
+__device__ __forceinline__ void correction_scalars(const CyclicQ &cq, T r0, T r1, T rn2, T rn1,
+                                                   T &c0, T &c1)
+{
+    if constexpr (K == 1) {
+        c0 = fma(T(cq.q[0][1]), rn1, T(cq.q[0][0]) * r0);
+    } else {
+        c0 = fma(T(cq.q[0][3]), rn1, fma(T(cq.q[0][2]), rn2, fma(T(cq.q[0][1]), r1, T(cq.q[0][0]) * r0)));
+        c1 = fma(T(cq.q[1][3]), rn1, fma(T(cq.q[1][2]), rn2, fma(T(cq.q[1][1]), r1, T(cq.q[1][0]) * r0)));
+    }
+}
+
 // Solve this lane's chunk in place: v holds the right-hand side rows on entry
 // and the solution rows on exit.  All 64 lanes of the wave must call it
 // together (the scans shuffle across the wave).
@@ -287,12 +302,7 @@ __device__ __forceinline__ void chunk_solve(T (&v)[C], const T *lds, const LaneG
                 rn1 = shfl(y1, last);
                 rn2 = (K == 2) ? fma(T(cq.u1_nm2), rn1, shfl(y2, last)) : T(0);
             }
-            if constexpr (K == 1) {
-                c0 = T(cq.q[0][0]) * r0 + T(cq.q[0][1]) * rn1;
-            } else {
-                c0 = T(cq.q[0][0]) * r0 + T(cq.q[0][1]) * r1 + T(cq.q[0][2]) * rn2 + T(cq.q[0][3]) * rn1;
-                c1 = T(cq.q[1][0]) * r0 + T(cq.q[1][1]) * r1 + T(cq.q[1][2]) * rn2 + T(cq.q[1][3]) * rn1;
-            }
+            correction_scalars<T, K>(cq, r0, r1, rn2, rn1, c0, c1);
         }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -332,12 +342,7 @@ __device__ __forceinline__ void chunk_solve(T (&v)[C], const T *lds, const LaneG
             __builtin_amdgcn_sched_barrier(0);
             T r0, r1, rn2, rn1;
             gather_ends<T, K, C>(v, lg, n, exact, r0, r1, rn2, rn1);
-            if constexpr (K == 1) {
-                c0 = T(cq.q[0][0]) * r0 + T(cq.q[0][1]) * rn1;
-            } else {
-                c0 = T(cq.q[0][0]) * r0 + T(cq.q[0][1]) * r1 + T(cq.q[0][2]) * rn2 + T(cq.q[0][3]) * rn1;
-                c1 = T(cq.q[1][0]) * r0 + T(cq.q[1][1]) * r1 + T(cq.q[1][2]) * rn2 + T(cq.q[1][3]) * rn1;
-            }
+            correction_scalars<T, K>(cq, r0, r1, rn2, rn1, c0, c1);
             const auto tp = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
             rows_up<C>([&](int t) {
                 T x = fma(tp.z0[t], c0, v[t]);
@@ -580,10 +585,10 @@ __global__ __launch_bounds__(kMaxBlockThreads) void refine_kernel(
                 ctop0 = cn.top[0][1] * (double)rn1;
                 cbot1 = cn.bot[1][0] * (double)r0;
             } else {
-                ctop0 = cn.top[0][0] * (double)rn2 + cn.top[0][1] * (double)rn1;
-                ctop1 = cn.top[1][0] * (double)rn2 + cn.top[1][1] * (double)rn1;
-                cbot2 = cn.bot[0][0] * (double)r0 + cn.bot[0][1] * (double)r1;
-                cbot1 = cn.bot[1][0] * (double)r0 + cn.bot[1][1] * (double)r1;
+                ctop0 = fma(cn.top[0][1], (double)rn1, cn.top[0][0] * (double)rn2);
+                ctop1 = fma(cn.top[1][1], (double)rn1, cn.top[1][0] * (double)rn2);
+                cbot2 = fma(cn.bot[0][1], (double)r1, cn.bot[0][0] * (double)r0);
+                cbot1 = fma(cn.bot[1][1], (double)r1, cn.bot[1][0] * (double)r0);
             }
         }
         const int nrow = opaque_v(g.n - row0);   // this chunk's row index of row n (may be <= 0 or > C)

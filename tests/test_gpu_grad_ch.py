@@ -103,6 +103,9 @@ def test_checkpointing_is_bitwise_neutral():
         bands = (-0.5 * D, 1 + D, -0.5 * D)
         mse_loss(banded_rollout(tu0, bands, steps, every), dev(y)).backward()
         grads.append((D.grad.numpy().copy(), host(tu0.grad)))
+    for every, (gD, gu) in zip((7, 30), grads[1:]):
+        say("checkpoint every", every, "max |dD diff|", np.max(np.abs(gD - grads[0][0])),
+            "max |du0 diff|", np.max(np.abs(gu - grads[0][1])))
     for gD, gu in grads[1:]:
         assert np.array_equal(gD, grads[0][0]) and np.array_equal(gu, grads[0][1])
 

@@ -209,6 +209,10 @@ def test_split_groups_match_single_wave_groups(kind, n, cyclic, monkeypatch):
         assert rel_err(x32, ref) < F32_TOL
         got[("r", q)] = host(f.solve(t, precision="f32r"))
         assert rel_err(got[("r", q)], ref) < F32R_TOL
+    monkeypatch.setenv("BANDBATCH_WAVES_PER_SYSTEM", "2")
+    assert np.array_equal(host(f.solve(t, precision="f32r")), got[("r", 2)])   # repeatable
+    for q in (2, 4):
+        say("  max |f32r diff| q=1 vs q=%d" % q, np.max(np.abs(got[("r", 1)] - got[("r", q)])))
     assert np.array_equal(got[1], got[2]) and np.array_equal(got[1], got[4])
     assert np.array_equal(got[("r", 1)], got[("r", 2)])
     assert np.array_equal(got[("r", 1)], got[("r", 4)])
