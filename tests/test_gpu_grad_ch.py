@@ -91,6 +91,11 @@ def test_rollout_gradients_match_oracle(precision, tol):
 
 
 def test_checkpointing_is_bitwise_neutral():
+    """Recomputing the states between checkpoints reproduces them exactly, so
+    the gradients of every band and of u0 do not depend on the checkpoint
+    interval.  The bands are the leaves here: a parameter feeding several
+    bands (D in A(D)) has its contributions summed by torch's autograd engine,
+    whose order across the CPU and GPU worker threads is not fixed."""
     from paper_2107_05395_amd import banded_rollout, mse_loss
     n, m, steps = 256, 200, 30
     D0 = inputs.rng(11).uniform(0.5, 1.5, n)
@@ -98,16 +103,14 @@ def test_checkpointing_is_bitwise_neutral():
     y = inputs.uniform_batch(n, m, seed=13)
     grads = []
     for every in (1, 7, 30):
-        D = torch.tensor(D0, requires_grad=True)
+        bands = [torch.tensor(v, requires_grad=True) for v in (-0.5 * D0, 1 + D0, -0.5 * D0)]
         tu0 = dev(u0).requires_grad_(True)
-        bands = (-0.5 * D, 1 + D, -0.5 * D)
         mse_loss(banded_rollout(tu0, bands, steps, every), dev(y)).backward()
-        grads.append((D.grad.numpy().copy(), host(tu0.grad)))
-    for every, (gD, gu) in zip((7, 30), grads[1:]):
-        say("checkpoint every", every, "max |dD diff|", np.max(np.abs(gD - grads[0][0])),
-            "max |du0 diff|", np.max(np.abs(gu - grads[0][1])))
-    for gD, gu in grads[1:]:
-        assert np.array_equal(gD, grads[0][0]) and np.array_equal(gu, grads[0][1])
+        grads.append([b.grad.numpy().copy() for b in bands] + [host(tu0.grad)])
+    for every, g in zip((7, 30), grads[1:]):
+        say("checkpoint every", every, "max diffs", [float(np.max(np.abs(a - b))) for a, b in zip(g, grads[0])])
+    for g in grads[1:]:
+        assert all(np.array_equal(a, b) for a, b in zip(g, grads[0]))
 
 
 # ---------------------------------------------------------------- Cahn-Hilliard
