@@ -1,6 +1,7 @@
 // api.cpp -- the extern "C" boundary of libbandbatch (declared in
 // include/bandbatch.h): argument checks, choice of the sweep decomposition,
 // lazy upload of the factor's coefficient tables, kernel dispatch.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -68,16 +69,22 @@ int lockstep_for(int S, size_t elem_bytes)
     return 1;
 }
 
-// Waves per system group (log2).  A full decomposition with many chunks per
-// system spreads each group over 2 or 4 waves so that a wave's load covers
-// at least 16 systems (128 B per row in double) -- see internal.h.
+// Waves per system group (log2) for a full decomposition (C >= 64) -- see
+// internal.h.  Measured on 2^29-element batches and on the 2^16-system
+// differentiated workload: the FP64/FP32 sweep (C = 128, one wave per SIMD)
+// runs fastest with 4-wave groups once P >= 8 (S = 32 or 16); the refinement
+// kernel (C = 64) with S = 16, i.e. Q = P/4.  P <= 4 keeps one wave.
 // BANDBATCH_WAVES_PER_SYSTEM = 1, 2 or 4 forces the group size where it is
 // valid (tuning); anything else keeps the automatic choice.
-int split_log2(int log2P, int C, int n)
+int split_log2(int log2P, int C, int n, bb::Op op)
 {
     if (C < 64 || ((int64_t)C << log2P) != n) return 0;
     int l = 0;
-    while (log2P - l > 2 && l < bb::kMaxLog2Q) ++l;
+    if (op == bb::Op::Refine)
+        l = log2P > 2 ? log2P - 2 : 0;
+    else
+        l = log2P >= 3 ? bb::kMaxLog2Q : 0;
+    if (l > bb::kMaxLog2Q) l = bb::kMaxLog2Q;
     if (const char *env = std::getenv("BANDBATCH_WAVES_PER_SYSTEM")) {
         const int q = std::atoi(env);
         const int fl = q == 1 ? 0 : q == 2 ? 1 : q == 4 ? 2 : -1;
@@ -231,7 +238,7 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
     g.exact = (f.n % C) == 0;
     g.m = m;
     g.ld = ld;
-    g.log2Q = split_log2(log2P, C, (int)f.n);
+    g.log2Q = split_log2(log2P, C, (int)f.n, op);
     const int S = (bb::kWave << g.log2Q) / P;
     g.groups = (m + S - 1) / S;
     g.lockstep = lockstep_for(S, p == BB_F32 ? sizeof(float) : sizeof(double));
@@ -412,7 +419,10 @@ bb_status bb_ch_step(bb_factor fh, const double *c_in, double *c_out, int64_t m,
     if (m == 0) return BB_OK;
     int dev;
     if ((st = current_device(&dev)) != BB_OK) return st;
-    const int C = bb::choose_chunk(f.n, max_chunk(BB_F64));
+    // The fused steps are bound by arithmetic and coefficient reads, not HBM:
+    // 64 rows per lane keeps two waves per SIMD to hide each other's
+    // latencies (measured 0.39 vs 0.52 ms per step at n = 256, m = 2^20).
+    const int C = bb::choose_chunk(f.n, std::min(max_chunk(BB_F64), bb::kChunkMaxCH));
     const int P = bb::lanes_for(f.n, C);
     int log2P = 0;
     while ((1 << log2P) < P) ++log2P;

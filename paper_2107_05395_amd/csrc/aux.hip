@@ -19,13 +19,16 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// One wave: rows [i0, i0 + kGradRows) x systems [kb * kGradSys, (kb+1) * kGradSys).
-// part[kb][band][i] = -sum over the wave's systems of lam[i,k] x[i+off,k].
-// The loads of row i+1 are issued before row i is reduced (one row in flight
-// ahead); lane i - i0 keeps row i's sums and the strip is stored at the end
-// as one coalesced store per band.
+// One wave: rows [i0, i0 + kGradRows) x the k-blocks kg*kpw .. (kg+1)*kpw - 1
+// of kGradSys systems each (blockIdx.x = kg).
+// part[kg][band][i] = -sum over those systems of lam[i,k] x[i+off,k], the
+// k-blocks added in ascending order.  Within a k-block the loads of row i+1
+// are issued before row i is reduced (one row in flight ahead); lane i - i0
+// keeps row i's sum and the strip is stored at the end, one coalesced store
+// per band.
 template <int NB>
 __global__ __launch_bounds__(256) void band_grad_partial(int n, int cyclic, int64_t m, int64_t ld,
+                                                         int64_t kpw,
                                                          const double *__restrict__ lam,
                                                          const double *__restrict__ x,
                                                          double *__restrict__ part)
@@ -37,86 +40,105 @@ __global__ __launch_bounds__(256) void band_grad_partial(int n, int cyclic, int6
     const int i0 = strip * kGradRows;
     if (i0 >= n) return;
     const int i1 = i0 + kGradRows < n ? i0 + kGradRows : n;
-    const int64_t kb = blockIdx.x;
-    int64_t ks[kGradR];
-    bool kv[kGradR];
-#pragma unroll
-    for (int r = 0; r < kGradR; ++r) {
-        ks[r] = kb * kGradSys + r * kWave + lane;
-        kv[r] = ks[r] < m;
-    }
-    auto load_x = [&](int row, int r) -> double {
-        if (row < 0 || row >= n) {
-            if (!cyclic) return 0.0;
-            row = (row % n + n) % n;
-        }
-        return kv[r] ? x[(int64_t)row * ld + ks[r]] : 0.0;
-    };
-    auto load_l = [&](int row, int r) -> double {
-        return (kv[r] && row < n) ? lam[(int64_t)row * ld + ks[r]] : 0.0;
-    };
-    // sliding window of x rows i-H .. i+H, and the next row's operands
-    double win[NB][kGradR], xn[kGradR], ln[kGradR];
-#pragma unroll
-    for (int w = 0; w < NB - 1; ++w)
-#pragma unroll
-        for (int r = 0; r < kGradR; ++r) win[w + 1][r] = load_x(i0 - H + w, r);
-#pragma unroll
-    for (int r = 0; r < kGradR; ++r) {
-        xn[r] = load_x(i0 + H, r);
-        ln[r] = load_l(i0, r);
-    }
+    const int64_t kblocks = (m + kGradSys - 1) / kGradSys;
+    const int64_t kb0 = (int64_t)blockIdx.x * kpw;
+    const int64_t kb1 = kb0 + kpw < kblocks ? kb0 + kpw : kblocks;
     double keep[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) keep[q] = 0.0;
-    for (int i = i0; i < i1; ++i) {
-        double l[kGradR];
+    for (int64_t kb = kb0; kb < kb1; ++kb) {
+        int64_t ks[kGradR];
+        bool kv[kGradR];
 #pragma unroll
         for (int r = 0; r < kGradR; ++r) {
-#pragma unroll
-            for (int w = 0; w < NB - 1; ++w) win[w][r] = win[w + 1][r];
-            win[NB - 1][r] = xn[r];
-            l[r] = ln[r];
+            ks[r] = kb * kGradSys + r * kWave + lane;
+            kv[r] = ks[r] < m;
         }
-        if (i + 1 < i1) {
+        auto load_x = [&](int row, int r) -> double {
+            if (row < 0 || row >= n) {
+                if (!cyclic) return 0.0;
+                row = (row % n + n) % n;
+            }
+            return kv[r] ? x[(int64_t)row * ld + ks[r]] : 0.0;
+        };
+        auto load_l = [&](int row, int r) -> double {
+            return (kv[r] && row < n) ? lam[(int64_t)row * ld + ks[r]] : 0.0;
+        };
+        // sliding window of x rows i-H .. i+H, and the next row's operands
+        double win[NB][kGradR], xn[kGradR], ln[kGradR];
+#pragma unroll
+        for (int w = 0; w < NB - 1; ++w)
+#pragma unroll
+            for (int r = 0; r < kGradR; ++r) win[w + 1][r] = load_x(i0 - H + w, r);
+#pragma unroll
+        for (int r = 0; r < kGradR; ++r) {
+            xn[r] = load_x(i0 + H, r);
+            ln[r] = load_l(i0, r);
+        }
+        for (int i = i0; i < i1; ++i) {
+            double l[kGradR];
 #pragma unroll
             for (int r = 0; r < kGradR; ++r) {
-                xn[r] = load_x(i + 1 + H, r);
-                ln[r] = load_l(i + 1, r);
+#pragma unroll
+                for (int w = 0; w < NB - 1; ++w) win[w][r] = win[w + 1][r];
+                win[NB - 1][r] = xn[r];
+                l[r] = ln[r];
+            }
+            if (i + 1 < i1) {
+#pragma unroll
+                for (int r = 0; r < kGradR; ++r) {
+                    xn[r] = load_x(i + 1 + H, r);
+                    ln[r] = load_l(i + 1, r);
+                }
+            }
+            double acc[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) acc[q] = 0.0;
+#pragma unroll
+            for (int r = 0; r < kGradR; ++r)
+#pragma unroll
+                for (int q = 0; q < NB; ++q) acc[q] = fma(l[r], win[q][r], acc[q]);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const double sum = wave_sum(acc[q]);
+                if (lane == i - i0) keep[q] -= sum;
             }
         }
-        double acc[NB];
-#pragma unroll
-        for (int q = 0; q < NB; ++q) acc[q] = 0.0;
-#pragma unroll
-        for (int r = 0; r < kGradR; ++r)
-#pragma unroll
-            for (int q = 0; q < NB; ++q) acc[q] = fma(l[r], win[q][r], acc[q]);
+    }
+    double *dst = part + (int64_t)blockIdx.x * NB * n;
+    if (lane < i1 - i0) {
+        const int i = i0 + lane;
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-            const double s = wave_sum(acc[q]);
             // entries outside a non-cyclic matrix have no gradient
             const bool inside = cyclic || (i + q - H >= 0 && i + q - H < n);
-            if (lane == i - i0) keep[q] = inside ? -s : 0.0;
+            dst[(int64_t)q * n + i] = inside ? keep[q] : 0.0;
         }
-    }
-    double *dst = part + (int64_t)kb * NB * n;
-    if (lane < i1 - i0) {
-#pragma unroll
-        for (int q = 0; q < NB; ++q) dst[(int64_t)q * n + i0 + lane] = keep[q];
     }
 }
 
-// grad[q*n + i] += sum over k-blocks (ascending) of part[kb][q][i]
-__global__ __launch_bounds__(256) void band_grad_fold(int64_t total, int64_t kblocks,
-                                                      const double *__restrict__ part,
-                                                      double *__restrict__ grad)
+// grad[e] += sum over the partial groups g of part[g][e]: the 16 waves of a
+// block each sum every 16th group (ascending), and the 16 sums are added in
+// a fixed order -- the same result on every run.
+constexpr int kFoldSubs = 16;
+__global__ __launch_bounds__(kFoldSubs * kWave) void band_grad_fold(int64_t total, int64_t groups,
+                                                                  const double *__restrict__ part,
+                                                                  double *__restrict__ grad)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= total) return;
+    __shared__ double red[kFoldSubs][kWave];
+    const int lane = threadIdx.x % kWave, sub = threadIdx.x / kWave;
+    const int64_t e = (int64_t)blockIdx.x * kWave + lane;
     double s = 0.0;
-    for (int64_t kb = 0; kb < kblocks; ++kb) s += part[kb * total + e];
-    grad[e] += s;
+    if (e < total)
+        for (int64_t g = sub; g < groups; g += kFoldSubs) s += part[g * total + e];
+    red[sub][lane] = s;
+    __syncthreads();
+    if (sub == 0 && e < total) {
+        double t = red[0][lane];
+#pragma unroll
+        for (int q = 1; q < kFoldSubs; ++q) t += red[q][lane];
+        grad[e] += t;
+    }
 }
 
 // ---------------------------------------------------------------- MSE
@@ -193,29 +215,45 @@ __global__ __launch_bounds__(256) void tri_thread_per_system(const double *__res
 
 }  // namespace
 
+// k-blocks per wave: enough waves (about 8192, four per SIMD on 256 CUs) to
+// keep HBM busy, few enough partial sums that the fold stays short.
+int64_t band_grad_kpw(int n, int64_t m)
+{
+    const int64_t kblocks = (m + kGradSys - 1) / kGradSys;
+    const int64_t strips = (n + kGradRows - 1) / kGradRows;
+    int64_t kpw = kblocks * strips / 8192;
+    return kpw < 1 ? 1 : kpw;
+}
+
 size_t band_grad_workspace(int nb, int n, int64_t m)
 {
     const int64_t kblocks = (m + kGradSys - 1) / kGradSys;
-    return (size_t)kblocks * nb * n * sizeof(double);
+    const int64_t kpw = band_grad_kpw(n, m);
+    const int64_t groups = (kblocks + kpw - 1) / kpw;
+    return (size_t)groups * nb * n * sizeof(double);
 }
 
 hipError_t launch_band_grad(int nb, bool cyclic, int n, int64_t m, int64_t ld, const double *lam,
                             const double *x, double *grad, void *ws, hipStream_t s)
 {
     const int64_t kblocks = (m + kGradSys - 1) / kGradSys;
+    const int64_t kpw = band_grad_kpw(n, m);
+    const int64_t groups = (kblocks + kpw - 1) / kpw;
     const int strips = (n + kGradRows - 1) / kGradRows;
     const int waves = 256 / kWave;
-    dim3 grid((unsigned)kblocks, (unsigned)((strips + waves - 1) / waves));
+    dim3 grid((unsigned)groups, (unsigned)((strips + waves - 1) / waves));
     double *part = (double *)ws;
     if (nb == 3)
-        hipLaunchKernelGGL(band_grad_partial<3>, grid, dim3(256), 0, s, n, (int)cyclic, m, ld, lam, x, part);
+        hipLaunchKernelGGL(band_grad_partial<3>, grid, dim3(256), 0, s, n, (int)cyclic, m, ld, kpw,
+                           lam, x, part);
     else
-        hipLaunchKernelGGL(band_grad_partial<5>, grid, dim3(256), 0, s, n, (int)cyclic, m, ld, lam, x, part);
+        hipLaunchKernelGGL(band_grad_partial<5>, grid, dim3(256), 0, s, n, (int)cyclic, m, ld, kpw,
+                           lam, x, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t total = (int64_t)nb * n;
-    hipLaunchKernelGGL(band_grad_fold, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, total,
-                       kblocks, (const double *)part, grad);
+    hipLaunchKernelGGL(band_grad_fold, dim3((unsigned)((total + kWave - 1) / kWave)),
+                       dim3(kFoldSubs * kWave), 0, s, total, groups, (const double *)part, grad);
     return hipGetLastError();
 }
 

@@ -75,6 +75,7 @@ constexpr int kMaxBlockThreads = 256;   // launch bound: up to 4 waves per workg
 constexpr int kChunkMin = 4;
 constexpr int kChunkMax = 128;
 constexpr int kChunkMaxRefine = 64;   // the refinement kernel holds 4 words per row
+constexpr int kChunkMaxCH = 64;       // fused Cahn-Hilliard steps: two waves per SIMD
 // Largest system sizes.  The coefficient tables of a workgroup live in LDS
 // (160 KB per CU): a tridiagonal table has up to 6 arrays of n (+pad) values,
 // a pentadiagonal one up to 11; at these limits the largest tables (periodic,
