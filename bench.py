@@ -112,6 +112,10 @@ def bench_tri(args, torch):
         ref = oracle.tri_solve(*bands, rhs_host[:, cols])
         err = rel_err_cols(x[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref)
         results[prec] = dict(seconds=t, wall=wall, err=err)
+    # a plain device-to-device copy of the same array: the achievable HBM rate
+    # for one read + one write stream on this part (context for the roofline)
+    ct, _ = time_launches(lambda: x.copy_(rhs), 10, 2, torch)
+    copy_gbs = algo_bytes * 10 / ct / 1e9
     # the paper's own mapping: one thread per system, intermediate through HBM
     pt, _ = time_launches(lambda: f.solve_thread_per_system(rhs, out=x), max(3, args.steps // 10),
                           1, torch)
@@ -134,6 +138,7 @@ def bench_tri(args, torch):
                  "ms_per_step": 1e3 * results["f32r"]["seconds"] / k,
                  "rel_err_vs_oracle": results["f32r"]["err"],
                  "hbm_gbs_algorithmic": algo_bytes * k / results["f32r"]["seconds"] / 1e9},
+        "copy_gbs": copy_gbs,
         "thread_per_system_design": {"ms_per_step": 1e3 * pt, "value": m / pt,
                                      "hbm_gbs_algorithmic": algo_bytes / pt / 1e9},
         "roofline": {"bound": "hbm", "achieved": algo_bytes / per_launch / 1e9,
