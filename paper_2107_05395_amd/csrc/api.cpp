@@ -55,6 +55,24 @@ int max_chunk(bb_precision p)
     return c;
 }
 
+// Rows per lane of a solve.  Systems whose size is 64 * 2^k (a full
+// decomposition at 64 rows) run at 64 rows per lane: about 170 VGPRs, two
+// waves per SIMD, with the system groups split over waves (split_log2).
+// Measured (FP64, 4 GiB batches, GB/s): tri n = 512 4881 vs 4743 at 128 rows;
+// tri n = 1024 4771 vs 4490; penta n = 1024 4269 vs 3949; tri n = 2048 3975
+// vs 3406; tri n = 256 4826 vs 4769.  Other sizes keep the largest chunk
+// (fewest lanes per system).  An explicit BANDBATCH_MAX_CHUNK disables the
+// preference.
+int solve_chunk(int64_t n, bb_precision p)
+{
+    const int cmax = max_chunk(p);
+    if (!std::getenv("BANDBATCH_MAX_CHUNK") && cmax >= 64) {
+        const int c64 = bb::choose_chunk(n, 64);
+        if (c64 == 64 && (int64_t)c64 * bb::lanes_for(n, c64) == n) return 64;
+    }
+    return bb::choose_chunk(n, cmax);
+}
+
 // Keep the waves of a workgroup in step at every iteration of the persistent
 // loop.  When one wave's segment of a row is shorter than a 128 B line the
 // neighbouring wave reads the rest of the line; in step, the second request
@@ -71,24 +89,28 @@ int lockstep_for(int S, size_t elem_bytes)
 
 // Waves per system group (log2) for a full decomposition (C >= 64) -- see
 // internal.h.  Measured on 2^29-element batches and on the 2^16-system
-// differentiated workload: the FP64/FP32 sweep (C = 128, one wave per SIMD)
-// runs fastest with 4-wave groups once P >= 8 (S = 32 or 16); the refinement
-// kernel (C = 64) with S = 16, i.e. Q = P/4.  P <= 4 keeps one wave.
-// BANDBATCH_WAVES_PER_SYSTEM = 1, 2 or 4 forces the group size where it is
-// valid (tuning); anything else keeps the automatic choice.
+// differentiated workload: the sweep at 64 rows per lane runs fastest with
+// 4-wave groups at P = 8 (S = 32) and 8-wave groups from P = 16 on (S = 32,
+// 16); at 128 rows (one wave per SIMD) with 4-wave groups from P = 8; the
+// refinement kernel (64 rows, one wave per SIMD) with S = 16, i.e. Q = P/4.
+// P <= 4 keeps one wave.
+// BANDBATCH_WAVES_PER_SYSTEM = 1, 2, 4 or 8 forces the group size where it
+// is valid (tuning); anything else keeps the automatic choice.
 int split_log2(int log2P, int C, int n, bb::Op op)
 {
     if (C < 64 || ((int64_t)C << log2P) != n) return 0;
+    const bool refine = op == bb::Op::Refine;
+    const int lmax = bb::max_log2q(C, refine);
     int l = 0;
-    if (op == bb::Op::Refine)
-        l = log2P > 2 ? log2P - 2 : 0;
+    if (refine || C > 64)
+        l = refine ? (log2P > 2 ? log2P - 2 : 0) : (log2P >= 3 ? 2 : 0);
     else
-        l = log2P >= 3 ? bb::kMaxLog2Q : 0;
-    if (l > bb::kMaxLog2Q) l = bb::kMaxLog2Q;
+        l = log2P >= 4 ? 3 : log2P == 3 ? 2 : 0;
+    if (l > lmax) l = lmax;
     if (const char *env = std::getenv("BANDBATCH_WAVES_PER_SYSTEM")) {
         const int q = std::atoi(env);
-        const int fl = q == 1 ? 0 : q == 2 ? 1 : q == 4 ? 2 : -1;
-        if (fl >= 0 && fl <= log2P) l = fl;
+        const int fl = q == 1 ? 0 : q == 2 ? 1 : q == 4 ? 2 : q == 8 ? 3 : -1;
+        if (fl >= 0 && fl <= log2P && fl <= lmax) l = fl;
     }
     return l;
 }
@@ -181,7 +203,7 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
     int dev;
     if ((st = current_device(&dev)) != BB_OK) return st;
 
-    const int C = bb::choose_chunk(f.n, max_chunk(p));
+    const int C = solve_chunk(f.n, p);
     const int P = bb::lanes_for(f.n, C);
     int log2P = 0;
     while ((1 << log2P) < P) ++log2P;
@@ -294,7 +316,7 @@ bb_status bb_factor_upload(bb_factor fh, void *stream)
     bb_status st = current_device(&dev);
     if (st != BB_OK) return st;
     for (bb_precision p : {BB_F64, BB_F32_REFINE}) {
-        const int C = bb::choose_chunk(f.n, max_chunk(p));
+        const int C = solve_chunk(f.n, p);
         const int P = bb::lanes_for(f.n, C);
         const int f32 = p != BB_F64;
         for (int adj = 0; adj < 2; ++adj) {
@@ -314,7 +336,7 @@ bb_status bb_factor_info(bb_factor fh, int64_t *n, int32_t *kind, int32_t *chunk
     if (!fh) return fail(BB_ERR_ARG, "factor is NULL");
     if (n) *n = fh->f.n;
     if (kind) *kind = fh->f.kind;
-    if (chunk) *chunk = bb::choose_chunk(fh->f.n, max_chunk(BB_F64));
+    if (chunk) *chunk = solve_chunk(fh->f.n, BB_F64);
     return BB_OK;
 }
 

@@ -478,7 +478,8 @@ __device__ __forceinline__ LaneGeom lane_geom(int log2P, int log2Q = 0)
 // QL > 0 the workgroup is exactly one group (2^QL waves): every wave of it has
 // the same group index, so the exchange barriers are reached uniformly.
 template <typename T, int K, int C, bool CYC, bool FULL, int QL>
-__global__ __launch_bounds__(kMaxBlockThreads) void sweep_kernel(const T *__restrict__ table,
+__global__ __launch_bounds__((kWave << QL) > kMaxBlockThreads ? (kWave << QL) : kMaxBlockThreads)
+void sweep_kernel(const T *__restrict__ table,
                                                               int64_t table_elems, CyclicQ cq,
                                                               SweepGeom g, const T *in, T *out)
 {
@@ -772,9 +773,11 @@ hipError_t sweep_c(const void *table, int64_t table_elems, const CyclicQ &q, con
     if (g.log2Q > 0) {
         // split groups: full decompositions with 64 or 128 rows per lane only
         if constexpr (C >= 64) {
-            if (!is_full(g) || g.log2Q > kMaxLog2Q || g.log2Q > g.log2P) return hipErrorInvalidValue;
+            if (!is_full(g) || g.log2Q > max_log2q(C, false) || g.log2Q > g.log2P)
+                return hipErrorInvalidValue;
             if (g.log2Q == 1) return sweep_split<T, K, CYC, C, 1>(table, table_elems, q, g, in, out, stream);
-            return sweep_split<T, K, CYC, C, 2>(table, table_elems, q, g, in, out, stream);
+            if (g.log2Q == 2) return sweep_split<T, K, CYC, C, 2>(table, table_elems, q, g, in, out, stream);
+            if constexpr (C <= 64) return sweep_split<T, K, CYC, C, 3>(table, table_elems, q, g, in, out, stream);
         }
         return hipErrorInvalidValue;
     }
@@ -794,7 +797,8 @@ hipError_t refine_c(const void *table, int64_t table_elems, const double *band,
     const size_t lds = (size_t)band_elems * sizeof(double) + (size_t)table_elems * sizeof(float);
     if (g.log2Q > 0) {
         if constexpr (C >= 64) {
-            if (!is_full(g) || g.log2Q > kMaxLog2Q || g.log2Q > g.log2P) return hipErrorInvalidValue;
+            if (!is_full(g) || g.log2Q > max_log2q(C, true) || g.log2Q > g.log2P)
+                return hipErrorInvalidValue;
             const size_t xl = (size_t)(split_exchange_len(g.log2Q) + (4LL * kWave << g.log2Q)) * sizeof(float);
             if (g.log2Q == 1)
                 return launch_grid_split(refine_kernel<K, C, CYC, true, 1>, lds + xl, g.groups, 2,

@@ -187,18 +187,22 @@ def test_factor_on_the_oracle_matrices_of_every_config():
 @pytest.mark.parametrize("kind,n,cyclic", [("tri", 512, False), ("tri", 1024, True),
                                            ("tri", 2048, False), ("penta", 512, True),
                                            ("penta", 1024, False), ("penta", 1024, True)])
-def test_split_groups_match_single_wave_groups(kind, n, cyclic, monkeypatch):
-    """A system group spread over 2 or 4 waves (boundary states exchanged
+@pytest.mark.parametrize("rows", [None, 128])
+def test_split_groups_match_single_wave_groups(kind, n, cyclic, rows, monkeypatch):
+    """A system group spread over 2, 4 or 8 waves (boundary states exchanged
     through LDS) computes exactly what a one-wave group computes: same
     operations in the same order, so the results are bitwise equal.  Solve,
-    adjoint, plain FP32 and FP32 + refinement."""
+    adjoint, plain FP32 and FP32 + refinement; the default rows per lane and
+    128 rows (a width the kernel cannot run falls back to the automatic one)."""
+    if rows:
+        monkeypatch.setenv("BANDBATCH_MAX_CHUNK", str(rows))   # 128 rows per lane, one wave per SIMD
     f, bands = make(kind, n, seed=17 * n, cyclic=cyclic)
     m = 1000                                   # not a multiple of any group width
     rhs = inputs.uniform_batch(n, m, seed=6000 + n)
     ref = oracle_solve(kind, bands, rhs, cyclic)
     t = dev(rhs)
     got = {}
-    for q in (1, 2, 4):
+    for q in (1, 2, 4, 8):
         monkeypatch.setenv("BANDBATCH_WAVES_PER_SYSTEM", str(q))
         say("split", kind, n, cyclic, "waves per system", q)
         got[q] = host(f.solve(t))
@@ -213,6 +217,6 @@ def test_split_groups_match_single_wave_groups(kind, n, cyclic, monkeypatch):
     assert np.array_equal(host(f.solve(t, precision="f32r")), got[("r", 2)])   # repeatable
     for q in (2, 4):
         say("  max |f32r diff| q=1 vs q=%d" % q, np.max(np.abs(got[("r", 1)] - got[("r", q)])))
-    assert np.array_equal(got[1], got[2]) and np.array_equal(got[1], got[4])
+    assert all(np.array_equal(got[1], got[q]) for q in (2, 4, 8))
     assert np.array_equal(got[("r", 1)], got[("r", 2)])
     assert np.array_equal(got[("r", 1)], got[("r", 4)])
