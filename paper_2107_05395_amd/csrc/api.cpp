@@ -459,9 +459,17 @@ bb_status bb_ch_step(bb_factor fh, const double *c_in, double *c_out, int64_t m,
     g.exact = (f.n % C) == 0;
     g.m = m;
     g.ld = ld;
-    g.groups = (m + bb::kWave / P - 1) / (bb::kWave / P);
-    g.lockstep = lockstep_for(bb::kWave / P, sizeof(double));
+    // One chunk per wave when the 64-row chunks tile n into 2, 4 or 8: the
+    // coefficients are then wave-uniform and come through the scalar cache
+    // instead of LDS, whose bandwidth bounds the fused steps otherwise.
+    // BANDBATCH_CH_UNIFORM=0 keeps the LDS kernel (tuning, testing).
     g.log2Q = 0;
+    const char *uni = std::getenv("BANDBATCH_CH_UNIFORM");
+    if (C == 64 && (int64_t)C * P == f.n && log2P >= 1 && log2P <= 3 && !(uni && std::atoi(uni) == 0))
+        g.log2Q = log2P;
+    const int S = (bb::kWave << g.log2Q) / P;
+    g.groups = (m + S - 1) / S;
+    g.lockstep = lockstep_for(S, sizeof(double));
     hipError_t e = bb::launch_ch((const double *)tab.ptr, tab.elems, f.primal.cor.q, g, alpha, steps,
                                  c_in, c_out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "Cahn-Hilliard launch");

@@ -110,7 +110,7 @@ inline int max_log2q(int C, bool refine) { return (refine || C > 64) ? 2 : 3; }
 
 // LDS elements of the exchange area of one split group: three phases
 // (forward scan: 2 per lane, backward scan: 2, periodic end values: 4).
-inline int64_t split_exchange_len(int log2Q) { return 8LL * kWave << log2Q; }
+__host__ __device__ constexpr int64_t split_exchange_len(int log2Q) { return 8LL * kWave << log2Q; }
 
 struct CyclicQ {
     double q[2][4];   // K x 2K, uses q[0][0..1] for K = 1

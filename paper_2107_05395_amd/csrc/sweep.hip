@@ -40,6 +40,32 @@ __device__ __forceinline__ int64_t opaque_s(int64_t x)
     return x;
 }
 
+__device__ __forceinline__ int opaque_u(int x)   // wave-uniform (SGPR) copy
+{
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
+// Where a kernel reads its coefficient table: from LDS, staged once per
+// workgroup (the lanes of a wave work on different chunks), or -- when every
+// lane of a wave works on the same chunk -- straight from the global table
+// through the scalar cache, the coefficient of each row arriving in SGPRs as
+// an operand of the lanes' FMAs.  base() re-derives the pointer from a value
+// the compiler cannot see through, so coefficient reads are not hoisted out
+// of the persistent loop.
+template <typename T>
+struct FromLds {
+    using ptr = const T *;
+    __device__ static ptr base(ptr p) { return p + opaque_v(0); }
+};
+
+template <typename T>
+struct FromScalar {
+    typedef const T __attribute__((address_space(4))) elem;   // constant address space
+    using ptr = elem *;
+    __device__ static ptr base(ptr p) { return p + opaque_u(0); }
+};
+
 // A branch the compiler cannot fold (always taken, on a uniform value it
 // cannot see).  Each pass runs in blocks of kFenceRows rows, each block inside
 // such a branch: a separate basic block, so the coefficient reads of one block
@@ -96,35 +122,36 @@ struct LaneGeom {
     int j, sl, S, P;
 };
 
-// This lane's view of a coefficient table staged in LDS (layout in internal.h).
-template <typename T, int K, bool CYC>
+// This lane's view of a coefficient table (layout in internal.h); Ptr is the
+// pointer type of the table's source (LDS or scalar).
+template <typename Ptr>
 struct LaneTable {
-    const T *wE1, *wE2, *wS1, *wS2;   // boundary-state weights (pass 1)
-    const T *s, *l1, *l2;             // forward recurrence (pass 2), l stored negated
-    const T *u1, *u2;                 // backward recurrence (pass 3), stored negated
-    const T *z0, *z1;                 // periodic correction, stored negated
-    const T *Mf, *Mb, *G;             // per-chunk KxK matrices
+    Ptr wE1, wE2, wS1, wS2;   // boundary-state weights (pass 1)
+    Ptr s, l1, l2;            // forward recurrence (pass 2), l stored negated
+    Ptr u1, u2;               // backward recurrence (pass 3), stored negated
+    Ptr z0, z1;               // periodic correction, stored negated
+    Ptr Mf, Mb, G;            // per-chunk KxK matrices
 };
 
-template <typename T, int K, int C, bool CYC>
-__device__ __forceinline__ LaneTable<T, K, CYC> lane_table(const T *lds, int P, int j)
+template <typename T, int K, int C, bool CYC, typename Ptr>
+__device__ __forceinline__ LaneTable<Ptr> lane_table(Ptr tab, int P, int j)
 {
     const int L = P * (C + 1);
     const int off = j * (C + 1);
-    LaneTable<T, K, CYC> tb;
+    LaneTable<Ptr> tb;
     int q = 0;
-    tb.wE1 = lds + (q++) * L + off;
-    tb.wE2 = (K == 2) ? lds + (q++) * L + off : nullptr;
-    tb.wS1 = lds + (q++) * L + off;
-    tb.wS2 = (K == 2) ? lds + (q++) * L + off : nullptr;
-    tb.s = lds + (q++) * L + off;
-    tb.l1 = lds + (q++) * L + off;
-    tb.l2 = (K == 2) ? lds + (q++) * L + off : nullptr;
-    tb.u1 = lds + (q++) * L + off;
-    tb.u2 = (K == 2) ? lds + (q++) * L + off : nullptr;
-    tb.z0 = CYC ? lds + (q++) * L + off : nullptr;
-    tb.z1 = (CYC && K == 2) ? lds + (q++) * L + off : nullptr;
-    tb.Mf = lds + q * L;
+    tb.wE1 = tab + (q++) * L + off;
+    tb.wE2 = (K == 2) ? tab + (q++) * L + off : nullptr;
+    tb.wS1 = tab + (q++) * L + off;
+    tb.wS2 = (K == 2) ? tab + (q++) * L + off : nullptr;
+    tb.s = tab + (q++) * L + off;
+    tb.l1 = tab + (q++) * L + off;
+    tb.l2 = (K == 2) ? tab + (q++) * L + off : nullptr;
+    tb.u1 = tab + (q++) * L + off;
+    tb.u2 = (K == 2) ? tab + (q++) * L + off : nullptr;
+    tb.z0 = CYC ? tab + (q++) * L + off : nullptr;
+    tb.z1 = (CYC && K == 2) ? tab + (q++) * L + off : nullptr;
+    tb.Mf = tab + q * L;
     tb.Mb = tb.Mf + P * K * K;
     tb.G = tb.Mb + P * K * K;
     return tb;
@@ -150,8 +177,8 @@ __device__ __forceinline__ void gather_ends(const T (&v)[C], const LaneGeom &lg,
 }
 
 // y <- M y + e for a KxK matrix M (row-major) and K-vectors
-template <typename T, int K>
-__device__ __forceinline__ void affine(const T *M, T &y1, T &y2, T e1, T e2)
+template <typename T, int K, typename Ptr>
+__device__ __forceinline__ void affine(Ptr M, T &y1, T &y2, T e1, T e2)
 {
     if constexpr (K == 1) {
         y1 = fma(M[0], y1, e1);
@@ -191,20 +218,21 @@ __device__ __forceinline__ void correction_scalars(const CyclicQ &cq, T r0, T r1
 //   pass 2: forward recurrence from H_j, writing y;
 //   pass 3: backward recurrence from F_j, writing x (periodic correction fused
 //           when the chunks tile n exactly, else applied afterwards).
-// Each pass re-derives its LDS pointers from an opaque base so the compiler
-// re-reads coefficients instead of keeping C of them live across passes.
+// Each pass re-derives its table pointers (LDS or scalar) from an opaque base
+// so the compiler re-reads coefficients instead of keeping C of them live
+// across passes.
 //
 // SPLIT: the group spans several waves of the workgroup; boundary states go
 // through the exchange area xch (split_exchange_len elements) with workgroup
 // barriers, so every wave of the workgroup must call it the same number of
 // times.  Split groups are always full decompositions (exact).
-template <typename T, int K, int C, bool CYC, bool SPLIT = false>
-__device__ __forceinline__ void chunk_solve(T (&v)[C], const T *lds, const LaneGeom &lg, int n,
-                                            int exact, const CyclicQ &cq, T *xch = nullptr)
+template <typename T, int K, int C, bool CYC, bool SPLIT = false, typename Src = FromLds<T>>
+__device__ __forceinline__ void chunk_solve(T (&v)[C], typename Src::ptr tab, const LaneGeom &lg,
+                                            int n, int exact, const CyclicQ &cq, T *xch = nullptr)
 {
     T e1 = T(0), e2 = T(0), o1 = T(0), o2 = T(0);
     {
-        const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
+        const auto tb = lane_table<T, K, C, CYC>(Src::base(tab), lg.P, lg.j);
         rows_up<C>([&](int t) {
             e1 = fma(tb.wE1[t], v[t], e1);
             o1 = fma(tb.wS1[t], v[t], o1);
@@ -216,7 +244,7 @@ __device__ __forceinline__ void chunk_solve(T (&v)[C], const T *lds, const LaneG
     }
     __builtin_amdgcn_sched_barrier(0);
     // history of this chunk: H_j = true (y_{start-1}, y_{start-2})
-    const auto tb = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
+    const auto tb = lane_table<T, K, C, CYC>(Src::base(tab), lg.P, lg.j);
     T h1 = T(0), h2 = T(0);
     const int me = lg.j * lg.S + lg.sl;   // (chunk, slot) index in the exchange area
     if constexpr (SPLIT) {
@@ -239,7 +267,7 @@ __device__ __forceinline__ void chunk_solve(T (&v)[C], const T *lds, const LaneG
     // zero-future start state of the true forward solution of this chunk
     T s1 = o1, s2 = o2;
     {
-        const T *Gm = tb.G + lg.j * K * K;
+        const auto Gm = tb.G + lg.j * K * K;
         if constexpr (K == 1) {
             s1 = fma(Gm[0], h1, o1);
         } else {
@@ -308,7 +336,7 @@ __device__ __forceinline__ void chunk_solve(T (&v)[C], const T *lds, const LaneG
     __builtin_amdgcn_sched_barrier(0);
     // pass 2: forward recurrence from the true history
     {
-        const auto tp = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
+        const auto tp = lane_table<T, K, C, CYC>(Src::base(tab), lg.P, lg.j);
         T y1 = h1, y2 = h2;
         rows_up<C>([&](int t) {
             T y = tp.s[t] * v[t];
@@ -322,7 +350,7 @@ __device__ __forceinline__ void chunk_solve(T (&v)[C], const T *lds, const LaneG
     __builtin_amdgcn_sched_barrier(0);
     // pass 3: backward recurrence from the true future (+ fused periodic correction)
     {
-        const auto tp = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
+        const auto tp = lane_table<T, K, C, CYC>(Src::base(tab), lg.P, lg.j);
         T x1 = f1, x2 = f2;
         rows_down<C>([&](int t) {
             T x = v[t];
@@ -343,7 +371,7 @@ __device__ __forceinline__ void chunk_solve(T (&v)[C], const T *lds, const LaneG
             T r0, r1, rn2, rn1;
             gather_ends<T, K, C>(v, lg, n, exact, r0, r1, rn2, rn1);
             correction_scalars<T, K>(cq, r0, r1, rn2, rn1, c0, c1);
-            const auto tp = lane_table<T, K, C, CYC>(lds + opaque_v(0), lg.P, lg.j);
+            const auto tp = lane_table<T, K, C, CYC>(Src::base(tab), lg.P, lg.j);
             rows_up<C>([&](int t) {
                 T x = fma(tp.z0[t], c0, v[t]);
                 if constexpr (K == 2) x = fma(tp.z1[t], c1, x);
@@ -454,6 +482,28 @@ __device__ __forceinline__ void store_chunk(const T (&v)[C], T *base, int row0, 
             *p = keep;
             p += (t + 1 < nv) ? ld : 0;
         }
+    }
+}
+
+// store_chunk of value(t), computed row by row inside the fenced row blocks,
+// so the values need not all be live at once.
+template <int C, bool FULL, typename F>
+__device__ __forceinline__ void store_chunk_fn(F &&value, double *base, int row0, int64_t k,
+                                               int64_t ld, int n)
+{
+    ld = opaque_s(ld);
+    if constexpr (FULL) {
+        double *p = base + (int64_t)row0 * ld + k;
+        rows_up<C>([&](int t) { p[(int64_t)t * ld] = value(t); });
+    } else if (row0 < n) {
+        const int nv = opaque_v(n - row0);
+        double *p = base + (int64_t)row0 * ld + k;
+        double keep = value(0);
+        rows_up<C>([&](int t) {
+            keep = t < nv ? value(t) : keep;
+            *p = keep;
+            p += (t + 1 < nv) ? ld : 0;
+        });
     }
 }
 
@@ -628,16 +678,44 @@ __global__ __launch_bounds__(kMaxBlockThreads) void refine_kernel(
         });
         __builtin_amdgcn_sched_barrier(0);
         chunk_solve<float, K, C, CYC, (QL > 0)>(dx, lds, lg, g.n, exact, cq, xch);
-        double xo[C];
-#pragma unroll
-        for (int t = 0; t < C; ++t) xo[t] = (double)x0[t] + (double)dx[t];
-        if (kval) store_chunk<double, C, FULL>(xo, out, row0, k, g.ld, g.n);
+        if (kval)
+            store_chunk_fn<C, FULL>([&](int t) { return (double)x0[t] + (double)dx[t]; }, out, row0,
+                                    k, g.ld, g.n);
     }
 }
 
 // ---------------------------------------------------------------- Cahn-Hilliard
 // `steps` steps of C <- A^{-1} (C + alpha d2(C^3 - C)), periodic, state in registers.
 __device__ __forceinline__ double ch_nl(double c) { return fma(c * c, c, -c); }
+
+// Right-hand side of one step on this lane's chunk, in place:
+// f_t = c_t + alpha (N_{t-1} - 2 N_t + N_{t+1}), N = c^3 - c, with the
+// neighbour rows cl (above the chunk) and cr (below it) and the periodic wrap
+// terms of rows 0 and n-1 (r0 = c_0, rn1 = c_{n-1} of the system).
+// nrow = n - (first row of the chunk); with FULL the chunks tile n and row
+// n-1 is the last row of the last chunk (last_chunk).
+template <int C, bool FULL>
+__device__ __forceinline__ void ch_rhs(double (&c)[C], double cl, double cr, double r0, double rn1,
+                                       double alpha, int j, bool last_chunk, int nrow)
+{
+    const double wrap_first = alpha * ch_nl(rn1);   // row 0 sees row n-1 on its left
+    const double wrap_last = alpha * ch_nl(r0);     // row n-1 sees row 0 on its right
+    double nprev = ch_nl(cl), ncur = ch_nl(c[0]);
+    rows_up<C>([&](int t) {
+        const double nnext = ch_nl(t + 1 < C ? c[t + 1] : cr);
+        double f = fma(alpha, fma(-2.0, ncur, nprev) + nnext, c[t]);
+        if (t == 0) f += (j == 0) ? wrap_first : 0.0;
+        if constexpr (FULL) {
+            if (t == C - 1) f += last_chunk ? wrap_last : 0.0;
+        } else {
+            f += (t == nrow - 1) ? wrap_last : 0.0;
+            f = t < nrow ? f : 0.0;
+        }
+        c[t] = f;
+        nprev = ncur;
+        ncur = nnext;
+    });
+}
 
 template <int C, bool FULL>
 __global__ __launch_bounds__(kMaxBlockThreads) void ch_kernel(const double *__restrict__ table,
@@ -673,24 +751,61 @@ __global__ __launch_bounds__(kMaxBlockThreads) void ch_kernel(const double *__re
             if (!has_right) cr = 0.0;
             double r0, r1, rn2, rn1;
             gather_ends<double, 2, C>(c, lg, g.n, exact, r0, r1, rn2, rn1);
-            const double wrap_first = alpha * ch_nl(rn1);   // row 0 sees row n-1 on its left
-            const double wrap_last = alpha * ch_nl(r0);     // row n-1 sees row 0 on its right
-            const int nrow = opaque_v(g.n - row0);
-            double nprev = ch_nl(cl), ncur = ch_nl(c[0]);
-            rows_up<C>([&](int t) {
-                const double nnext = ch_nl(t + 1 < C ? c[t + 1] : cr);
-                double f = fma(alpha, nprev - 2.0 * ncur + nnext, c[t]);
-                if (t == 0) f += (lg.j == 0) ? wrap_first : 0.0;
-                f += (t == nrow - 1) ? wrap_last : 0.0;
-                if constexpr (!FULL) f = t < nrow ? f : 0.0;
-                c[t] = f;
-                nprev = ncur;
-                ncur = nnext;
-            });
+            ch_rhs<C, FULL>(c, cl, cr, r0, rn1, alpha, lg.j, lg.j == lg.P - 1, opaque_v(g.n - row0));
             __builtin_amdgcn_sched_barrier(0);
             chunk_solve<double, 2, C, true>(c, smem_d, lg, g.n, exact, cq);
         }
         if (kval) store_chunk<double, C, FULL>(c, out, row0, k, g.ld, g.n);
+    }
+}
+
+// The same steps with one chunk per wave: a workgroup of P = 2^QL waves holds
+// one group of 64 systems, wave j their rows j*C .. j*C + C - 1.  Every lane
+// of a wave then needs the same coefficient row at the same time, so the
+// coefficients come from the global table through the scalar cache (no LDS
+// staging, no LDS reads) and the chunk-boundary values go through the LDS
+// exchange area: rows 0 and C-1 of every chunk for the stencil and the wrap
+// terms, then the three phases of chunk_solve.
+template <int C, int QL>
+__global__ __launch_bounds__((kWave << QL) > kMaxBlockThreads ? (kWave << QL) : kMaxBlockThreads)
+void ch_kernel_uniform(const double *__restrict__ table, CyclicQ cq, SweepGeom g, double alpha,
+                       int64_t steps, const double *in, double *out)
+{
+    using Src = FromScalar<double>;
+    extern __shared__ double smem_d[];
+    double *xch = smem_d;                                   // chunk_solve phases
+    double *xd = smem_d + split_exchange_len(QL);           // rows 0, C-1 per (chunk, slot)
+    const typename Src::ptr tab = (typename Src::ptr)table;
+
+    LaneGeom lg = lane_geom(QL, QL);
+    lg.j = __builtin_amdgcn_readfirstlane(lg.j);            // the wave's chunk: uniform
+    const int row0 = lg.j * C;
+    const bool has_left = lg.j > 0, has_right = lg.j < lg.P - 1;
+    const int me = 2 * (lg.j * kWave + lg.sl);
+    const int lft = 2 * ((has_left ? lg.j - 1 : lg.j) * kWave + lg.sl) + 1;
+    const int rgt = 2 * ((has_right ? lg.j + 1 : lg.j) * kWave + lg.sl);
+    const int first = 2 * lg.sl, last = 2 * ((lg.P - 1) * kWave + lg.sl) + 1;
+    const GroupRange gr = group_range(g.groups, QL);
+
+    for (int64_t blk = gr.first; blk < gr.end; blk += gr.stride) {
+        const int64_t grp = begin_block(gr, blk, g.lockstep);
+        if (grp >= g.groups) continue;
+        const int64_t k = grp * kWave + lg.sl;
+        const bool kval = k < g.m;
+        double c[C];
+        load_chunk<double, C, true>(c, in, row0, kval ? k : g.m - 1, g.ld, g.n);
+
+        for (int64_t step = 0; step < steps; ++step) {
+            xd[me] = c[0];
+            xd[me + 1] = c[C - 1];
+            __syncthreads();
+            const double cl = has_left ? xd[lft] : 0.0;
+            const double cr = has_right ? xd[rgt] : 0.0;
+            ch_rhs<C, true>(c, cl, cr, xd[first], xd[last], alpha, lg.j, !has_right, C);
+            __builtin_amdgcn_sched_barrier(0);
+            chunk_solve<double, 2, C, true, true, Src>(c, tab, lg, g.n, 1, cq, xch);
+        }
+        if (kval) store_chunk<double, C, true>(c, out, row0, k, g.ld, g.n);
     }
 }
 
@@ -878,6 +993,16 @@ hipError_t launch_ch(const double *table, int64_t table_elems, const CyclicQ &q,
                      const SweepGeom &g, double alpha, int64_t steps, const double *in,
                      double *out, hipStream_t s)
 {
+    if (g.log2Q > 0) {
+        // one chunk per wave (host checks: full decomposition, log2Q == log2P)
+        if (g.C != 64 || g.log2Q != g.log2P || g.log2Q > 3 || !is_full(g)) return hipErrorInvalidValue;
+        const size_t xl = (size_t)(split_exchange_len(g.log2Q) + (2LL * kWave << g.log2Q)) * sizeof(double);
+        switch (g.log2Q) {
+        case 1: return launch_grid_split(ch_kernel_uniform<64, 1>, xl, g.groups, 2, s, table, q, g, alpha, steps, in, out);
+        case 2: return launch_grid_split(ch_kernel_uniform<64, 2>, xl, g.groups, 4, s, table, q, g, alpha, steps, in, out);
+        default: return launch_grid_split(ch_kernel_uniform<64, 3>, xl, g.groups, 8, s, table, q, g, alpha, steps, in, out);
+        }
+    }
     const size_t lds = (size_t)table_elems * sizeof(double);
 #define BB_CH(CC)                                                                              \
     case CC:                                                                                   \

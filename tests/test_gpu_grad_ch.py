@@ -160,3 +160,20 @@ def test_ch_in_place():
     t = dev(c0)
     f.ch_step(t, alpha, steps=3, out=t)
     assert rel_err(host(t), oracle.ch_step(c0, sigma, alpha, steps=3)) < 1e-12
+
+
+@pytest.mark.parametrize("n", [128, 256, 512])
+def test_ch_uniform_chunks_match_lds_kernel(n, monkeypatch):
+    """With one 64-row chunk per wave the CH kernel reads its coefficients
+    through the scalar cache; the arithmetic is the same as the LDS kernel's,
+    so the two agree bitwise, and both match the oracle."""
+    f, sigma, alpha = _ch(n)
+    m, steps = 1000, 7
+    c0 = inputs.uniform_batch(n, m, seed=23 + n, lo=-0.1, hi=0.1)
+    ref = oracle.ch_step(c0, sigma, alpha, steps=steps)
+    uni = host(f.ch_step(dev(c0), alpha, steps=steps))
+    monkeypatch.setenv("BANDBATCH_CH_UNIFORM", "0")
+    lds = host(f.ch_step(dev(c0), alpha, steps=steps))
+    say("ch uniform vs lds", n, float(np.max(np.abs(uni - lds))), rel_err(uni, ref))
+    assert rel_err(uni, ref) < 1e-12
+    assert np.array_equal(uni, lds)
