@@ -529,9 +529,8 @@ __device__ __forceinline__ LaneGeom lane_geom(int log2P, int log2Q = 0)
 // the same group index, so the exchange barriers are reached uniformly.
 template <typename T, int K, int C, bool CYC, bool FULL, int QL>
 __global__ __launch_bounds__((kWave << QL) > kMaxBlockThreads ? (kWave << QL) : kMaxBlockThreads)
-void sweep_kernel(const T *__restrict__ table,
-                                                              int64_t table_elems, CyclicQ cq,
-                                                              SweepGeom g, const T *in, T *out)
+void sweep_kernel(const T *__restrict__ table, int64_t table_elems, CyclicQ cq, SweepGeom g,
+                  const T *in, T *out)
 {
     static_assert(QL == 0 || FULL, "split groups are full decompositions");
     extern __shared__ double smem_d[];
