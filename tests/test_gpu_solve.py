@@ -220,3 +220,21 @@ def test_split_groups_match_single_wave_groups(kind, n, cyclic, rows, monkeypatc
     assert all(np.array_equal(got[1], got[q]) for q in (2, 4, 8))
     assert np.array_equal(got[("r", 1)], got[("r", 2)])
     assert np.array_equal(got[("r", 1)], got[("r", 4)])
+
+
+def test_workgroup_shape_and_lockstep_do_not_change_results(monkeypatch):
+    """Waves per workgroup and the lockstep barrier only change which waves run
+    together, not the arithmetic: bitwise equal results (ragged n, so the
+    groups are one wave each)."""
+    n, m = 300, 777
+    f, bands = make("penta", n, seed=31, cyclic=True)
+    rhs = inputs.uniform_batch(n, m, seed=32)
+    t = dev(rhs)
+    outs = []
+    for w in ("1", "2", "4"):
+        for lock in ("0", "1"):
+            monkeypatch.setenv("BANDBATCH_WAVES_PER_BLOCK", w)
+            monkeypatch.setenv("BANDBATCH_LOCKSTEP", lock)
+            outs.append(host(f.solve(t)))
+    assert rel_err(outs[0], oracle_solve("penta", bands, rhs, True)) < F64_TOL
+    assert all(np.array_equal(o, outs[0]) for o in outs[1:])
