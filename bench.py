@@ -29,9 +29,12 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
+KERNEL_SOURCES = ("sweep_core.h", "sweep.hip", "refine.hip", "ch.hip", "internal.h")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("sweep.hip", "internal.h"):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2107_05395_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

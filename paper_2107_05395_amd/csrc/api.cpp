@@ -55,21 +55,17 @@ int max_chunk(bb_precision p)
     return c;
 }
 
-// Rows per lane of a solve.  Systems whose size is 64 * 2^k (a full
-// decomposition at 64 rows) run at 64 rows per lane: about 170 VGPRs, two
-// waves per SIMD, with the system groups split over waves (split_log2).
-// Measured (FP64, 4 GiB batches, GB/s): tri n = 512 4881 vs 4743 at 128 rows;
-// tri n = 1024 4771 vs 4490; penta n = 1024 4269 vs 3949; tri n = 2048 3975
-// vs 3406; tri n = 256 4826 vs 4769.  Other sizes keep the largest chunk
-// (fewest lanes per system).  An explicit BANDBATCH_MAX_CHUNK disables the
-// preference.
+// Rows per lane of a solve: 64 (about 170 VGPRs, two waves per SIMD), with
+// the system groups split over 4 or 8 waves from 8 chunks on (split_log2).
+// Measured against 128 rows per lane (FP64, 4 GiB batches, GB/s, best split
+// each): tri n = 512 4881 vs 4749; n = 1024 4771 vs 4490; n = 2048 3975 vs
+// 3406; penta n = 1024 4269 vs 3949; ragged tri n = 1000 3992 vs 3701,
+// n = 2000 3635 vs 3200, penta n = 1000 3994 vs 3328.  Systems of 64 rows or
+// fewer take one lane.  BANDBATCH_MAX_CHUNK overrides (tuning).
 int solve_chunk(int64_t n, bb_precision p)
 {
     const int cmax = max_chunk(p);
-    if (!std::getenv("BANDBATCH_MAX_CHUNK") && cmax >= 64) {
-        const int c64 = bb::choose_chunk(n, 64);
-        if (c64 == 64 && (int64_t)c64 * bb::lanes_for(n, c64) == n) return 64;
-    }
+    if (!std::getenv("BANDBATCH_MAX_CHUNK") && cmax >= 64) return bb::choose_chunk(n, 64);
     return bb::choose_chunk(n, cmax);
 }
 
@@ -87,8 +83,8 @@ int lockstep_for(int S, size_t elem_bytes)
     return 1;
 }
 
-// Waves per system group (log2) for a full decomposition (C >= 64) -- see
-// internal.h.  Measured on 2^29-element batches and on the 2^16-system
+// Waves per system group (log2) for C >= 64 (the refinement kernel: full
+// decompositions only) -- see internal.h.  Measured on 2^29-element batches and on the 2^16-system
 // differentiated workload: the sweep at 64 rows per lane runs fastest with
 // 4-wave groups at P = 8 (S = 32) and 8-wave groups from P = 16 on (S = 32,
 // 16); at 128 rows (one wave per SIMD) with 4-wave groups from P = 8; the
@@ -98,8 +94,8 @@ int lockstep_for(int S, size_t elem_bytes)
 // is valid (tuning); anything else keeps the automatic choice.
 int split_log2(int log2P, int C, int n, bb::Op op)
 {
-    if (C < 64 || ((int64_t)C << log2P) != n) return 0;
     const bool refine = op == bb::Op::Refine;
+    if (C < 64 || (refine && ((int64_t)C << log2P) != n)) return 0;
     const int lmax = bb::max_log2q(C, refine);
     int l = 0;
     if (refine || C > 64)

@@ -30,9 +30,10 @@
 // segments (S*8 bytes per load instruction).  A system group can instead span
 // Q = 2^log2Q waves of one workgroup: each wave holds P/Q chunks of
 // S = 64Q/P systems, and the scans read the other waves' boundary states
-// through a small LDS exchange area (barriers instead of shuffles).  Only
-// full decompositions (P*C == n) with C >= 64 of the solve and refinement
-// kernels are split; the Cahn-Hilliard kernel is not.
+// through a small LDS exchange area (barriers instead of shuffles).  The
+// solve kernel splits any decomposition with C >= 64, the refinement kernel
+// only full ones (P*C == n); the Cahn-Hilliard kernel splits a full 64-row
+// decomposition into one chunk per wave.
 //
 // Coefficient table (one per direction, precision and chunk size)
 // ----------------------------------------------------------------
@@ -111,6 +112,8 @@ inline int max_log2q(int C, bool refine) { return (refine || C > 64) ? 2 : 3; }
 // LDS elements of the exchange area of one split group: three phases
 // (forward scan: 2 per lane, backward scan: 2, periodic end values: 4).
 __host__ __device__ constexpr int64_t split_exchange_len(int log2Q) { return 8LL * kWave << log2Q; }
+// ... and of a fourth phase: rows 0, 1, n-2, n-1 of every (chunk, slot).
+__host__ __device__ constexpr int64_t split_ends_len(int log2Q) { return 4LL * kWave << log2Q; }
 
 struct CyclicQ {
     double q[2][4];   // K x 2K, uses q[0][0..1] for K = 1
@@ -132,6 +135,13 @@ hipError_t launch_sweep(int K, bool cyclic, Op op, bool f32, const void *table,
                         int64_t table_elems, const double *band_table, int64_t band_elems,
                         const CyclicQ &q, const Corners &corners, const SweepGeom &g,
                         const void *in, void *out, hipStream_t stream);
+
+// FP32 sweeps + one FP64-residual refinement (refine.hip); launch_sweep
+// forwards Op::Refine here.
+hipError_t launch_refine(int K, bool cyclic, const void *table, int64_t table_elems,
+                         const double *band_table, int64_t band_elems, const CyclicQ &q,
+                         const Corners &corners, const SweepGeom &g, const void *in, void *out,
+                         hipStream_t stream);
 
 // Cahn-Hilliard steps with the state resident on chip (cyclic penta, double).
 hipError_t launch_ch(const double *table, int64_t table_elems, const CyclicQ &q,

@@ -186,7 +186,10 @@ def test_factor_on_the_oracle_matrices_of_every_config():
 
 @pytest.mark.parametrize("kind,n,cyclic", [("tri", 512, False), ("tri", 1024, True),
                                            ("tri", 2048, False), ("penta", 512, True),
-                                           ("penta", 1024, False), ("penta", 1024, True)])
+                                           ("penta", 1024, False), ("penta", 1024, True),
+                                           ("tri", 1000, True), ("tri", 1500, False),
+                                           ("penta", 600, True), ("penta", 1000, False),
+                                           ("tri", 1536, True)])
 @pytest.mark.parametrize("rows", [None, 128])
 def test_split_groups_match_single_wave_groups(kind, n, cyclic, rows, monkeypatch):
     """A system group spread over 2, 4 or 8 waves (boundary states exchanged
