@@ -6,8 +6,9 @@ r = 1.0, n = 512 unknowns, m = 2^20 interleaved right-hand sides drawn
 uniform[-1, 1) from a fixed seed; one "step" is one batched FP64 solve of all
 m systems (factorisation on the host, once, outside the timed region, as in
 Carroll et al. arXiv:2107.05395, Section 3).  The FP32-sweep + FP64-residual
-refinement form, the paper's thread-per-system design and the FP64 oracle on
-the host cores are measured alongside and reported in the same JSON line.
+refinement form (double and FP32 right-hand sides), the paper's
+thread-per-system design, a same-size device copy and the FP64 oracle on the
+host cores are measured alongside and reported in the same JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--gpus 1]
 """
@@ -29,7 +30,7 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-KERNEL_SOURCES = ("sweep_core.h", "sweep.hip", "refine.hip", "ch.hip", "internal.h")
+KERNEL_SOURCES = ("sweep_core.h", "sweep_kernel.h", "sweep.hip", "sweep_f32.hip", "refine_kernel.h", "refine.hip", "refine_f32rhs.hip", "ch.hip", "internal.h")
 
 
 def kernel_source_hash() -> str:
@@ -115,6 +116,16 @@ def bench_tri(args, torch):
         ref = oracle.tri_solve(*bands, rhs_host[:, cols])
         err = rel_err_cols(x[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref)
         results[prec] = dict(seconds=t, wall=wall, err=err)
+    # FP32 right-hand-side data (the same draws rounded), refined to double:
+    # 4 B read + 8 B written per row
+    rhs32 = rhs.float()
+    t32, _ = time_launches(lambda: f.solve(rhs32, out=x, precision="f32rhs"), args.steps,
+                           args.warmup, torch)
+    import oracle
+    cols32 = np.unique(np.r_[np.linspace(0, m - 1, 254).astype(np.int64), 0, m - 1])
+    ref32 = oracle.tri_solve(*bands, rhs_host[:, cols32].astype(np.float32).astype(np.float64))
+    err32 = rel_err_cols(x[:, torch.from_numpy(cols32).cuda()].cpu().numpy(), ref32)
+    del rhs32
     # a plain device-to-device copy of the same array: the achievable HBM rate
     # for one read + one write stream on this part (context for the roofline)
     ct, _ = time_launches(lambda: x.copy_(rhs), 10, 2, torch)
@@ -141,6 +152,10 @@ def bench_tri(args, torch):
                  "ms_per_step": 1e3 * results["f32r"]["seconds"] / k,
                  "rel_err_vs_oracle": results["f32r"]["err"],
                  "hbm_gbs_algorithmic": algo_bytes * k / results["f32r"]["seconds"] / 1e9},
+        "f32rhs": {"value": m * k / t32, "unit": "systems/s", "ms_per_step": 1e3 * t32 / k,
+                   "rel_err_vs_oracle": err32, "hbm_gbs_algorithmic": 12.0 * n * m * k / t32 / 1e9,
+                   "note": "FP32 right-hand sides (the same draws rounded), double solution; "
+                           "oracle on the rounded values"},
         "copy_gbs": copy_gbs,
         "thread_per_system_design": {"ms_per_step": 1e3 * pt, "value": m / pt,
                                      "hbm_gbs_algorithmic": algo_bytes / pt / 1e9},
@@ -175,6 +190,12 @@ def bench_penta(args, torch):
         t, _ = time_launches(lambda: f.solve(rhs, out=x, precision=prec), args.steps, args.warmup, torch)
         err = rel_err_cols(x[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref)
         out[prec] = (t, err)
+    rhs32 = rhs.float()
+    t, _ = time_launches(lambda: f.solve(rhs32, out=x, precision="f32rhs"), args.steps, args.warmup,
+                         torch)
+    ref32 = oracle.penta_solve(*bands, rhs_host[:, cols].astype(np.float32).astype(np.float64))
+    out["f32rhs"] = (t, rel_err_cols(x[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref32))
+    del rhs32
     k = args.steps
     per = out["f64"][0] / k
     return {
@@ -186,6 +207,9 @@ def bench_penta(args, torch):
         "rel_err_vs_oracle": out["f64"][1],
         "f32r": {"value": m * k / out["f32r"][0], "rel_err_vs_oracle": out["f32r"][1],
                  "ms_per_step": 1e3 * out["f32r"][0] / k},
+        "f32rhs": {"value": m * k / out["f32rhs"][0], "rel_err_vs_oracle": out["f32rhs"][1],
+                   "ms_per_step": 1e3 * out["f32rhs"][0] / k,
+                   "hbm_gbs_algorithmic": 12.0 * n * m * k / out["f32rhs"][0] / 1e9},
         "roofline": {"bound": "hbm", "achieved": algo_bytes / per / 1e9, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": algo_bytes / per / 1e9 / PEAK_HBM_GBS,
                      "traffic": measured_traffic(args.workload, "f64")},

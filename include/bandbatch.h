@@ -57,7 +57,10 @@ typedef enum {
     BB_F32_REFINE = 1, /* double rhs and x; sweeps in float with the factor rounded to float, then one
                           residual r = b - A x0 in double with the original bands and a float correction
                           sweep: x = x0 + A^{-1} r.  Relative error ~ (kappa eps32)^2 + kappa eps64. */
-    BB_F32 = 2         /* float rhs and x, float sweeps; no refinement */
+    BB_F32 = 2,        /* float rhs and x, float sweeps; no refinement */
+    BB_F32_RHS_REFINE = 3 /* float rhs (FP32 data, 4 B per entry read), double x: the BB_F32_REFINE
+                          sweeps and refinement, the residual taken with the rhs promoted exactly to
+                          double.  rhs and x must not overlap. */
 } bb_precision;
 
 typedef struct bb_factor_s *bb_factor;
@@ -108,11 +111,13 @@ int64_t bb_max_n(void);
  * x[:,k] = A^{-1} rhs[:,k] for 0 <= k < m (Appendix A/B batched sweeps, with
  * the periodic correction of Section 3.3 when the factor is cyclic).
  * rhs, x: device, interleaved [i*ld + k]; double for BB_F64 and BB_F32_REFINE,
- * float for BB_F32.  m >= 0 (m == 0 enqueues nothing), ld >= max(m, 1).
+ * float for BB_F32; float rhs and double x for BB_F32_RHS_REFINE (same ld).
+ * m >= 0 (m == 0 enqueues nothing), ld >= max(m, 1).
  * The tri entry point requires a tri factor (cyclic or not), the penta one a
  * penta factor; the _cyclic names additionally require a cyclic factor.
  * Errors: BB_ERR_ARG (wrong factor kind, null pointer, m or ld out of range,
- * unknown precision), BB_ERR_HIP, BB_ERR_OOM (first upload). */
+ * unknown precision, rhs == x with BB_F32_RHS_REFINE), BB_ERR_HIP, BB_ERR_OOM
+ * (first upload). */
 bb_status bb_solve_batch_tri(bb_factor f, const void *rhs, void *x, int64_t m, int64_t ld,
                              bb_precision p, void *stream);
 bb_status bb_solve_batch_penta(bb_factor f, const void *rhs, void *x, int64_t m, int64_t ld,

@@ -51,7 +51,7 @@ int max_chunk(bb_precision p)
         const int v = std::atoi(env);
         if (v >= bb::kChunkMin && v <= bb::kChunkMax && (v & (v - 1)) == 0) c = v;
     }
-    if (p == BB_F32_REFINE && c > bb::kChunkMaxRefine) c = bb::kChunkMaxRefine;
+    if ((p == BB_F32_REFINE || p == BB_F32_RHS_REFINE) && c > bb::kChunkMaxRefine) c = bb::kChunkMaxRefine;
     return c;
 }
 
@@ -94,7 +94,7 @@ int lockstep_for(int S, size_t elem_bytes)
 // is valid (tuning); anything else keeps the automatic choice.
 int split_log2(int log2P, int C, int n, bb::Op op)
 {
-    const bool refine = op == bb::Op::Refine;
+    const bool refine = op != bb::Op::Solve;
     if (C < 64 || (refine && ((int64_t)C << log2P) != n)) return 0;
     const int lmax = bb::max_log2q(C, refine);
     int l = 0;
@@ -194,7 +194,10 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
     bb::Factor &f = fh->f;
     if (f.K != want_k) return fail(BB_ERR_ARG, want_k == 1 ? "not a tridiagonal factor" : "not a pentadiagonal factor");
     if (want_cyclic == 1 && !f.cyclic) return fail(BB_ERR_ARG, "not a cyclic factor");
-    if (p != BB_F64 && p != BB_F32_REFINE && p != BB_F32) return fail(BB_ERR_ARG, "unknown precision");
+    if (p != BB_F64 && p != BB_F32_REFINE && p != BB_F32 && p != BB_F32_RHS_REFINE)
+        return fail(BB_ERR_ARG, "unknown precision");
+    if (p == BB_F32_RHS_REFINE && m > 0 && in == out)
+        return fail(BB_ERR_ARG, "BB_F32_RHS_REFINE reads float and writes double: rhs and x must not overlap");
     if (m == 0) { g_last_error.clear(); return BB_OK; }
     int dev;
     if ((st = current_device(&dev)) != BB_OK) return st;
@@ -211,8 +214,8 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
     if (st != BB_OK) return st;
     bb::Corners corners = f.corners;
     bb::Op op = bb::Op::Solve;
-    if (p == BB_F32_REFINE) {
-        op = bb::Op::Refine;
+    if (p == BB_F32_REFINE || p == BB_F32_RHS_REFINE) {
+        op = p == BB_F32_REFINE ? bb::Op::Refine : bb::Op::RefineF32Rhs;
         if (adjoint) {
             // residual of the transposed system: bands and corners of A^T
             st = device_table(f, f.dev, std::make_tuple(dev, 1, 0, C, 1), false,

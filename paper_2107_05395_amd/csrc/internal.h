@@ -125,7 +125,8 @@ struct Corners {      // periodic corner entries of the original matrix (refinem
     double bot[2][2];  // K = 2: A[n-2][0], A[n-2][1]; A[n-1][0], A[n-1][1].  K = 1: bot[1][0] = A[n-1][0]
 };
 
-enum class Op : int { Solve = 0, Refine = 1 };
+// Refine: double right-hand sides; RefineF32Rhs: FP32 right-hand sides.
+enum class Op : int { Solve = 0, Refine = 1, RefineF32Rhs = 2 };
 
 // Launch the chunked sweep kernel.
 //   T_io / T_sweep: double/double (FP64), float/float (FP32), double/float (refine)
@@ -136,12 +137,24 @@ hipError_t launch_sweep(int K, bool cyclic, Op op, bool f32, const void *table,
                         const CyclicQ &q, const Corners &corners, const SweepGeom &g,
                         const void *in, void *out, hipStream_t stream);
 
+// Float solves (sweep_f32.hip); launch_sweep forwards f32 here.
+hipError_t launch_sweep_f32(int K, bool cyclic, const void *table, int64_t table_elems,
+                            const CyclicQ &q, const SweepGeom &g, const void *in, void *out,
+                            hipStream_t stream);
+
 // FP32 sweeps + one FP64-residual refinement (refine.hip); launch_sweep
-// forwards Op::Refine here.
-hipError_t launch_refine(int K, bool cyclic, const void *table, int64_t table_elems,
+// forwards Op::Refine and Op::RefineF32Rhs here.
+hipError_t launch_refine(int K, bool cyclic, bool f32_rhs, const void *table, int64_t table_elems,
                          const double *band_table, int64_t band_elems, const CyclicQ &q,
                          const Corners &corners, const SweepGeom &g, const void *in, void *out,
                          hipStream_t stream);
+
+// The FP32-right-hand-side instantiation (refine_f32rhs.hip); launch_refine
+// forwards f32_rhs here.
+hipError_t launch_refine_f32rhs(int K, bool cyclic, const void *table, int64_t table_elems,
+                                const double *band_table, int64_t band_elems, const CyclicQ &q,
+                                const Corners &corners, const SweepGeom &g, const void *in,
+                                void *out, hipStream_t stream);
 
 // Cahn-Hilliard steps with the state resident on chip (cyclic penta, double).
 hipError_t launch_ch(const double *table, int64_t table_elems, const CyclicQ &q,

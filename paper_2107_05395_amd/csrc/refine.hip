@@ -1,195 +1,22 @@
-// refine.hip -- FP32 sweeps with one FP64-residual refinement in a single
-// kernel; building blocks in sweep_core.h.
-#include "sweep_core.h"
+// refine.hip -- FP32 sweeps with one FP64-residual refinement, double
+// right-hand sides; kernel in refine_kernel.h.
+#include "refine_kernel.h"
 
 namespace bb {
-namespace {
 
-// ---------------------------------------------------------------- refine
-// x0 = solve_f32(b); r = b - A x0 in double with the original bands;
-// x = x0 + solve_f32(r), stored as double.
-// QL > 0: split groups as in sweep_kernel; the exchange area holds the three
-// phases of chunk_solve followed by rows 0, 1, C-2, C-1 of every chunk.
-template <int K, int C, bool CYC, bool FULL, int QL>
-__global__ __launch_bounds__(kMaxBlockThreads) void refine_kernel(
-    const float *__restrict__ table, int64_t table_elems, const double *__restrict__ band_table,
-    int64_t band_elems, CyclicQ cq, Corners cn, SweepGeom g, const double *in, double *out)
-{
-    static_assert(QL == 0 || (FULL && C >= 2), "split groups are full decompositions");
-    extern __shared__ double smem_d[];
-    double *lds_band = smem_d;
-    float *lds = reinterpret_cast<float *>(smem_d + band_elems);
-    stage_table(lds_band, band_table, band_elems);
-    stage_table(lds, table, table_elems);
-    __syncthreads();
-    float *xch = lds + table_elems;
-
-    const LaneGeom lg = lane_geom(g.log2P, QL);
-    const int lane = threadIdx.x % kWave;
-    const int L = lg.P * (C + 1);
-    const int row0 = lg.j * C;
-    const bool has_left = lg.j > 0, has_right = lg.j < lg.P - 1;
-    const int left = has_left ? lane - lg.S : lane;
-    const int right = has_right ? lane + lg.S : lane;
-    const int exact = FULL || g.exact;
-    const GroupRange gr = group_range(g.groups, QL);
-
-    for (int64_t blk = gr.first; blk < gr.end; blk += gr.stride) {
-        const int64_t grp = begin_block(gr, blk, g.lockstep);
-        if (grp >= g.groups) continue;
-        const int64_t k = grp * lg.S + lg.sl;
-        const bool kval = k < g.m;
-        double b[C];
-        load_chunk<double, C, FULL>(b, in, row0, kval ? k : g.m - 1, g.ld, g.n);
-        float x0[C];
-#pragma unroll
-        for (int t = 0; t < C; ++t) x0[t] = (float)b[t];
-        chunk_solve<float, K, C, CYC, (QL > 0)>(x0, lds, lg, g.n, exact, cq, xch);
-        __builtin_amdgcn_sched_barrier(0);
-
-        // neighbours across the chunk boundaries (zero outside the matrix) and,
-        // periodic, rows 0, 1, n-2, n-1 of the system
-        float xl1, xl2, xr1, xr2, r0 = 0.f, r1 = 0.f, rn2 = 0.f, rn1 = 0.f;
-        if constexpr (QL > 0) {
-            float *xd = xch + 8 * lg.P * lg.S;
-            const int me = 4 * (lg.j * lg.S + lg.sl);
-            xd[me] = x0[0];
-            xd[me + 1] = x0[1];
-            xd[me + 2] = x0[C - 2];
-            xd[me + 3] = x0[C - 1];
-            __syncthreads();
-            const int lft = 4 * ((has_left ? lg.j - 1 : lg.j) * lg.S + lg.sl);
-            const int rgt = 4 * ((has_right ? lg.j + 1 : lg.j) * lg.S + lg.sl);
-            xl1 = has_left ? xd[lft + 3] : 0.f;
-            xl2 = has_left ? xd[lft + 2] : 0.f;
-            xr1 = has_right ? xd[rgt] : 0.f;
-            xr2 = has_right ? xd[rgt + 1] : 0.f;
-            if constexpr (CYC) {
-                const int first = 4 * lg.sl, last = 4 * ((lg.P - 1) * lg.S + lg.sl);
-                r0 = xd[first];
-                r1 = xd[first + 1];
-                rn2 = xd[last + 2];
-                rn1 = xd[last + 3];
-            }
-        } else {
-            xl1 = shfl(x0[C - 1], left);
-            xl2 = shfl(x0[C - 2], left);
-            xr1 = shfl(x0[0], right);
-            xr2 = shfl(x0[1], right);
-            if (!has_left) xl1 = xl2 = 0.f;
-            if (!has_right) xr1 = xr2 = 0.f;
-            if constexpr (CYC) gather_ends<float, K, C>(x0, lg, g.n, exact, r0, r1, rn2, rn1);
-        }
-        double ctop0 = 0.0, ctop1 = 0.0, cbot2 = 0.0, cbot1 = 0.0;
-        if constexpr (CYC) {
-            if constexpr (K == 1) {
-                ctop0 = cn.top[0][1] * (double)rn1;
-                cbot1 = cn.bot[1][0] * (double)r0;
-            } else {
-                ctop0 = fma(cn.top[0][1], (double)rn1, cn.top[0][0] * (double)rn2);
-                ctop1 = fma(cn.top[1][1], (double)rn1, cn.top[1][0] * (double)rn2);
-                cbot2 = fma(cn.bot[0][1], (double)r1, cn.bot[0][0] * (double)r0);
-                cbot1 = fma(cn.bot[1][1], (double)r1, cn.bot[1][0] * (double)r0);
-            }
-        }
-        const int nrow = opaque_v(g.n - row0);   // this chunk's row index of row n (may be <= 0 or > C)
-        const double *band[5];
-        {
-            const int off = opaque_v(lg.j * (C + 1));
-#pragma unroll
-            for (int q = 0; q < 2 * K + 1; ++q) band[q] = lds_band + q * L + off;
-        }
-        float dx[C];
-        rows_up<C>([&](int t) {
-            const double xm1 = t >= 1 ? (double)x0[t - 1] : (double)xl1;
-            const double xp1 = t + 1 < C ? (double)x0[t + 1] : (double)xr1;
-            double ax = band[K][t] * (double)x0[t];
-            ax = fma(band[K - 1][t], xm1, ax);
-            ax = fma(band[K + 1][t], xp1, ax);
-            if constexpr (K == 2) {
-                const double xm2 = t >= 2 ? (double)x0[t - 2] : (t == 1 ? (double)xl1 : (double)xl2);
-                const double xp2 = t + 2 < C ? (double)x0[t + 2]
-                                             : (t + 1 < C ? (double)xr1 : (double)xr2);
-                ax = fma(band[0][t], xm2, ax);
-                ax = fma(band[4][t], xp2, ax);
-            }
-            double r = b[t] - ax;
-            if constexpr (CYC) {
-                // corner terms of the periodic matrix: rows 0, 1 (chunk 0) and n-2, n-1
-                if (t == 0) r -= (lg.j == 0) ? ctop0 : 0.0;
-                if constexpr (K == 2) {
-                    if (t == 1) r -= (lg.j == 0) ? ctop1 : 0.0;
-                    r -= (t == nrow - 2) ? cbot2 : 0.0;
-                }
-                r -= (t == nrow - 1) ? cbot1 : 0.0;
-            }
-            if constexpr (!FULL) r = t < nrow ? r : 0.0;
-            dx[t] = (float)r;
-        });
-        __builtin_amdgcn_sched_barrier(0);
-        chunk_solve<float, K, C, CYC, (QL > 0)>(dx, lds, lg, g.n, exact, cq, xch);
-        if (kval)
-            store_chunk_fn<C, FULL>([&](int t) { return (double)x0[t] + (double)dx[t]; }, out, row0,
-                                    k, g.ld, g.n);
-    }
-}
-
-template <int K, bool CYC, int C>
-hipError_t refine_c(const void *table, int64_t table_elems, const double *band,
-                    int64_t band_elems, const CyclicQ &q, const Corners &cn, const SweepGeom &g,
-                    const void *in, void *out, hipStream_t stream)
-{
-    const size_t lds = (size_t)band_elems * sizeof(double) + (size_t)table_elems * sizeof(float);
-    if (g.log2Q > 0) {
-        if constexpr (C >= 64) {
-            if (!is_full(g) || g.log2Q > max_log2q(C, true) || g.log2Q > g.log2P)
-                return hipErrorInvalidValue;
-            const size_t xl = (size_t)(split_exchange_len(g.log2Q) + (4LL * kWave << g.log2Q)) * sizeof(float);
-            if (g.log2Q == 1)
-                return launch_grid_split(refine_kernel<K, C, CYC, true, 1>, lds + xl, g.groups, 2,
-                                         stream, (const float *)table, table_elems, band,
-                                         band_elems, q, cn, g, (const double *)in, (double *)out);
-            return launch_grid_split(refine_kernel<K, C, CYC, true, 2>, lds + xl, g.groups, 4,
-                                     stream, (const float *)table, table_elems, band, band_elems,
-                                     q, cn, g, (const double *)in, (double *)out);
-        }
-        return hipErrorInvalidValue;
-    }
-    if (is_full(g))
-        return launch_grid(refine_kernel<K, C, CYC, true, 0>, lds, g.groups, stream,
-                           (const float *)table, table_elems, band, band_elems, q, cn, g,
-                           (const double *)in, (double *)out);
-    return launch_grid(refine_kernel<K, C, CYC, false, 0>, lds, g.groups, stream,
-                       (const float *)table, table_elems, band, band_elems, q, cn, g,
-                       (const double *)in, (double *)out);
-}
-
-template <int K, bool CYC>
-hipError_t refine_dispatch(const void *table, int64_t te, const double *band, int64_t be,
-                           const CyclicQ &q, const Corners &cn, const SweepGeom &g,
-                           const void *in, void *out, hipStream_t s)
-{
-    switch (g.C) {
-    case 4: return refine_c<K, CYC, 4>(table, te, band, be, q, cn, g, in, out, s);
-    case 8: return refine_c<K, CYC, 8>(table, te, band, be, q, cn, g, in, out, s);
-    case 16: return refine_c<K, CYC, 16>(table, te, band, be, q, cn, g, in, out, s);
-    case 32: return refine_c<K, CYC, 32>(table, te, band, be, q, cn, g, in, out, s);
-    case 64: return refine_c<K, CYC, 64>(table, te, band, be, q, cn, g, in, out, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-}  // namespace
-
-hipError_t launch_refine(int K, bool cyclic, const void *table, int64_t table_elems,
+hipError_t launch_refine(int K, bool cyclic, bool f32_rhs, const void *table, int64_t table_elems,
                          const double *band_table, int64_t band_elems, const CyclicQ &q,
                          const Corners &cn, const SweepGeom &g, const void *in, void *out,
                          hipStream_t s)
 {
-    if (K == 1) return cyclic ? refine_dispatch<1, true>(table, table_elems, band_table, band_elems, q, cn, g, in, out, s)
-                              : refine_dispatch<1, false>(table, table_elems, band_table, band_elems, q, cn, g, in, out, s);
-    return cyclic ? refine_dispatch<2, true>(table, table_elems, band_table, band_elems, q, cn, g, in, out, s)
-                  : refine_dispatch<2, false>(table, table_elems, band_table, band_elems, q, cn, g, in, out, s);
+    if (f32_rhs)
+        return launch_refine_f32rhs(K, cyclic, table, table_elems, band_table, band_elems, q, cn, g,
+                                    in, out, s);
+    if (K == 1)
+        return cyclic ? refine_dispatch<1, true, double>(table, table_elems, band_table, band_elems, q, cn, g, in, out, s)
+                      : refine_dispatch<1, false, double>(table, table_elems, band_table, band_elems, q, cn, g, in, out, s);
+    return cyclic ? refine_dispatch<2, true, double>(table, table_elems, band_table, band_elems, q, cn, g, in, out, s)
+                  : refine_dispatch<2, false, double>(table, table_elems, band_table, band_elems, q, cn, g, in, out, s);
 }
 
 }  // namespace bb

@@ -99,11 +99,12 @@ class Factor:
     def _run(self, fname: str, rhs: torch.Tensor, out, precision: str):
         if precision not in _lib.PRECISION:
             raise ValueError("precision must be one of %s" % list(_lib.PRECISION))
-        dtype = torch.float32 if precision == "f32" else torch.float64
-        m, ld = _batch_view(rhs, self.n, dtype, "rhs")
+        in_dtype = torch.float32 if precision in ("f32", "f32rhs") else torch.float64
+        out_dtype = torch.float32 if precision == "f32" else torch.float64
+        m, ld = _batch_view(rhs, self.n, in_dtype, "rhs")
         if out is None:
-            out = torch.empty_like(rhs)
-        m2, ld2 = _batch_view(out, self.n, dtype, "out")
+            out = torch.empty_like(rhs, dtype=out_dtype)
+        m2, ld2 = _batch_view(out, self.n, out_dtype, "out")
         if (m2, ld2) != (m, ld) or out.device != rhs.device:
             raise ValueError("out must match rhs in shape, strides and device")
         with torch.cuda.device(rhs.device):
@@ -114,7 +115,12 @@ class Factor:
 
     def solve(self, rhs: torch.Tensor, out: torch.Tensor | None = None,
               precision: str = "f64") -> torch.Tensor:
-        """x = A^{-1} rhs for every column (out may be rhs: in place)."""
+        """x = A^{-1} rhs for every column.
+
+        precision: "f64" (double rhs and x), "f32r" (double rhs and x, float
+        sweeps + one double residual refinement), "f32" (float rhs and x, no
+        refinement), "f32rhs" (float rhs data, double x, refined like "f32r").
+        out may be rhs (in place) except with "f32rhs"."""
         return self._run("bb_solve_batch_" + self.kind.replace("_cyclic", ""), rhs, out, precision)
 
     def adjoint(self, g: torch.Tensor, out: torch.Tensor | None = None,

@@ -119,6 +119,7 @@ def test_solve_argument_checks_need_no_gpu(L):
     assert L.bb_solve_batch_tri(h, fake, fake, 8, 4, 0, None) == -1        # ld < m
     assert L.bb_solve_batch_tri(h, None, fake, 4, 4, 0, None) == -1
     assert L.bb_solve_batch_tri(h, fake, fake, 4, 4, 7, None) == -1        # bad precision
+    assert L.bb_solve_batch_tri(h, fake, fake, 4, 4, 3, None) == -1        # float rhs aliasing double x
     assert L.bb_solve_batch_penta(h, fake, fake, 4, 4, 0, None) == -1      # wrong kind
     assert L.bb_solve_batch_tri(hp, fake, fake, 4, 4, 0, None) == -1
     assert L.bb_solve_batch_tri_cyclic(h, fake, fake, 4, 4, 0, None) == -1  # not cyclic

@@ -3,8 +3,9 @@ configuration bench.py times (same library calls, same chunking), on sampled
 systems the oracle solves one by one, plus properties that hold at any size.
 
   * diffusion n=256, m=1024: every system.
-  * diffusion n=512, m=2^20: FP64 and FP32+refine, 512 sampled systems.
-  * hyperdiffusion n=1024, m=2^18 (sine-mode RHS): FP64 and FP32+refine, sampled.
+  * diffusion n=512, m=2^20: FP64, FP32+refine and FP32 right-hand sides with
+    refinement, 512 sampled systems.
+  * hyperdiffusion n=1024, m=2^18 (sine-mode RHS): the same three forms, sampled.
   * Cahn-Hilliard n=256, m=2^20: 10 fused steps, sampled systems; mass of
     every system conserved.
   * differentiated diffusion n=1024, m=2^16, T=100, checkpoint every 10:
@@ -73,6 +74,11 @@ def test_diffusion_n512_m2p20_sampled():
     # the paper's mapping on the same input
     f.solve_thread_per_system(t, out=x)
     assert rel_err(cols_of(x, cols), ref) < 1e-12
+    # FP32 right-hand-side data (the same draws rounded), refined to double
+    t32 = t.float()
+    ref32 = oracle.tri_solve(*bands, rhs[:, cols].astype(np.float32).astype(np.float64))
+    f.solve(t32, out=x, precision="f32rhs")
+    assert rel_err(cols_of(x, cols), ref32) < 1e-10
 
 
 def test_hyperdiffusion_n1024_m2p18_sampled():
@@ -91,6 +97,10 @@ def test_hyperdiffusion_n1024_m2p18_sampled():
         err = rel_err(cols_of(x, cols), ref)
         say(prec, "max rel err", err)
         assert err < tol
+    t32 = t.float()
+    ref32 = oracle.penta_solve(*bands, rhs[:, cols].astype(np.float32).astype(np.float64))
+    f.solve(t32, out=x, precision="f32rhs")
+    assert rel_err(cols_of(x, cols), ref32) < 1e-10
 
 
 def test_cahn_hilliard_n256_m2p20_sampled():

@@ -99,6 +99,25 @@ def test_refine_f32r(kind, cyclic, n):
 
 @pytest.mark.parametrize("kind", ["tri", "penta"])
 @pytest.mark.parametrize("cyclic", [False, True])
+@pytest.mark.parametrize("n", [64, 300, 512, 1024])
+def test_refine_f32_rhs(kind, cyclic, n):
+    """FP32 right-hand-side data, double solution: against the oracle solving
+    with the same (float) values promoted to double."""
+    say("f32rhs", kind, cyclic, n)
+    f, bands = make(kind, n, seed=9 * n, cyclic=cyclic, dominant=False)
+    rhs32 = inputs.uniform_batch(n, 333, seed=4500 + n).astype(np.float32)
+    t = dev(rhs32, torch.float32)
+    x = f.solve(t, precision="f32rhs")
+    assert x.dtype == torch.float64
+    err = rel_err(host(x), oracle_solve(kind, bands, rhs32.astype(np.float64), cyclic))
+    say("  rel err", err)
+    assert err < F32R_TOL
+    lam = host(f.adjoint(t, precision="f32rhs"))
+    assert rel_err(lam, oracle_adjoint(kind, bands, rhs32.astype(np.float64), cyclic)) < F32R_TOL
+
+
+@pytest.mark.parametrize("kind", ["tri", "penta"])
+@pytest.mark.parametrize("cyclic", [False, True])
 def test_plain_f32(kind, cyclic):
     n = 512
     f, bands = make(kind, n, seed=11, cyclic=cyclic, dominant=False)
