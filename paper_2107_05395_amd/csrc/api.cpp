@@ -88,8 +88,10 @@ int lockstep_for(int S, size_t elem_bytes)
 // differentiated workload: the sweep at 64 rows per lane runs fastest with
 // 4-wave groups at P = 8 (S = 32) and 8-wave groups from P = 16 on (S = 32,
 // 16); at 128 rows (one wave per SIMD) with 4-wave groups from P = 8; the
-// refinement kernel (64 rows, one wave per SIMD) with S = 16, i.e. Q = P/4.
-// P <= 4 keeps one wave.
+// refinement kernel (64 rows, one wave per SIMD) with S = 16, i.e. Q = P/4;
+// with FP32 right-hand sides (two waves per SIMD for tri) with 4-wave groups
+// from P = 4 (tri n = 512: 1.59 vs 1.80 ms at Q = 2).  P <= 4 otherwise keeps
+// one wave.
 // BANDBATCH_WAVES_PER_SYSTEM = 1, 2, 4 or 8 forces the group size where it
 // is valid (tuning); anything else keeps the automatic choice.
 int split_log2(int log2P, int C, int n, bb::Op op)
@@ -98,8 +100,12 @@ int split_log2(int log2P, int C, int n, bb::Op op)
     if (C < 64 || (refine && ((int64_t)C << log2P) != n)) return 0;
     const int lmax = bb::max_log2q(C, refine);
     int l = 0;
-    if (refine || C > 64)
-        l = refine ? (log2P > 2 ? log2P - 2 : 0) : (log2P >= 3 ? 2 : 0);
+    if (op == bb::Op::RefineF32Rhs)   // float input: fewer registers, 4-wave groups from P = 4
+        l = log2P >= 2 ? 2 : 0;
+    else if (refine)
+        l = log2P > 2 ? log2P - 2 : 0;
+    else if (C > 64)
+        l = log2P >= 3 ? 2 : 0;
     else
         l = log2P >= 4 ? 3 : log2P == 3 ? 2 : 0;
     if (l > lmax) l = lmax;
