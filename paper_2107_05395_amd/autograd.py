@@ -22,6 +22,18 @@ def _factor_from(bands, kind: str, cyclic: bool) -> Factor:
     return Factor.tri(*host, cyclic=cyclic) if kind == "tri" else Factor.penta(*host, cyclic=cyclic)
 
 
+_SIDE_STREAMS: dict = {}
+
+
+def _side_stream(device) -> "torch.cuda.Stream":
+    """One extra stream per device (default priority) for work that may
+    overlap the main chain of solves."""
+    key = torch.device(device).index
+    if key not in _SIDE_STREAMS:
+        _SIDE_STREAMS[key] = torch.cuda.Stream(device=device)
+    return _SIDE_STREAMS[key]
+
+
 def _kind(nb: int) -> str:
     if nb not in (3, 5):
         raise ValueError("need 3 (tri) or 5 (penta) bands")
@@ -76,7 +88,15 @@ class BandedRollout(torch.autograd.Function):
     def backward(ctx, g_out):
         f, steps, every, prec = ctx.factor, ctx.steps, ctx.every, ctx.precision
         g = g_out.contiguous()
+        main = torch.cuda.current_stream(g.device)
+        # The band-gradient reductions depend only on lam_t and u_t, not on the
+        # next adjoint solve: they run on a second stream (default priority)
+        # so they overlap the chain of solves; their order among themselves,
+        # and so the sums, stay fixed.
+        side = _side_stream(g.device)
+        side.wait_stream(main)
         gb = torch.zeros(f.nbands, f.n, dtype=torch.float64, device=g.device)
+        gb.record_stream(side)
         # segments [s, e): states u_s .. u_e; checkpoint i holds u_{i*every}
         for i in reversed(range(len(ctx.checkpoints))):
             s = i * every
@@ -86,9 +106,14 @@ class BandedRollout(torch.autograd.Function):
                 states.append(f.solve(states[-1], precision=prec))
             for t in range(e, s, -1):          # u_t = A^{-1} u_{t-1}
                 lam = f.adjoint(g, precision=prec)
-                f.band_grad(lam, states[t - s], gb)
+                side.wait_stream(main)
+                with torch.cuda.stream(side):
+                    f.band_grad(lam, states[t - s], gb)
+                lam.record_stream(side)
+                states[t - s].record_stream(side)
                 g = lam
             del states
+        main.wait_stream(side)
         ctx.checkpoints = None
         return (g, None, None, None, *[gb[q].to(d) for q, d in enumerate(ctx.band_devices)])
 
