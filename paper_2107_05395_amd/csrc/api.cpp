@@ -73,14 +73,15 @@ int solve_chunk(int64_t n, bb_precision p)
 // loop.  When one wave's segment of a row is shorter than a 128 B line the
 // neighbouring wave reads the rest of the line; in step, the second request
 // hits in L2 (measured: 64 B segments otherwise re-read 1.7x the bytes).  It
-// measured no worse with full-line segments, so it is on by default.
+// measured no worse with full-line segments, so it is on for one-wave groups.
+// A split group is its whole workgroup and its exchange barriers already keep
+// the waves together: there the extra barrier only costs (measured tri
+// n = 1024, m = 2^16: 0.267 vs 0.293 ms), so it is off.
 // BANDBATCH_LOCKSTEP=0/1 overrides (tuning).
-int lockstep_for(int S, size_t elem_bytes)
+int lockstep_for(bool split)
 {
-    (void)S;
-    (void)elem_bytes;
     if (const char *env = std::getenv("BANDBATCH_LOCKSTEP")) return std::atoi(env) != 0;
-    return 1;
+    return split ? 0 : 1;
 }
 
 // Waves per system group (log2) for C >= 64 (the refinement kernel: full
@@ -268,7 +269,7 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
     g.log2Q = split_log2(log2P, C, (int)f.n, op);
     const int S = (bb::kWave << g.log2Q) / P;
     g.groups = (m + S - 1) / S;
-    g.lockstep = lockstep_for(S, p == BB_F32 ? sizeof(float) : sizeof(double));
+    g.lockstep = lockstep_for(g.log2Q > 0);
     hipError_t e = bb::launch_sweep(f.K, f.cyclic, op, f32 && p == BB_F32, tab.ptr, tab.elems,
                                     (const double *)band.ptr, band.elems, dir.cor.q, corners, g,
                                     in, out, (hipStream_t)stream);
@@ -474,7 +475,7 @@ bb_status bb_ch_step(bb_factor fh, const double *c_in, double *c_out, int64_t m,
         g.log2Q = log2P;
     const int S = (bb::kWave << g.log2Q) / P;
     g.groups = (m + S - 1) / S;
-    g.lockstep = lockstep_for(S, sizeof(double));
+    g.lockstep = lockstep_for(g.log2Q > 0);
     hipError_t e = bb::launch_ch((const double *)tab.ptr, tab.elems, f.primal.cor.q, g, alpha, steps,
                                  c_in, c_out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "Cahn-Hilliard launch");
