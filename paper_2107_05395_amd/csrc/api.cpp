@@ -74,9 +74,11 @@ int solve_chunk(int64_t n, bb_precision p)
 // neighbouring wave reads the rest of the line; in step, the second request
 // hits in L2 (measured: 64 B segments otherwise re-read 1.7x the bytes).  It
 // measured no worse with full-line segments, so it is on for one-wave groups.
-// A split group is its whole workgroup and its exchange barriers already keep
-// the waves together: there the extra barrier only costs (measured tri
-// n = 1024, m = 2^16: 0.267 vs 0.293 ms), so it is off.
+// A split group of the solve kernel is its whole workgroup and its exchange
+// barriers already keep the waves together: there the extra barrier only
+// costs (measured tri n = 1024, m = 2^16: 0.267 vs 0.293 ms), so it is off.
+// The refinement kernel keeps it (penta n = 1024 with FP32 right-hand sides:
+// 1.46 vs 1.56 ms without).
 // BANDBATCH_LOCKSTEP=0/1 overrides (tuning).
 int lockstep_for(bool split)
 {
@@ -269,7 +271,7 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
     g.log2Q = split_log2(log2P, C, (int)f.n, op);
     const int S = (bb::kWave << g.log2Q) / P;
     g.groups = (m + S - 1) / S;
-    g.lockstep = lockstep_for(g.log2Q > 0);
+    g.lockstep = lockstep_for(g.log2Q > 0 && op == bb::Op::Solve);
     hipError_t e = bb::launch_sweep(f.K, f.cyclic, op, f32 && p == BB_F32, tab.ptr, tab.elems,
                                     (const double *)band.ptr, band.elems, dir.cor.q, corners, g,
                                     in, out, (hipStream_t)stream);
