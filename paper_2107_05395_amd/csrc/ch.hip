@@ -102,10 +102,11 @@ void ch_kernel_uniform(const double *__restrict__ table, CyclicQ cq, SweepGeom g
     lg.j = __builtin_amdgcn_readfirstlane(lg.j);            // the wave's chunk: uniform
     const int row0 = lg.j * C;
     const bool has_left = lg.j > 0, has_right = lg.j < lg.P - 1;
-    const int me = 2 * (lg.j * kWave + lg.sl);
-    const int lft = 2 * ((has_left ? lg.j - 1 : lg.j) * kWave + lg.sl) + 1;
-    const int rgt = 2 * ((has_right ? lg.j + 1 : lg.j) * kWave + lg.sl);
-    const int first = 2 * lg.sl, last = 2 * ((lg.P - 1) * kWave + lg.sl) + 1;
+    const int PS = lg.P * kWave;   // xd: [2][P*64], rows 0 and C-1 of (chunk, slot)
+    const int me = lg.j * kWave + lg.sl;
+    const int lft = (has_left ? lg.j - 1 : lg.j) * kWave + lg.sl;
+    const int rgt = (has_right ? lg.j + 1 : lg.j) * kWave + lg.sl;
+    const int first = lg.sl, last = (lg.P - 1) * kWave + lg.sl;
     const GroupRange gr = group_range(g.groups, QL);
 
     for (int64_t blk = gr.first; blk < gr.end; blk += gr.stride) {
@@ -118,11 +119,11 @@ void ch_kernel_uniform(const double *__restrict__ table, CyclicQ cq, SweepGeom g
 
         for (int64_t step = 0; step < steps; ++step) {
             xd[me] = c[0];
-            xd[me + 1] = c[C - 1];
+            xd[PS + me] = c[C - 1];
             __syncthreads();
-            const double cl = has_left ? xd[lft] : 0.0;
+            const double cl = has_left ? xd[PS + lft] : 0.0;
             const double cr = has_right ? xd[rgt] : 0.0;
-            ch_rhs<C, true>(c, cl, cr, xd[first], xd[last], alpha, lg.j, !has_right, C);
+            ch_rhs<C, true>(c, cl, cr, xd[first], xd[PS + last], alpha, lg.j, !has_right, C);
             __builtin_amdgcn_sched_barrier(0);
             chunk_solve<double, 2, C, true, true, Src>(c, tab, lg, g.n, 1, cq, xch);
         }

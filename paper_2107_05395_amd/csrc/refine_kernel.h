@@ -57,25 +57,26 @@ __global__ __launch_bounds__(kMaxBlockThreads) void refine_kernel(
         // periodic, rows 0, 1, n-2, n-1 of the system
         float xl1, xl2, xr1, xr2, r0 = 0.f, r1 = 0.f, rn2 = 0.f, rn1 = 0.f;
         if constexpr (QL > 0) {
-            float *xd = xch + 8 * lg.P * lg.S;
-            const int me = 4 * (lg.j * lg.S + lg.sl);
+            const int PS = lg.P * lg.S;
+            float *xd = xch + 8 * PS;   // [4][P*S]: rows 0, 1, C-2, C-1 of (chunk, slot)
+            const int me = lg.j * lg.S + lg.sl;
             xd[me] = x0[0];
-            xd[me + 1] = x0[1];
-            xd[me + 2] = x0[C - 2];
-            xd[me + 3] = x0[C - 1];
+            xd[PS + me] = x0[1];
+            xd[2 * PS + me] = x0[C - 2];
+            xd[3 * PS + me] = x0[C - 1];
             __syncthreads();
-            const int lft = 4 * ((has_left ? lg.j - 1 : lg.j) * lg.S + lg.sl);
-            const int rgt = 4 * ((has_right ? lg.j + 1 : lg.j) * lg.S + lg.sl);
-            xl1 = has_left ? xd[lft + 3] : 0.f;
-            xl2 = has_left ? xd[lft + 2] : 0.f;
+            const int lft = (has_left ? lg.j - 1 : lg.j) * lg.S + lg.sl;
+            const int rgt = (has_right ? lg.j + 1 : lg.j) * lg.S + lg.sl;
+            xl1 = has_left ? xd[3 * PS + lft] : 0.f;
+            xl2 = has_left ? xd[2 * PS + lft] : 0.f;
             xr1 = has_right ? xd[rgt] : 0.f;
-            xr2 = has_right ? xd[rgt + 1] : 0.f;
+            xr2 = has_right ? xd[PS + rgt] : 0.f;
             if constexpr (CYC) {
-                const int first = 4 * lg.sl, last = 4 * ((lg.P - 1) * lg.S + lg.sl);
+                const int first = lg.sl, last = (lg.P - 1) * lg.S + lg.sl;
                 r0 = xd[first];
-                r1 = xd[first + 1];
-                rn2 = xd[last + 2];
-                rn1 = xd[last + 3];
+                r1 = xd[PS + first];
+                rn2 = xd[2 * PS + last];
+                rn1 = xd[3 * PS + last];
             }
         } else {
             xl1 = shfl(x0[C - 1], left);

@@ -252,15 +252,18 @@ __device__ __forceinline__ void chunk_solve(T (&v)[C], typename Src::ptr tab, co
     // history of this chunk: H_j = true (y_{start-1}, y_{start-2})
     const auto tb = lane_table<T, K, C, CYC>(Src::base(tab), lg.P, lg.j);
     T h1 = T(0), h2 = T(0);
-    const int me = lg.j * lg.S + lg.sl;   // (chunk, slot) index in the exchange area
+    // exchange area: structure of arrays of P*S entries, (chunk, slot) at
+    // chunk*S + slot, so a wave's accesses are consecutive words
+    const int me = lg.j * lg.S + lg.sl;
+    const int PS = lg.P * lg.S;
     if constexpr (SPLIT) {
-        T *xa = xch;
-        xa[2 * me] = e1;
-        xa[2 * me + 1] = e2;
+        T *xa = xch;   // [2][P*S]
+        xa[me] = e1;
+        xa[PS + me] = e2;
         __syncthreads();
         for (int i = 0; i < lg.j; ++i) {
-            const int src = 2 * (i * lg.S + lg.sl);
-            affine<T, K>(tb.Mf + i * K * K, h1, h2, xa[src], xa[src + 1]);
+            const int src = i * lg.S + lg.sl;
+            affine<T, K>(tb.Mf + i * K * K, h1, h2, xa[src], xa[PS + src]);
         }
     } else {
         for (int i = 0; i < lg.P; ++i) {
@@ -284,13 +287,13 @@ __device__ __forceinline__ void chunk_solve(T (&v)[C], typename Src::ptr tab, co
     // future of this chunk: F_j = true (x_{end+1}, x_{end+2})
     T f1 = T(0), f2 = T(0);
     if constexpr (SPLIT) {
-        T *xb = xch + 2 * lg.P * lg.S;
-        xb[2 * me] = s1;
-        xb[2 * me + 1] = s2;
+        T *xb = xch + 2 * PS;   // [2][P*S]
+        xb[me] = s1;
+        xb[PS + me] = s2;
         __syncthreads();
         for (int i = lg.P - 1; i > lg.j; --i) {
-            const int src = 2 * (i * lg.S + lg.sl);
-            affine<T, K>(tb.Mb + i * K * K, f1, f2, xb[src], xb[src + 1]);
+            const int src = i * lg.S + lg.sl;
+            affine<T, K>(tb.Mb + i * K * K, f1, f2, xb[src], xb[PS + src]);
         }
     } else {
         for (int i = lg.P - 1; i >= 0; --i) {
@@ -320,16 +323,16 @@ __device__ __forceinline__ void chunk_solve(T (&v)[C], typename Src::ptr tab, co
             const int last = (n / C - 1) * lg.S + lg.sl;
             T r0, r1, rn1, rn2;
             if constexpr (SPLIT) {
-                T *xc = xch + 4 * lg.P * lg.S;
-                xc[4 * me] = x0;
-                xc[4 * me + 1] = x1;
-                xc[4 * me + 2] = y1;
-                xc[4 * me + 3] = y2;
+                T *xc = xch + 4 * PS;   // [4][P*S]
+                xc[me] = x0;
+                xc[PS + me] = x1;
+                xc[2 * PS + me] = y1;
+                xc[3 * PS + me] = y2;
                 __syncthreads();
-                r0 = xc[4 * lg.sl];
-                r1 = xc[4 * lg.sl + 1];
-                rn1 = xc[4 * last + 2];
-                rn2 = (K == 2) ? fma(T(cq.u1_nm2), rn1, xc[4 * last + 3]) : T(0);
+                r0 = xc[lg.sl];
+                r1 = xc[PS + lg.sl];
+                rn1 = xc[2 * PS + last];
+                rn2 = (K == 2) ? fma(T(cq.u1_nm2), rn1, xc[3 * PS + last]) : T(0);
             } else {
                 r0 = shfl(x0, lg.sl);
                 r1 = (K == 2) ? shfl(x1, lg.sl) : T(0);
@@ -378,16 +381,16 @@ __device__ __forceinline__ void chunk_solve(T (&v)[C], typename Src::ptr tab, co
             if constexpr (SPLIT) {
                 // rows 0, 1 (chunk 0) and n-2, n-1 (wherever they sit) through
                 // the fourth phase of the exchange area
-                T *xd = xch + 8 * lg.P * lg.S;
-                xd[4 * me] = v[0];
-                xd[4 * me + 1] = v[1];
-                xd[4 * me + 2] = pick(v, (n - 2) % C);
-                xd[4 * me + 3] = pick(v, (n - 1) % C);
+                T *xd = xch + 8 * PS;   // [4][P*S]
+                xd[me] = v[0];
+                xd[PS + me] = v[1];
+                xd[2 * PS + me] = pick(v, (n - 2) % C);
+                xd[3 * PS + me] = pick(v, (n - 1) % C);
                 __syncthreads();
-                r0 = xd[4 * lg.sl];
-                r1 = (K == 2) ? xd[4 * lg.sl + 1] : T(0);
-                rn2 = (K == 2) ? xd[4 * (((n - 2) / C) * lg.S + lg.sl) + 2] : T(0);
-                rn1 = xd[4 * (((n - 1) / C) * lg.S + lg.sl) + 3];
+                r0 = xd[lg.sl];
+                r1 = (K == 2) ? xd[PS + lg.sl] : T(0);
+                rn2 = (K == 2) ? xd[2 * PS + ((n - 2) / C) * lg.S + lg.sl] : T(0);
+                rn1 = xd[3 * PS + ((n - 1) / C) * lg.S + lg.sl];
             } else {
                 gather_ends<T, K, C>(v, lg, n, exact, r0, r1, rn2, rn1);
             }
