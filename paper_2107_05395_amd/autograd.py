@@ -25,10 +25,10 @@ def _factor_from(bands, kind: str, cyclic: bool) -> Factor:
 _SIDE_STREAMS: dict = {}
 
 
-def _side_stream(device) -> "torch.cuda.Stream":
-    """One extra stream per device (default priority) for work that may
-    overlap the main chain of solves."""
-    key = torch.device(device).index
+def _side_stream(device, which: int) -> "torch.cuda.Stream":
+    """Extra streams per device (default priority) for work that may overlap
+    the main chain of solves."""
+    key = (torch.device(device).index, which)
     if key not in _SIDE_STREAMS:
         _SIDE_STREAMS[key] = torch.cuda.Stream(device=device)
     return _SIDE_STREAMS[key]
@@ -90,20 +90,38 @@ class BandedRollout(torch.autograd.Function):
         g = g_out.contiguous()
         main = torch.cuda.current_stream(g.device)
         # The band-gradient reductions depend only on lam_t and u_t, not on the
-        # next adjoint solve: they run on a second stream (default priority)
-        # so they overlap the chain of solves; their order among themselves,
-        # and so the sums, stay fixed.
-        side = _side_stream(g.device)
+        # next adjoint solve: they run on a second stream so they overlap the
+        # chain of solves; their order among themselves, and so the sums, stay
+        # fixed.  The states of the next segment (walking backwards) depend
+        # only on its checkpoint: they are recomputed on a third stream while
+        # the current segment's adjoints run.  All streams default priority.
+        side = _side_stream(g.device, 0)
+        ahead = _side_stream(g.device, 1)
         side.wait_stream(main)
+        ahead.wait_stream(main)
         gb = torch.zeros(f.nbands, f.n, dtype=torch.float64, device=g.device)
         gb.record_stream(side)
+
+        def recompute(i):
+            # states u_s .. u_e of segment i from checkpoint i, on `ahead`
+            s = i * every
+            states = [ctx.checkpoints[i]]
+            with torch.cuda.stream(ahead):
+                for _ in range(s, min(s + every, steps)):
+                    states.append(f.solve(states[-1], precision=prec))
+            return states
+
         # segments [s, e): states u_s .. u_e; checkpoint i holds u_{i*every}
-        for i in reversed(range(len(ctx.checkpoints))):
+        last = len(ctx.checkpoints) - 1
+        pending = recompute(last)
+        for i in reversed(range(last + 1)):
             s = i * every
             e = min(s + every, steps)
-            states = [ctx.checkpoints[i]]
-            for _ in range(s, e):
-                states.append(f.solve(states[-1], precision=prec))
+            main.wait_stream(ahead)                 # this segment's states are ready
+            states = pending
+            for u in states:
+                u.record_stream(main)
+            pending = recompute(i - 1) if i > 0 else None
             for t in range(e, s, -1):          # u_t = A^{-1} u_{t-1}
                 lam = f.adjoint(g, precision=prec)
                 side.wait_stream(main)
