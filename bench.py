@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
+PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -237,6 +238,22 @@ def bench_ch(args, torch):
     cols = np.arange(0, m, m // 64)
     ref = oracle.ch_step(c_host[:, cols], sigma, alpha, steps=steps_per_launch)
     err = rel_err_cols(out[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref)
+    # Roofline: one step per launch streams the ensemble through HBM (16 B per
+    # row); fused steps keep it in registers and are bound by FP64 arithmetic.
+    # Algorithmic FP64 operations per row and step of the scheme (Section 5.1):
+    # N = C^3 - C (3), the stencil f = C + a(N_{i-1} - 2N_i + N_{i+1}) (5), the
+    # LR forward step with stored reciprocal (5), the back substitution (4)
+    # and the periodic rank-2 correction (4).
+    flops_row_step = 21.0
+    if steps_per_launch == 1:
+        ach = algo_bytes_per_step / per_step / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": None}
+    else:
+        ach = flops_row_step * n * m / per_step / 1e12
+        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
+                "note": "algorithmic FP64 operations of the scheme, 21 per row and step"}
     return {
         "metric": "system-steps/s", "value": m * total_steps / t, "unit": "system-steps/s",
         "n_gpus": 1, "steps": total_steps, "warmup": args.warmup, "ms_per_step": 1e3 * per_step,
@@ -245,6 +262,7 @@ def bench_ch(args, torch):
         "config": {"workload": args.workload, "n": n, "m": m, "steps_per_launch": steps_per_launch},
         "rel_err_vs_oracle": err,
         "hbm_equivalent_gbs": algo_bytes_per_step / per_step / 1e9,
+        "roofline": roof,
     }
 
 
