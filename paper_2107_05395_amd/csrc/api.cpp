@@ -100,7 +100,7 @@ int lockstep_for(bool split)
 int split_log2(int log2P, int C, int n, bb::Op op)
 {
     const bool refine = op != bb::Op::Solve;
-    if (C < 64 || (refine && ((int64_t)C << log2P) != n)) return 0;
+    if (C < (refine ? 32 : 64) || (refine && ((int64_t)C << log2P) != n)) return 0;
     const int lmax = bb::max_log2q(C, refine);
     int l = 0;
     if (op == bb::Op::RefineF32Rhs)   // float input: fewer registers, 4-wave groups from P = 4

@@ -104,10 +104,10 @@ struct SweepGeom {
     int log2Q;      // waves per system group (0: a group is one wave)
 };
 
-// Split groups of up to 4 waves, or 8 when C <= 64 (two waves per SIMD);
-// the refinement kernel uses at most 4.
+// Split groups of up to 4 waves, or 8 when the kernel runs two waves per SIMD
+// (solve: C <= 64; refinement: C <= 32).
 constexpr int kMaxLog2Q = 3;
-inline int max_log2q(int C, bool refine) { return (refine || C > 64) ? 2 : 3; }
+inline int max_log2q(int C, bool refine) { return (refine ? C > 32 : C > 64) ? 2 : 3; }
 
 // LDS elements of the exchange area of one split group: three phases
 // (forward scan: 2 per lane, backward scan: 2, periodic end values: 4).

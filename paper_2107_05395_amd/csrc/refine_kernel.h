@@ -17,7 +17,8 @@ namespace {
 // TB: type of the right-hand sides in memory -- double, or float when the
 // right-hand sides are FP32 data (promoted exactly for the residual).
 template <int K, int C, bool CYC, bool FULL, int QL, typename TB>
-__global__ __launch_bounds__(kMaxBlockThreads) void refine_kernel(
+__global__ __launch_bounds__((kWave << QL) > kMaxBlockThreads ? (kWave << QL) : kMaxBlockThreads)
+void refine_kernel(
     const float *__restrict__ table, int64_t table_elems, const double *__restrict__ band_table,
     int64_t band_elems, CyclicQ cq, Corners cn, SweepGeom g, const TB *in, double *out)
 {
@@ -148,7 +149,7 @@ hipError_t refine_c(const void *table, int64_t table_elems, const double *band,
 {
     const size_t lds = (size_t)band_elems * sizeof(double) + (size_t)table_elems * sizeof(float);
     if (g.log2Q > 0) {
-        if constexpr (C >= 64) {
+        if constexpr (C >= 32) {
             if (!is_full(g) || g.log2Q > max_log2q(C, true) || g.log2Q > g.log2P)
                 return hipErrorInvalidValue;
             const size_t xl = (size_t)(split_exchange_len(g.log2Q) + (4LL * kWave << g.log2Q)) * sizeof(float);
@@ -156,9 +157,14 @@ hipError_t refine_c(const void *table, int64_t table_elems, const double *band,
                 return launch_grid_split(refine_kernel<K, C, CYC, true, 1, TB>, lds + xl, g.groups, 2,
                                          stream, (const float *)table, table_elems, band,
                                          band_elems, q, cn, g, (const TB *)in, (double *)out);
-            return launch_grid_split(refine_kernel<K, C, CYC, true, 2, TB>, lds + xl, g.groups, 4,
-                                     stream, (const float *)table, table_elems, band, band_elems,
-                                     q, cn, g, (const TB *)in, (double *)out);
+            if (g.log2Q == 2)
+                return launch_grid_split(refine_kernel<K, C, CYC, true, 2, TB>, lds + xl, g.groups, 4,
+                                         stream, (const float *)table, table_elems, band,
+                                         band_elems, q, cn, g, (const TB *)in, (double *)out);
+            if constexpr (C <= 32)
+                return launch_grid_split(refine_kernel<K, C, CYC, true, 3, TB>, lds + xl, g.groups, 8,
+                                         stream, (const float *)table, table_elems, band,
+                                         band_elems, q, cn, g, (const TB *)in, (double *)out);
         }
         return hipErrorInvalidValue;
     }

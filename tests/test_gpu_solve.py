@@ -209,15 +209,16 @@ def test_factor_on_the_oracle_matrices_of_every_config():
                                            ("tri", 1000, True), ("tri", 1500, False),
                                            ("penta", 600, True), ("penta", 1000, False),
                                            ("tri", 1536, True)])
-@pytest.mark.parametrize("rows", [None, 128])
+@pytest.mark.parametrize("rows", [None, 128, 32])
 def test_split_groups_match_single_wave_groups(kind, n, cyclic, rows, monkeypatch):
     """A system group spread over 2, 4 or 8 waves (boundary states exchanged
     through LDS) computes exactly what a one-wave group computes: same
     operations in the same order, so the results are bitwise equal.  Solve,
-    adjoint, plain FP32 and FP32 + refinement; the default rows per lane and
-    128 rows (a width the kernel cannot run falls back to the automatic one)."""
+    adjoint, plain FP32 and FP32 + refinement; the default rows per lane, 128
+    rows and 32 rows (refinement groups of up to 8 waves; a width a kernel
+    cannot run falls back to the automatic one)."""
     if rows:
-        monkeypatch.setenv("BANDBATCH_MAX_CHUNK", str(rows))   # 128 rows per lane, one wave per SIMD
+        monkeypatch.setenv("BANDBATCH_MAX_CHUNK", str(rows))
     f, bands = make(kind, n, seed=17 * n, cyclic=cyclic)
     m = 1000                                   # not a multiple of any group width
     rhs = inputs.uniform_batch(n, m, seed=6000 + n)
