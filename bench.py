@@ -165,7 +165,9 @@ def bench_tri(args, torch):
                      "frac": algo_bytes / per_launch / 1e9 / PEAK_HBM_GBS,
                      "traffic": traffic,
                      "kernel": "sweep_kernel<double,1,%d,false,full>" % f.chunk(),
-                     "algorithmic_bytes_per_launch": algo_bytes},
+                     "algorithmic_bytes_per_launch": algo_bytes,
+                     "copy_ceiling_gbs": copy_gbs,
+                     "frac_of_copy": algo_bytes / per_launch / 1e9 / copy_gbs},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_tri(bands, n, seed + 100, args.cpu_seconds)
