@@ -144,7 +144,8 @@ __global__ __launch_bounds__(kFoldSubs * kWave) void band_grad_fold(int64_t tota
 // ---------------------------------------------------------------- MSE
 constexpr int kMseCols = 1024;   // systems per block (4 per thread)
 
-__global__ __launch_bounds__(256) void mse_partial(int n, int64_t m, int64_t ld, double scale,
+// One block per (row, 1024 systems): the block grid is (columns, n).
+__global__ __launch_bounds__(256) void mse_partial(int64_t m, int64_t ld, double scale,
                                                    const double *u,
                                                    const double *__restrict__ y,
                                                    double *grad,
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(256) void mse_fold(int64_t parts, double scale,
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0) *loss = red[0] * scale;
@@ -267,7 +268,7 @@ hipError_t launch_mse(const double *u, const double *target, double *grad, doubl
 {
     const int64_t cols = (m + kMseCols - 1) / kMseCols;
     const double scale = 1.0 / ((double)n * (double)m);
-    hipLaunchKernelGGL(mse_partial, dim3((unsigned)cols, (unsigned)n), dim3(256), 0, s, n, m, ld,
+    hipLaunchKernelGGL(mse_partial, dim3((unsigned)cols, (unsigned)n), dim3(256), 0, s, m, ld,
                        scale, u, target, grad, (double *)ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
