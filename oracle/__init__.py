@@ -64,6 +64,7 @@ def _load():
         lib.oracle_band_grad.argtypes = [ctypes.c_int, ctypes.c_int, i64, i64, i64, P, P, P]
         lib.oracle_band_grad.restype = None
         lib.oracle_ch_step_batch.argtypes = [i64, i64, i64, ctypes.c_double, ctypes.c_double, P, P]
+        lib.oracle_cn_step_batch.argtypes = [ctypes.c_int, i64, i64, i64] + [P] * 8
         lib.oracle_num_threads.argtypes = []
         _lib = lib
     return _lib
@@ -191,6 +192,47 @@ def ch_step(c, sigma: float, alpha: float, steps: int = 1) -> np.ndarray:
     out = np.empty_like(c)
     for _ in range(steps):
         _check(_load().oracle_ch_step_batch(n, m, m, sigma, alpha, _p(c), _p(out)))
+        c, out = out, c
+    return c
+
+
+# --------------------------------------------------------------------------
+# Crank-Nicolson steppers of the benchmark problems (Section 3: periodic
+# diffusion; Section 4: periodic hyperdiffusion).  A step is A C' = B C with B
+# the explicit half of the scheme, a constant stencil w of 2K+1 weights.
+
+def cn_diffusion(n: int, sigma: float):
+    """LHS bands (-s, 1+2s, -s) and RHS stencil (s, 1-2s, s), s = dt/(2 dx^2)."""
+    bands = (np.full(n, -sigma), np.full(n, 1.0 + 2.0 * sigma), np.full(n, -sigma))
+    return bands, np.array([sigma, 1.0 - 2.0 * sigma, sigma])
+
+
+def cn_hyperdiffusion(n: int, sigma: float):
+    """LHS bands (s, -4s, 1+6s, -4s, s) and RHS stencil (-s, 4s, 1-6s, 4s, -s), s = dt/(2 dx^4)."""
+    bands = (np.full(n, sigma), np.full(n, -4.0 * sigma), np.full(n, 1.0 + 6.0 * sigma),
+             np.full(n, -4.0 * sigma), np.full(n, sigma))
+    return bands, np.array([-sigma, 4.0 * sigma, 1.0 - 6.0 * sigma, 4.0 * sigma, -sigma])
+
+
+def cn_step(bands, w, c, steps: int = 1, cyclic: bool = True) -> np.ndarray:
+    """`steps` steps C <- A^{-1} (B C) of a batch c (n, m); 3 bands + 3 weights
+    (tri) or 5 + 5 (penta).  Cyclic: B wraps mod n like A; else the terms of B
+    outside the system are left out."""
+    c = np.array(c, dtype=np.float64, order="C", copy=True)
+    n, m = c.shape
+    nb = len(bands)
+    if nb not in (3, 5) or len(w) != nb:
+        raise ValueError("need 3 bands and 3 weights (tri) or 5 and 5 (penta)")
+    kind = (1 if cyclic else 0) if nb == 3 else (3 if cyclic else 2)
+    bands = [_f64(v) for v in bands] + [np.zeros(n)] * (5 - nb)
+    for v in bands:
+        if v.shape != (n,):
+            raise ValueError("band length must equal n")
+    w = _f64(w)
+    out = np.empty_like(c)
+    for _ in range(steps):
+        _check(_load().oracle_cn_step_batch(kind, n, m, m, *(_p(v) for v in bands), _p(w),
+                                            _p(c), _p(out)))
         c, out = out, c
     return c
 

@@ -367,6 +367,62 @@ int oracle_ch_step_batch(int64_t n, int64_t m, int64_t ld, double sigma, double 
     return status;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Crank-Nicolson time steps of the benchmark problems: periodic diffusion
+ * (Section 3, benchmark problem: LHS bands -s, 1+2s, -s; right-hand side
+ * s C_{i-1} + (1-2s) C_i + s C_{i+1}, s = dt/(2 dx^2)) and periodic
+ * hyperdiffusion (Section 4, benchmark problem: LHS bands s, -4s, 1+6s, -4s, s;
+ * right-hand side -s, 4s, 1-6s, 4s, -s, s = dt/(2 dx^4)).  One step is
+ *     A C^{n+1} = B C^n,   (B C)_i = sum_{d=-K..K} w[d+K] C_{i+d},
+ * with K = 1 (tri, kind 0/1) or 2 (penta, kind 2/3).  Cyclic kinds wrap the
+ * indices of B mod n like the matrix; the others leave out the terms whose
+ * index falls outside 0..n-1 (zero boundary values).  The solve is the
+ * per-system solver of oracle_solve_batch.                                 */
+int oracle_cn_step_batch(int kind, int64_t n, int64_t m, int64_t ld, const double *a,
+                         const double *b, const double *c, const double *d, const double *e,
+                         const double *w, const double *c_in, double *c_out)
+{
+    if (n < 1 || m < 0 || ld < m || kind < 0 || kind > 3) return ERR_SIZE;
+    const int K = (kind < 2) ? 1 : 2;
+    const int cyclic = (kind == 1 || kind == 3);
+    int status = OK;
+#pragma omp parallel
+    {
+        double *col = (double *)malloc(sizeof(double) * (size_t)n * 17);
+        double *f = col + n, *sol = col + 2 * n, *work = col + 3 * n;   /* 14n of workspace */
+        int my = OK;
+#pragma omp for schedule(static)
+        for (int64_t k = 0; k < m; ++k) {
+            for (int64_t i = 0; i < n; ++i) col[i] = c_in[i * ld + k];
+            for (int64_t i = 0; i < n; ++i) {
+                double acc = 0.0;
+                for (int dd = -K; dd <= K; ++dd) {
+                    int64_t r = i + dd;
+                    if (r < 0 || r >= n) {
+                        if (!cyclic) continue;
+                        r = wrap(r, n);
+                    }
+                    acc += w[dd + K] * col[r];
+                }
+                f[i] = acc;
+            }
+            int s;
+            switch (kind) {
+            case 0: s = oracle_tri_solve(n, a, b, c, f, sol, work); break;
+            case 1: s = oracle_tri_cyclic_solve(n, a, b, c, f, sol, work); break;
+            case 2: s = oracle_penta_solve(n, a, b, c, d, e, f, sol, work); break;
+            default: s = oracle_penta_cyclic_solve(n, a, b, c, d, e, f, sol, work); break;
+            }
+            if (s && !my) my = s;
+            for (int64_t i = 0; i < n; ++i) c_out[i * ld + k] = s ? NAN : sol[i];
+        }
+        free(col);
+#pragma omp critical
+        { if (my && !status) status = my; }
+    }
+    return status;
+}
+
 /* number of OpenMP threads a parallel region gets (for reporting) */
 #ifdef _OPENMP
 #include <omp.h>

@@ -60,6 +60,22 @@ def ch_penta_bands(n: int, sigma: float):
     return hyperdiffusion_penta_bands(n, sigma)
 
 
+def cn_diffusion_problem(n: int, sigma: float):
+    """Crank-Nicolson periodic diffusion (Section 3 benchmark problem), sigma =
+    dt/(2 dx^2): LHS bands (-sigma, 1 + 2 sigma, -sigma) on every row and the
+    explicit stencil (sigma, 1 - 2 sigma, sigma) of rows i-1, i, i+1."""
+    bands = (np.full(n, -sigma), np.full(n, 1.0 + 2.0 * sigma), np.full(n, -sigma))
+    return bands, (sigma, 1.0 - 2.0 * sigma, sigma)
+
+
+def cn_hyperdiffusion_problem(n: int, sigma: float):
+    """Crank-Nicolson periodic hyperdiffusion (Section 4 benchmark problem),
+    sigma = dt/(2 dx^4): LHS bands (sigma, -4 sigma, 1 + 6 sigma, -4 sigma, sigma)
+    and the explicit stencil (-sigma, 4 sigma, 1 - 6 sigma, 4 sigma, -sigma)."""
+    return (hyperdiffusion_penta_bands(n, sigma),
+            (-sigma, 4.0 * sigma, 1.0 - 6.0 * sigma, 4.0 * sigma, -sigma))
+
+
 def variable_diffusion_bands(D: np.ndarray, r: float):
     """A(D) = I + r diag(D) T2, T2 = tridiag(-1, 2, -1): rows (-r D_i, 1 + 2 r D_i, -r D_i)."""
     D = np.asarray(D, dtype=np.float64)
