@@ -31,7 +31,9 @@ PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-KERNEL_SOURCES = ("sweep_core.h", "sweep_kernel.h", "sweep.hip", "sweep_f32.hip", "refine_kernel.h", "refine.hip", "refine_f32rhs.hip", "ch.hip", "internal.h")
+KERNEL_SOURCES = ("sweep_core.h", "sweep_kernel.h", "sweep.hip", "sweep_f32.hip", "refine_kernel.h",
+                  "refine.hip", "refine_f32rhs.hip", "stepper.h", "ch.hip", "cn_stencil.h",
+                  "cn_tri.hip", "cn_penta.hip", "internal.h")
 
 
 def kernel_source_hash() -> str:
@@ -268,6 +270,104 @@ def bench_ch(args, torch):
     }
 
 
+# The paper's own times for 1000 steps on the same grid (Tesla V100; Section
+# 3 and Section 4 benchmark tables, cuThomasConstantBatch and
+# cuPentConstantBatch columns), keyed by (M, N), as printed.  Context only:
+# other hardware, and the printed unit is not certain.
+PAPER_CN_TABLE = {
+    "diffusion": {(64, 64): 0.097, (64, 256): 0.161, (64, 1024): 0.510,
+                  (4096, 64): 0.101, (4096, 256): 0.255, (4096, 1024): 1.020,
+                  (65536, 64): 1.278, (65536, 256): 5.015, (65536, 1024): 20.268},
+    "hyperdiffusion": {(64, 64): 369.902, (64, 256): 461.727, (64, 1024): 658.475,
+                       (4096, 64): 460.857, (4096, 256): 429.127, (4096, 1024): 1344.377,
+                       (65536, 64): 1786.018, (65536, 256): 6535.750, (65536, 1024): 25893.904},
+}
+
+# Algorithmic FP64 operations per row and Crank-Nicolson step: the explicit
+# stencil (3 points: 5; 5 points: 9), the forward sweep with stored
+# reciprocal (tri 3, penta 5), the back substitution (tri 2, penta 4) and the
+# periodic correction (rank 1: 2, rank 2: 4).
+CN_FLOPS_ROW_STEP = {"diffusion": 12.0, "hyperdiffusion": 22.0}
+
+
+def cpu_baseline_cn(bands, w, n, seed, budget_s):
+    import oracle
+    from paper_2107_05395_amd import inputs
+    m_s = 1 << 12
+    c = inputs.uniform_batch(n, m_s, seed=seed)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        c = oracle.cn_step(bands, w, c, steps=5)
+        steps += 5
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": steps * m_s / el, "unit": "system-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d x oracle.cn_step on %d systems of n=%d (the largest grid point's n), %.1f s"
+                      % (steps, m_s, n, el)}
+
+
+def bench_cn(args, torch):
+    """Crank-Nicolson time stepping over the paper's benchmark grid: every
+    (n, m) point runs the workload's step count twice, all steps in one fused
+    launch (state on chip) and one launch per step (state through HBM)."""
+    from paper_2107_05395_amd import Factor, inputs
+    import oracle
+    spec = dict(inputs.WORKLOADS[args.workload])
+    prob, sigma, T, seed = spec["problem"], spec["sigma"], spec["steps"], spec["seed"]
+    build = inputs.cn_diffusion_problem if prob == "diffusion" else inputs.cn_hyperdiffusion_problem
+    grid = []
+    last = None
+    for n in spec["ns"]:
+        bands, w = build(n, sigma)
+        f = Factor.tri(*bands, cyclic=True) if prob == "diffusion" else Factor.penta(*bands, cyclic=True)
+        f.upload()
+        for m in spec["ms"]:
+            c_host = inputs.uniform_batch(n, m, seed=seed + n + m)
+            c = torch.from_numpy(c_host).cuda()
+            out = torch.empty_like(c)
+            tf, _ = time_launches(lambda: f.cn_step(c, w, steps=T, out=out), 1, 1, torch)
+            cols = np.unique(np.r_[np.linspace(0, m - 1, 16).astype(np.int64), m - 1])
+            ref = oracle.cn_step(bands, w, c_host[:, cols], steps=T)
+            err = rel_err_cols(out[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref)
+            bufs = [c.clone(), out]
+
+            def per_step():
+                for i in range(T):
+                    f.cn_step(bufs[i & 1], w, out=bufs[(i + 1) & 1])
+            tp, _ = time_launches(per_step, 1, 1, torch)
+            grid.append({"n": n, "m": m, "fused_ms": 1e3 * tf, "per_step_launch_ms": 1e3 * tp,
+                         "fused_system_steps_per_s": m * T / tf,
+                         "per_step_hbm_gbs": 16.0 * n * m * T / tp / 1e9,
+                         "rel_err_vs_oracle": err,
+                         "paper_v100_cuconstant_time": PAPER_CN_TABLE[prob][(m, n)]})
+            last = (n, m, tf, tp, bands, w)
+            del c, out, bufs
+    n, m, tf, tp, bands, w = last
+    flops = CN_FLOPS_ROW_STEP[prob] * n * m * T
+    line = {
+        "metric": "system-steps/s", "value": m * T / tf, "unit": "system-steps/s",
+        "n_gpus": 1, "steps": T, "warmup": 1, "ms_per_step": 1e3 * tf / T,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded uniform[-1,1) initial states)",
+        "config": {"workload": args.workload, "n": n, "m": m, "sigma": sigma, "periodic": True,
+                   "steps_per_launch": T},
+        "grid": grid,
+        "roofline": {"bound": "alu", "achieved": flops / tf / 1e12, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": flops / tf / 1e12 / PEAK_FP64_TFLOPS,
+                     "traffic": None,
+                     "note": "fused launch; algorithmic FP64 operations %d per row and step"
+                             % CN_FLOPS_ROW_STEP[prob]},
+        "per_step_roofline": {"bound": "hbm", "achieved": 16.0 * n * m * T / tp / 1e9,
+                              "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                              "frac": 16.0 * n * m * T / tp / 1e9 / PEAK_HBM_GBS},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_cn(bands, w, n, seed + 1, args.cpu_seconds)
+    return line
+
+
 def bench_adjoint(args, torch):
     """One step = forward rollout of T implicit steps (checkpoint every c), the
     mean-squared-error loss, and the backward pass: adjoint solves with the
@@ -385,6 +485,8 @@ def main():
         line = bench_ch(args, torch)
     elif kind == "adjoint":
         line = bench_adjoint(args, torch)
+    elif kind == "cn":
+        line = bench_cn(args, torch)
     else:
         sys.exit("workload %s is not a bench workload" % args.workload)
     line["device"] = torch.cuda.get_device_name(0)

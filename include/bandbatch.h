@@ -94,13 +94,17 @@ bb_status bb_factor_shared_penta_cyclic(const double *a, const double *b, const 
  * make sure no enqueued work still uses it (synchronise the streams first). */
 bb_status bb_factor_destroy(bb_factor f);
 
-/* Copy the factor's coefficient tables to the current device now, ordered on
- * `stream`, instead of on the first solve. */
+/* Copy the factor's coefficient tables for large batches to the current
+ * device now, ordered on `stream`, instead of on the first solve.  A call
+ * whose decomposition differs (a small batch: fewer than 2^16 lanes of 64-row
+ * chunks; the fused steppers) builds its own table on first use.  That first
+ * call allocates device memory; make it before capturing the calls in a HIP
+ * graph. */
 bb_status bb_factor_upload(bb_factor f, void *stream);
 
 /* Matrix size, kind (0 tri, 1 tri cyclic, 2 penta, 3 penta cyclic) and the
- * number of unknowns per lane ("chunk") the sweeps use for this n.  Any out
- * pointer may be NULL. */
+ * number of unknowns per lane ("chunk") the sweeps use for this n on large
+ * batches (small batches take shorter chunks).  Any out pointer may be NULL. */
 bb_status bb_factor_info(bb_factor f, int64_t *n, int32_t *kind, int32_t *chunk);
 
 /* Largest n the sweep kernels are built for (2048: the shared coefficient
@@ -174,6 +178,25 @@ bb_status bb_band_grad(bb_factor f, const double *lam, const double *x, int64_t 
  * Errors: BB_ERR_ARG (not a cyclic penta factor, sizes), BB_ERR_HIP. */
 bb_status bb_ch_step(bb_factor f, const double *c_in, double *c_out, int64_t m, int64_t ld,
                      double alpha, int64_t steps, void *stream);
+
+/* ---------------------------------------------------------------- Crank-Nicolson
+ * `steps` Crank-Nicolson steps of m systems (Section 3 benchmark problem:
+ * periodic diffusion; Section 4 benchmark problem: periodic hyperdiffusion):
+ *     A C^{n+1} = B C^n,   (B C)_i = sum_{d=-K..K} w[d+K] C_{i+d},
+ * with A the factor's matrix, K = 1 (tridiagonal factor) or 2 (pentadiagonal).
+ * Cyclic factor: the indices of B wrap mod n like A.  Otherwise the terms of
+ * B whose row falls outside 0..n-1 are left out (zero boundary values).
+ *   diffusion:      A rows (-s, 1 + 2s, -s),           w = (s, 1 - 2s, s),            s = dt/(2 dx^2)
+ *   hyperdiffusion: A rows (s, -4s, 1 + 6s, -4s, s),   w = (-s, 4s, 1 - 6s, 4s, -s),  s = dt/(2 dx^4)
+ * All `steps` steps of a system run inside one kernel with the state held on
+ * chip, reading c_in once and writing c_out once; steps = 1 per call gives the
+ * one-launch-per-step form (one read and one write of the batch per step).
+ * w: host, 2K+1 finite doubles, read before the call returns.
+ * c_in, c_out: device double, interleaved, same ld; c_in == c_out is allowed
+ * (in place), any other overlap is not.  steps >= 1.
+ * Errors: BB_ERR_ARG (w NULL or not finite, steps, sizes), BB_ERR_HIP. */
+bb_status bb_cn_step(bb_factor f, const double *w, const double *c_in, double *c_out, int64_t m,
+                     int64_t ld, int64_t steps, void *stream);
 
 /* ---------------------------------------------------------------- loss
  * Mean-squared-error loss of a batch against a target and its gradient:

@@ -55,18 +55,41 @@ int max_chunk(bb_precision p)
     return c;
 }
 
+// Small batches: with fewer than 2^16 lanes of 64-row chunks in flight (one
+// wave per SIMD) a solve or a time step is bound by the latency of its
+// dependency chain -- about 3C rows of the three passes plus the scans over
+// the P chunks -- not by bandwidth, and shorter chunks win: C = the power of
+// two >= 2 sqrt(n), at most 32, as long as that leaves at most 32 chunks per
+// system.  Measured (solves captured in a HIP graph, us per tri solve, C = 64
+// vs the rule): n = 64, m = 2^12: 6.5 vs 4.0; n = 256, m = 2^10: 7.4 vs 5.9;
+// n = 1024, m = 2^6: 14.5 vs 11.3; n = 1024, m = 2^10: 15.5 vs 14.4; not
+// applied at n = 2048, m = 2^8 (15.8 at 64 rows, 22.3 at 32).  Fused
+// Crank-Nicolson steps, ms per 1000 (m = 2^6 and 2^12): tri n = 64 1.72 vs
+// 2.58; n = 256 2.95 vs 3.61; n = 1024 6.2 vs 7.8; penta n = 64 2.35 vs
+// 4.14; n = 256 5.5 vs 6.3; n = 1024 12.0 vs 13.6.
+int latency_chunk(int64_t n, int64_t m, int C)
+{
+    if (m * bb::lanes_for(n, C) >= (int64_t(1) << 16)) return C;
+    int c = bb::kChunkMin;
+    while (c < 32 && (int64_t)c * c < 4 * n) c *= 2;
+    const int cc = bb::choose_chunk(n, c);
+    return (cc < C && bb::lanes_for(n, cc) <= 32) ? cc : C;
+}
+
 // Rows per lane of a solve: 64 (about 170 VGPRs, two waves per SIMD), with
 // the system groups split over 4 or 8 waves from 8 chunks on (split_log2).
 // Measured against 128 rows per lane (FP64, 4 GiB batches, GB/s, best split
 // each): tri n = 512 4881 vs 4749; n = 1024 4771 vs 4490; n = 2048 3975 vs
 // 3406; penta n = 1024 4269 vs 3949; ragged tri n = 1000 3992 vs 3701,
 // n = 2000 3635 vs 3200, penta n = 1000 3994 vs 3328.  Systems of 64 rows or
-// fewer take one lane.  BANDBATCH_MAX_CHUNK overrides (tuning).
-int solve_chunk(int64_t n, bb_precision p)
+// fewer take one lane; small batches follow latency_chunk.
+// BANDBATCH_MAX_CHUNK overrides (tuning).
+int solve_chunk(int64_t n, int64_t m, bb_precision p)
 {
     const int cmax = max_chunk(p);
-    if (!std::getenv("BANDBATCH_MAX_CHUNK") && cmax >= 64) return bb::choose_chunk(n, 64);
-    return bb::choose_chunk(n, cmax);
+    if (std::getenv("BANDBATCH_MAX_CHUNK")) return bb::choose_chunk(n, cmax);
+    const int C = bb::choose_chunk(n, std::min(cmax, 64));
+    return m > 0 ? latency_chunk(n, m, C) : C;
 }
 
 // Keep the waves of a workgroup in step at every iteration of the persistent
@@ -118,6 +141,62 @@ int split_log2(int log2P, int C, int n, bb::Op op)
         if (fl >= 0 && fl <= log2P && fl <= lmax) l = fl;
     }
     return l;
+}
+
+// Decomposition of the fused steppers (Cahn-Hilliard, Crank-Nicolson).
+struct StepPlan {
+    int C, P, log2P, log2Q;
+    bool scalar;   // one chunk per wave, coefficients through the scalar cache
+};
+
+// Rows per lane: 64 (two waves per SIMD), or latency_chunk for small
+// batches.  Systems split over several waves when the chunks tile n: one
+// chunk per wave with scalar coefficients up to 8 chunks, else the LDS table
+// with 32 systems per group (4 waves at P = 8, 8 waves from P = 16; n = 1024,
+// m = 2^16: 0.063 vs 0.096 ms per tri step over one wave per group).
+// BANDBATCH_MAX_CHUNK, BANDBATCH_CH_UNIFORM=0 (no scalar kernel) and
+// BANDBATCH_WAVES_PER_SYSTEM=1/2/4/8 override (tuning, testing).
+StepPlan step_plan(int64_t n, int64_t m)
+{
+    int C = bb::choose_chunk(n, std::min(max_chunk(BB_F64), bb::kChunkMaxCH));
+    if (!std::getenv("BANDBATCH_MAX_CHUNK")) C = latency_chunk(n, m, C);
+    StepPlan pl;
+    pl.C = C;
+    pl.P = bb::lanes_for(n, C);
+    pl.log2P = 0;
+    while ((1 << pl.log2P) < pl.P) ++pl.log2P;
+    const bool full = (int64_t)C * pl.P == n;
+    const char *uni = std::getenv("BANDBATCH_CH_UNIFORM");
+    pl.scalar = full && C == 64 && pl.log2P <= 3 && !(uni && std::atoi(uni) == 0);
+    pl.log2Q = 0;
+    if (pl.scalar)
+        pl.log2Q = pl.log2P;
+    else if (full && C >= 32 && pl.log2P >= 3)
+        pl.log2Q = pl.log2P >= 4 ? 3 : 2;
+    if (const char *env = std::getenv("BANDBATCH_WAVES_PER_SYSTEM")) {
+        if (!pl.scalar && full && C >= 32) {
+            const int q = std::atoi(env);
+            const int fl = q == 1 ? 0 : q == 2 ? 1 : q == 4 ? 2 : q == 8 ? 3 : -1;
+            if (fl >= 0 && fl <= pl.log2P) pl.log2Q = fl;
+        }
+    }
+    return pl;
+}
+
+bb::SweepGeom step_geom(int64_t n, int64_t m, int64_t ld, const StepPlan &pl)
+{
+    bb::SweepGeom g;
+    g.n = (int)n;
+    g.C = pl.C;
+    g.log2P = pl.log2P;
+    g.exact = (n % pl.C) == 0;
+    g.m = m;
+    g.ld = ld;
+    g.log2Q = pl.log2Q;
+    const int S = (bb::kWave << g.log2Q) / pl.P;
+    g.groups = (m + S - 1) / S;
+    g.lockstep = lockstep_for(g.log2Q > 0);
+    return g;
 }
 
 bb_status make(int kind, const double *a, const double *b, const double *c, const double *d,
@@ -211,7 +290,7 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
     int dev;
     if ((st = current_device(&dev)) != BB_OK) return st;
 
-    const int C = solve_chunk(f.n, p);
+    const int C = solve_chunk(f.n, m, p);
     const int P = bb::lanes_for(f.n, C);
     int log2P = 0;
     while ((1 << log2P) < P) ++log2P;
@@ -324,7 +403,7 @@ bb_status bb_factor_upload(bb_factor fh, void *stream)
     bb_status st = current_device(&dev);
     if (st != BB_OK) return st;
     for (bb_precision p : {BB_F64, BB_F32_REFINE}) {
-        const int C = solve_chunk(f.n, p);
+        const int C = solve_chunk(f.n, 0, p);
         const int P = bb::lanes_for(f.n, C);
         const int f32 = p != BB_F64;
         for (int adj = 0; adj < 2; ++adj) {
@@ -344,7 +423,7 @@ bb_status bb_factor_info(bb_factor fh, int64_t *n, int32_t *kind, int32_t *chunk
     if (!fh) return fail(BB_ERR_ARG, "factor is NULL");
     if (n) *n = fh->f.n;
     if (kind) *kind = fh->f.kind;
-    if (chunk) *chunk = solve_chunk(fh->f.n, BB_F64);
+    if (chunk) *chunk = solve_chunk(fh->f.n, 0, BB_F64);
     return BB_OK;
 }
 
@@ -449,38 +528,49 @@ bb_status bb_ch_step(bb_factor fh, const double *c_in, double *c_out, int64_t m,
     if (m == 0) return BB_OK;
     int dev;
     if ((st = current_device(&dev)) != BB_OK) return st;
-    // The fused steps are bound by arithmetic and coefficient reads, not HBM:
-    // 64 rows per lane keeps two waves per SIMD to hide each other's
-    // latencies (measured 0.39 vs 0.52 ms per step at n = 256, m = 2^20).
-    const int C = bb::choose_chunk(f.n, std::min(max_chunk(BB_F64), bb::kChunkMaxCH));
-    const int P = bb::lanes_for(f.n, C);
-    int log2P = 0;
-    while ((1 << log2P) < P) ++log2P;
+    // The fused steps are bound by arithmetic and coefficient reads, not HBM
+    // (64 rows per lane, two waves per SIMD: 0.39 vs 0.52 ms per step at
+    // n = 256, m = 2^20 against 128 rows per lane); see step_plan.
+    const StepPlan pl = step_plan(f.n, m);
     bb::DeviceTable tab;
-    st = device_table(f, f.dev, std::make_tuple(dev, 0, 0, C, 0), false,
-                      [&] { return bb::build_table(f.primal, 2, true, f.n, C, P); }, &tab);
+    st = device_table(f, f.dev, std::make_tuple(dev, 0, 0, pl.C, 0), false,
+                      [&] { return bb::build_table(f.primal, 2, true, f.n, pl.C, pl.P); }, &tab);
     if (st != BB_OK) return st;
-    bb::SweepGeom g;
-    g.n = (int)f.n;
-    g.C = C;
-    g.log2P = log2P;
-    g.exact = (f.n % C) == 0;
-    g.m = m;
-    g.ld = ld;
-    // One chunk per wave when the 64-row chunks tile n into 2, 4 or 8: the
-    // coefficients are then wave-uniform and come through the scalar cache
-    // instead of LDS, whose bandwidth bounds the fused steps otherwise.
-    // BANDBATCH_CH_UNIFORM=0 keeps the LDS kernel (tuning, testing).
-    g.log2Q = 0;
-    const char *uni = std::getenv("BANDBATCH_CH_UNIFORM");
-    if (C == 64 && (int64_t)C * P == f.n && log2P >= 1 && log2P <= 3 && !(uni && std::atoi(uni) == 0))
-        g.log2Q = log2P;
-    const int S = (bb::kWave << g.log2Q) / P;
-    g.groups = (m + S - 1) / S;
-    g.lockstep = lockstep_for(g.log2Q > 0);
-    hipError_t e = bb::launch_ch((const double *)tab.ptr, tab.elems, f.primal.cor.q, g, alpha, steps,
-                                 c_in, c_out, (hipStream_t)stream);
+    const bb::SweepGeom g = step_geom(f.n, m, ld, pl);
+    hipError_t e = bb::launch_ch((const double *)tab.ptr, tab.elems, f.primal.cor.q, g, pl.scalar,
+                                 alpha, steps, c_in, c_out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "Cahn-Hilliard launch");
+    return BB_OK;
+}
+
+bb_status bb_cn_step(bb_factor fh, const double *w, const double *c_in, double *c_out, int64_t m,
+                     int64_t ld, int64_t steps, void *stream)
+{
+    bb_status st = check_batch(fh, c_in, c_out, m, ld);
+    if (st != BB_OK) return st;
+    bb::Factor &f = fh->f;
+    if (!w) return fail(BB_ERR_ARG, "stencil pointer is NULL");
+    for (int d = 0; d <= 2 * f.K; ++d)
+        if (!std::isfinite(w[d])) return fail(BB_ERR_ARG, "stencil weight is not finite");
+    if (steps < 1) return fail(BB_ERR_ARG, "steps < 1");
+    if (m == 0) { g_last_error.clear(); return BB_OK; }
+    int dev;
+    if ((st = current_device(&dev)) != BB_OK) return st;
+    const StepPlan pl = step_plan(f.n, m);
+    bb::DeviceTable tab;
+    st = device_table(f, f.dev, std::make_tuple(dev, 0, 0, pl.C, 0), false,
+                      [&] { return bb::build_table(f.primal, f.K, f.cyclic, f.n, pl.C, pl.P); }, &tab);
+    if (st != BB_OK) return st;
+    const bb::SweepGeom g = step_geom(f.n, m, ld, pl);
+    double wk[5] = {0, 0, 0, 0, 0};
+    for (int d = 0; d <= 2 * f.K; ++d) wk[d] = w[d];
+    hipError_t e = f.K == 1
+        ? bb::launch_cn_tri(f.cyclic, (const double *)tab.ptr, tab.elems, f.primal.cor.q, g,
+                            pl.scalar, wk, steps, c_in, c_out, (hipStream_t)stream)
+        : bb::launch_cn_penta(f.cyclic, (const double *)tab.ptr, tab.elems, f.primal.cor.q, g,
+                              pl.scalar, wk, steps, c_in, c_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "Crank-Nicolson launch");
+    g_last_error.clear();
     return BB_OK;
 }
 

@@ -1,0 +1,15 @@
+// cn_penta.hip -- fused Crank-Nicolson steps with a pentadiagonal LHS
+// (periodic hyperdiffusion, Section 4 benchmark problem); the policy is in
+// cn_stencil.h.
+#include "cn_stencil.h"
+
+namespace bb {
+
+hipError_t launch_cn_penta(bool cyclic, const double *table, int64_t table_elems,
+                           const CyclicQ &q, const SweepGeom &g, bool scalar, const double *w,
+                           int64_t steps, const double *in, double *out, hipStream_t s)
+{
+    return launch_cn_k<2>(cyclic, table, table_elems, q, g, scalar, w, steps, in, out, s);
+}
+
+}  // namespace bb

@@ -1,0 +1,82 @@
+// cn_stencil.h -- the right-hand side of a Crank-Nicolson step as a policy of
+// the fused stepper (stepper.h): periodic diffusion (Section 3 benchmark
+// problem, K = 1) and periodic hyperdiffusion (Section 4 benchmark problem,
+// K = 2), and their non-periodic forms.  cn_tri.hip and cn_penta.hip
+// instantiate it.
+#pragma once
+
+#include "stepper.h"
+
+namespace bb {
+namespace {
+
+// f_i = sum_{d=-K..K} w[d+K] c_{i+d}: the explicit half B of the scheme, a
+// constant stencil of 2K+1 weights.  Periodic (CYC): indices wrap mod n like
+// the matrix.  Otherwise the terms whose row falls outside the system are left
+// out.  The sum is one fma chain from the leftmost term, so every kernel that
+// uses the policy rounds it the same way.
+template <int K, bool CYC>
+struct StencilRhs {
+    static constexpr int R = K;
+    double w[2 * K + 1];
+
+    template <int C, bool FULL>
+    __device__ __forceinline__ void operator()(double (&c)[C], const Halo &h, int j,
+                                               bool last_chunk, int nrow) const
+    {
+        // rows j*C - 1, j*C - 2: the previous chunk, or rows n-1, n-2 (periodic)
+        double m1 = h.l1, m2 = h.l2;
+        if (j == 0) {
+            m1 = CYC ? h.en1 : 0.0;
+            m2 = CYC ? h.en2 : 0.0;
+        }
+        // rows j*C + C, j*C + C + 1: the next chunk, or rows 0, 1 (periodic)
+        // after the last chunk of a full decomposition
+        double q1 = h.r1, q2 = h.r2;
+        if constexpr (FULL) {
+            if (last_chunk) {
+                q1 = CYC ? h.e0 : 0.0;
+                q2 = CYC ? h.e1 : 0.0;
+            }
+        }
+        // ragged: rows past n-1 of the system are rows 0, 1 (periodic) or absent
+        const double past0 = CYC ? h.e0 : 0.0, past1 = CYC ? h.e1 : 0.0;
+        rows_up<C>([&](int t) {
+            const double cur = c[t];
+            double p1 = t + 1 < C ? c[t + 1] : q1;
+            if constexpr (!FULL) p1 = t + 1 < nrow ? p1 : (t + 1 == nrow ? past0 : past1);
+            double f;
+            if constexpr (K == 1) {
+                f = fma(w[2], p1, fma(w[1], cur, w[0] * m1));
+            } else {
+                double p2 = t + 2 < C ? c[t + 2] : (t + 2 == C ? q1 : q2);
+                if constexpr (!FULL) p2 = t + 2 < nrow ? p2 : (t + 2 == nrow ? past0 : past1);
+                f = fma(w[4], p2, fma(w[3], p1, fma(w[2], cur, fma(w[1], m1, w[0] * m2))));
+            }
+            if constexpr (!FULL) f = t < nrow ? f : 0.0;
+            c[t] = f;
+            m2 = m1;
+            m1 = cur;
+        });
+    }
+};
+
+template <int K>
+hipError_t launch_cn_k(bool cyclic, const double *table, int64_t table_elems, const CyclicQ &q,
+                       const SweepGeom &g, bool scalar, const double *w, int64_t steps,
+                       const double *in, double *out, hipStream_t s)
+{
+    if (cyclic) {
+        StencilRhs<K, true> r;
+        for (int d = 0; d <= 2 * K; ++d) r.w[d] = w[d];
+        return launch_stepper<StencilRhs<K, true>, K, true>(table, table_elems, q, g, scalar, r,
+                                                            steps, in, out, s);
+    }
+    StencilRhs<K, false> r;
+    for (int d = 0; d <= 2 * K; ++d) r.w[d] = w[d];
+    return launch_stepper<StencilRhs<K, false>, K, false>(table, table_elems, q, g, scalar, r,
+                                                          steps, in, out, s);
+}
+
+}  // namespace
+}  // namespace bb

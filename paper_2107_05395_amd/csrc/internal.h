@@ -32,8 +32,9 @@
 // S = 64Q/P systems, and the scans read the other waves' boundary states
 // through a small LDS exchange area (barriers instead of shuffles).  The
 // solve kernel splits any decomposition with C >= 64, the refinement kernel
-// only full ones (P*C == n); the Cahn-Hilliard kernel splits a full 64-row
-// decomposition into one chunk per wave.
+// only full ones (P*C == n); the fused steppers (stepper.h) split full 32- and
+// 64-row decompositions, into one chunk per wave with the coefficients in
+// scalar registers up to P = 8, else with the table in LDS.
 //
 // Coefficient table (one per direction, precision and chunk size)
 // ----------------------------------------------------------------
@@ -157,9 +158,22 @@ hipError_t launch_refine_f32rhs(int K, bool cyclic, const void *table, int64_t t
                                 void *out, hipStream_t stream);
 
 // Cahn-Hilliard steps with the state resident on chip (cyclic penta, double).
+// scalar: one 64-row chunk per wave with scalar coefficients (log2Q ==
+// log2P <= 3); else log2Q > 0 splits a full decomposition (C = 32, 64) over
+// 2^log2Q waves with the table in LDS, and log2Q == 0 keeps one wave per group.
 hipError_t launch_ch(const double *table, int64_t table_elems, const CyclicQ &q,
-                     const SweepGeom &g, double alpha, int64_t steps, const double *in,
-                     double *out, hipStream_t stream);
+                     const SweepGeom &g, bool scalar, double alpha, int64_t steps,
+                     const double *in, double *out, hipStream_t stream);
+
+// Crank-Nicolson steps x <- A^{-1} (B x) with B a constant (2K+1)-point
+// stencil w (host array of 2K+1, copied into the kernel arguments), state on
+// chip (cn_tri.hip, cn_penta.hip); scalar / log2Q as for launch_ch.
+hipError_t launch_cn_tri(bool cyclic, const double *table, int64_t table_elems, const CyclicQ &q,
+                         const SweepGeom &g, bool scalar, const double *w, int64_t steps,
+                         const double *in, double *out, hipStream_t stream);
+hipError_t launch_cn_penta(bool cyclic, const double *table, int64_t table_elems,
+                           const CyclicQ &q, const SweepGeom &g, bool scalar, const double *w,
+                           int64_t steps, const double *in, double *out, hipStream_t stream);
 
 // The paper's thread-per-system mapping (Appendix A), kept as a measured
 // baseline design: forward intermediate written to and re-read from `x`.

@@ -1,0 +1,223 @@
+// stepper.h -- fused implicit time steps with the state kept on chip: every
+// step builds the right-hand side of a system from its current state (an
+// explicit stencil, possibly nonlinear) and solves the shared banded LHS,
+// `steps` times per launch, reading the batch once and writing it once.
+// The right-hand-side rule is a policy (Rhs); ch.hip (Cahn-Hilliard, Section
+// 5.1) and cn.hip (Crank-Nicolson diffusion and hyperdiffusion, Sections 3
+// and 4 benchmark problems) instantiate it.
+//
+// An Rhs policy provides
+//   static constexpr int R;   // rows of halo it reads on each side (1 or 2)
+//   template <int C, bool FULL>
+//   void operator()(double (&c)[C], const Halo &h, int j, bool last_chunk, int nrow) const;
+// which overwrites the chunk c (rows j*C .. j*C + C - 1 of the system) with
+// the right-hand side.  nrow = n - j*C (rows of the chunk that are real when
+// the decomposition is ragged); last_chunk: j == P - 1.
+#pragma once
+
+#include <type_traits>
+
+#include "sweep_core.h"
+
+namespace bb {
+namespace {
+
+// Values around a chunk: the R rows above it (l1 = row j*C - 1, l2 = row
+// j*C - 2; 0 for the first chunk) and below it (r1 = row j*C + C, r2 = row
+// j*C + C + 1; 0 past the last chunk), and rows 0, 1, n-2, n-1 of the system
+// (for periodic wrap-around).  Entries an Rhs with R = 1 does not read stay 0.
+struct Halo {
+    double l1, l2, r1, r2;
+    double e0, e1, en2, en1;
+};
+
+// One lane per chunk; the lanes of a system sit in one wave (shuffles) and
+// the coefficient table is staged in LDS.
+template <class Rhs, int K, bool CYC, int C, bool FULL>
+__global__ __launch_bounds__(kMaxBlockThreads) void step_kernel(const double *__restrict__ table,
+                                                             int64_t table_elems, CyclicQ cq,
+                                                             SweepGeom g, Rhs rhs, int64_t steps,
+                                                             const double *in, double *out)
+{
+    extern __shared__ double smem_d[];
+    stage_table(smem_d, table, table_elems);
+    __syncthreads();
+
+    const LaneGeom lg = lane_geom(g.log2P);
+    const int lane = threadIdx.x % kWave;
+    const int row0 = lg.j * C;
+    const bool has_left = lg.j > 0, has_right = lg.j < lg.P - 1;
+    const int left = has_left ? lane - lg.S : lane;
+    const int right = has_right ? lane + lg.S : lane;
+    const int exact = FULL || g.exact;
+    const GroupRange gr = group_range(g.groups);
+
+    for (int64_t blk = gr.first; blk < gr.end; blk += gr.stride) {
+        const int64_t grp = begin_block(gr, blk, g.lockstep);
+        if (grp >= g.groups) continue;
+        const int64_t k = grp * lg.S + lg.sl;
+        const bool kval = k < g.m;
+        double c[C];
+        load_chunk<double, C, FULL>(c, in, row0, kval ? k : g.m - 1, g.ld, g.n);
+
+        for (int64_t step = 0; step < steps; ++step) {
+            Halo h = {};
+            h.l1 = shfl(c[C - 1], left);
+            h.r1 = shfl(c[0], right);
+            if (!has_left) h.l1 = 0.0;
+            if (!has_right) h.r1 = 0.0;
+            if constexpr (Rhs::R == 2) {
+                h.l2 = shfl(c[C - 2], left);
+                h.r2 = shfl(c[1], right);
+                if (!has_left) h.l2 = 0.0;
+                if (!has_right) h.r2 = 0.0;
+            }
+            gather_ends<double, 2, C>(c, lg, g.n, exact, h.e0, h.e1, h.en2, h.en1);
+            rhs.template operator()<C, FULL>(c, h, lg.j, lg.j == lg.P - 1, opaque_v(g.n - row0));
+            __builtin_amdgcn_sched_barrier(0);
+            chunk_solve<double, K, C, CYC>(c, smem_d, lg, g.n, exact, cq);
+        }
+        if (kval) store_chunk<double, C, FULL>(c, out, row0, k, g.ld, g.n);
+    }
+}
+
+// The same steps with a system group split over the Q = 2^QL waves of a
+// workgroup (chunks tile n exactly): wave q holds chunks q*P/Q ..
+// (q+1)*P/Q - 1 of S = 64Q/P systems, and every chunk-boundary value goes
+// through the LDS exchange area: the first and last R rows of every chunk
+// for the stencil and the wrap-around, then the phases of chunk_solve.
+// SCALAR (one chunk per wave, P == Q): every lane of a wave needs the same
+// coefficient row at the same time, so the coefficients come from the global
+// table through the scalar cache (no LDS staging, no LDS reads).  Otherwise
+// the table is staged in LDS ahead of the exchange area.
+template <class Rhs, int K, bool CYC, int C, int QL, bool SCALAR>
+__global__ __launch_bounds__((kWave << QL) > kMaxBlockThreads ? (kWave << QL) : kMaxBlockThreads)
+void step_kernel_split(const double *__restrict__ table, int64_t table_elems, CyclicQ cq,
+                       SweepGeom g, Rhs rhs, int64_t steps, const double *in, double *out)
+{
+    using Src = typename std::conditional<SCALAR, FromScalar<double>, FromLds<double>>::type;
+    constexpr int R = Rhs::R;
+    extern __shared__ double smem_d[];
+    const int64_t tl = SCALAR ? 0 : table_elems;
+    double *xch = smem_d + tl;                              // chunk_solve phases
+    double *xd = xch + split_exchange_len(QL);              // [2R][P*S]: rows 0, C-1, 1, C-2
+    typename Src::ptr tab;
+    if constexpr (SCALAR) {
+        tab = (typename Src::ptr)table;
+    } else {
+        stage_table(smem_d, table, table_elems);
+        __syncthreads();
+        tab = smem_d;
+    }
+
+    LaneGeom lg = lane_geom(g.log2P, QL);
+    if constexpr (SCALAR) lg.j = __builtin_amdgcn_readfirstlane(lg.j);   // the wave's chunk
+    const int row0 = lg.j * C;
+    const bool has_left = lg.j > 0, has_right = lg.j < lg.P - 1;
+    const int PS = lg.P * lg.S;
+    const int me = lg.j * lg.S + lg.sl;
+    const int lft = (has_left ? lg.j - 1 : lg.j) * lg.S + lg.sl;
+    const int rgt = (has_right ? lg.j + 1 : lg.j) * lg.S + lg.sl;
+    const int first = lg.sl, last = (lg.P - 1) * lg.S + lg.sl;
+    const GroupRange gr = group_range(g.groups, QL);
+
+    for (int64_t blk = gr.first; blk < gr.end; blk += gr.stride) {
+        const int64_t grp = begin_block(gr, blk, g.lockstep);
+        if (grp >= g.groups) continue;
+        const int64_t k = grp * lg.S + lg.sl;
+        const bool kval = k < g.m;
+        double c[C];
+        load_chunk<double, C, true>(c, in, row0, kval ? k : g.m - 1, g.ld, g.n);
+
+        for (int64_t step = 0; step < steps; ++step) {
+            xd[me] = c[0];
+            xd[PS + me] = c[C - 1];
+            if constexpr (R == 2) {
+                xd[2 * PS + me] = c[1];
+                xd[3 * PS + me] = c[C - 2];
+            }
+            __syncthreads();
+            Halo h = {};
+            h.l1 = has_left ? xd[PS + lft] : 0.0;
+            h.r1 = has_right ? xd[rgt] : 0.0;
+            h.e0 = xd[first];
+            h.en1 = xd[PS + last];
+            if constexpr (R == 2) {
+                h.l2 = has_left ? xd[3 * PS + lft] : 0.0;
+                h.r2 = has_right ? xd[2 * PS + rgt] : 0.0;
+                h.e1 = xd[2 * PS + first];
+                h.en2 = xd[3 * PS + last];
+            }
+            rhs.template operator()<C, true>(c, h, lg.j, !has_right, C);
+            __builtin_amdgcn_sched_barrier(0);
+            chunk_solve<double, K, C, CYC, true, Src>(c, tab, lg, g.n, 1, cq, xch);
+        }
+        if (kval) store_chunk<double, C, true>(c, out, row0, k, g.ld, g.n);
+    }
+}
+
+// LDS bytes of the split kernel beyond the staged table: the chunk_solve
+// exchange plus 2R rows per (chunk, slot).
+constexpr size_t split_step_lds(int QL, int R)
+{
+    return (size_t)(split_exchange_len(QL) + ((2LL * R * kWave) << QL)) * sizeof(double);
+}
+
+// Launch `steps` fused steps.  g.log2Q > 0 selects the split kernel (full
+// decomposition, log2Q <= 3), with the coefficients through the scalar cache
+// when `scalar` (then log2Q == log2P and C == 64); `scalar` with
+// g.log2Q == g.log2P == 0 runs one-chunk systems the same way.  Otherwise the
+// LDS kernel with one wave per group.
+template <class Rhs, int K, bool CYC>
+hipError_t launch_stepper(const double *table, int64_t table_elems, const CyclicQ &q,
+                          const SweepGeom &g, bool scalar, const Rhs &rhs, int64_t steps,
+                          const double *in, double *out, hipStream_t s)
+{
+    if (scalar) {
+        if (g.C != 64 || g.log2Q != g.log2P || g.log2Q > 3 || !is_full(g)) return hipErrorInvalidValue;
+        const size_t xl = split_step_lds(g.log2Q, Rhs::R);
+        switch (g.log2Q) {
+        case 0: return launch_grid_split(step_kernel_split<Rhs, K, CYC, 64, 0, true>, xl, g.groups, 1, s, table, table_elems, q, g, rhs, steps, in, out);
+        case 1: return launch_grid_split(step_kernel_split<Rhs, K, CYC, 64, 1, true>, xl, g.groups, 2, s, table, table_elems, q, g, rhs, steps, in, out);
+        case 2: return launch_grid_split(step_kernel_split<Rhs, K, CYC, 64, 2, true>, xl, g.groups, 4, s, table, table_elems, q, g, rhs, steps, in, out);
+        default: return launch_grid_split(step_kernel_split<Rhs, K, CYC, 64, 3, true>, xl, g.groups, 8, s, table, table_elems, q, g, rhs, steps, in, out);
+        }
+    }
+    if (g.log2Q > 0) {
+        // LDS table, group split over 2^log2Q waves: 32- and 64-row chunks
+        if (g.log2Q > 3 || g.log2Q > g.log2P || !is_full(g)) return hipErrorInvalidValue;
+        const size_t xl = (size_t)table_elems * sizeof(double) + split_step_lds(g.log2Q, Rhs::R);
+#define BB_SPLIT(CC)                                                                                     \
+        case CC:                                                                                         \
+            switch (g.log2Q) {                                                                           \
+            case 1: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 1, false>, xl, g.groups, 2, s, table, table_elems, q, g, rhs, steps, in, out); \
+            case 2: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 2, false>, xl, g.groups, 4, s, table, table_elems, q, g, rhs, steps, in, out); \
+            default: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 3, false>, xl, g.groups, 8, s, table, table_elems, q, g, rhs, steps, in, out); \
+            }
+        switch (g.C) {
+            BB_SPLIT(32)
+            BB_SPLIT(64)
+        default: return hipErrorInvalidValue;
+        }
+#undef BB_SPLIT
+    }
+    const size_t lds = (size_t)table_elems * sizeof(double);
+#define BB_STEP(CC)                                                                            \
+    case CC:                                                                                   \
+        return is_full(g) ? launch_grid(step_kernel<Rhs, K, CYC, CC, true>, lds, g.groups, s,   \
+                                        table, table_elems, q, g, rhs, steps, in, out)          \
+                          : launch_grid(step_kernel<Rhs, K, CYC, CC, false>, lds, g.groups, s,  \
+                                        table, table_elems, q, g, rhs, steps, in, out);
+    switch (g.C) {
+        BB_STEP(4)
+        BB_STEP(8)
+        BB_STEP(16)
+        BB_STEP(32)
+        BB_STEP(64)
+    default: return hipErrorInvalidValue;
+    }
+#undef BB_STEP
+}
+
+}  // namespace
+}  // namespace bb

@@ -115,4 +115,13 @@ WORKLOADS = {
                                         steps=5000, seed=SEED_BASE + 3),
     "adjoint_diffusion_n1024_m65536": dict(kind="adjoint", n=1024, m=1 << 16, r=0.5, steps=100,
                                            checkpoint=10, seed=SEED_BASE + 4),
+    # Crank-Nicolson time stepping on the grid of the paper's benchmark tables
+    # (1000 steps; n = 64, 256, 1024; m = 2^6, 2^12, 2^16); the step size is
+    # not printed, sigma = 1 is this build's choice (it does not change the work)
+    "cn_diffusion_grid": dict(kind="cn", problem="diffusion", ns=(64, 256, 1024),
+                              ms=(1 << 6, 1 << 12, 1 << 16), sigma=1.0, steps=1000,
+                              seed=SEED_BASE + 5),
+    "cn_hyperdiffusion_grid": dict(kind="cn", problem="hyperdiffusion", ns=(64, 256, 1024),
+                                   ms=(1 << 6, 1 << 12, 1 << 16), sigma=1.0, steps=1000,
+                                   seed=SEED_BASE + 6),
 }

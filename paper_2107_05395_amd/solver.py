@@ -173,6 +173,25 @@ class Factor:
                                    int(steps), _stream_ptr(c)))
         return out
 
+    def cn_step(self, c: torch.Tensor, w, steps: int = 1,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+        """`steps` Crank-Nicolson steps A c' = B c with B the constant stencil w
+        (3 weights for a tri factor, 5 for a penta one); periodic when the
+        factor is cyclic.  out may be c itself (in place)."""
+        m, ld = _batch_view(c, self.n, torch.float64, "c")
+        if out is None:
+            out = torch.empty_like(c)
+        if _batch_view(out, self.n, torch.float64, "out") != (m, ld):
+            raise ValueError("out must match c in shape and strides")
+        if len(w) != self.nbands:
+            raise ValueError("need %d stencil weights" % self.nbands)
+        wv = (ctypes.c_double * len(w))(*(float(x) for x in w))
+        with torch.cuda.device(c.device):
+            check(lib().bb_cn_step(self._handle, ctypes.cast(wv, ctypes.c_void_p),
+                                   ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                   m, ld, int(steps), _stream_ptr(c)))
+        return out
+
 
 def mse_loss_grad(u: torch.Tensor, target: torch.Tensor, grad: torch.Tensor | None = None):
     """(loss as a 0-d device tensor, dloss/du) for loss = mean((u - target)^2)."""

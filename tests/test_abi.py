@@ -34,7 +34,7 @@ def test_header_declares_expected_entry_points():
     for must in ["bb_factor_shared_tri", "bb_factor_shared_penta", "bb_factor_shared_tri_cyclic",
                  "bb_factor_shared_penta_cyclic", "bb_solve_batch_tri", "bb_solve_batch_penta",
                  "bb_solve_batch_tri_adjoint", "bb_solve_batch_penta_adjoint", "bb_band_grad",
-                 "bb_ch_step", "bb_status_string", "bb_last_error_message"]:
+                 "bb_ch_step", "bb_cn_step", "bb_status_string", "bb_last_error_message"]:
         assert must in names
 
 
@@ -124,6 +124,13 @@ def test_solve_argument_checks_need_no_gpu(L):
     assert L.bb_solve_batch_tri(hp, fake, fake, 4, 4, 0, None) == -1
     assert L.bb_solve_batch_tri_cyclic(h, fake, fake, 4, 4, 0, None) == -1  # not cyclic
     assert L.bb_ch_step(h, fake, fake, 4, 4, 1.0, 1, None) == -1           # not cyclic penta
+    w3 = (ctypes.c_double * 3)(0.5, 0.0, 0.5)
+    bad = (ctypes.c_double * 3)(0.5, float("nan"), 0.5)
+    assert L.bb_cn_step(h, None, fake, fake, 4, 4, 1, None) == -1           # no stencil
+    assert L.bb_cn_step(h, bad, fake, fake, 4, 4, 1, None) == -1            # weight not finite
+    assert L.bb_cn_step(h, w3, fake, fake, 4, 4, 0, None) == -1             # steps < 1
+    assert L.bb_cn_step(h, w3, fake, fake, 8, 4, 1, None) == -1             # ld < m
+    assert L.bb_cn_step(h, w3, None, None, 0, 1, 1, None) == 0              # m = 0: nothing to do
     assert L.bb_solve_batch_tri(h, None, None, 0, 1, 0, None) == 0         # m = 0: nothing to do
     assert L.bb_band_grad(h, fake, fake, 4, 4, None, None, 0, None) == -1
     assert L.bb_solve_batch_tri_thread_per_system(hp, fake, fake, 4, 4, None) == -1

@@ -1,0 +1,167 @@
+"""GPU parity of the fused Crank-Nicolson steps (Section 3 and Section 4
+benchmark problems: periodic diffusion and hyperdiffusion, and their
+non-periodic forms) against the FP64 oracle, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2107_05395_amd import inputs
+from tests.gpu_util import dev, host, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib_loaded():
+    from paper_2107_05395_amd import solver  # noqa: F401
+    oracle.build()
+
+
+def _problem(kind, n, sigma):
+    return (inputs.cn_diffusion_problem(n, sigma) if kind == "tri" else
+            inputs.cn_hyperdiffusion_problem(n, sigma))
+
+
+def _factor(kind, bands, cyclic):
+    from paper_2107_05395_amd import Factor
+    return Factor.tri(*bands, cyclic=cyclic) if kind == "tri" else Factor.penta(*bands, cyclic=cyclic)
+
+
+# n: 64 (one chunk per system), 256 and 512 (one chunk per wave, 4 and 8
+# waves), 1024 (16 chunks, LDS kernel), ragged 100 / 1000 / 333, tiny 5 / 7
+CASES = [(kind, cyc, n) for kind in ("tri", "penta") for cyc in (True, False)
+         for n in (64, 256, 512, 1024, 100, 333, 1000, 7)] + [("penta", True, 5), ("tri", True, 3)]
+
+
+@pytest.mark.parametrize("kind,cyclic,n", CASES)
+def test_cn_steps_match_oracle(kind, cyclic, n):
+    m, steps = 300, 6   # 300 systems: several groups and a ragged last group
+    say("cn", kind, "cyclic" if cyclic else "open", "n", n, "m", m)
+    bands, w = _problem(kind, n, 0.7)
+    if not cyclic:   # a non-symmetric stencil and row-dependent bands as well
+        bands = (inputs.random_dominant_tri(n, n) if kind == "tri" else inputs.random_dominant_penta(n, n))
+        w = tuple(inputs.rng(n + 1).uniform(-1, 1, len(w)))
+    f = _factor(kind, bands, cyclic)
+    c0 = inputs.uniform_batch(n, m, seed=40 + n)
+    ref = oracle.cn_step(bands, w, c0, steps=steps, cyclic=cyclic)
+    out = host(f.cn_step(dev(c0), w, steps=steps))
+    err = rel_err(out, ref)
+    say("  rel err", err)
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["tri", "penta"])
+@pytest.mark.parametrize("chunk", ["4", "8", "16", "32"])
+def test_cn_chunk_sizes_match_oracle(kind, chunk, monkeypatch):
+    """Every chunk size the stepper is built for, full (n = 256) and ragged
+    (n = 250) decompositions, against the oracle."""
+    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", chunk)
+    for n in (256, 250):
+        bands, w = _problem(kind, n, 1.3)
+        f = _factor(kind, bands, True)
+        c0 = inputs.uniform_batch(n, 130, seed=50 + n)
+        ref = oracle.cn_step(bands, w, c0, steps=5)
+        assert rel_err(host(f.cn_step(dev(c0), w, steps=5)), ref) < 1e-12, (n, chunk)
+
+
+@pytest.mark.parametrize("kind,n", [("tri", 64), ("tri", 256), ("tri", 512), ("tri", 1024),
+                                    ("tri", 2048), ("penta", 64), ("penta", 256), ("penta", 512),
+                                    ("penta", 1024)])
+def test_cn_kernel_variants_agree_bitwise(kind, n, monkeypatch):
+    """One chunk per wave with scalar coefficients, a group split over several
+    waves with the table in LDS, and one wave per group with the table in LDS
+    do the same arithmetic in the same order: bitwise equal results, at a
+    batch large enough for 64-row chunks (2^16 + 37 systems, ragged last
+    group); sampled systems against the oracle."""
+    m, steps = (1 << 16) + 37, 3
+    say("cn variants", kind, n)
+    bands, w = _problem(kind, n, 0.9)
+    f = _factor(kind, bands, True)
+    c0h = inputs.uniform_batch(n, m, seed=60 + n)
+    c0 = dev(c0h)
+    a = host(f.cn_step(c0, w, steps=steps))
+    cols = np.r_[np.arange(0, m, 997), m - 5:m]
+    ref = oracle.cn_step(bands, w, np.ascontiguousarray(c0h[:, cols]), steps=steps)
+    assert rel_err(a[:, cols], ref) < 1e-12
+    monkeypatch.setenv("BANDBATCH_CH_UNIFORM", "0")
+    b = host(f.cn_step(c0, w, steps=steps))
+    assert np.array_equal(a, b)
+    monkeypatch.setenv("BANDBATCH_WAVES_PER_SYSTEM", "1")
+    b = host(f.cn_step(c0, w, steps=steps))
+    assert np.array_equal(a, b)
+    for q in ("2", "4", "8"):
+        if (1 << {"2": 1, "4": 2, "8": 3}[q]) <= n // 64:
+            monkeypatch.setenv("BANDBATCH_WAVES_PER_SYSTEM", q)
+            assert np.array_equal(a, host(f.cn_step(c0, w, steps=steps))), q
+
+
+@pytest.mark.parametrize("kind", ["tri", "penta"])
+def test_cn_split_groups_with_32_row_chunks(kind, monkeypatch):
+    """32-row chunks split over 2, 4 and 8 waves (LDS table) equal one wave per
+    group, bitwise, and match the oracle."""
+    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", "32")
+    n, m = 1024, 5000
+    bands, w = _problem(kind, n, 1.1)
+    f = _factor(kind, bands, True)
+    c0h = inputs.uniform_batch(n, m, seed=65)
+    c0 = dev(c0h)
+    a = host(f.cn_step(c0, w, steps=4))
+    assert rel_err(a, oracle.cn_step(bands, w, c0h, steps=4)) < 1e-12
+    for q in ("1", "2", "4", "8"):
+        monkeypatch.setenv("BANDBATCH_WAVES_PER_SYSTEM", q)
+        assert np.array_equal(a, host(f.cn_step(c0, w, steps=4))), q
+
+
+@pytest.mark.parametrize("kind", ["tri", "penta"])
+def test_cn_fused_steps_equal_single_steps_and_in_place(kind):
+    """k steps in one launch equal k launches of one step (the state passes
+    through memory unchanged in double), and in-place calls equal
+    out-of-place ones."""
+    n, m = 512, 777
+    bands, w = _problem(kind, n, 2.0)
+    f = _factor(kind, bands, True)
+    c0 = dev(inputs.uniform_batch(n, m, seed=70))
+    fused = host(f.cn_step(c0, w, steps=8))
+    t = c0.clone()
+    for _ in range(8):
+        t = f.cn_step(t, w)
+    assert np.array_equal(host(t), fused)
+    t = c0.clone()
+    f.cn_step(t, w, steps=8, out=t)
+    assert np.array_equal(host(t), fused)
+
+
+@pytest.mark.parametrize("kind", ["tri", "penta"])
+def test_cn_fourier_modes_and_mean_at_size(kind):
+    """A Fourier mode of wavenumber k is multiplied by the exact factor
+    G_k = (1 - s L_k)/(1 + s L_k) per step, and the mean is conserved, at a
+    workload size of the paper's grid (n = 1024, 2^12 systems, 100 steps)."""
+    n, m, steps, s = 1024, 1 << 12, 100, 0.6
+    bands, w = _problem(kind, n, s)
+    f = _factor(kind, bands, True)
+    i = np.arange(n)
+    ks = np.arange(m) % (n // 2 + 1)
+    c0 = np.cos(2 * math.pi * np.outer(i, ks) / n)
+    out = host(f.cn_step(dev(c0), w, steps=steps))
+    lam = 2 - 2 * np.cos(2 * math.pi * ks / n)
+    L = lam if kind == "tri" else lam * lam
+    G = (1 - s * L) / (1 + s * L)
+    err = np.max(np.abs(out - c0 * G ** steps))
+    say("cn", kind, "mode error", err)
+    assert err < 1e-12 * steps
+    # the sum is exact in exact arithmetic; each step may move it by a few
+    # n eps |f|, with |f| <= sum |w| max |c| and max |c| <= 1 here
+    rnd = inputs.uniform_batch(n, 256, seed=71)
+    out = host(f.cn_step(dev(rnd), w, steps=steps))
+    bound = 8 * steps * n * np.finfo(float).eps * float(np.sum(np.abs(w)))
+    assert np.max(np.abs(out.sum(axis=0) - rnd.sum(axis=0))) < bound
+
+
+def test_cn_rejects_wrong_stencil_length():
+    bands, w = _problem("tri", 64, 0.5)
+    f = _factor("tri", bands, True)
+    with pytest.raises(ValueError):
+        f.cn_step(dev(inputs.uniform_batch(64, 4, seed=1)), (1, 2, 3, 4, 5))

@@ -167,6 +167,7 @@ def test_ch_uniform_chunks_match_lds_kernel(n, monkeypatch):
     """With one 64-row chunk per wave the CH kernel reads its coefficients
     through the scalar cache; the arithmetic is the same as the LDS kernel's,
     so the two agree bitwise, and both match the oracle."""
+    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", "64")   # a small batch would take shorter chunks
     f, sigma, alpha = _ch(n)
     m, steps = 1000, 7
     c0 = inputs.uniform_batch(n, m, seed=23 + n, lo=-0.1, hi=0.1)

@@ -1,0 +1,60 @@
+"""The C-ABI entry points enqueue kernels only (no allocation, no memset, no
+host synchronisation once a call's coefficient table exists), so a sequence
+of solves and fused steps can be captured in a HIP graph and replayed.  Each
+replay must reproduce the eager results bitwise, with eager work and
+synchronisations between the replays."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2107_05395_amd import inputs
+from tests.gpu_util import dev, host, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_solves_and_steps_replay_in_a_graph():
+    from paper_2107_05395_amd import Factor
+    n, m = 512, 3000
+    tri = Factor.tri(*inputs.diffusion_tri_bands(n, 1.0))
+    pb, pw = inputs.cn_hyperdiffusion_problem(n, 0.8)
+    penta = Factor.penta(*pb, cyclic=True)
+    sigma, alpha = inputs.ch_parameters(n=n)
+    ch = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
+    rhs_h = inputs.uniform_batch(n, m, seed=81)
+    rhs = dev(rhs_h)
+    c0 = dev(inputs.uniform_batch(n, m, seed=82, lo=-0.1, hi=0.1))
+    outs = [torch.empty_like(rhs) for _ in range(5)]
+
+    def work():
+        tri.solve(rhs, out=outs[0])
+        tri.solve(rhs, out=outs[1], precision="f32r")
+        penta.solve(rhs, out=outs[2])
+        penta.cn_step(rhs, pw, steps=5, out=outs[3])
+        ch.ch_step(c0, alpha, steps=3, out=outs[4])
+
+    work()                                     # eager: builds and uploads every table
+    torch.cuda.synchronize()
+    eager = [host(o) for o in outs]
+    assert rel_err(eager[0], oracle.tri_solve(*inputs.diffusion_tri_bands(n, 1.0), rhs_h)) < 1e-12
+    assert rel_err(eager[3], oracle.cn_step(pb, pw, rhs_h, steps=5)) < 1e-12
+
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            work()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        tri.solve(c0, out=torch.empty_like(c0))   # unrelated eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, o in enumerate(outs):
+            assert np.array_equal(host(o), eager[i]), (rep, i)
+        say("graph replay", rep, "ok")

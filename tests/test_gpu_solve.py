@@ -209,16 +209,15 @@ def test_factor_on_the_oracle_matrices_of_every_config():
                                            ("tri", 1000, True), ("tri", 1500, False),
                                            ("penta", 600, True), ("penta", 1000, False),
                                            ("tri", 1536, True)])
-@pytest.mark.parametrize("rows", [None, 128, 32])
+@pytest.mark.parametrize("rows", [64, 128, 32])
 def test_split_groups_match_single_wave_groups(kind, n, cyclic, rows, monkeypatch):
     """A system group spread over 2, 4 or 8 waves (boundary states exchanged
     through LDS) computes exactly what a one-wave group computes: same
     operations in the same order, so the results are bitwise equal.  Solve,
-    adjoint, plain FP32 and FP32 + refinement; the default rows per lane, 128
-    rows and 32 rows (refinement groups of up to 8 waves; a width a kernel
-    cannot run falls back to the automatic one)."""
-    if rows:
-        monkeypatch.setenv("BANDBATCH_MAX_CHUNK", str(rows))
+    adjoint, plain FP32 and FP32 + refinement; 64 rows per lane (the default
+    for large batches), 128 rows and 32 rows (refinement groups of up to 8
+    waves; a width a kernel cannot run falls back to the automatic one)."""
+    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", str(rows))
     f, bands = make(kind, n, seed=17 * n, cyclic=cyclic)
     m = 1000                                   # not a multiple of any group width
     rhs = inputs.uniform_batch(n, m, seed=6000 + n)
@@ -243,6 +242,22 @@ def test_split_groups_match_single_wave_groups(kind, n, cyclic, rows, monkeypatc
     assert all(np.array_equal(got[1], got[q]) for q in (2, 4, 8))
     assert np.array_equal(got[("r", 1)], got[("r", 2)])
     assert np.array_equal(got[("r", 1)], got[("r", 4)])
+
+
+@pytest.mark.parametrize("n,m,rows", [(256, 1024, 32), (64, 4096, 16), (1024, 64, 32),
+                                      (2048, 256, 64)])
+def test_small_batches_take_short_chunks(n, m, rows, monkeypatch):
+    """With fewer than 2^16 lanes of 64-row chunks the solve takes the
+    latency rule's chunk (the power of two >= 2 sqrt(n), at most 32, at most
+    32 chunks per system): bitwise what forcing that chunk gives, and within
+    the FP64 tolerance of the oracle."""
+    f, bands = make("tri", n, seed=n + m)
+    rhs = inputs.uniform_batch(n, m, seed=n + m + 1)
+    t = dev(rhs)
+    auto = host(f.solve(t))
+    assert rel_err(auto, oracle_solve("tri", bands, rhs, False)) < F64_TOL
+    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", str(rows))
+    assert np.array_equal(auto, host(f.solve(t)))
 
 
 def test_workgroup_shape_and_lockstep_do_not_change_results(monkeypatch):
