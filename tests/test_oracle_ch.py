@@ -66,3 +66,48 @@ def test_ch_step_leaves_its_input_alone(oracle):
     keep = c.copy()
     oracle.ch_step(c, sigma, alpha, steps=3)
     assert np.array_equal(c, keep)
+
+
+# ---------------------------------------------------------------- coarsening statistics
+
+def test_domain_size_of_constant_states(oracle):
+    """<C^2> = c^2 for a constant state: l = 1 / (1 - c^2) (up to the
+    rounding of the 64-term sum, ~n eps, amplified by c^2 / (1 - c^2))."""
+    vals = np.array([0.0, 0.3, -0.5, 0.9])
+    c = np.tile(vals, (64, 1))
+    assert np.allclose(oracle.ch_domain_size(c), 1.0 / (1.0 - vals ** 2), rtol=1e-13, atol=0)
+
+
+def test_domain_size_of_cosine_modes(oracle):
+    """A grid cosine a cos(2 pi k i / n), 0 < k < n/2, has mean square a^2 / 2
+    exactly (discrete orthogonality); k = n/2 gives a^2."""
+    n = 96
+    i = np.arange(n)
+    cols, ref = [], []
+    for k, a in ((1, 0.4), (7, 0.9), (47, 0.2), (48, 0.5)):
+        cols.append(a * np.cos(2 * math.pi * k * i / n))
+        ref.append(1.0 / (1.0 - (a * a if k == n // 2 else a * a / 2)))
+    assert np.allclose(oracle.ch_domain_size(np.stack(cols, axis=1)), ref, rtol=1e-14, atol=0)
+
+
+def test_domain_size_matches_parseval(oracle):
+    """<C^2> from the FFT coefficients (Parseval) for random states."""
+    n, m = 128, 9
+    c = inputs.uniform_batch(n, m, seed=91, lo=-0.9, hi=0.9)
+    ms = np.sum(np.abs(np.fft.fft(c, axis=0)) ** 2, axis=0) / n ** 2
+    assert np.allclose(oracle.ch_domain_size(c), 1.0 / (1.0 - ms), rtol=1e-13, atol=0)
+
+
+def test_coarsening_samples_follow_the_steps(oracle):
+    """lbar after every `every` steps is the mean of l over the runs of the
+    state reached by that many single steps."""
+    n, m = 32, 5
+    sigma, alpha = inputs.ch_parameters(n=n)
+    c0 = inputs.uniform_batch(n, m, seed=92, lo=-0.1, hi=0.1)
+    lbar, cT = oracle.ch_coarsening(c0, sigma, alpha, steps=7, every=3)
+    assert lbar.shape == (2,)
+    c = c0
+    for s, want in ((3, lbar[0]), (3, lbar[1])):
+        c = oracle.ch_step(c, sigma, alpha, steps=s)
+        assert abs(np.mean(oracle.ch_domain_size(c)) - want) < 1e-15 * want
+    assert np.array_equal(cT, oracle.ch_step(c, sigma, alpha, steps=1))
