@@ -34,26 +34,32 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ("sweep_core.h", "sweep_kernel.h", "sweep.hip", "sweep_f32.hip", "refine_kernel.h",
                   "refine.hip", "refine_f32rhs.hip", "stepper.h", "ch.hip", "cn_stencil.h",
                   "cn_tri.hip", "cn_penta.hip", "internal.h")
+# the device sources behind each kernel whose HBM traffic is recorded
+KERNEL_FAMILIES = {
+    "sweep": ("sweep_core.h", "sweep_kernel.h", "sweep.hip", "internal.h"),
+    "refine": ("sweep_core.h", "refine_kernel.h", "refine.hip", "internal.h"),
+    "stepper": ("sweep_core.h", "stepper.h", "cn_stencil.h", "cn_tri.hip", "ch.hip", "internal.h"),
+}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(family: str | None = None) -> str:
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in (KERNEL_FAMILIES[family] if family else KERNEL_SOURCES):
         with open(os.path.join(ROOT, "paper_2107_05395_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, precision: str):
+def measured_traffic(workload: str, precision: str, family: str):
     """HBM bytes per launch from the committed rocprofv3 counter runs, or None
-    when they were taken on a different kernel source."""
+    when they were taken on a different source of that kernel family."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
     entry = rec.get("%s/%s" % (workload, precision))
-    if not entry or entry.get("source_hash") != kernel_source_hash():
+    if not entry or entry.get("source_hash") != kernel_source_hash(family):
         return None
     return entry.get("bytes_per_launch")
 
@@ -141,7 +147,7 @@ def bench_tri(args, torch):
     k = args.steps
     t64 = results["f64"]["seconds"]
     per_launch = t64 / k
-    traffic = measured_traffic(args.workload, "f64")
+    traffic = measured_traffic(args.workload, "f64", "sweep")
     line = {
         "metric": "systems solved/s", "value": m * k / t64, "unit": "systems/s",
         "n_gpus": 1, "steps": k, "warmup": args.warmup, "ms_per_step": 1e3 * per_launch,
@@ -217,7 +223,7 @@ def bench_penta(args, torch):
                    "hbm_gbs_algorithmic": 12.0 * n * m * k / out["f32rhs"][0] / 1e9},
         "roofline": {"bound": "hbm", "achieved": algo_bytes / per / 1e9, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": algo_bytes / per / 1e9 / PEAK_HBM_GBS,
-                     "traffic": measured_traffic(args.workload, "f64")},
+                     "traffic": measured_traffic(args.workload, "f64", "sweep")},
     }
 
 
@@ -361,10 +367,100 @@ def bench_cn(args, torch):
                              % CN_FLOPS_ROW_STEP[prob]},
         "per_step_roofline": {"bound": "hbm", "achieved": 16.0 * n * m * T / tp / 1e9,
                               "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                              "frac": 16.0 * n * m * T / tp / 1e9 / PEAK_HBM_GBS},
+                              "frac": 16.0 * n * m * T / tp / 1e9 / PEAK_HBM_GBS,
+                              "traffic": measured_traffic(args.workload,
+                                                          "per_step_n%d_m%d" % (n, m), "stepper")},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_cn(bands, w, n, seed + 1, args.cpu_seconds)
+    return line
+
+
+def bench_ch_coarsening(args, torch):
+    """The coarsening campaign: m runs of the Cahn-Hilliard scheme to t = T
+    with the ensemble-mean typical domain size lbar(t) = mean 1/(1 - <C^2>)
+    taken at every step inside the stepping kernel, then a straight-line fit
+    of lbar against log t (the paper fits lbar against log t and reports the
+    correlation coefficient)."""
+    from paper_2107_05395_amd import Factor, inputs
+    import oracle
+    spec = dict(inputs.WORKLOADS[args.workload])
+    n, L, m, gamma, T, seed = (spec[k] for k in ("n", "length", "m", "gamma", "T", "seed"))
+    dx = L / n
+    dt = 0.1 * dx
+    steps = int(round(T / dt))
+    sigma, alpha = inputs.ch_parameters(n=n, length=L, gamma=gamma, dt=dt)
+    f = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
+    f.upload()
+    # parity first: 256 runs, 20 steps, lbar at every step against the oracle
+    c_small = inputs.uniform_batch(n, 256, seed=seed + 1, lo=-0.1, hi=0.1)
+    _, lb_small = f.ch_step_stats(torch.from_numpy(c_small).cuda(), alpha, steps=20, every=1)
+    ref_small, _ = oracle.ch_coarsening(c_small, sigma, alpha, 20, 1)
+    err = float(np.max(np.abs(lb_small.cpu().numpy() - ref_small) / ref_small))
+
+    c = torch.from_numpy(inputs.uniform_batch(n, m, seed=seed, lo=-0.1, hi=0.1)).cuda()
+    nxt = torch.empty_like(c)
+    f.ch_step_stats(c, alpha, steps=4, every=1, out=nxt)          # warm-up (tables, code)
+    chunk = 2000
+    lbars = []
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        nxt, lb = f.ch_step_stats(c, alpha, steps=k, every=1, out=nxt)
+        lbars.append(lb)
+        c, nxt = nxt, c
+        done += k
+    stop.record()
+    torch.cuda.synchronize()
+    secs = start.elapsed_time(stop) / 1e3
+    lbar = torch.cat(lbars).cpu().numpy()
+    t = dt * np.arange(1, steps + 1)
+
+    def fit(t0):
+        # samples evenly spaced in log t between t0 and T
+        idx = np.unique(np.searchsorted(t, np.exp(np.linspace(np.log(t0), np.log(t[-1]), 400))))
+        idx = idx[idx < steps]
+        x, y = np.log(t[idx]), lbar[idx]
+        slope, icpt = np.polyfit(x, y, 1)
+        return {"t_from": t0, "r": float(np.corrcoef(x, y)[0, 1]), "slope": float(slope),
+                "intercept": float(icpt), "points": int(len(idx))}
+
+    flops = 21.0 * n * m * steps
+    line = {
+        "metric": "system-steps/s", "value": m * steps / secs, "unit": "system-steps/s",
+        "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": 1e3 * secs / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded uniform[-0.1,0.1) initial states)",
+        "config": {"workload": args.workload, "n": n, "L": L, "m": m, "gamma": gamma, "dt": dt,
+                   "T": steps * dt, "statistic_every": 1, "steps_per_launch": chunk},
+        "lbar_rel_err_vs_oracle_256_runs_20_steps": err,
+        "coarsening": {"fit_log_t": [fit(1.0), fit(10.0)],
+                       "lbar_at": {"%g" % tt: float(lbar[min(steps - 1, int(round(tt / dt)) - 1)])
+                                   for tt in (0.1, 1.0, 10.0, 50.0, 100.0)},
+                       "paper_r": 0.9989 if abs(L - 2 * np.pi) < 1e-9 else 0.9996},
+        "roofline": {"bound": "alu", "achieved": flops / secs / 1e12, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": flops / secs / 1e12 / PEAK_FP64_TFLOPS,
+                     "traffic": None,
+                     "note": "algorithmic FP64 operations of the scheme, 21 per row and step "
+                             "(the statistic adds 2 per row at each sample)"},
+    }
+    if not args.no_cpu_baseline:
+        m_s = 1 << 12
+        cs = inputs.uniform_batch(n, m_s, seed=seed + 2, lo=-0.1, hi=0.1)
+        done_s, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            cs = oracle.ch_step(cs, sigma, alpha, steps=10)
+            oracle.ch_domain_size(cs)
+            done_s += 10
+        el = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": done_s * m_s / el, "unit": "system-steps/s",
+                                "cores": oracle.num_threads(), "kind": "oracle",
+                                "sample": "%d steps of %d runs (n=%d) with oracle.ch_step, "
+                                          "domain sizes every 10 steps, %.1f s"
+                                          % (done_s, m_s, n, el)}
     return line
 
 
@@ -419,8 +515,9 @@ def probe(torch):
     """One dispatch of each kernel of interest, for rocprofv3 counter runs:
     a plain copy of known size (4 GiB read + 4 GiB written), the FP64 and
     FP32+refine sweeps and the thread-per-system design on the bench workload,
-    the FP64 pentadiagonal sweep on the hyperdiffusion workload, and one
-    launch of 10 fused Cahn-Hilliard steps on the n=256, m=2^20 ensemble."""
+    the FP64 pentadiagonal sweep on the hyperdiffusion workload, one launch
+    of 10 fused Cahn-Hilliard steps on the n=256, m=2^20 ensemble, and one
+    Crank-Nicolson diffusion step (n=1024, m=2^16, periodic)."""
     from paper_2107_05395_amd import Factor, inputs
     n, m = 512, 1 << 20
     rhs = torch.rand(n, m, dtype=torch.float64, device="cuda")
@@ -446,6 +543,13 @@ def probe(torch):
     c = torch.rand(n, m, dtype=torch.float64, device="cuda").mul_(0.2).sub_(0.1)
     h = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
     h.ch_step(c, alpha, steps=10)
+    torch.cuda.synchronize()
+    del c
+    n, m = 1024, 1 << 16
+    bands, w = inputs.cn_diffusion_problem(n, 1.0)
+    cn = Factor.tri(*bands, cyclic=True)
+    c = torch.rand(n, m, dtype=torch.float64, device="cuda")
+    cn.cn_step(c, w, steps=1, out=torch.empty_like(c))
     torch.cuda.synchronize()
     print(json.dumps({"probe": "done"}), flush=True)
 
@@ -487,6 +591,8 @@ def main():
         line = bench_adjoint(args, torch)
     elif kind == "cn":
         line = bench_cn(args, torch)
+    elif kind == "ch_coarsening":
+        line = bench_ch_coarsening(args, torch)
     else:
         sys.exit("workload %s is not a bench workload" % args.workload)
     line["device"] = torch.cuda.get_device_name(0)

@@ -179,6 +179,26 @@ bb_status bb_band_grad(bb_factor f, const double *lam, const double *x, int64_t 
 bb_status bb_ch_step(bb_factor f, const double *c_in, double *c_out, int64_t m, int64_t ld,
                      double alpha, int64_t steps, void *stream);
 
+/* Cahn-Hilliard steps as bb_ch_step plus the coarsening statistic of the
+ * ensemble (Section 5, batched 1D scaling): the typical domain size of run k,
+ * l_k = 1 / (1 - <C^2>_k) with <C^2>_k = (1/n) sum_i C[i,k]^2, averaged over
+ * the m runs, after every `every` steps, computed inside the stepping kernel
+ * from the state on chip:
+ *     lbar[s] = (1/m) sum_k l_k  after (s + 1) * every steps,  s < steps / every.
+ * lbar: device, steps / every doubles (nothing is written when that is 0).
+ * workspace: device scratch of at least bb_ch_stats_workspace_bytes(f, m,
+ * steps / every) bytes, caller-owned: one row of partial sums per group of
+ * runs the kernel handles together (at most m rows, 8 bytes per sample; m/64
+ * rows for 64-row chunks tiling n into at most 8).  The sums run in a fixed
+ * order that does not depend on the device: lbar is bitwise reproducible,
+ * and c_out is bitwise what bb_ch_step writes.
+ * Errors: as bb_ch_step; BB_ERR_ARG also for every < 1, lbar NULL, or a
+ * smaller workspace. */
+size_t bb_ch_stats_workspace_bytes(bb_factor f, int64_t m, int64_t samples);
+bb_status bb_ch_step_stats(bb_factor f, const double *c_in, double *c_out, int64_t m, int64_t ld,
+                           double alpha, int64_t steps, int64_t every, double *lbar,
+                           void *workspace, size_t workspace_bytes, void *stream);
+
 /* ---------------------------------------------------------------- Crank-Nicolson
  * `steps` Crank-Nicolson steps of m systems (Section 3 benchmark problem:
  * periodic diffusion; Section 4 benchmark problem: periodic hyperdiffusion):

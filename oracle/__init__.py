@@ -246,14 +246,8 @@ def cn_step(bands, w, c, steps: int = 1, cyclic: bool = True) -> np.ndarray:
 def ch_domain_size(c) -> np.ndarray:
     """l_k = 1 / (1 - (1/n) sum_i c[i,k]^2) for every run k of an (n, m) batch."""
     c = _f64(c)
-    n, m = c.shape
-    out = np.empty(m)
-    for k in range(m):
-        acc = 0.0
-        for i in range(n):
-            acc += c[i, k] * c[i, k]
-        out[k] = 1.0 / (1.0 - acc / n)
-    return out
+    n = c.shape[0]
+    return 1.0 / (1.0 - np.sum(c * c, axis=0) / n)
 
 
 def ch_coarsening(c0, sigma: float, alpha: float, steps: int, every: int):

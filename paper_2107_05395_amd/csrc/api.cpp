@@ -516,8 +516,20 @@ bb_status bb_band_grad(bb_factor fh, const double *lam, const double *x, int64_t
     return BB_OK;
 }
 
-bb_status bb_ch_step(bb_factor fh, const double *c_in, double *c_out, int64_t m, int64_t ld,
-                     double alpha, int64_t steps, void *stream)
+namespace {
+
+// One row of `samples` partial sums per group of systems of the stepper.
+size_t ch_stats_bytes(int64_t n, int64_t m, int64_t samples)
+{
+    if (samples < 1 || m < 1) return 0;
+    const StepPlan pl = step_plan(n, m);
+    const bb::SweepGeom g = step_geom(n, m, m, pl);
+    return (size_t)g.groups * (size_t)samples * sizeof(double);
+}
+
+bb_status ch_steps(bb_factor fh, const double *c_in, double *c_out, int64_t m, int64_t ld,
+                   double alpha, int64_t steps, int64_t every, double *lbar, void *workspace,
+                   size_t workspace_bytes, void *stream)
 {
     bb_status st = check_batch(fh, c_in, c_out, m, ld);
     if (st != BB_OK) return st;
@@ -525,7 +537,14 @@ bb_status bb_ch_step(bb_factor fh, const double *c_in, double *c_out, int64_t m,
     if (f.kind != bb::kPentaCyclic) return fail(BB_ERR_ARG, "needs a cyclic pentadiagonal factor");
     if (steps < 1) return fail(BB_ERR_ARG, "steps < 1");
     if (!std::isfinite(alpha)) return fail(BB_ERR_ARG, "alpha is not finite");
-    if (m == 0) return BB_OK;
+    if (every < 1) return fail(BB_ERR_ARG, "every < 1");
+    const int64_t samples = lbar ? steps / every : 0;
+    if (m == 0) { g_last_error.clear(); return BB_OK; }
+    if (samples > 0) {
+        if (!workspace) return fail(BB_ERR_ARG, "workspace is NULL");
+        if (workspace_bytes < ch_stats_bytes(f.n, m, samples))
+            return fail(BB_ERR_ARG, "workspace too small (bb_ch_stats_workspace_bytes)");
+    }
     int dev;
     if ((st = current_device(&dev)) != BB_OK) return st;
     // The fused steps are bound by arithmetic and coefficient reads, not HBM
@@ -538,9 +557,34 @@ bb_status bb_ch_step(bb_factor fh, const double *c_in, double *c_out, int64_t m,
     if (st != BB_OK) return st;
     const bb::SweepGeom g = step_geom(f.n, m, ld, pl);
     hipError_t e = bb::launch_ch((const double *)tab.ptr, tab.elems, f.primal.cor.q, g, pl.scalar,
-                                 alpha, steps, c_in, c_out, (hipStream_t)stream);
+                                 alpha, steps, c_in, c_out, (hipStream_t)stream, every, samples,
+                                 (double *)workspace, lbar);
     if (e != hipSuccess) return hip_fail(e, "Cahn-Hilliard launch");
+    g_last_error.clear();
     return BB_OK;
+}
+
+}  // namespace
+
+bb_status bb_ch_step(bb_factor fh, const double *c_in, double *c_out, int64_t m, int64_t ld,
+                     double alpha, int64_t steps, void *stream)
+{
+    return ch_steps(fh, c_in, c_out, m, ld, alpha, steps, 1, nullptr, nullptr, 0, stream);
+}
+
+size_t bb_ch_stats_workspace_bytes(bb_factor f, int64_t m, int64_t samples)
+{
+    if (!f || m < 1 || samples < 1) return 0;
+    return ch_stats_bytes(f->f.n, m, samples);
+}
+
+bb_status bb_ch_step_stats(bb_factor fh, const double *c_in, double *c_out, int64_t m, int64_t ld,
+                           double alpha, int64_t steps, int64_t every, double *lbar,
+                           void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!lbar) return fail(BB_ERR_ARG, "lbar is NULL");
+    return ch_steps(fh, c_in, c_out, m, ld, alpha, steps, every, lbar, workspace, workspace_bytes,
+                    stream);
 }
 
 bb_status bb_cn_step(bb_factor fh, const double *w, const double *c_in, double *c_out, int64_t m,

@@ -50,14 +50,40 @@ struct ChRhs {
     }
 };
 
+// lbar[s] = inv_m * sum over groups of partial[group][s], groups in order.
+__global__ void stats_fold(const double *__restrict__ partial, int64_t groups, int64_t samples,
+                           double inv_m, double *__restrict__ lbar)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= samples) return;
+    double acc = 0.0;
+    for (int64_t r = 0; r < groups; ++r) acc += partial[r * samples + s];
+    lbar[s] = acc * inv_m;
+}
+
 }  // namespace
 
 hipError_t launch_ch(const double *table, int64_t table_elems, const CyclicQ &q,
                      const SweepGeom &g, bool scalar, double alpha, int64_t steps,
-                     const double *in, double *out, hipStream_t s)
+                     const double *in, double *out, hipStream_t s, int64_t every,
+                     int64_t samples, double *partial, double *lbar)
 {
-    return launch_stepper<ChRhs, 2, true>(table, table_elems, q, g, scalar, ChRhs{alpha}, steps,
-                                          in, out, s);
+    if (!partial || samples < 1)
+        return launch_stepper<ChRhs, 2, true>(table, table_elems, q, g, scalar, ChRhs{alpha},
+                                              steps, in, out, s);
+    StepStats st;
+    st.partial = partial;
+    st.every = every;
+    st.samples = samples;
+    st.inv_n = 1.0 / g.n;
+    hipError_t e = launch_stepper<ChRhs, 2, true, true>(table, table_elems, q, g, scalar,
+                                                        ChRhs{alpha}, steps, in, out, s, st);
+    if (e != hipSuccess) return e;
+    const int threads = 256;
+    hipLaunchKernelGGL(stats_fold, dim3((unsigned)((samples + threads - 1) / threads)),
+                       dim3(threads), 0, s, (const double *)partial, g.groups, samples,
+                       1.0 / (double)g.m, lbar);
+    return hipGetLastError();
 }
 
 }  // namespace bb

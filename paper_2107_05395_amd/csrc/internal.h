@@ -161,9 +161,13 @@ hipError_t launch_refine_f32rhs(int K, bool cyclic, const void *table, int64_t t
 // scalar: one 64-row chunk per wave with scalar coefficients (log2Q ==
 // log2P <= 3); else log2Q > 0 splits a full decomposition (C = 32, 64) over
 // 2^log2Q waves with the table in LDS, and log2Q == 0 keeps one wave per group.
+// With partial != nullptr and samples >= 1, also the typical domain size:
+// lbar[s] = mean over the m runs of 1 / (1 - <c^2>) after (s + 1) * every
+// steps; partial is a workspace of g.groups * samples doubles.
 hipError_t launch_ch(const double *table, int64_t table_elems, const CyclicQ &q,
                      const SweepGeom &g, bool scalar, double alpha, int64_t steps,
-                     const double *in, double *out, hipStream_t stream);
+                     const double *in, double *out, hipStream_t stream, int64_t every = 1,
+                     int64_t samples = 0, double *partial = nullptr, double *lbar = nullptr);
 
 // Crank-Nicolson steps x <- A^{-1} (B x) with B a constant (2K+1)-point
 // stencil w (host array of 2K+1, copied into the kernel arguments), state on

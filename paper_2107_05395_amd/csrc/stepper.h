@@ -31,13 +31,46 @@ struct Halo {
     double e0, e1, en2, en1;
 };
 
+// Optional per-run statistic of the fused steps (Cahn-Hilliard coarsening,
+// Section 5, batched 1D scaling), compiled in only where asked for (STATS):
+// after every `every` steps, each system's typical domain size
+// 1 / (1 - <c^2>), <c^2> = (1/n) sum_i c_i^2, summed over the systems of its
+// group in a fixed order and stored at [group][sample] of `partial` (each
+// entry written once; no read-modify-write inside the step loop).
+struct StepStats {
+    double *partial = nullptr;
+    int64_t every = 1, samples = 0;
+    double inv_n = 0.0;
+};
+
+// sum of squares of this lane's rows (padding rows hold 0): four interleaved
+// partial sums (rows t mod 4) keep the dependency chain short, combined in a
+// fixed order
+template <int C>
+__device__ __forceinline__ double chunk_sum_sq(const double (&c)[C])
+{
+    double ss[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < C; ++t) ss[t & 3] = fma(c[t], c[t], ss[t & 3]);
+    return (ss[0] + ss[1]) + (ss[2] + ss[3]);
+}
+
+// Sum of v over the S lanes of each block of S consecutive lanes (S a power
+// of two), a fixed butterfly: every lane of the block gets the same sum.
+__device__ __forceinline__ double block_sum(double v, int S)
+{
+    for (int off = 1; off < S; off <<= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
 // One lane per chunk; the lanes of a system sit in one wave (shuffles) and
 // the coefficient table is staged in LDS.
-template <class Rhs, int K, bool CYC, int C, bool FULL>
+template <class Rhs, int K, bool CYC, int C, bool FULL, bool STATS>
 __global__ __launch_bounds__(kMaxBlockThreads) void step_kernel(const double *__restrict__ table,
                                                              int64_t table_elems, CyclicQ cq,
                                                              SweepGeom g, Rhs rhs, int64_t steps,
-                                                             const double *in, double *out)
+                                                             StepStats st, const double *in,
+                                                             double *out)
 {
     extern __shared__ double smem_d[];
     stage_table(smem_d, table, table_elems);
@@ -76,6 +109,15 @@ __global__ __launch_bounds__(kMaxBlockThreads) void step_kernel(const double *__
             rhs.template operator()<C, FULL>(c, h, lg.j, lg.j == lg.P - 1, opaque_v(g.n - row0));
             __builtin_amdgcn_sched_barrier(0);
             chunk_solve<double, K, C, CYC>(c, smem_d, lg, g.n, exact, cq);
+            if (STATS && (step + 1) % st.every == 0) {
+                // chunks of a system: lanes j*S + sl of this wave, summed in chunk order
+                const double ss = chunk_sum_sq<C>(c);
+                double tot = 0.0;
+                for (int i = 0; i < lg.P; ++i) tot += shfl(ss, i * lg.S + lg.sl);
+                const double ell = kval ? 1.0 / (1.0 - tot * st.inv_n) : 0.0;
+                const double sum = block_sum(ell, lg.S);   // the group: lanes 0 .. S-1
+                if (lane == 0) st.partial[grp * st.samples + (step + 1) / st.every - 1] = sum;
+            }
         }
         if (kval) store_chunk<double, C, FULL>(c, out, row0, k, g.ld, g.n);
     }
@@ -90,10 +132,11 @@ __global__ __launch_bounds__(kMaxBlockThreads) void step_kernel(const double *__
 // coefficient row at the same time, so the coefficients come from the global
 // table through the scalar cache (no LDS staging, no LDS reads).  Otherwise
 // the table is staged in LDS ahead of the exchange area.
-template <class Rhs, int K, bool CYC, int C, int QL, bool SCALAR>
+template <class Rhs, int K, bool CYC, int C, int QL, bool SCALAR, bool STATS>
 __global__ __launch_bounds__((kWave << QL) > kMaxBlockThreads ? (kWave << QL) : kMaxBlockThreads)
 void step_kernel_split(const double *__restrict__ table, int64_t table_elems, CyclicQ cq,
-                       SweepGeom g, Rhs rhs, int64_t steps, const double *in, double *out)
+                       SweepGeom g, Rhs rhs, int64_t steps, StepStats st, const double *in,
+                       double *out)
 {
     using Src = typename std::conditional<SCALAR, FromScalar<double>, FromLds<double>>::type;
     constexpr int R = Rhs::R;
@@ -101,6 +144,7 @@ void step_kernel_split(const double *__restrict__ table, int64_t table_elems, Cy
     const int64_t tl = SCALAR ? 0 : table_elems;
     double *xch = smem_d + tl;                              // chunk_solve phases
     double *xd = xch + split_exchange_len(QL);              // [2R][P*S]: rows 0, C-1, 1, C-2
+    double *xs = xd + ((2LL * R * kWave) << QL);            // [P*S]: sums of squares
     typename Src::ptr tab;
     if constexpr (SCALAR) {
         tab = (typename Src::ptr)table;
@@ -110,7 +154,9 @@ void step_kernel_split(const double *__restrict__ table, int64_t table_elems, Cy
         tab = smem_d;
     }
 
-    LaneGeom lg = lane_geom(g.log2P, QL);
+    // SCALAR: P == Q (the host checks log2P == QL), so the geometry is known
+    // at compile time: S = 64, one chunk per wave
+    LaneGeom lg = lane_geom(SCALAR ? QL : g.log2P, QL);
     if constexpr (SCALAR) lg.j = __builtin_amdgcn_readfirstlane(lg.j);   // the wave's chunk
     const int row0 = lg.j * C;
     const bool has_left = lg.j > 0, has_right = lg.j < lg.P - 1;
@@ -151,16 +197,30 @@ void step_kernel_split(const double *__restrict__ table, int64_t table_elems, Cy
             rhs.template operator()<C, true>(c, h, lg.j, !has_right, C);
             __builtin_amdgcn_sched_barrier(0);
             chunk_solve<double, K, C, CYC, true, Src>(c, tab, lg, g.n, 1, cq, xch);
+            if (STATS && (step + 1) % st.every == 0) {
+                // chunks of a system through LDS, summed in chunk order, by
+                // wave 0 (it holds chunk 0: lanes 0 .. S-1 are the group)
+                xs[me] = chunk_sum_sq<C>(c);
+                __syncthreads();
+                if (threadIdx.x < kWave) {
+                    double tot = 0.0;
+                    for (int i = 0; i < lg.P; ++i) tot += xs[i * lg.S + lg.sl];
+                    const double ell = kval ? 1.0 / (1.0 - tot * st.inv_n) : 0.0;
+                    const double sum = block_sum(ell, lg.S);
+                    if (threadIdx.x == 0)
+                        st.partial[grp * st.samples + (step + 1) / st.every - 1] = sum;
+                }
+            }
         }
         if (kval) store_chunk<double, C, true>(c, out, row0, k, g.ld, g.n);
     }
 }
 
 // LDS bytes of the split kernel beyond the staged table: the chunk_solve
-// exchange plus 2R rows per (chunk, slot).
+// exchange, 2R rows per (chunk, slot) and one sum of squares per (chunk, slot).
 constexpr size_t split_step_lds(int QL, int R)
 {
-    return (size_t)(split_exchange_len(QL) + ((2LL * R * kWave) << QL)) * sizeof(double);
+    return (size_t)(split_exchange_len(QL) + ((2LL * R * kWave) << QL) + (kWave << QL)) * sizeof(double);
 }
 
 // Launch `steps` fused steps.  g.log2Q > 0 selects the split kernel (full
@@ -168,19 +228,20 @@ constexpr size_t split_step_lds(int QL, int R)
 // when `scalar` (then log2Q == log2P and C == 64); `scalar` with
 // g.log2Q == g.log2P == 0 runs one-chunk systems the same way.  Otherwise the
 // LDS kernel with one wave per group.
-template <class Rhs, int K, bool CYC>
+template <class Rhs, int K, bool CYC, bool STATS = false>
 hipError_t launch_stepper(const double *table, int64_t table_elems, const CyclicQ &q,
                           const SweepGeom &g, bool scalar, const Rhs &rhs, int64_t steps,
-                          const double *in, double *out, hipStream_t s)
+                          const double *in, double *out, hipStream_t s,
+                          StepStats st = StepStats{})
 {
     if (scalar) {
         if (g.C != 64 || g.log2Q != g.log2P || g.log2Q > 3 || !is_full(g)) return hipErrorInvalidValue;
         const size_t xl = split_step_lds(g.log2Q, Rhs::R);
         switch (g.log2Q) {
-        case 0: return launch_grid_split(step_kernel_split<Rhs, K, CYC, 64, 0, true>, xl, g.groups, 1, s, table, table_elems, q, g, rhs, steps, in, out);
-        case 1: return launch_grid_split(step_kernel_split<Rhs, K, CYC, 64, 1, true>, xl, g.groups, 2, s, table, table_elems, q, g, rhs, steps, in, out);
-        case 2: return launch_grid_split(step_kernel_split<Rhs, K, CYC, 64, 2, true>, xl, g.groups, 4, s, table, table_elems, q, g, rhs, steps, in, out);
-        default: return launch_grid_split(step_kernel_split<Rhs, K, CYC, 64, 3, true>, xl, g.groups, 8, s, table, table_elems, q, g, rhs, steps, in, out);
+        case 0: return launch_grid_split(step_kernel_split<Rhs, K, CYC, 64, 0, true, STATS>, xl, g.groups, 1, s, table, table_elems, q, g, rhs, steps, st, in, out);
+        case 1: return launch_grid_split(step_kernel_split<Rhs, K, CYC, 64, 1, true, STATS>, xl, g.groups, 2, s, table, table_elems, q, g, rhs, steps, st, in, out);
+        case 2: return launch_grid_split(step_kernel_split<Rhs, K, CYC, 64, 2, true, STATS>, xl, g.groups, 4, s, table, table_elems, q, g, rhs, steps, st, in, out);
+        default: return launch_grid_split(step_kernel_split<Rhs, K, CYC, 64, 3, true, STATS>, xl, g.groups, 8, s, table, table_elems, q, g, rhs, steps, st, in, out);
         }
     }
     if (g.log2Q > 0) {
@@ -190,9 +251,9 @@ hipError_t launch_stepper(const double *table, int64_t table_elems, const Cyclic
 #define BB_SPLIT(CC)                                                                                     \
         case CC:                                                                                         \
             switch (g.log2Q) {                                                                           \
-            case 1: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 1, false>, xl, g.groups, 2, s, table, table_elems, q, g, rhs, steps, in, out); \
-            case 2: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 2, false>, xl, g.groups, 4, s, table, table_elems, q, g, rhs, steps, in, out); \
-            default: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 3, false>, xl, g.groups, 8, s, table, table_elems, q, g, rhs, steps, in, out); \
+            case 1: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 1, false, STATS>, xl, g.groups, 2, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            case 2: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 2, false, STATS>, xl, g.groups, 4, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            default: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 3, false, STATS>, xl, g.groups, 8, s, table, table_elems, q, g, rhs, steps, st, in, out); \
             }
         switch (g.C) {
             BB_SPLIT(32)
@@ -204,10 +265,10 @@ hipError_t launch_stepper(const double *table, int64_t table_elems, const Cyclic
     const size_t lds = (size_t)table_elems * sizeof(double);
 #define BB_STEP(CC)                                                                            \
     case CC:                                                                                   \
-        return is_full(g) ? launch_grid(step_kernel<Rhs, K, CYC, CC, true>, lds, g.groups, s,   \
-                                        table, table_elems, q, g, rhs, steps, in, out)          \
-                          : launch_grid(step_kernel<Rhs, K, CYC, CC, false>, lds, g.groups, s,  \
-                                        table, table_elems, q, g, rhs, steps, in, out);
+        return is_full(g) ? launch_grid(step_kernel<Rhs, K, CYC, CC, true, STATS>, lds, g.groups, s,   \
+                                        table, table_elems, q, g, rhs, steps, st, in, out)      \
+                          : launch_grid(step_kernel<Rhs, K, CYC, CC, false, STATS>, lds, g.groups, s,  \
+                                        table, table_elems, q, g, rhs, steps, st, in, out);
     switch (g.C) {
         BB_STEP(4)
         BB_STEP(8)

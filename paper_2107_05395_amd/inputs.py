@@ -115,6 +115,13 @@ WORKLOADS = {
                                         steps=5000, seed=SEED_BASE + 3),
     "adjoint_diffusion_n1024_m65536": dict(kind="adjoint", n=1024, m=1 << 16, r=0.5, steps=100,
                                            checkpoint=10, seed=SEED_BASE + 4),
+    # Cahn-Hilliard coarsening campaigns (Section 5, batched 1D scaling): 2^20
+    # runs, dx = 2 pi / 256, dt = 0.1 dx, T = 100, gamma = 0.01, initial states
+    # uniform[-0.1, 0.1); domain lengths 2 pi (n = 256) and 4 pi (n = 512)
+    "ch_coarsening_L2pi": dict(kind="ch_coarsening", n=256, length=2.0 * math.pi, m=1 << 20,
+                               gamma=0.01, T=100.0, seed=SEED_BASE + 7),
+    "ch_coarsening_L4pi": dict(kind="ch_coarsening", n=512, length=4.0 * math.pi, m=1 << 20,
+                               gamma=0.01, T=100.0, seed=SEED_BASE + 8),
     # Crank-Nicolson time stepping on the grid of the paper's benchmark tables
     # (1000 steps; n = 64, 256, 1024; m = 2^6, 2^12, 2^16); the step size is
     # not printed, sigma = 1 is this build's choice (it does not change the work)

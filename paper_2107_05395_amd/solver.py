@@ -173,6 +173,28 @@ class Factor:
                                    int(steps), _stream_ptr(c)))
         return out
 
+    def ch_step_stats(self, c: torch.Tensor, alpha: float, steps: int, every: int = 1,
+                      out: torch.Tensor | None = None):
+        """Cahn-Hilliard steps plus the ensemble-mean typical domain size
+        1/(1 - <C^2>) after every `every` steps -> (state, lbar float64 tensor
+        of steps // every entries on the device)."""
+        m, ld = _batch_view(c, self.n, torch.float64, "c")
+        if out is None:
+            out = torch.empty_like(c)
+        if _batch_view(out, self.n, torch.float64, "out") != (m, ld):
+            raise ValueError("out must match c in shape and strides")
+        samples = int(steps) // int(every) if every >= 1 else 0
+        lbar = torch.empty(max(samples, 1), dtype=torch.float64, device=c.device)
+        with torch.cuda.device(c.device):
+            nbytes = lib().bb_ch_stats_workspace_bytes(self._handle, m, samples)
+            ws = torch.empty(max(nbytes, 8), dtype=torch.uint8, device=c.device)
+            check(lib().bb_ch_step_stats(self._handle, ctypes.c_void_p(c.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), m, ld, float(alpha),
+                                         int(steps), int(every), ctypes.c_void_p(lbar.data_ptr()),
+                                         ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                         _stream_ptr(c)))
+        return out, lbar[:samples]
+
     def cn_step(self, c: torch.Tensor, w, steps: int = 1,
                 out: torch.Tensor | None = None) -> torch.Tensor:
         """`steps` Crank-Nicolson steps A c' = B c with B the constant stencil w

@@ -126,6 +126,14 @@ def test_solve_argument_checks_need_no_gpu(L):
     assert L.bb_ch_step(h, fake, fake, 4, 4, 1.0, 1, None) == -1           # not cyclic penta
     w3 = (ctypes.c_double * 3)(0.5, 0.0, 0.5)
     bad = (ctypes.c_double * 3)(0.5, float("nan"), 0.5)
+    assert L.bb_ch_step_stats(h, fake, fake, 4, 4, 1.0, 4, 1, fake, fake, 1 << 20, None) == -1  # not cyclic penta
+    _, hc = _factor(L, "penta_cyclic", inputs.ch_penta_bands(n, 0.3), n)
+    assert L.bb_ch_step_stats(hc, fake, fake, 4, 4, 1.0, 4, 0, fake, fake, 1 << 20, None) == -1  # every < 1
+    assert L.bb_ch_step_stats(hc, fake, fake, 4, 4, 1.0, 4, 1, None, fake, 1 << 20, None) == -1  # no lbar
+    assert L.bb_ch_step_stats(hc, fake, fake, 4, 4, 1.0, 4, 1, fake, None, 1 << 20, None) == -1  # no workspace
+    assert L.bb_ch_stats_workspace_bytes(hc, 4, 4) == 8 * 4             # one group of 4 runs, 4 samples
+    assert L.bb_ch_step_stats(hc, fake, fake, 4, 4, 1.0, 4, 1, fake, fake, 8 * 4 - 1, None) == -1  # too small
+    L.bb_factor_destroy(hc)
     assert L.bb_cn_step(h, None, fake, fake, 4, 4, 1, None) == -1           # no stencil
     assert L.bb_cn_step(h, bad, fake, fake, 4, 4, 1, None) == -1            # weight not finite
     assert L.bb_cn_step(h, w3, fake, fake, 4, 4, 0, None) == -1             # steps < 1

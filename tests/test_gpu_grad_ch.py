@@ -178,3 +178,63 @@ def test_ch_uniform_chunks_match_lds_kernel(n, monkeypatch):
     say("ch uniform vs lds", n, float(np.max(np.abs(uni - lds))), rel_err(uni, ref))
     assert rel_err(uni, ref) < 1e-12
     assert np.array_equal(uni, lds)
+
+
+# ---------------------------------------------------------------- coarsening statistics
+
+@pytest.mark.parametrize("n,m", [(256, 300), (256, (1 << 16) + 5), (64, 5000), (1024, 700),
+                                 (1000, 333), (512, 70000)])
+def test_ch_domain_size_statistic_matches_oracle(n, m):
+    """lbar after every 3 steps (mean over the runs of 1/(1 - <C^2>)), computed
+    inside the stepping kernel, against the oracle; the state is bitwise what
+    the plain steps give, and a second call reproduces lbar bitwise."""
+    say("ch stats", n, m)
+    f, sigma, alpha = _ch(n)
+    steps, every = 11, 3
+    c0 = inputs.uniform_batch(n, m, seed=90 + n, lo=-0.5, hi=0.5)
+    ref_lbar, ref_c = oracle.ch_coarsening(c0, sigma, alpha, steps, every)
+    t = dev(c0)
+    out, lbar = f.ch_step_stats(t, alpha, steps=steps, every=every)
+    lb = host(lbar)
+    assert lb.shape == (3,)
+    # relative to lbar - 1 = <C^2> / (1 - <C^2>), the part the state decides
+    err = float(np.max(np.abs(lb - ref_lbar) / (ref_lbar - 1.0)))
+    say("  lbar", lb, "rel err of lbar - 1", err)
+    assert err < 1e-11
+    # The hyperdiffusion smooths the U[-0.5, 0.5) start to a tenth of its norm
+    # within a few steps, while the rounding of the explicit right-hand side
+    # (about eps alpha |C^3 - C|) reaches the low modes, which the solve passes
+    # undamped, at the scale of the start: bound the error against that scale.
+    assert np.max(np.abs(host(out) - ref_c)) < 2e-12 * np.max(np.abs(c0))
+    assert np.array_equal(host(out), host(f.ch_step(t, alpha, steps=steps)))
+    _, lbar2 = f.ch_step_stats(t, alpha, steps=steps, every=every)
+    assert np.array_equal(host(lbar2), lb)
+
+
+def test_ch_domain_size_statistic_kernel_variants(monkeypatch):
+    """Scalar-coefficient, LDS split and LDS one-wave kernels group the runs
+    differently, so their sums round differently, but each matches the
+    oracle (130 samples, one per step)."""
+    n, m, steps, every = 512, 3000, 130, 1
+    f, sigma, alpha = _ch(n)
+    c0 = inputs.uniform_batch(n, m, seed=95, lo=-0.5, hi=0.5)
+    ref, _ = oracle.ch_coarsening(c0, sigma, alpha, steps, every)
+    t = dev(c0)
+    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", "64")
+    for env in ({}, {"BANDBATCH_CH_UNIFORM": "0"},
+                {"BANDBATCH_CH_UNIFORM": "0", "BANDBATCH_WAVES_PER_SYSTEM": "1"}):
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        _, lbar = f.ch_step_stats(t, alpha, steps=steps, every=every)
+        err = float(np.max(np.abs(host(lbar) - ref) / (ref - 1.0)))
+        say("  variant", env, "rel err of lbar - 1", err)
+        assert err < 1e-11
+
+
+def test_ch_domain_size_statistic_without_samples():
+    n, m = 256, 100
+    f, sigma, alpha = _ch(n)
+    c0 = inputs.uniform_batch(n, m, seed=96, lo=-0.1, hi=0.1)
+    out, lbar = f.ch_step_stats(dev(c0), alpha, steps=2, every=5)
+    assert lbar.numel() == 0
+    assert rel_err(host(out), oracle.ch_step(c0, sigma, alpha, steps=2)) < 1e-12
