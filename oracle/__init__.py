@@ -65,6 +65,10 @@ def _load():
         lib.oracle_band_grad.restype = None
         lib.oracle_ch_step_batch.argtypes = [i64, i64, i64, ctypes.c_double, ctypes.c_double, P, P]
         lib.oracle_cn_step_batch.argtypes = [ctypes.c_int, i64, i64, i64] + [P] * 8
+        lib.oracle_weno5.argtypes = [P, i64, i64, ctypes.c_int]
+        lib.oracle_weno5.restype = ctypes.c_double
+        lib.oracle_ch_forced_step_batch.argtypes = [i64, i64, i64, ctypes.c_double, ctypes.c_double,
+                                                    P, P, P, P, P]
         lib.oracle_num_threads.argtypes = []
         _lib = lib
     return _lib
@@ -233,6 +237,39 @@ def cn_step(bands, w, c, steps: int = 1, cyclic: bool = True) -> np.ndarray:
     for _ in range(steps):
         _check(_load().oracle_cn_step_batch(kind, n, m, m, *(_p(v) for v in bands), _p(w),
                                             _p(c), _p(out)))
+        c, out = out, c
+    return c
+
+
+# --------------------------------------------------------------------------
+# Forced Cahn-Hilliard equation in the frame of the travelling wave (the
+# forced flow-pattern section): the Section 5.1 step plus an advection term
+# v dC/deta, differenced with the fifth-order Hamilton-Jacobi WENO scheme the
+# paper cites, and the forcing f0 k cos(k eta), with v, f0, k per run.
+
+def weno5(phi, plus: bool) -> np.ndarray:
+    """dx times the one-sided WENO5 derivative of a periodic grid function at
+    every point (right-biased when plus)."""
+    phi = _f64(phi)
+    n = phi.shape[0]
+    return np.array([_load().oracle_weno5(_p(phi), n, i, int(plus)) for i in range(n)])
+
+
+def ch_forced_parameters(dt: float, dx: float, v, f0, k):
+    """Per-run (beta, amp, kdx) = (dt v / dx, dt f0 k, k dx)."""
+    v, f0, k = (np.asarray(x, dtype=np.float64) for x in (v, f0, k))
+    return dt * v / dx, dt * f0 * k, k * dx
+
+
+def ch_forced_step(c, sigma: float, alpha: float, beta, amp, kdx, steps: int = 1) -> np.ndarray:
+    c = np.array(c, dtype=np.float64, order="C", copy=True)
+    n, m = c.shape
+    beta, amp, kdx = (np.ascontiguousarray(np.broadcast_to(np.asarray(x, dtype=np.float64), (m,)))
+                      for x in (beta, amp, kdx))
+    out = np.empty_like(c)
+    for _ in range(steps):
+        _check(_load().oracle_ch_forced_step_batch(n, m, m, sigma, alpha, _p(beta), _p(amp),
+                                                   _p(kdx), _p(c), _p(out)))
         c, out = out, c
     return c
 

@@ -368,6 +368,95 @@ int oracle_ch_step_batch(int64_t n, int64_t m, int64_t ld, double sigma, double 
 }
 
 /* ------------------------------------------------------------------------ */
+/* One-sided fifth-order WENO derivative for Hamilton-Jacobi equations (Jiang
+ * and Peng; the scheme the paper cites for the advection term of the forced
+ * Cahn-Hilliard equation), undivided (it returns dx times the derivative) on
+ * a periodic grid function phi.  plus != 0: the right-biased derivative,
+ * from phi_{i-2} .. phi_{i+3}; plus == 0: the left-biased one, from
+ * phi_{i-3} .. phi_{i+2}.  v1..v5 are the five one-sided differences ordered
+ * from the far upwind end; three third-order candidates are blended with
+ * weights 0.1, 0.6, 0.3 divided by (smoothness + eps)^2.                     */
+double oracle_weno5(const double *phi, int64_t n, int64_t i, int plus)
+{
+    double v[5];
+    for (int q = 0; q < 5; ++q) {
+        if (plus) {           /* D+ phi_j = phi_{j+1} - phi_j, j = i+2 .. i-2 */
+            const int64_t j = i + 2 - q;
+            v[q] = phi[wrap(j + 1, n)] - phi[wrap(j, n)];
+        } else {              /* D- phi_j = phi_j - phi_{j-1}, j = i-2 .. i+2 */
+            const int64_t j = i - 2 + q;
+            v[q] = phi[wrap(j, n)] - phi[wrap(j - 1, n)];
+        }
+    }
+    const double p1 = v[0] / 3.0 - 7.0 * v[1] / 6.0 + 11.0 * v[2] / 6.0;
+    const double p2 = -v[1] / 6.0 + 5.0 * v[2] / 6.0 + v[3] / 3.0;
+    const double p3 = v[2] / 3.0 + 5.0 * v[3] / 6.0 - v[4] / 6.0;
+    const double a = v[0] - 2.0 * v[1] + v[2], b = v[0] - 4.0 * v[1] + 3.0 * v[2];
+    const double c = v[1] - 2.0 * v[2] + v[3], d = v[1] - v[3];
+    const double e = v[2] - 2.0 * v[3] + v[4], g = 3.0 * v[2] - 4.0 * v[3] + v[4];
+    const double s1 = 13.0 / 12.0 * a * a + 0.25 * b * b;
+    const double s2 = 13.0 / 12.0 * c * c + 0.25 * d * d;
+    const double s3 = 13.0 / 12.0 * e * e + 0.25 * g * g;
+    double vmax = 0.0;
+    for (int q = 0; q < 5; ++q) vmax = fmax(vmax, v[q] * v[q]);
+    const double eps = 1e-6 * vmax + 1e-99;
+    const double w1 = 0.1 / ((s1 + eps) * (s1 + eps));
+    const double w2 = 0.6 / ((s2 + eps) * (s2 + eps));
+    const double w3 = 0.3 / ((s3 + eps) * (s3 + eps));
+    return (w1 * p1 + w2 * p2 + w3 * p3) / (w1 + w2 + w3);
+}
+
+/* One semi-implicit step of the forced Cahn-Hilliard equation in the frame
+ * of the travelling wave (the forced flow-pattern section, numerical
+ * scheme): the Cahn-Hilliard step above with two more right-hand-side terms,
+ * run k having its own parameters,
+ *     f_i = C_i + alpha (N_{i-1} - 2 N_i + N_{i+1})
+ *           + beta_k W_i(C) + amp_k cos(kdx_k i),
+ * W the undivided WENO derivative upwinded for dC/dt = v dC/deta (beta > 0:
+ * right-biased, beta < 0: left-biased, beta = 0: no term), with
+ * beta = dt v / dx, amp = dt f0 k, kdx = k dx, eta_i = i dx.              */
+int oracle_ch_forced_step_batch(int64_t n, int64_t m, int64_t ld, double sigma, double alpha,
+                                const double *beta, const double *amp, const double *kdx,
+                                const double *c_in, double *c_out)
+{
+    if (n < 5 || m < 0 || ld < m) return ERR_SIZE;
+    double *band = (double *)malloc(sizeof(double) * (size_t)n * 5);
+    double *ba = band, *bb = band + n, *bc = band + 2 * n, *bd = band + 3 * n, *be = band + 4 * n;
+    for (int64_t i = 0; i < n; ++i) {
+        ba[i] = sigma; bb[i] = -4.0 * sigma; bc[i] = 1.0 + 6.0 * sigma;
+        bd[i] = -4.0 * sigma; be[i] = sigma;
+    }
+    int status = OK;
+#pragma omp parallel
+    {
+        double *col = (double *)malloc(sizeof(double) * (size_t)n * 18);
+        double *nl = col + n, *f = col + 2 * n, *sol = col + 3 * n, *work = col + 4 * n;
+        int my = OK;
+#pragma omp for schedule(static)
+        for (int64_t k = 0; k < m; ++k) {
+            for (int64_t i = 0; i < n; ++i) {
+                col[i] = c_in[i * ld + k];
+                nl[i] = col[i] * col[i] * col[i] - col[i];
+            }
+            for (int64_t i = 0; i < n; ++i) {
+                double r = col[i] + alpha * (nl[wrap(i - 1, n)] - 2.0 * nl[i] + nl[wrap(i + 1, n)]);
+                if (beta[k] != 0.0) r += beta[k] * oracle_weno5(col, n, i, beta[k] > 0.0);
+                r += amp[k] * cos(kdx[k] * (double)i);
+                f[i] = r;
+            }
+            int s = oracle_penta_cyclic_solve(n, ba, bb, bc, bd, be, f, sol, work);
+            if (s && !my) my = s;
+            for (int64_t i = 0; i < n; ++i) c_out[i * ld + k] = s ? NAN : sol[i];
+        }
+        free(col);
+#pragma omp critical
+        { if (my && !status) status = my; }
+    }
+    free(band);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Crank-Nicolson time steps of the benchmark problems: periodic diffusion
  * (Section 3, benchmark problem: LHS bands -s, 1+2s, -s; right-hand side
  * s C_{i-1} + (1-2s) C_i + s C_{i+1}, s = dt/(2 dx^2)) and periodic

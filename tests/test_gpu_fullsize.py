@@ -14,6 +14,11 @@ systems the oracle solves one by one, plus properties that hold at any size.
     full launch must equal the oracle's sum over the sample, scaled by
     |sample|/m); and a central finite-difference check of dL/dD on the
     full random batch.
+  * Crank-Nicolson grid, largest point (n=1024, m=2^16, periodic tri and
+    penta, 1000 steps): the fused launch and 1000 single-step launches,
+    sampled systems.
+  * Cahn-Hilliard coarsening, L = 2 pi (n=256, m=2^20, dt = 0.1 dx): the
+    statistic after each of 4 steps over all 2^20 runs against the oracle.
 """
 import numpy as np
 import pytest
@@ -174,3 +179,48 @@ def test_differentiated_diffusion_n1024_m2p16():
         fd = (run(D0 + h * v, "f64", False) - run(D0 - h * v, "f64", False)) / (2 * h)
         say("fd", fd, dD @ v)
         assert abs(fd - dD @ v) <= 1e-6 * abs(fd)
+
+
+@pytest.mark.parametrize("workload", ["cn_diffusion_grid", "cn_hyperdiffusion_grid"])
+def test_crank_nicolson_grid_largest_point_sampled(workload):
+    from paper_2107_05395_amd import Factor
+    spec = inputs.WORKLOADS[workload]
+    n, m, T, sigma = max(spec["ns"]), max(spec["ms"]), spec["steps"], spec["sigma"]
+    diff = spec["problem"] == "diffusion"
+    bands, w = (inputs.cn_diffusion_problem if diff else inputs.cn_hyperdiffusion_problem)(n, sigma)
+    f = Factor.tri(*bands, cyclic=True) if diff else Factor.penta(*bands, cyclic=True)
+    c0 = inputs.uniform_batch(n, m, seed=spec["seed"] + n + m)
+    cols = sample_cols(m, 64, seed=5)
+    ref = oracle.cn_step(bands, w, c0[:, cols], steps=T)
+    t = torch.from_numpy(c0).cuda()
+    fused = f.cn_step(t, w, steps=T)
+    err = rel_err(cols_of(fused, cols), ref)
+    a, b = t.clone(), torch.empty_like(t)
+    for _ in range(T):
+        f.cn_step(a, w, out=b)
+        a, b = b, a
+    err1 = rel_err(cols_of(a, cols), ref)
+    say(workload, "fused", err, "per step", err1)
+    # after 1000 steps the states have decayed to near their means while the
+    # rounding accumulated at the scale of the start: bound by the start
+    assert np.max(np.abs(cols_of(fused, cols) - ref)) < 1e-12 * T ** 0.5 * np.max(np.abs(c0[:, cols]))
+    assert np.max(np.abs(cols_of(a, cols) - ref)) < 1e-12 * T ** 0.5 * np.max(np.abs(c0[:, cols]))
+
+
+def test_ch_coarsening_statistic_full_batch():
+    from paper_2107_05395_amd import Factor
+    spec = inputs.WORKLOADS["ch_coarsening_L2pi"]
+    n, m, L, gamma = spec["n"], spec["m"], spec["length"], spec["gamma"]
+    dt = 0.1 * L / n
+    sigma, alpha = inputs.ch_parameters(n=n, length=L, gamma=gamma, dt=dt)
+    f = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
+    c0 = inputs.uniform_batch(n, m, seed=spec["seed"], lo=-0.1, hi=0.1)
+    steps = 4
+    ref, ref_c = oracle.ch_coarsening(c0, sigma, alpha, steps, 1)
+    out, lbar = f.ch_step_stats(torch.from_numpy(c0).cuda(), alpha, steps=steps, every=1)
+    lb = lbar.cpu().numpy()
+    err = float(np.max(np.abs(lb - ref) / (ref - 1.0)))
+    say("coarsening full batch lbar", lb, "rel err of lbar - 1", err)
+    assert err < 1e-11
+    cols = sample_cols(m, 512, seed=6)
+    assert rel_err(cols_of(out, cols), ref_c[:, cols]) < 1e-12
