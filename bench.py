@@ -464,6 +464,90 @@ def bench_ch_coarsening(args, torch):
     return line
 
 
+FORCED_FLOPS_ROW_STEP = 112
+
+
+def bench_ch_forced(args, torch):
+    """A flow-pattern batch of the forced Cahn-Hilliard equation: every run of
+    a grid over (f0, <C>) stepped to t = T in launches of many fused steps."""
+    from paper_2107_05395_amd import Factor, inputs
+    import oracle
+    spec = dict(inputs.WORKLOADS[args.workload])
+    n, L, G, gamma, T, seed = (spec[k] for k in ("n", "length", "grid", "gamma", "T", "seed"))
+    m = G * G
+    dx = L / n
+    dt = 0.1 * dx
+    steps = int(round(T / dt))
+    sigma, alpha = inputs.ch_parameters(n=n, length=L, gamma=gamma, dt=dt)
+    f0 = np.repeat(np.linspace(spec["f0"][0], spec["f0"][1], G), G)
+    mean = np.tile(np.linspace(spec["mean"][0], spec["mean"][1], G), G)
+    beta, amp, kdx = oracle.ch_forced_parameters(dt, dx, np.full(m, spec["v"]), f0,
+                                                 np.full(m, spec["k"]))
+    f = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
+    f.upload()
+    c_host = mean + inputs.uniform_batch(n, m, seed=seed, lo=-0.1, hi=0.1)
+    # parity first: 64 sampled runs, 20 steps, against the oracle
+    cols = np.unique(np.r_[np.linspace(0, m - 1, 64).astype(np.int64), m - 1])
+    ref = oracle.ch_forced_step(c_host[:, cols], sigma, alpha, beta[cols], amp[cols], kdx[cols],
+                                steps=20)
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    pb, pa, pk = dv(beta), dv(amp), dv(kdx)
+    c = dv(c_host)
+    nxt = torch.empty_like(c)
+    f.ch_forced_step(c, alpha, pb, pa, pk, steps=20, out=nxt)
+    err = rel_err_cols(nxt[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref)
+    chunk = 2000
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        f.ch_forced_step(c, alpha, pb, pa, pk, steps=k, out=nxt)
+        c, nxt = nxt, c
+        done += k
+    stop.record()
+    torch.cuda.synchronize()
+    secs = start.elapsed_time(stop) / 1e3
+    final = c
+    flops = FORCED_FLOPS_ROW_STEP * n * m * steps
+    # per-run summaries of the final state (what a classifier would start from)
+    cmin = final.min(dim=0).values.cpu().numpy()
+    cmax = final.max(dim=0).values.cpu().numpy()
+    domains = float(np.mean((cmin < -0.5) & (cmax > 0.5)))
+    line = {
+        "metric": "system-steps/s", "value": m * steps / secs, "unit": "system-steps/s",
+        "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": 1e3 * secs / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded <C> + uniform[-0.1,0.1) initial states on a parameter grid)",
+        "config": {"workload": args.workload, "n": n, "L": L, "m": m, "grid": [G, G],
+                   "v": spec["v"], "k": spec["k"], "f0": spec["f0"], "mean": spec["mean"],
+                   "gamma": gamma, "dt": dt, "T": steps * dt, "steps_per_launch": chunk},
+        "rel_err_vs_oracle_64_runs_20_steps": err,
+        "fraction_of_runs_with_both_phases": domains,
+        "roofline": {"bound": "alu", "achieved": flops / secs / 1e12, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": flops / secs / 1e12 / PEAK_FP64_TFLOPS,
+                     "traffic": None,
+                     "note": "algorithmic FP64 operations, %d per row and step: the Cahn-Hilliard "
+                             "step 21, the WENO5 derivative 81 (differences 5, candidates 15, "
+                             "smoothness 33, eps 11, weights 9, blend 8), the advection and "
+                             "forcing terms with the cosine rotation 10" % FORCED_FLOPS_ROW_STEP},
+    }
+    if not args.no_cpu_baseline:
+        m_s = 1 << 10
+        cs = c_host[:, :m_s].copy()
+        done_s, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            cs = oracle.ch_forced_step(cs, sigma, alpha, beta[:m_s], amp[:m_s], kdx[:m_s], steps=5)
+            done_s += 5
+        el = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": done_s * m_s / el, "unit": "system-steps/s",
+                                "cores": oracle.num_threads(), "kind": "oracle",
+                                "sample": "%d steps of %d runs (n=%d) with oracle.ch_forced_step, "
+                                          "%.1f s" % (done_s, m_s, n, el)}
+    return line
+
+
 def bench_adjoint(args, torch):
     """One step = forward rollout of T implicit steps (checkpoint every c), the
     mean-squared-error loss, and the backward pass: adjoint solves with the
@@ -593,6 +677,8 @@ def main():
         line = bench_cn(args, torch)
     elif kind == "ch_coarsening":
         line = bench_ch_coarsening(args, torch)
+    elif kind == "ch_forced":
+        line = bench_ch_forced(args, torch)
     else:
         sys.exit("workload %s is not a bench workload" % args.workload)
     line["device"] = torch.cuda.get_device_name(0)

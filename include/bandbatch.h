@@ -199,6 +199,26 @@ bb_status bb_ch_step_stats(bb_factor f, const double *c_in, double *c_out, int64
                            double alpha, int64_t steps, int64_t every, double *lbar,
                            void *workspace, size_t workspace_bytes, void *stream);
 
+/* Forced Cahn-Hilliard steps in the frame of the travelling wave eta = x - vt
+ * (the forced flow-pattern section, numerical scheme):
+ *     C^{n+1} + dt gamma d4 C^{n+1} = C^n + dt [d2 (C^3 - C)^n + v dC^n/deta
+ *                                              + f0 k cos(k eta)],
+ * i.e. bb_ch_step's right-hand side plus, for run k,
+ *     beta[k] W_i(C) + amp[k] cos(kdx[k] i),
+ * with W_i dx times the fifth-order Hamilton-Jacobi WENO derivative of the
+ * run's state at row i, upwinded for dC/dt = v dC/deta (right-biased
+ * differences when beta > 0, left-biased when beta < 0), and eta_i = i dx.
+ * Per-run parameters: beta = dt v / dx, amp = dt f0 k, kdx = k dx.
+ * `f` must be the cyclic penta factor of the Cahn-Hilliard LHS (bb_ch_step).
+ * beta, amp, kdx: device, m doubles each.  c_in, c_out: device double,
+ * interleaved, same ld; in place allowed.  All `steps` steps run inside one
+ * kernel with the state on chip.
+ * Errors: BB_ERR_ARG (not a cyclic penta factor, NULL parameters, sizes),
+ * BB_ERR_HIP. */
+bb_status bb_ch_forced_step(bb_factor f, const double *c_in, double *c_out, int64_t m, int64_t ld,
+                            double alpha, const double *beta, const double *amp,
+                            const double *kdx, int64_t steps, void *stream);
+
 /* ---------------------------------------------------------------- Crank-Nicolson
  * `steps` Crank-Nicolson steps of m systems (Section 3 benchmark problem:
  * periodic diffusion; Section 4 benchmark problem: periodic hyperdiffusion):

@@ -587,6 +587,34 @@ bb_status bb_ch_step_stats(bb_factor fh, const double *c_in, double *c_out, int6
                     stream);
 }
 
+bb_status bb_ch_forced_step(bb_factor fh, const double *c_in, double *c_out, int64_t m,
+                            int64_t ld, double alpha, const double *beta, const double *amp,
+                            const double *kdx, int64_t steps, void *stream)
+{
+    bb_status st = check_batch(fh, c_in, c_out, m, ld);
+    if (st != BB_OK) return st;
+    bb::Factor &f = fh->f;
+    if (f.kind != bb::kPentaCyclic) return fail(BB_ERR_ARG, "needs a cyclic pentadiagonal factor");
+    if (steps < 1) return fail(BB_ERR_ARG, "steps < 1");
+    if (!std::isfinite(alpha)) return fail(BB_ERR_ARG, "alpha is not finite");
+    if (m > 0 && (!beta || !amp || !kdx)) return fail(BB_ERR_ARG, "parameter pointer is NULL");
+    if (m == 0) { g_last_error.clear(); return BB_OK; }
+    int dev;
+    if ((st = current_device(&dev)) != BB_OK) return st;
+    const StepPlan pl = step_plan(f.n, m);
+    bb::DeviceTable tab;
+    st = device_table(f, f.dev, std::make_tuple(dev, 0, 0, pl.C, 0), false,
+                      [&] { return bb::build_table(f.primal, 2, true, f.n, pl.C, pl.P); }, &tab);
+    if (st != BB_OK) return st;
+    const bb::SweepGeom g = step_geom(f.n, m, ld, pl);
+    hipError_t e = bb::launch_ch_forced((const double *)tab.ptr, tab.elems, f.primal.cor.q, g,
+                                        pl.scalar, alpha, beta, amp, kdx, steps, c_in, c_out,
+                                        (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "forced Cahn-Hilliard launch");
+    g_last_error.clear();
+    return BB_OK;
+}
+
 bb_status bb_cn_step(bb_factor fh, const double *w, const double *c_in, double *c_out, int64_t m,
                      int64_t ld, int64_t steps, void *stream)
 {

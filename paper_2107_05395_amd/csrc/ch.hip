@@ -42,9 +42,11 @@ __device__ __forceinline__ void ch_rhs(double (&c)[C], double cl, double cr, dou
 struct ChRhs {
     static constexpr int R = 1;
     double alpha;
+    struct State {};
+    __device__ State lane_state(int64_t, int) const { return State{}; }
     template <int C, bool FULL>
     __device__ __forceinline__ void operator()(double (&c)[C], const Halo &h, int j,
-                                               bool last_chunk, int nrow) const
+                                               bool last_chunk, int nrow, const State &) const
     {
         ch_rhs<C, FULL>(c, h.l1, h.r1, h.e0, h.en1, alpha, j, last_chunk, nrow);
     }

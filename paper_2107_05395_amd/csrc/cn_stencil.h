@@ -19,10 +19,12 @@ template <int K, bool CYC>
 struct StencilRhs {
     static constexpr int R = K;
     double w[2 * K + 1];
+    struct State {};
+    __device__ State lane_state(int64_t, int) const { return State{}; }
 
     template <int C, bool FULL>
     __device__ __forceinline__ void operator()(double (&c)[C], const Halo &h, int j,
-                                               bool last_chunk, int nrow) const
+                                               bool last_chunk, int nrow, const State &) const
     {
         // rows j*C - 1, j*C - 2: the previous chunk, or rows n-1, n-2 (periodic)
         double m1 = h.l1, m2 = h.l2;

@@ -169,6 +169,14 @@ hipError_t launch_ch(const double *table, int64_t table_elems, const CyclicQ &q,
                      const double *in, double *out, hipStream_t stream, int64_t every = 1,
                      int64_t samples = 0, double *partial = nullptr, double *lbar = nullptr);
 
+// Forced Cahn-Hilliard steps in the frame of the travelling wave
+// (ch_forced.hip): per run k, beta[k] = dt v / dx, amp[k] = dt f0 k,
+// kdx[k] = k dx (device arrays of m doubles); scalar / log2Q as for launch_ch.
+hipError_t launch_ch_forced(const double *table, int64_t table_elems, const CyclicQ &q,
+                            const SweepGeom &g, bool scalar, double alpha, const double *beta,
+                            const double *amp, const double *kdx, int64_t steps,
+                            const double *in, double *out, hipStream_t stream);
+
 // Crank-Nicolson steps x <- A^{-1} (B x) with B a constant (2K+1)-point
 // stencil w (host array of 2K+1, copied into the kernel arguments), state on
 // chip (cn_tri.hip, cn_penta.hip); scalar / log2Q as for launch_ch.

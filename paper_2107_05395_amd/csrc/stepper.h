@@ -7,9 +7,12 @@
 // and 4 benchmark problems) instantiate it.
 //
 // An Rhs policy provides
-//   static constexpr int R;   // rows of halo it reads on each side (1 or 2)
+//   static constexpr int R;   // rows of halo it reads on each side (1, 2 or 3)
+//   struct State;             // per-lane data of the system it works on
+//   State lane_state(int64_t k, int row0) const;   // system k, chunk from row0
 //   template <int C, bool FULL>
-//   void operator()(double (&c)[C], const Halo &h, int j, bool last_chunk, int nrow) const;
+//   void operator()(double (&c)[C], const Halo &h, int j, bool last_chunk, int nrow,
+//                   const State &s) const;
 // which overwrites the chunk c (rows j*C .. j*C + C - 1 of the system) with
 // the right-hand side.  nrow = n - j*C (rows of the chunk that are real when
 // the decomposition is ragged); last_chunk: j == P - 1.
@@ -22,13 +25,13 @@
 namespace bb {
 namespace {
 
-// Values around a chunk: the R rows above it (l1 = row j*C - 1, l2 = row
-// j*C - 2; 0 for the first chunk) and below it (r1 = row j*C + C, r2 = row
-// j*C + C + 1; 0 past the last chunk), and rows 0, 1, n-2, n-1 of the system
-// (for periodic wrap-around).  Entries an Rhs with R = 1 does not read stay 0.
+// Values around a chunk: the R rows above it (l1 = row j*C - 1, l2, l3;
+// 0 for the first chunk) and below it (r1 = row j*C + C, r2, r3; 0 past the
+// last chunk), and rows 0, 1, 2, n-3, n-2, n-1 of the system (for periodic
+// wrap-around).  Entries a smaller R does not read stay 0.
 struct Halo {
-    double l1, l2, r1, r2;
-    double e0, e1, en2, en1;
+    double l1, l2, l3, r1, r2, r3;
+    double e0, e1, e2, en3, en2, en1;
 };
 
 // Optional per-run statistic of the fused steps (Cahn-Hilliard coarsening,
@@ -92,6 +95,7 @@ __global__ __launch_bounds__(kMaxBlockThreads) void step_kernel(const double *__
         const bool kval = k < g.m;
         double c[C];
         load_chunk<double, C, FULL>(c, in, row0, kval ? k : g.m - 1, g.ld, g.n);
+        const typename Rhs::State ls = rhs.lane_state(kval ? k : g.m - 1, row0);
 
         for (int64_t step = 0; step < steps; ++step) {
             Halo h = {};
@@ -99,14 +103,25 @@ __global__ __launch_bounds__(kMaxBlockThreads) void step_kernel(const double *__
             h.r1 = shfl(c[0], right);
             if (!has_left) h.l1 = 0.0;
             if (!has_right) h.r1 = 0.0;
-            if constexpr (Rhs::R == 2) {
+            if constexpr (Rhs::R >= 2) {
                 h.l2 = shfl(c[C - 2], left);
                 h.r2 = shfl(c[1], right);
                 if (!has_left) h.l2 = 0.0;
                 if (!has_right) h.r2 = 0.0;
             }
+            if constexpr (Rhs::R >= 3) {
+                h.l3 = shfl(c[C - 3], left);
+                h.r3 = shfl(c[2], right);
+                if (!has_left) h.l3 = 0.0;
+                if (!has_right) h.r3 = 0.0;
+            }
             gather_ends<double, 2, C>(c, lg, g.n, exact, h.e0, h.e1, h.en2, h.en1);
-            rhs.template operator()<C, FULL>(c, h, lg.j, lg.j == lg.P - 1, opaque_v(g.n - row0));
+            if constexpr (Rhs::R >= 3) {
+                h.e2 = shfl(c[2], lg.sl);
+                h.en3 = exact ? shfl(c[C - 3], (g.n / C - 1) * lg.S + lg.sl)
+                              : shfl(pick(c, (g.n - 3) % C), ((g.n - 3) / C) * lg.S + lg.sl);
+            }
+            rhs.template operator()<C, FULL>(c, h, lg.j, lg.j == lg.P - 1, opaque_v(g.n - row0), ls);
             __builtin_amdgcn_sched_barrier(0);
             chunk_solve<double, K, C, CYC>(c, smem_d, lg, g.n, exact, cq);
             if (STATS && (step + 1) % st.every == 0) {
@@ -143,7 +158,7 @@ void step_kernel_split(const double *__restrict__ table, int64_t table_elems, Cy
     extern __shared__ double smem_d[];
     const int64_t tl = SCALAR ? 0 : table_elems;
     double *xch = smem_d + tl;                              // chunk_solve phases
-    double *xd = xch + split_exchange_len(QL);              // [2R][P*S]: rows 0, C-1, 1, C-2
+    double *xd = xch + split_exchange_len(QL);              // [2R][P*S]: rows 0, C-1, 1, C-2, 2, C-3
     double *xs = xd + ((2LL * R * kWave) << QL);            // [P*S]: sums of squares
     typename Src::ptr tab;
     if constexpr (SCALAR) {
@@ -174,13 +189,18 @@ void step_kernel_split(const double *__restrict__ table, int64_t table_elems, Cy
         const bool kval = k < g.m;
         double c[C];
         load_chunk<double, C, true>(c, in, row0, kval ? k : g.m - 1, g.ld, g.n);
+        const typename Rhs::State ls = rhs.lane_state(kval ? k : g.m - 1, row0);
 
         for (int64_t step = 0; step < steps; ++step) {
             xd[me] = c[0];
             xd[PS + me] = c[C - 1];
-            if constexpr (R == 2) {
+            if constexpr (R >= 2) {
                 xd[2 * PS + me] = c[1];
                 xd[3 * PS + me] = c[C - 2];
+            }
+            if constexpr (R >= 3) {
+                xd[4 * PS + me] = c[2];
+                xd[5 * PS + me] = c[C - 3];
             }
             __syncthreads();
             Halo h = {};
@@ -188,13 +208,19 @@ void step_kernel_split(const double *__restrict__ table, int64_t table_elems, Cy
             h.r1 = has_right ? xd[rgt] : 0.0;
             h.e0 = xd[first];
             h.en1 = xd[PS + last];
-            if constexpr (R == 2) {
+            if constexpr (R >= 2) {
                 h.l2 = has_left ? xd[3 * PS + lft] : 0.0;
                 h.r2 = has_right ? xd[2 * PS + rgt] : 0.0;
                 h.e1 = xd[2 * PS + first];
                 h.en2 = xd[3 * PS + last];
             }
-            rhs.template operator()<C, true>(c, h, lg.j, !has_right, C);
+            if constexpr (R >= 3) {
+                h.l3 = has_left ? xd[5 * PS + lft] : 0.0;
+                h.r3 = has_right ? xd[4 * PS + rgt] : 0.0;
+                h.e2 = xd[4 * PS + first];
+                h.en3 = xd[5 * PS + last];
+            }
+            rhs.template operator()<C, true>(c, h, lg.j, !has_right, C, ls);
             __builtin_amdgcn_sched_barrier(0);
             chunk_solve<double, K, C, CYC, true, Src>(c, tab, lg, g.n, 1, cq, xch);
             if (STATS && (step + 1) % st.every == 0) {

@@ -122,6 +122,13 @@ WORKLOADS = {
                                gamma=0.01, T=100.0, seed=SEED_BASE + 7),
     "ch_coarsening_L4pi": dict(kind="ch_coarsening", n=512, length=4.0 * math.pi, m=1 << 20,
                                gamma=0.01, T=100.0, seed=SEED_BASE + 8),
+    # forced Cahn-Hilliard flow-pattern batch (the forced flow-pattern
+    # section): L = 2 pi, n = 512, dt = 0.1 dx, T = 50, gamma = 0.01, v and k
+    # fixed per batch, a 768 x 768 grid of (f0 in [0, 2], <C> in [0, 1.5]),
+    # initial states <C> + uniform[-0.1, 0.1)
+    "ch_forced_flowmap_v05": dict(kind="ch_forced", n=512, length=2.0 * math.pi, grid=768,
+                                  v=0.5, k=1.0, f0=(0.0, 2.0), mean=(0.0, 1.5), gamma=0.01,
+                                  T=50.0, seed=SEED_BASE + 9),
     # Crank-Nicolson time stepping on the grid of the paper's benchmark tables
     # (1000 steps; n = 64, 256, 1024; m = 2^6, 2^12, 2^16); the step size is
     # not printed, sigma = 1 is this build's choice (it does not change the work)

@@ -195,6 +195,30 @@ class Factor:
                                          _stream_ptr(c)))
         return out, lbar[:samples]
 
+    def ch_forced_step(self, c: torch.Tensor, alpha: float, beta: torch.Tensor,
+                       amp: torch.Tensor, kdx: torch.Tensor, steps: int = 1,
+                       out: torch.Tensor | None = None) -> torch.Tensor:
+        """Forced Cahn-Hilliard steps in the frame of the travelling wave; per
+        run k: beta[k] = dt v / dx, amp[k] = dt f0 k, kdx[k] = k dx (float64
+        device tensors of m entries)."""
+        m, ld = _batch_view(c, self.n, torch.float64, "c")
+        for name, t in (("beta", beta), ("amp", amp), ("kdx", kdx)):
+            if (t.dtype != torch.float64 or t.device != c.device or t.numel() != m
+                    or not t.is_contiguous()):
+                raise ValueError("%s must be a contiguous float64 tensor of m entries on c's device" % name)
+        if out is None:
+            out = torch.empty_like(c)
+        if _batch_view(out, self.n, torch.float64, "out") != (m, ld):
+            raise ValueError("out must match c in shape and strides")
+        with torch.cuda.device(c.device):
+            check(lib().bb_ch_forced_step(self._handle, ctypes.c_void_p(c.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr()), m, ld, float(alpha),
+                                          ctypes.c_void_p(beta.data_ptr()),
+                                          ctypes.c_void_p(amp.data_ptr()),
+                                          ctypes.c_void_p(kdx.data_ptr()), int(steps),
+                                          _stream_ptr(c)))
+        return out
+
     def cn_step(self, c: torch.Tensor, w, steps: int = 1,
                 out: torch.Tensor | None = None) -> torch.Tensor:
         """`steps` Crank-Nicolson steps A c' = B c with B the constant stencil w

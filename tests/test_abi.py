@@ -34,7 +34,8 @@ def test_header_declares_expected_entry_points():
     for must in ["bb_factor_shared_tri", "bb_factor_shared_penta", "bb_factor_shared_tri_cyclic",
                  "bb_factor_shared_penta_cyclic", "bb_solve_batch_tri", "bb_solve_batch_penta",
                  "bb_solve_batch_tri_adjoint", "bb_solve_batch_penta_adjoint", "bb_band_grad",
-                 "bb_ch_step", "bb_cn_step", "bb_status_string", "bb_last_error_message"]:
+                 "bb_ch_step", "bb_ch_step_stats", "bb_ch_forced_step", "bb_cn_step",
+                 "bb_status_string", "bb_last_error_message"]:
         assert must in names
 
 
@@ -133,6 +134,10 @@ def test_solve_argument_checks_need_no_gpu(L):
     assert L.bb_ch_step_stats(hc, fake, fake, 4, 4, 1.0, 4, 1, fake, None, 1 << 20, None) == -1  # no workspace
     assert L.bb_ch_stats_workspace_bytes(hc, 4, 4) == 8 * 4             # one group of 4 runs, 4 samples
     assert L.bb_ch_step_stats(hc, fake, fake, 4, 4, 1.0, 4, 1, fake, fake, 8 * 4 - 1, None) == -1  # too small
+    assert L.bb_ch_forced_step(h, fake, fake, 4, 4, 1.0, fake, fake, fake, 1, None) == -1  # not cyclic penta
+    assert L.bb_ch_forced_step(hc, fake, fake, 4, 4, 1.0, None, fake, fake, 1, None) == -1  # no beta
+    assert L.bb_ch_forced_step(hc, fake, fake, 4, 4, 1.0, fake, fake, fake, 0, None) == -1  # steps < 1
+    assert L.bb_ch_forced_step(hc, None, None, 0, 1, 1.0, None, None, None, 1, None) == 0   # m = 0
     L.bb_factor_destroy(hc)
     assert L.bb_cn_step(h, None, fake, fake, 4, 4, 1, None) == -1           # no stencil
     assert L.bb_cn_step(h, bad, fake, fake, 4, 4, 1, None) == -1            # weight not finite

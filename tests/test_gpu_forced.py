@@ -1,0 +1,101 @@
+"""GPU parity of the fused forced Cahn-Hilliard steps in the frame of the
+travelling wave (per-run advection speed and forcing, HJ-WENO5 advection)
+against the FP64 oracle, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2107_05395_amd import inputs
+from tests.gpu_util import dev, host, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib_loaded():
+    from paper_2107_05395_amd import solver  # noqa: F401
+    oracle.build()
+
+
+def _setup(n, m, seed, L=2 * math.pi):
+    """Flow-pattern style batch: dt = 0.1 dx, gamma = 0.01; per run a speed
+    v in [-1, 1] (some exactly 0), amplitude f0 in [0, 2], wavenumber k in
+    {1, 2, 3}, mean concentration in [0, 1.5] plus U[-0.1, 0.1)."""
+    from paper_2107_05395_amd import Factor
+    dx = L / n
+    dt = 0.1 * dx
+    sigma, alpha = inputs.ch_parameters(n=n, length=L, gamma=0.01, dt=dt)
+    g = inputs.rng(seed)
+    v = g.uniform(-1, 1, m)
+    v[::7] = 0.0
+    f0 = g.uniform(0, 2, m)
+    k = g.integers(1, 4, m).astype(np.float64) * (2 * math.pi / L)
+    mean = g.uniform(0, 1.5, m)
+    c0 = mean + inputs.uniform_batch(n, m, seed=seed + 1, lo=-0.1, hi=0.1)
+    beta, amp, kdx = oracle.ch_forced_parameters(dt, dx, v, f0, k)
+    f = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
+    return f, sigma, alpha, c0, beta, amp, kdx
+
+
+@pytest.mark.parametrize("n,m", [(256, 300), (512, 300), (64, 300), (1024, 300), (300, 200),
+                                 (1000, 100), (7, 50), (5, 40), (256, (1 << 16) + 3),
+                                 (64, 70000)])
+def test_forced_steps_match_oracle(n, m):
+    say("forced", n, m)
+    f, sigma, alpha, c0, beta, amp, kdx = _setup(n, m, seed=n + m)
+    steps = 5
+    cols = np.unique(np.r_[np.linspace(0, m - 1, 300).astype(np.int64), m - 1])
+    ref = oracle.ch_forced_step(c0[:, cols], sigma, alpha, beta[cols], amp[cols], kdx[cols],
+                                steps=steps)
+    out = host(f.ch_forced_step(dev(c0), alpha, dev(beta), dev(amp), dev(kdx), steps=steps))
+    err = rel_err(out[:, cols], ref)
+    say("  rel err", err)
+    assert err < 1e-11
+
+
+@pytest.mark.parametrize("n", [64, 256, 512, 1024])
+def test_forced_kernel_variants_agree_bitwise(n, monkeypatch):
+    """Scalar coefficients with one chunk per wave, the LDS split group and
+    the LDS one-wave group do the same arithmetic (64-row chunks forced)."""
+    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", "64")
+    m = 3000
+    f, sigma, alpha, c0, beta, amp, kdx = _setup(n, m, seed=7 * n)
+    args = (dev(beta), dev(amp), dev(kdx))
+    t = dev(c0)
+    a = host(f.ch_forced_step(t, alpha, *args, steps=4))
+    monkeypatch.setenv("BANDBATCH_CH_UNIFORM", "0")
+    assert np.array_equal(a, host(f.ch_forced_step(t, alpha, *args, steps=4)))
+    monkeypatch.setenv("BANDBATCH_WAVES_PER_SYSTEM", "1")
+    assert np.array_equal(a, host(f.ch_forced_step(t, alpha, *args, steps=4)))
+
+
+@pytest.mark.parametrize("chunk", ["4", "8", "16", "32"])
+def test_forced_chunk_sizes_match_oracle(chunk, monkeypatch):
+    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", chunk)
+    for n in (256, 250):
+        f, sigma, alpha, c0, beta, amp, kdx = _setup(n, 130, seed=11 + n)
+        ref = oracle.ch_forced_step(c0, sigma, alpha, beta, amp, kdx, steps=3)
+        out = host(f.ch_forced_step(dev(c0), alpha, dev(beta), dev(amp), dev(kdx), steps=3))
+        assert rel_err(out, ref) < 1e-11, (n, chunk)
+
+
+def test_forced_without_forcing_matches_plain_steps_and_in_place():
+    n, m = 256, 500
+    f, sigma, alpha, c0, beta, amp, kdx = _setup(n, m, seed=3)
+    z = torch.zeros(m, dtype=torch.float64, device="cuda")
+    t = dev(c0)
+    a = host(f.ch_forced_step(t, alpha, z, z, dev(kdx), steps=6))
+    b = host(f.ch_step(t, alpha, steps=6))
+    assert rel_err(a, b) < 1e-13
+    f.ch_forced_step(t, alpha, dev(beta), dev(amp), dev(kdx), steps=6, out=t)
+    ref = oracle.ch_forced_step(c0, sigma, alpha, beta, amp, kdx, steps=6)
+    assert rel_err(host(t), ref) < 1e-11
+
+
+def test_forced_rejects_bad_parameter_tensors():
+    f, sigma, alpha, c0, beta, amp, kdx = _setup(64, 10, seed=4)
+    with pytest.raises(ValueError):
+        f.ch_forced_step(dev(c0), alpha, dev(beta[:5]), dev(amp), dev(kdx))
