@@ -19,6 +19,8 @@ systems the oracle solves one by one, plus properties that hold at any size.
     sampled systems.
   * Cahn-Hilliard coarsening, L = 2 pi (n=256, m=2^20, dt = 0.1 dx): the
     statistic after each of 4 steps over all 2^20 runs against the oracle.
+  * forced Cahn-Hilliard flow-pattern batch (768 x 768 runs, n=512): 20
+    steps, sampled runs.
 """
 import numpy as np
 import pytest
@@ -224,3 +226,30 @@ def test_ch_coarsening_statistic_full_batch():
     assert err < 1e-11
     cols = sample_cols(m, 512, seed=6)
     assert rel_err(cols_of(out, cols), ref_c[:, cols]) < 1e-12
+
+
+def test_forced_flowmap_batch_sampled():
+    """The forced flow-pattern batch at its full size (768 x 768 runs, n = 512)
+    in the bench's launch configuration, 20 steps, sampled runs."""
+    import math
+    from paper_2107_05395_amd import Factor
+    spec = inputs.WORKLOADS["ch_forced_flowmap_v05"]
+    n, L, G = spec["n"], spec["length"], spec["grid"]
+    m = G * G
+    dx = L / n
+    dt = 0.1 * dx
+    sigma, alpha = inputs.ch_parameters(n=n, length=L, gamma=spec["gamma"], dt=dt)
+    f0 = np.repeat(np.linspace(spec["f0"][0], spec["f0"][1], G), G)
+    mean = np.tile(np.linspace(spec["mean"][0], spec["mean"][1], G), G)
+    beta, amp, kdx = oracle.ch_forced_parameters(dt, dx, np.full(m, spec["v"]), f0,
+                                                 np.full(m, spec["k"]))
+    c0 = mean + inputs.uniform_batch(n, m, seed=spec["seed"], lo=-0.1, hi=0.1)
+    cols = sample_cols(m, 256, seed=7)
+    ref = oracle.ch_forced_step(c0[:, cols], sigma, alpha, beta[cols], amp[cols], kdx[cols],
+                                steps=20)
+    f = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = f.ch_forced_step(dv(c0), alpha, dv(beta), dv(amp), dv(kdx), steps=20)
+    err = rel_err(cols_of(out, cols), ref)
+    say("forced flow-map batch, 20 steps, rel err", err)
+    assert err < 1e-11
