@@ -669,7 +669,7 @@ def main():
                     help="one dispatch of each kernel (for rocprofv3 counter runs); no timing")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs every system of a batch on a "
+        print("bench.py measures one GPU only: the library runs every system of a batch on a "
               "single MI355X and has no multi-GPU path (requested --gpus %d)" % args.gpus,
               file=sys.stderr)
         print(json.dumps({"error": "single-GPU benchmark; --gpus %d not supported" % args.gpus}))

@@ -131,7 +131,7 @@ WORKLOADS = {
                                   T=50.0, seed=SEED_BASE + 9),
     # Crank-Nicolson time stepping on the grid of the paper's benchmark tables
     # (1000 steps; n = 64, 256, 1024; m = 2^6, 2^12, 2^16); the step size is
-    # not printed, sigma = 1 is this build's choice (it does not change the work)
+    # not printed; sigma = 1 is taken here (it does not change the work)
     "cn_diffusion_grid": dict(kind="cn", problem="diffusion", ns=(64, 256, 1024),
                               ms=(1 << 6, 1 << 12, 1 << 16), sigma=1.0, steps=1000,
                               seed=SEED_BASE + 5),
