@@ -31,7 +31,11 @@ __device__ __forceinline__ double weno5(double v1, double v2, double v3, double 
     const double vm = fmax(fmax(fmax(v1 * v1, v2 * v2), fmax(v3 * v3, v4 * v4)), v5 * v5);
     const double eps = fma(1e-6, vm, 1e-99);
     const double t1 = s1 + eps, t2 = s2 + eps, t3 = s3 + eps;
-    const double w1 = 0.1 / (t1 * t1), w2 = 0.6 / (t2 * t2), w3 = 0.3 / (t3 * t3);
+    // 1/t_k from one division: t_k >= 1e-99, so t1 t2 t3 >= 1e-297 stays a
+    // normal double (and below 1e8 for differences of O(1) states)
+    const double inv = 1.0 / (t1 * t2 * t3);
+    const double r1 = t2 * t3 * inv, r2 = t1 * t3 * inv, r3 = t1 * t2 * inv;
+    const double w1 = 0.1 * r1 * r1, w2 = 0.6 * r2 * r2, w3 = 0.3 * r3 * r3;
     return fma(w1, p1, fma(w2, p2, w3 * p3)) / (w1 + w2 + w3);
 }
 
