@@ -32,13 +32,15 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 KERNEL_SOURCES = ("sweep_core.h", "sweep_kernel.h", "sweep.hip", "sweep_f32.hip", "refine_kernel.h",
-                  "refine.hip", "refine_f32rhs.hip", "stepper.h", "ch.hip", "cn_stencil.h",
-                  "cn_tri.hip", "cn_penta.hip", "internal.h")
+                  "refine.hip", "refine_f32rhs.hip", "stepper.h", "ch.hip", "ch_forced.hip",
+                  "cn_stencil.h", "cn_tri.hip", "cn_penta.hip", "internal.h")
 # the device sources behind each kernel whose HBM traffic is recorded
 KERNEL_FAMILIES = {
     "sweep": ("sweep_core.h", "sweep_kernel.h", "sweep.hip", "internal.h"),
     "refine": ("sweep_core.h", "refine_kernel.h", "refine.hip", "internal.h"),
-    "stepper": ("sweep_core.h", "stepper.h", "cn_stencil.h", "cn_tri.hip", "ch.hip", "internal.h"),
+    "stepper_cn": ("sweep_core.h", "stepper.h", "cn_stencil.h", "cn_tri.hip", "internal.h"),
+    "stepper_ch": ("sweep_core.h", "stepper.h", "ch.hip", "internal.h"),
+    "stepper_forced": ("sweep_core.h", "stepper.h", "ch_forced.hip", "internal.h"),
 }
 
 
@@ -387,7 +389,7 @@ def bench_cn(args, torch):
                               "peak": PEAK_HBM_GBS, "unit": "GB/s",
                               "frac": 16.0 * n * m * T / tp / 1e9 / PEAK_HBM_GBS,
                               "traffic": measured_traffic(args.workload,
-                                                          "per_step_n%d_m%d" % (n, m), "stepper")},
+                                                          "per_step_n%d_m%d" % (n, m), "stepper_cn")},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_cn(bands, w, n, seed + 1, args.cpu_seconds)
