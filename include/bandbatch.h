@@ -189,7 +189,7 @@ bb_status bb_ch_step(bb_factor f, const double *c_in, double *c_out, int64_t m, 
  * workspace: device scratch of at least bb_ch_stats_workspace_bytes(f, m,
  * steps / every) bytes, caller-owned: one row of partial sums per group of
  * runs the kernel handles together (at most m rows, 8 bytes per sample; m/64
- * rows for 64-row chunks tiling n into at most 8).  The sums run in a fixed
+ * rows when the chunks tile n into at most 8).  The sums run in a fixed
  * order that does not depend on the device: lbar is bitwise reproducible,
  * and c_out is bitwise what bb_ch_step writes.
  * Errors: as bb_ch_step; BB_ERR_ARG also for every < 1, lbar NULL, or a

@@ -167,7 +167,7 @@ StepPlan step_plan(int64_t n, int64_t m)
     while ((1 << pl.log2P) < pl.P) ++pl.log2P;
     const bool full = (int64_t)C * pl.P == n;
     const char *uni = std::getenv("BANDBATCH_CH_UNIFORM");
-    pl.scalar = full && C == 64 && pl.log2P <= 3 && !(uni && std::atoi(uni) == 0);
+    pl.scalar = full && C >= 16 && pl.log2P <= 3 && !(uni && std::atoi(uni) == 0);
     pl.log2Q = 0;
     if (pl.scalar)
         pl.log2Q = pl.log2P;

@@ -251,7 +251,7 @@ constexpr size_t split_step_lds(int QL, int R)
 
 // Launch `steps` fused steps.  g.log2Q > 0 selects the split kernel (full
 // decomposition, log2Q <= 3), with the coefficients through the scalar cache
-// when `scalar` (then log2Q == log2P and C == 64); `scalar` with
+// when `scalar` (then log2Q == log2P and C is 16, 32 or 64); `scalar` with
 // g.log2Q == g.log2P == 0 runs one-chunk systems the same way.  Otherwise the
 // LDS kernel with one wave per group.
 template <class Rhs, int K, bool CYC, bool STATS = false>
@@ -261,14 +261,25 @@ hipError_t launch_stepper(const double *table, int64_t table_elems, const Cyclic
                           StepStats st = StepStats{})
 {
     if (scalar) {
-        if (g.C != 64 || g.log2Q != g.log2P || g.log2Q > 3 || !is_full(g)) return hipErrorInvalidValue;
+        // one chunk per wave: 16-, 32- or 64-row chunks tiling n into at most 8
+        if ((g.C != 16 && g.C != 32 && g.C != 64) || g.log2Q != g.log2P || g.log2Q > 3 || !is_full(g))
+            return hipErrorInvalidValue;
         const size_t xl = split_step_lds(g.log2Q, Rhs::R);
-        switch (g.log2Q) {
-        case 0: return launch_grid_split(step_kernel_split<Rhs, K, CYC, 64, 0, true, STATS>, xl, g.groups, 1, s, table, table_elems, q, g, rhs, steps, st, in, out);
-        case 1: return launch_grid_split(step_kernel_split<Rhs, K, CYC, 64, 1, true, STATS>, xl, g.groups, 2, s, table, table_elems, q, g, rhs, steps, st, in, out);
-        case 2: return launch_grid_split(step_kernel_split<Rhs, K, CYC, 64, 2, true, STATS>, xl, g.groups, 4, s, table, table_elems, q, g, rhs, steps, st, in, out);
-        default: return launch_grid_split(step_kernel_split<Rhs, K, CYC, 64, 3, true, STATS>, xl, g.groups, 8, s, table, table_elems, q, g, rhs, steps, st, in, out);
+#define BB_SCALAR(CC)                                                                                    \
+        case CC:                                                                                         \
+            switch (g.log2Q) {                                                                           \
+            case 0: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 0, true, STATS>, xl, g.groups, 1, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            case 1: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 1, true, STATS>, xl, g.groups, 2, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            case 2: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 2, true, STATS>, xl, g.groups, 4, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            default: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 3, true, STATS>, xl, g.groups, 8, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            }
+        switch (g.C) {
+            BB_SCALAR(16)
+            BB_SCALAR(32)
+            BB_SCALAR(64)
+        default: return hipErrorInvalidValue;
         }
+#undef BB_SCALAR
     }
     if (g.log2Q > 0) {
         // LDS table, group split over 2^log2Q waves: 32- and 64-row chunks
