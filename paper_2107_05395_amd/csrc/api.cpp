@@ -150,7 +150,7 @@ struct StepPlan {
 };
 
 // Rows per lane: 64 (two waves per SIMD), or latency_chunk for small
-// batches.  Systems split over several waves when the chunks tile n: one
+// batches, or 32 below two waves per SIMD where that keeps one chunk per wave.  Systems split over several waves when the chunks tile n: one
 // chunk per wave with scalar coefficients up to 8 chunks, else the LDS table
 // with 32 systems per group (4 waves at P = 8, 8 waves from P = 16; n = 1024,
 // m = 2^16: 0.063 vs 0.096 ms per tri step over one wave per group).
@@ -159,7 +159,19 @@ struct StepPlan {
 StepPlan step_plan(int64_t n, int64_t m)
 {
     int C = bb::choose_chunk(n, std::min(max_chunk(BB_F64), bb::kChunkMaxCH));
-    if (!std::getenv("BANDBATCH_MAX_CHUNK")) C = latency_chunk(n, m, C);
+    if (!std::getenv("BANDBATCH_MAX_CHUNK")) {
+        const int64_t lanes64 = m * bb::lanes_for(n, C);
+        C = latency_chunk(n, m, C);
+        // Fewer than two waves per SIMD at 64 rows: 32-row chunks (still one
+        // per wave, scalar coefficients) double the waves.  Measured, ms per
+        // 200 fused steps, 64 vs 32 rows: penta n = 64, m = 2^16 0.84 vs
+        // 0.71; n = 128, m = 2^15 1.18 vs 0.80; n = 256, m = 2^14 1.22 vs
+        // 0.98; CH n = 64, m = 2^16 0.87 vs 0.67; equal or worse from 2^17
+        // lanes on.
+        if (C == 64 && lanes64 < (int64_t(1) << 17) && 32LL * bb::lanes_for(n, 32) == n &&
+            bb::lanes_for(n, 32) <= 8)
+            C = 32;
+    }
     StepPlan pl;
     pl.C = C;
     pl.P = bb::lanes_for(n, C);

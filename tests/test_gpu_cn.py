@@ -165,3 +165,20 @@ def test_cn_rejects_wrong_stencil_length():
     f = _factor("tri", bands, True)
     with pytest.raises(ValueError):
         f.cn_step(dev(inputs.uniform_batch(64, 4, seed=1)), (1, 2, 3, 4, 5))
+
+
+@pytest.mark.parametrize("kind,n", [("tri", 64), ("tri", 128), ("tri", 256), ("penta", 64),
+                                    ("penta", 256)])
+def test_cn_short_chunk_scalar_kernel_matches_lds(kind, n, monkeypatch):
+    """Small batches take 16- or 32-row chunks; when they tile n into at most
+    eight the scalar-coefficient kernel runs them: bitwise what the LDS
+    kernel gives, and the oracle's result."""
+    m = 1000
+    bands, w = _problem(kind, n, 0.8)
+    f = _factor(kind, bands, True)
+    c0h = inputs.uniform_batch(n, m, seed=80 + n)
+    c0 = dev(c0h)
+    a = host(f.cn_step(c0, w, steps=7))
+    assert rel_err(a, oracle.cn_step(bands, w, c0h, steps=7)) < 1e-12
+    monkeypatch.setenv("BANDBATCH_CH_UNIFORM", "0")
+    assert np.array_equal(a, host(f.cn_step(c0, w, steps=7)))
