@@ -336,8 +336,9 @@ def cpu_baseline_cn(bands, w, n, seed, budget_s):
 
 def bench_cn(args, torch):
     """Crank-Nicolson time stepping over the paper's benchmark grid: every
-    (n, m) point runs the workload's step count twice, all steps in one fused
-    launch (state on chip) and one launch per step (state through HBM)."""
+    (n, m) point runs the workload's step count three ways: all steps in one
+    fused launch (state on chip), one launch per step (state through HBM),
+    and those single-step launches replayed from a HIP graph."""
     from paper_2107_05395_amd import Factor, inputs
     import oracle
     spec = dict(inputs.WORKLOADS[args.workload])
@@ -363,7 +364,18 @@ def bench_cn(args, torch):
                 for i in range(T):
                     f.cn_step(bufs[i & 1], w, out=bufs[(i + 1) & 1])
             tp, _ = time_launches(per_step, 1, 1, torch)
+            # the same T single-step launches replayed from a HIP graph
+            g = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                with torch.cuda.graph(g, stream=side):
+                    per_step()
+            torch.cuda.current_stream().wait_stream(side)
+            tg, _ = time_launches(g.replay, 1, 1, torch)
+            del g
             grid.append({"n": n, "m": m, "fused_ms": 1e3 * tf, "per_step_launch_ms": 1e3 * tp,
+                         "per_step_graph_ms": 1e3 * tg,
                          "fused_system_steps_per_s": m * T / tf,
                          "per_step_hbm_gbs": 16.0 * n * m * T / tp / 1e9,
                          "rel_err_vs_oracle": err,
