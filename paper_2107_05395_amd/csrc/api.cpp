@@ -211,6 +211,11 @@ bb::SweepGeom step_geom(int64_t n, int64_t m, int64_t ld, const StepPlan &pl)
     return g;
 }
 
+// Decomposition, device table (the factor's own primal FP64 table for that
+// chunk size, shared with the solves) and launch geometry of a fused stepper.
+bb_status stepper_setup(bb::Factor &f, int dev, int64_t m, int64_t ld, StepPlan *pl,
+                        bb::DeviceTable *tab, bb::SweepGeom *g);
+
 bb_status make(int kind, const double *a, const double *b, const double *c, const double *d,
                const double *e, int64_t n, bb_factor *out)
 {
@@ -273,6 +278,19 @@ bb_status device_table(bb::Factor &f, std::map<Key, bb::DeviceTable> &cache, con
     if (e != hipSuccess) { (void)hipFree(t.ptr); return hip_fail(e, "hipMemcpy of the coefficient table"); }
     cache[key] = t;
     *out = t;
+    return BB_OK;
+}
+
+bb_status stepper_setup(bb::Factor &f, int dev, int64_t m, int64_t ld, StepPlan *pl,
+                        bb::DeviceTable *tab, bb::SweepGeom *g)
+{
+    *pl = step_plan(f.n, m);
+    const int C = pl->C, P = pl->P;
+    bb_status st = device_table(f, f.dev, std::make_tuple(dev, 0, 0, C, 0), false,
+                                [&] { return bb::build_table(f.primal, f.K, f.cyclic, f.n, C, P); },
+                                tab);
+    if (st != BB_OK) return st;
+    *g = step_geom(f.n, m, ld, *pl);
     return BB_OK;
 }
 
@@ -562,12 +580,10 @@ bb_status ch_steps(bb_factor fh, const double *c_in, double *c_out, int64_t m, i
     // The fused steps are bound by arithmetic and coefficient reads, not HBM
     // (64 rows per lane, two waves per SIMD: 0.39 vs 0.52 ms per step at
     // n = 256, m = 2^20 against 128 rows per lane); see step_plan.
-    const StepPlan pl = step_plan(f.n, m);
+    StepPlan pl;
     bb::DeviceTable tab;
-    st = device_table(f, f.dev, std::make_tuple(dev, 0, 0, pl.C, 0), false,
-                      [&] { return bb::build_table(f.primal, 2, true, f.n, pl.C, pl.P); }, &tab);
-    if (st != BB_OK) return st;
-    const bb::SweepGeom g = step_geom(f.n, m, ld, pl);
+    bb::SweepGeom g;
+    if ((st = stepper_setup(f, dev, m, ld, &pl, &tab, &g)) != BB_OK) return st;
     hipError_t e = bb::launch_ch((const double *)tab.ptr, tab.elems, f.primal.cor.q, g, pl.scalar,
                                  alpha, steps, c_in, c_out, (hipStream_t)stream, every, samples,
                                  (double *)workspace, lbar);
@@ -613,12 +629,10 @@ bb_status bb_ch_forced_step(bb_factor fh, const double *c_in, double *c_out, int
     if (m == 0) { g_last_error.clear(); return BB_OK; }
     int dev;
     if ((st = current_device(&dev)) != BB_OK) return st;
-    const StepPlan pl = step_plan(f.n, m);
+    StepPlan pl;
     bb::DeviceTable tab;
-    st = device_table(f, f.dev, std::make_tuple(dev, 0, 0, pl.C, 0), false,
-                      [&] { return bb::build_table(f.primal, 2, true, f.n, pl.C, pl.P); }, &tab);
-    if (st != BB_OK) return st;
-    const bb::SweepGeom g = step_geom(f.n, m, ld, pl);
+    bb::SweepGeom g;
+    if ((st = stepper_setup(f, dev, m, ld, &pl, &tab, &g)) != BB_OK) return st;
     hipError_t e = bb::launch_ch_forced((const double *)tab.ptr, tab.elems, f.primal.cor.q, g,
                                         pl.scalar, alpha, beta, amp, kdx, steps, c_in, c_out,
                                         (hipStream_t)stream);
@@ -640,12 +654,10 @@ bb_status bb_cn_step(bb_factor fh, const double *w, const double *c_in, double *
     if (m == 0) { g_last_error.clear(); return BB_OK; }
     int dev;
     if ((st = current_device(&dev)) != BB_OK) return st;
-    const StepPlan pl = step_plan(f.n, m);
+    StepPlan pl;
     bb::DeviceTable tab;
-    st = device_table(f, f.dev, std::make_tuple(dev, 0, 0, pl.C, 0), false,
-                      [&] { return bb::build_table(f.primal, f.K, f.cyclic, f.n, pl.C, pl.P); }, &tab);
-    if (st != BB_OK) return st;
-    const bb::SweepGeom g = step_geom(f.n, m, ld, pl);
+    bb::SweepGeom g;
+    if ((st = stepper_setup(f, dev, m, ld, &pl, &tab, &g)) != BB_OK) return st;
     double wk[5] = {0, 0, 0, 0, 0};
     for (int d = 0; d <= 2 * f.K; ++d) wk[d] = w[d];
     hipError_t e = f.K == 1
