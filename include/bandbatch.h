@@ -111,6 +111,18 @@ bb_status bb_factor_info(bb_factor f, int64_t *n, int32_t *kind, int32_t *chunk)
  * tables are staged in LDS). */
 int64_t bb_max_n(void);
 
+/* The decomposition a call with m systems takes, without running it: rows per
+ * lane (chunk), lanes per system (lanes, a power of two, chunk * lanes >= n),
+ * waves per system group (waves: 1, 2, 4 or 8), and for the fused steppers
+ * whether the coefficients are read through the scalar cache (scalar; one
+ * chunk per wave).  what = 0: a solve or adjoint of precision p; what = 1:
+ * the fused steppers (bb_ch_step, bb_ch_step_stats, bb_ch_forced_step,
+ * bb_cn_step; p is ignored).  Host only: no device is touched.  The tuning
+ * variables of the library are honoured.  Any out pointer may be NULL.
+ * Errors: BB_ERR_ARG (NULL factor, m < 1, what or p unknown). */
+bb_status bb_plan(bb_factor f, int64_t m, int32_t what, bb_precision p, int32_t *chunk,
+                  int32_t *lanes, int32_t *waves, int32_t *scalar);
+
 /* ---------------------------------------------------------------- solves
  * x[:,k] = A^{-1} rhs[:,k] for 0 <= k < m (Appendix A/B batched sweeps, with
  * the periodic correction of Section 3.3 when the factor is cyclic).

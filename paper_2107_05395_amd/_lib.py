@@ -33,6 +33,9 @@ SIGNATURES = {
     "bb_factor_info": (_S, [_FACTOR, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32),
                             ctypes.POINTER(ctypes.c_int32)]),
     "bb_max_n": (_I64, []),
+    "bb_plan": (_S, [_FACTOR, _I64, ctypes.c_int32, _S, ctypes.POINTER(ctypes.c_int32),
+                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                     ctypes.POINTER(ctypes.c_int32)]),
     "bb_solve_batch_tri": (_S, [_FACTOR, _P, _P, _I64, _I64, _S, _P]),
     "bb_solve_batch_penta": (_S, [_FACTOR, _P, _P, _I64, _I64, _S, _P]),
     "bb_solve_batch_tri_cyclic": (_S, [_FACTOR, _P, _P, _I64, _I64, _S, _P]),

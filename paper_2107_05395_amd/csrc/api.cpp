@@ -448,6 +448,39 @@ bb_status bb_factor_upload(bb_factor fh, void *stream)
     return BB_OK;
 }
 
+bb_status bb_plan(bb_factor fh, int64_t m, int32_t what, bb_precision p, int32_t *chunk,
+                  int32_t *lanes, int32_t *waves, int32_t *scalar)
+{
+    if (!fh) return fail(BB_ERR_ARG, "factor is NULL");
+    if (m < 1) return fail(BB_ERR_ARG, "m < 1");
+    if (what != 0 && what != 1) return fail(BB_ERR_ARG, "what must be 0 (solve) or 1 (fused steps)");
+    if (p != BB_F64 && p != BB_F32_REFINE && p != BB_F32 && p != BB_F32_RHS_REFINE)
+        return fail(BB_ERR_ARG, "unknown precision");
+    const bb::Factor &f = fh->f;
+    int C, P, log2Q, sc = 0;
+    if (what == 0) {
+        C = solve_chunk(f.n, m, p);
+        P = bb::lanes_for(f.n, C);
+        int log2P = 0;
+        while ((1 << log2P) < P) ++log2P;
+        const bb::Op op = p == BB_F32_REFINE ? bb::Op::Refine
+                        : p == BB_F32_RHS_REFINE ? bb::Op::RefineF32Rhs : bb::Op::Solve;
+        log2Q = split_log2(log2P, C, (int)f.n, op);
+    } else {
+        const StepPlan pl = step_plan(f.n, m);
+        C = pl.C;
+        P = pl.P;
+        log2Q = pl.log2Q;
+        sc = pl.scalar ? 1 : 0;
+    }
+    if (chunk) *chunk = C;
+    if (lanes) *lanes = P;
+    if (waves) *waves = 1 << log2Q;
+    if (scalar) *scalar = sc;
+    g_last_error.clear();
+    return BB_OK;
+}
+
 bb_status bb_factor_info(bb_factor fh, int64_t *n, int32_t *kind, int32_t *chunk)
 {
     if (!fh) return fail(BB_ERR_ARG, "factor is NULL");

@@ -140,6 +140,14 @@ class Factor:
                 m, ld, _stream_ptr(rhs)))
         return out
 
+    def plan(self, m: int, stepper: bool = False, precision: str = "f64") -> dict:
+        """The decomposition a call with m systems takes (host only)."""
+        out = [ctypes.c_int32() for _ in range(4)]
+        check(lib().bb_plan(self._handle, int(m), 1 if stepper else 0, _lib.PRECISION[precision],
+                            *(ctypes.byref(o) for o in out)))
+        return dict(chunk=out[0].value, lanes=out[1].value, waves=out[2].value,
+                    scalar=bool(out[3].value))
+
     def band_grad(self, lam: torch.Tensor, x: torch.Tensor,
                   grad: torch.Tensor | None = None) -> torch.Tensor:
         """grad[band, i] += -sum_k lam[i,k] x[i+band-nb/2, k]  ->  (nbands, n) float64."""
