@@ -82,6 +82,7 @@ def test_cn_kernel_variants_agree_bitwise(kind, n, monkeypatch):
     f = _factor(kind, bands, True)
     c0h = inputs.uniform_batch(n, m, seed=60 + n)
     c0 = dev(c0h)
+    say("  plan", f.plan(m, stepper=True))
     a = host(f.cn_step(c0, w, steps=steps))
     cols = np.r_[np.arange(0, m, 997), m - 5:m]
     ref = oracle.cn_step(bands, w, np.ascontiguousarray(c0h[:, cols]), steps=steps)
@@ -178,7 +179,10 @@ def test_cn_short_chunk_scalar_kernel_matches_lds(kind, n, monkeypatch):
     f = _factor(kind, bands, True)
     c0h = inputs.uniform_batch(n, m, seed=80 + n)
     c0 = dev(c0h)
+    pl = f.plan(m, stepper=True)
+    assert pl["scalar"] and pl["chunk"] in (16, 32), pl
     a = host(f.cn_step(c0, w, steps=7))
     assert rel_err(a, oracle.cn_step(bands, w, c0h, steps=7)) < 1e-12
     monkeypatch.setenv("BANDBATCH_CH_UNIFORM", "0")
+    assert not f.plan(m, stepper=True)["scalar"]
     assert np.array_equal(a, host(f.cn_step(c0, w, steps=7)))

@@ -252,6 +252,7 @@ def test_small_batches_take_short_chunks(n, m, rows, monkeypatch):
     32 chunks per system): bitwise what forcing that chunk gives, and within
     the FP64 tolerance of the oracle."""
     f, bands = make("tri", n, seed=n + m)
+    assert f.plan(m)["chunk"] == rows
     rhs = inputs.uniform_batch(n, m, seed=n + m + 1)
     t = dev(rhs)
     auto = host(f.solve(t))
