@@ -99,3 +99,31 @@ def test_forced_rejects_bad_parameter_tensors():
     f, sigma, alpha, c0, beta, amp, kdx = _setup(64, 10, seed=4)
     with pytest.raises(ValueError):
         f.ch_forced_step(dev(c0), alpha, dev(beta[:5]), dev(amp), dev(kdx))
+
+
+def test_steppers_on_strided_batches():
+    """ld > m (a column slice of a wider array) for the Crank-Nicolson, the
+    Cahn-Hilliard-with-statistic and the forced steps: the same results as
+    on contiguous arrays, and the columns past m untouched."""
+    n, m, extra = 256, 700, 37
+    f, sigma, alpha, c0, beta, amp, kdx = _setup(n, m, seed=21)
+    wide = torch.zeros(n, m + extra, dtype=torch.float64, device="cuda")
+    wide[:, :m] = dev(c0)
+    wide[:, m:] = 7.0
+    out_wide = torch.full_like(wide, 9.0)
+    view, oview = wide[:, :m], out_wide[:, :m]
+    got = f.ch_forced_step(view, alpha, dev(beta), dev(amp), dev(kdx), steps=4, out=oview)
+    ref = f.ch_forced_step(dev(c0), alpha, dev(beta), dev(amp), dev(kdx), steps=4)
+    assert np.array_equal(host(got), host(ref))
+    assert torch.all(out_wide[:, m:] == 9.0) and torch.all(wide[:, m:] == 7.0)
+    out_wide.fill_(9.0)
+    _, lb = f.ch_step_stats(view, alpha, steps=4, every=2, out=oview)
+    _, lb_ref = f.ch_step_stats(dev(c0), alpha, steps=4, every=2)
+    assert np.array_equal(host(lb), host(lb_ref)) and torch.all(out_wide[:, m:] == 9.0)
+    from paper_2107_05395_amd import Factor
+    bands, w = inputs.cn_hyperdiffusion_problem(n, 0.5)
+    g = Factor.penta(*bands, cyclic=True)
+    out_wide.fill_(9.0)
+    got = g.cn_step(view, w, steps=3, out=oview)
+    assert np.array_equal(host(got), host(g.cn_step(dev(c0), w, steps=3)))
+    assert torch.all(out_wide[:, m:] == 9.0)
