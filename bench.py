@@ -613,7 +613,16 @@ def bench_adjoint(args, torch):
         out[prec] = (t, rel_err_cols(du0, du0_ref))
     k = args.steps
     t64 = out["f64"][0]
+    # algorithmic HBM bytes of one training step: T forward solves, T solves
+    # recomputed from the checkpoints, T adjoint solves (16 B per row each),
+    # T band-gradient reductions (read lambda and u: 16 B per row) and the
+    # loss (read u and target, write the gradient: 24 B per row)
+    step_bytes = (4 * T * 16.0 + 24.0) * n * m
     return {
+        "roofline": {"bound": "hbm", "achieved": step_bytes * k / t64 / 1e9, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": step_bytes * k / t64 / 1e9 / PEAK_HBM_GBS,
+                     "traffic": None,
+                     "note": "whole training step, %.0f GB of algorithmic traffic" % (step_bytes / 1e9)},
         "metric": "system-steps/s (forward + backward)", "value": m * T * k / t64,
         "unit": "system-steps/s", "n_gpus": 1, "steps": k, "warmup": args.warmup,
         "ms_per_step": 1e3 * t64 / k, "higher_is_better": True, "scaling": "weak",
