@@ -613,11 +613,14 @@ def bench_adjoint(args, torch):
         out[prec] = (t, rel_err_cols(du0, du0_ref))
     k = args.steps
     t64 = out["f64"][0]
-    # algorithmic HBM bytes of one training step: T forward solves, T solves
-    # recomputed from the checkpoints, T adjoint solves (16 B per row each),
-    # T band-gradient reductions (read lambda and u: 16 B per row) and the
-    # loss (read u and target, write the gradient: 24 B per row)
-    step_bytes = (4 * T * 16.0 + 24.0) * n * m
+    # algorithmic HBM bytes of one FP64 training step: the forward pass in
+    # ceil(T/c) fused launches (read the checkpoint, write the next one or
+    # u_T), T single steps recomputed from the checkpoints, T adjoint solves
+    # (16 B per row each), T band-gradient reductions (read lambda and u:
+    # 16 B per row) and the loss (read u and target, write the gradient:
+    # 24 B per row)
+    segments = -(-T // every)
+    step_bytes = ((segments + 3 * T) * 16.0 + 24.0) * n * m
     return {
         "roofline": {"bound": "hbm", "achieved": step_bytes * k / t64 / 1e9, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": step_bytes * k / t64 / 1e9 / PEAK_HBM_GBS,

@@ -8,7 +8,12 @@ Both run in libbandbatch's kernels; torch only sees the results.
 ``banded_rollout`` differentiates T implicit steps u_t = A^{-1} u_{t-1}
 with activation checkpointing: the forward pass keeps every
 ``checkpoint_every``-th state, and the backward pass recomputes each segment
-from its checkpoint before walking it backwards.
+from its checkpoint before walking it backwards.  In FP64 the steps run in
+the fused time-stepping kernel with the identity as right-hand-side
+stencil: the forward pass takes one launch per segment with the state held
+on chip, and the recomputation steps one launch per state.  Both take the
+same kernel and decomposition, and a fused launch of k steps reproduces k
+single-step launches bitwise, so the recomputed states equal the forward's.
 """
 from __future__ import annotations
 
@@ -65,6 +70,18 @@ def banded_solve(rhs, bands, cyclic: bool = False, precision: str = "f64"):
     return BandedSolve.apply(rhs, cyclic, precision, *bands)
 
 
+def _advance(f: Factor, u, k: int, precision: str):
+    """u_{t+k} from u_t: k solves u' = A^{-1} u.  FP64 runs them in one launch
+    of the fused stepper (A u' = I u); other precisions solve step by step."""
+    if precision == "f64":
+        identity = [0.0] * f.nbands
+        identity[f.nbands // 2] = 1.0
+        return f.cn_step(u, identity, steps=k)
+    for _ in range(k):
+        u = f.solve(u, precision=precision)
+    return u
+
+
 class BandedRollout(torch.autograd.Function):
     """u_T after `steps` solves u_t = A(bands)^{-1} u_{t-1}, checkpointed."""
 
@@ -75,9 +92,12 @@ class BandedRollout(torch.autograd.Function):
         f = _factor_from(bands, _kind(len(bands)), False)
         u = u0.detach().contiguous()
         checkpoints = [u]
-        for t in range(1, steps + 1):
-            u = f.solve(u, precision=precision)
-            if t % checkpoint_every == 0 and t < steps:
+        t = 0
+        while t < steps:
+            k = min(checkpoint_every, steps - t)
+            u = _advance(f, u, k, precision)
+            t += k
+            if t < steps:
                 checkpoints.append(u)
         ctx.factor, ctx.steps, ctx.every, ctx.precision = f, steps, checkpoint_every, precision
         ctx.band_devices = [b.device for b in bands]
@@ -108,7 +128,7 @@ class BandedRollout(torch.autograd.Function):
             states = [ctx.checkpoints[i]]
             with torch.cuda.stream(ahead):
                 for _ in range(s, min(s + every, steps)):
-                    states.append(f.solve(states[-1], precision=prec))
+                    states.append(_advance(f, states[-1], 1, prec))
             return states
 
         # segments [s, e): states u_s .. u_e; checkpoint i holds u_{i*every}
