@@ -117,7 +117,7 @@ int64_t bb_max_n(void);
  * whether the coefficients are read through the scalar cache (scalar; one
  * chunk per wave).  what = 0: a solve or adjoint of precision p; what = 1:
  * the fused steppers (bb_ch_step, bb_ch_step_stats, bb_ch_forced_step,
- * bb_cn_step; p is ignored).  Host only: no device is touched.  The tuning
+ * bb_cn_step, bb_cn_trajectory; p is ignored).  Host only: no device is touched.  The tuning
  * variables of the library are honoured.  Any out pointer may be NULL.
  * Errors: BB_ERR_ARG (NULL factor, m < 1, what or p unknown). */
 bb_status bb_plan(bb_factor f, int64_t m, int32_t what, bb_precision p, int32_t *chunk,
@@ -249,6 +249,18 @@ bb_status bb_ch_forced_step(bb_factor f, const double *c_in, double *c_out, int6
  * Errors: BB_ERR_ARG (w NULL or not finite, steps, sizes), BB_ERR_HIP. */
 bb_status bb_cn_step(bb_factor f, const double *w, const double *c_in, double *c_out, int64_t m,
                      int64_t ld, int64_t steps, void *stream);
+
+/* The same steps, keeping every state: the state after step s (s = 0 ..
+ * steps-1) goes to traj + s * n * ld, each an interleaved n x ld array like
+ * c_in.  One kernel for all steps, reading c_in once and writing each state
+ * once; the states are bitwise those of `steps` calls of bb_cn_step with
+ * steps = 1 (same kernel and decomposition).  With w the identity (w[K] = 1,
+ * the rest 0) this is a trajectory of implicit solves A u_{s+1} = u_s, which
+ * the recomputation between checkpoints of a differentiated rollout uses.
+ * traj: device double, steps * n * ld elements, not overlapping c_in.
+ * Errors: as bb_cn_step, and BB_ERR_ARG if steps * n * ld overflows. */
+bb_status bb_cn_trajectory(bb_factor f, const double *w, const double *c_in, double *traj,
+                           int64_t m, int64_t ld, int64_t steps, void *stream);
 
 /* ---------------------------------------------------------------- loss
  * Mean-squared-error loss of a batch against a target and its gradient:

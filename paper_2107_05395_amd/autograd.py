@@ -11,9 +11,10 @@ with activation checkpointing: the forward pass keeps every
 from its checkpoint before walking it backwards.  In FP64 the steps run in
 the fused time-stepping kernel with the identity as right-hand-side
 stencil: the forward pass takes one launch per segment with the state held
-on chip, and the recomputation steps one launch per state.  Both take the
-same kernel and decomposition, and a fused launch of k steps reproduces k
-single-step launches bitwise, so the recomputed states equal the forward's.
+on chip, and the recomputation of a segment one launch of the same kernel
+that also stores every intermediate state.  A fused launch of k steps, a
+trajectory launch and k single-step launches agree bitwise (same kernel
+arithmetic and decomposition), so the recomputed states equal the forward's.
 """
 from __future__ import annotations
 
@@ -70,13 +71,28 @@ def banded_solve(rhs, bands, cyclic: bool = False, precision: str = "f64"):
     return BandedSolve.apply(rhs, cyclic, precision, *bands)
 
 
+def _identity(f: Factor):
+    w = [0.0] * f.nbands
+    w[f.nbands // 2] = 1.0
+    return w
+
+
+def _trajectory(f: Factor, u, k: int, precision: str):
+    """[u_{t+1}, ..., u_{t+k}] from u_t."""
+    if precision == "f64":
+        return list(f.cn_trajectory(u, _identity(f), k).unbind(0))
+    out = []
+    for _ in range(k):
+        u = f.solve(u, precision=precision)
+        out.append(u)
+    return out
+
+
 def _advance(f: Factor, u, k: int, precision: str):
     """u_{t+k} from u_t: k solves u' = A^{-1} u.  FP64 runs them in one launch
     of the fused stepper (A u' = I u); other precisions solve step by step."""
     if precision == "f64":
-        identity = [0.0] * f.nbands
-        identity[f.nbands // 2] = 1.0
-        return f.cn_step(u, identity, steps=k)
+        return f.cn_step(u, _identity(f), steps=k)
     for _ in range(k):
         u = f.solve(u, precision=precision)
     return u
@@ -125,11 +141,9 @@ class BandedRollout(torch.autograd.Function):
         def recompute(i):
             # states u_s .. u_e of segment i from checkpoint i, on `ahead`
             s = i * every
-            states = [ctx.checkpoints[i]]
             with torch.cuda.stream(ahead):
-                for _ in range(s, min(s + every, steps)):
-                    states.append(_advance(f, states[-1], 1, prec))
-            return states
+                return [ctx.checkpoints[i]] + _trajectory(f, ctx.checkpoints[i],
+                                                          min(s + every, steps) - s, prec)
 
         # segments [s, e): states u_s .. u_e; checkpoint i holds u_{i*every}
         last = len(ctx.checkpoints) - 1

@@ -674,16 +674,24 @@ bb_status bb_ch_forced_step(bb_factor fh, const double *c_in, double *c_out, int
     return BB_OK;
 }
 
-bb_status bb_cn_step(bb_factor fh, const double *w, const double *c_in, double *c_out, int64_t m,
-                     int64_t ld, int64_t steps, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Fused Crank-Nicolson steps; traj: store every step's state (step s at
+// out + s * n * ld) rather than only the last.
+bb_status cn_steps(bb_factor fh, const double *w, const double *c_in, double *out, int64_t m,
+                   int64_t ld, int64_t steps, bool traj, void *stream)
 {
-    bb_status st = check_batch(fh, c_in, c_out, m, ld);
+    bb_status st = check_batch(fh, c_in, out, m, ld);
     if (st != BB_OK) return st;
     bb::Factor &f = fh->f;
     if (!w) return fail(BB_ERR_ARG, "stencil pointer is NULL");
     for (int d = 0; d <= 2 * f.K; ++d)
         if (!std::isfinite(w[d])) return fail(BB_ERR_ARG, "stencil weight is not finite");
     if (steps < 1) return fail(BB_ERR_ARG, "steps < 1");
+    const int64_t stride = traj ? f.n * ld : 0;
+    if (traj && steps > (int64_t(1) << 62) / stride) return fail(BB_ERR_ARG, "steps * n * ld overflows");
     if (m == 0) { g_last_error.clear(); return BB_OK; }
     int dev;
     if ((st = current_device(&dev)) != BB_OK) return st;
@@ -695,12 +703,28 @@ bb_status bb_cn_step(bb_factor fh, const double *w, const double *c_in, double *
     for (int d = 0; d <= 2 * f.K; ++d) wk[d] = w[d];
     hipError_t e = f.K == 1
         ? bb::launch_cn_tri(f.cyclic, (const double *)tab.ptr, tab.elems, f.primal.cor.q, g,
-                            pl.scalar, wk, steps, c_in, c_out, (hipStream_t)stream)
+                            pl.scalar, wk, steps, stride, c_in, out, (hipStream_t)stream)
         : bb::launch_cn_penta(f.cyclic, (const double *)tab.ptr, tab.elems, f.primal.cor.q, g,
-                              pl.scalar, wk, steps, c_in, c_out, (hipStream_t)stream);
+                              pl.scalar, wk, steps, stride, c_in, out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "Crank-Nicolson launch");
     g_last_error.clear();
     return BB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bb_status bb_cn_step(bb_factor fh, const double *w, const double *c_in, double *c_out, int64_t m,
+                     int64_t ld, int64_t steps, void *stream)
+{
+    return cn_steps(fh, w, c_in, c_out, m, ld, steps, false, stream);
+}
+
+bb_status bb_cn_trajectory(bb_factor fh, const double *w, const double *c_in, double *traj,
+                           int64_t m, int64_t ld, int64_t steps, void *stream)
+{
+    return cn_steps(fh, w, c_in, traj, m, ld, steps, true, stream);
 }
 
 size_t bb_mse_workspace_bytes(int64_t n, int64_t m)

@@ -7,9 +7,9 @@ namespace bb {
 
 hipError_t launch_cn_penta(bool cyclic, const double *table, int64_t table_elems,
                            const CyclicQ &q, const SweepGeom &g, bool scalar, const double *w,
-                           int64_t steps, const double *in, double *out, hipStream_t s)
+                           int64_t steps, int64_t traj_stride, const double *in, double *out, hipStream_t s)
 {
-    return launch_cn_k<2>(cyclic, table, table_elems, q, g, scalar, w, steps, in, out, s);
+    return launch_cn_k<2>(cyclic, table, table_elems, q, g, scalar, w, steps, traj_stride, in, out, s);
 }
 
 }  // namespace bb

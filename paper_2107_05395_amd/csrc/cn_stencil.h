@@ -63,21 +63,32 @@ struct StencilRhs {
     }
 };
 
+// traj_stride > 0: store the state after every step s at out + s * traj_stride
+// (a trajectory) instead of only the last one.
+template <int K, bool CYC>
+hipError_t launch_cn_kc(const double *table, int64_t table_elems, const CyclicQ &q,
+                        const SweepGeom &g, bool scalar, const double *w, int64_t steps,
+                        int64_t traj_stride, const double *in, double *out, hipStream_t s)
+{
+    StencilRhs<K, CYC> r;
+    for (int d = 0; d <= 2 * K; ++d) r.w[d] = w[d];
+    if (traj_stride > 0) {
+        StepStats st;
+        st.traj_stride = traj_stride;
+        return launch_stepper<StencilRhs<K, CYC>, K, CYC, false, true>(table, table_elems, q, g, scalar,
+                                                                      r, steps, in, out, s, st);
+    }
+    return launch_stepper<StencilRhs<K, CYC>, K, CYC>(table, table_elems, q, g, scalar, r, steps, in,
+                                                      out, s);
+}
+
 template <int K>
 hipError_t launch_cn_k(bool cyclic, const double *table, int64_t table_elems, const CyclicQ &q,
                        const SweepGeom &g, bool scalar, const double *w, int64_t steps,
-                       const double *in, double *out, hipStream_t s)
+                       int64_t traj_stride, const double *in, double *out, hipStream_t s)
 {
-    if (cyclic) {
-        StencilRhs<K, true> r;
-        for (int d = 0; d <= 2 * K; ++d) r.w[d] = w[d];
-        return launch_stepper<StencilRhs<K, true>, K, true>(table, table_elems, q, g, scalar, r,
-                                                            steps, in, out, s);
-    }
-    StencilRhs<K, false> r;
-    for (int d = 0; d <= 2 * K; ++d) r.w[d] = w[d];
-    return launch_stepper<StencilRhs<K, false>, K, false>(table, table_elems, q, g, scalar, r,
-                                                          steps, in, out, s);
+    return cyclic ? launch_cn_kc<K, true>(table, table_elems, q, g, scalar, w, steps, traj_stride, in, out, s)
+                  : launch_cn_kc<K, false>(table, table_elems, q, g, scalar, w, steps, traj_stride, in, out, s);
 }
 
 }  // namespace

@@ -180,12 +180,14 @@ hipError_t launch_ch_forced(const double *table, int64_t table_elems, const Cycl
 // Crank-Nicolson steps x <- A^{-1} (B x) with B a constant (2K+1)-point
 // stencil w (host array of 2K+1, copied into the kernel arguments), state on
 // chip (cn_tri.hip, cn_penta.hip); scalar / log2Q as for launch_ch.
+// traj_stride > 0: every step's state, step s at out + s * traj_stride.
 hipError_t launch_cn_tri(bool cyclic, const double *table, int64_t table_elems, const CyclicQ &q,
                          const SweepGeom &g, bool scalar, const double *w, int64_t steps,
-                         const double *in, double *out, hipStream_t stream);
+                         int64_t traj_stride, const double *in, double *out, hipStream_t stream);
 hipError_t launch_cn_penta(bool cyclic, const double *table, int64_t table_elems,
                            const CyclicQ &q, const SweepGeom &g, bool scalar, const double *w,
-                           int64_t steps, const double *in, double *out, hipStream_t stream);
+                           int64_t steps, int64_t traj_stride, const double *in, double *out,
+                           hipStream_t stream);
 
 // The paper's thread-per-system mapping (Appendix A), kept as a measured
 // baseline design: forward intermediate written to and re-read from `x`.

@@ -44,6 +44,7 @@ struct StepStats {
     double *partial = nullptr;
     int64_t every = 1, samples = 0;
     double inv_n = 0.0;
+    int64_t traj_stride = 0;   // TRAJ: elements between the states of consecutive steps in `out`
 };
 
 // sum of squares of this lane's rows (padding rows hold 0): four interleaved
@@ -68,7 +69,9 @@ __device__ __forceinline__ double block_sum(double v, int S)
 
 // One lane per chunk; the lanes of a system sit in one wave (shuffles) and
 // the coefficient table is staged in LDS.
-template <class Rhs, int K, bool CYC, int C, bool FULL, bool STATS>
+// TRAJ: the state after every step s (0-based) is stored at
+// out + s * st.traj_stride instead of only the last one at out.
+template <class Rhs, int K, bool CYC, int C, bool FULL, bool STATS, bool TRAJ>
 __global__ __launch_bounds__(kMaxBlockThreads) void step_kernel(const double *__restrict__ table,
                                                              int64_t table_elems, CyclicQ cq,
                                                              SweepGeom g, Rhs rhs, int64_t steps,
@@ -133,8 +136,13 @@ __global__ __launch_bounds__(kMaxBlockThreads) void step_kernel(const double *__
                 const double sum = block_sum(ell, lg.S);   // the group: lanes 0 .. S-1
                 if (lane == 0) st.partial[grp * st.samples + (step + 1) / st.every - 1] = sum;
             }
+            if constexpr (TRAJ) {
+                if (kval) store_chunk<double, C, FULL>(c, out + step * st.traj_stride, row0, k, g.ld, g.n);
+            }
         }
-        if (kval) store_chunk<double, C, FULL>(c, out, row0, k, g.ld, g.n);
+        if constexpr (!TRAJ) {
+            if (kval) store_chunk<double, C, FULL>(c, out, row0, k, g.ld, g.n);
+        }
     }
 }
 
@@ -147,7 +155,7 @@ __global__ __launch_bounds__(kMaxBlockThreads) void step_kernel(const double *__
 // coefficient row at the same time, so the coefficients come from the global
 // table through the scalar cache (no LDS staging, no LDS reads).  Otherwise
 // the table is staged in LDS ahead of the exchange area.
-template <class Rhs, int K, bool CYC, int C, int QL, bool SCALAR, bool STATS>
+template <class Rhs, int K, bool CYC, int C, int QL, bool SCALAR, bool STATS, bool TRAJ>
 __global__ __launch_bounds__((kWave << QL) > kMaxBlockThreads ? (kWave << QL) : kMaxBlockThreads)
 void step_kernel_split(const double *__restrict__ table, int64_t table_elems, CyclicQ cq,
                        SweepGeom g, Rhs rhs, int64_t steps, StepStats st, const double *in,
@@ -237,8 +245,13 @@ void step_kernel_split(const double *__restrict__ table, int64_t table_elems, Cy
                         st.partial[grp * st.samples + (step + 1) / st.every - 1] = sum;
                 }
             }
+            if constexpr (TRAJ) {
+                if (kval) store_chunk<double, C, true>(c, out + step * st.traj_stride, row0, k, g.ld, g.n);
+            }
         }
-        if (kval) store_chunk<double, C, true>(c, out, row0, k, g.ld, g.n);
+        if constexpr (!TRAJ) {
+            if (kval) store_chunk<double, C, true>(c, out, row0, k, g.ld, g.n);
+        }
     }
 }
 
@@ -253,8 +266,9 @@ constexpr size_t split_step_lds(int QL, int R)
 // decomposition, log2Q <= 3), with the coefficients through the scalar cache
 // when `scalar` (then log2Q == log2P and C is 16, 32 or 64); `scalar` with
 // g.log2Q == g.log2P == 0 runs one-chunk systems the same way.  Otherwise the
-// LDS kernel with one wave per group.
-template <class Rhs, int K, bool CYC, bool STATS = false>
+// LDS kernel with one wave per group.  TRAJ: every step's state, see
+// step_kernel.
+template <class Rhs, int K, bool CYC, bool STATS = false, bool TRAJ = false>
 hipError_t launch_stepper(const double *table, int64_t table_elems, const CyclicQ &q,
                           const SweepGeom &g, bool scalar, const Rhs &rhs, int64_t steps,
                           const double *in, double *out, hipStream_t s,
@@ -268,10 +282,10 @@ hipError_t launch_stepper(const double *table, int64_t table_elems, const Cyclic
 #define BB_SCALAR(CC)                                                                                    \
         case CC:                                                                                         \
             switch (g.log2Q) {                                                                           \
-            case 0: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 0, true, STATS>, xl, g.groups, 1, s, table, table_elems, q, g, rhs, steps, st, in, out); \
-            case 1: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 1, true, STATS>, xl, g.groups, 2, s, table, table_elems, q, g, rhs, steps, st, in, out); \
-            case 2: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 2, true, STATS>, xl, g.groups, 4, s, table, table_elems, q, g, rhs, steps, st, in, out); \
-            default: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 3, true, STATS>, xl, g.groups, 8, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            case 0: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 0, true, STATS, TRAJ>, xl, g.groups, 1, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            case 1: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 1, true, STATS, TRAJ>, xl, g.groups, 2, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            case 2: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 2, true, STATS, TRAJ>, xl, g.groups, 4, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            default: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 3, true, STATS, TRAJ>, xl, g.groups, 8, s, table, table_elems, q, g, rhs, steps, st, in, out); \
             }
         switch (g.C) {
             BB_SCALAR(16)
@@ -288,9 +302,9 @@ hipError_t launch_stepper(const double *table, int64_t table_elems, const Cyclic
 #define BB_SPLIT(CC)                                                                                     \
         case CC:                                                                                         \
             switch (g.log2Q) {                                                                           \
-            case 1: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 1, false, STATS>, xl, g.groups, 2, s, table, table_elems, q, g, rhs, steps, st, in, out); \
-            case 2: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 2, false, STATS>, xl, g.groups, 4, s, table, table_elems, q, g, rhs, steps, st, in, out); \
-            default: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 3, false, STATS>, xl, g.groups, 8, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            case 1: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 1, false, STATS, TRAJ>, xl, g.groups, 2, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            case 2: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 2, false, STATS, TRAJ>, xl, g.groups, 4, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            default: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 3, false, STATS, TRAJ>, xl, g.groups, 8, s, table, table_elems, q, g, rhs, steps, st, in, out); \
             }
         switch (g.C) {
             BB_SPLIT(32)
@@ -302,9 +316,9 @@ hipError_t launch_stepper(const double *table, int64_t table_elems, const Cyclic
     const size_t lds = (size_t)table_elems * sizeof(double);
 #define BB_STEP(CC)                                                                            \
     case CC:                                                                                   \
-        return is_full(g) ? launch_grid(step_kernel<Rhs, K, CYC, CC, true, STATS>, lds, g.groups, s,   \
+        return is_full(g) ? launch_grid(step_kernel<Rhs, K, CYC, CC, true, STATS, TRAJ>, lds, g.groups, s,   \
                                         table, table_elems, q, g, rhs, steps, st, in, out)      \
-                          : launch_grid(step_kernel<Rhs, K, CYC, CC, false, STATS>, lds, g.groups, s,  \
+                          : launch_grid(step_kernel<Rhs, K, CYC, CC, false, STATS, TRAJ>, lds, g.groups, s,  \
                                         table, table_elems, q, g, rhs, steps, st, in, out);
     switch (g.C) {
         BB_STEP(4)

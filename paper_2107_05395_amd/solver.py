@@ -246,6 +246,24 @@ class Factor:
                                    m, ld, int(steps), _stream_ptr(c)))
         return out
 
+    def cn_trajectory(self, c: torch.Tensor, w, steps: int) -> torch.Tensor:
+        """The states after each of `steps` Crank-Nicolson steps from c, as a
+        (steps, n, m) tensor whose [s] has c's row stride; bitwise equal to
+        `steps` calls of cn_step with steps=1."""
+        m, ld = _batch_view(c, self.n, torch.float64, "c")
+        if len(w) != self.nbands:
+            raise ValueError("need %d stencil weights" % self.nbands)
+        if steps < 1:
+            raise ValueError("steps must be >= 1")
+        traj = torch.empty((steps, self.n, ld), dtype=torch.float64, device=c.device)[:, :, :m]
+        wv = (ctypes.c_double * len(w))(*(float(x) for x in w))
+        with torch.cuda.device(c.device):
+            check(lib().bb_cn_trajectory(self._handle, ctypes.cast(wv, ctypes.c_void_p),
+                                         ctypes.c_void_p(c.data_ptr()),
+                                         ctypes.c_void_p(traj.data_ptr()), m, ld, int(steps),
+                                         _stream_ptr(c)))
+        return traj
+
 
 def mse_loss_grad(u: torch.Tensor, target: torch.Tensor, grad: torch.Tensor | None = None):
     """(loss as a 0-d device tensor, dloss/du) for loss = mean((u - target)^2)."""

@@ -186,3 +186,55 @@ def test_cn_short_chunk_scalar_kernel_matches_lds(kind, n, monkeypatch):
     monkeypatch.setenv("BANDBATCH_CH_UNIFORM", "0")
     assert not f.plan(m, stepper=True)["scalar"]
     assert np.array_equal(a, host(f.cn_step(c0, w, steps=7)))
+
+
+# decompositions: n = 256 one chunk per wave (scalar coefficients), 1024 the
+# LDS split kernel (16 chunks, 8 waves), 1000 / 333 ragged (one wave per
+# group), 7 tiny; m = 300 takes the small-batch chunks, 5000 the large ones
+TRAJ_CASES = [("tri", True, 256, 5000), ("tri", False, 1024, 5000), ("tri", True, 1000, 300),
+              ("penta", True, 256, 5000), ("penta", False, 1024, 5000), ("penta", True, 333, 300),
+              ("tri", False, 7, 70), ("penta", True, 5, 33)]
+
+
+@pytest.mark.parametrize("kind,cyclic,n,m", TRAJ_CASES)
+def test_cn_trajectory_equals_single_steps(kind, cyclic, n, m):
+    """Every state of a trajectory launch is bitwise the state after the same
+    number of single-step launches, the last one equals the fused launch, and
+    the states match the oracle."""
+    say("trajectory", kind, cyclic, n, m)
+    bands, w = _problem(kind, n, 0.9)
+    f = _factor(kind, bands, cyclic)
+    c0h = inputs.uniform_batch(n, m, seed=90 + n)
+    c0 = dev(c0h)
+    steps = 6
+    traj = f.cn_trajectory(c0, w, steps)
+    assert traj.shape == (steps, n, m)
+    t = c0
+    for s in range(steps):
+        t = f.cn_step(t, w)
+        assert np.array_equal(host(traj[s]), host(t)), s
+    assert np.array_equal(host(traj[-1]), host(f.cn_step(c0, w, steps=steps)))
+    assert rel_err(host(traj[2]), oracle.cn_step(bands, w, c0h, steps=3, cyclic=cyclic)) < 1e-12
+
+
+def test_cn_trajectory_strided_and_identity_stencil():
+    """A strided batch (ld > m) gives the same states as a contiguous one;
+    with the identity stencil the states are implicit solves A u' = u,
+    checked against the oracle's solves."""
+    n, m, ld, steps = 512, 1000, 1152, 4
+    bands = inputs.diffusion_tri_bands(n, 0.7)
+    f = _factor("tri", bands, False)
+    c0h = inputs.uniform_batch(n, m, seed=95)
+    big = torch.zeros(n, ld, dtype=torch.float64, device="cuda")
+    big[:, :m] = dev(c0h)
+    ident = (0.0, 1.0, 0.0)
+    ts = f.cn_trajectory(big[:, :m], ident, steps)
+    assert ts.stride(1) == ld
+    tc = f.cn_trajectory(dev(c0h), ident, steps)
+    u = c0h
+    for s in range(steps):
+        assert np.array_equal(host(ts[s]), host(tc[s])), s
+        u = oracle.tri_solve(*bands, u)
+        assert rel_err(host(tc[s]), u) < 1e-12, s
+    with pytest.raises(ValueError):
+        f.cn_trajectory(dev(c0h), ident, 0)
