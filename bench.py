@@ -615,13 +615,13 @@ def bench_adjoint(args, torch):
     t64 = out["f64"][0]
     # algorithmic HBM bytes of one FP64 training step: the forward pass in
     # ceil(T/c) fused launches (read the checkpoint, write the next one or
-    # u_T: 16 B per row each), the recomputation in one trajectory launch per
-    # segment (read the checkpoint: 8 B per row, write every state: 8 B per
-    # row and step), T adjoint solves (16 B per row each), T band-gradient
-    # reductions (read lambda and u: 16 B per row) and the loss (read u and
-    # target, write the gradient: 24 B per row)
+    # u_T: 16 B per row each); per segment one trajectory launch recomputing
+    # the states and one stepping the adjoints on A^T (each reads its start
+    # once, 8 B per row, and writes every state, 8 B per row and step); T
+    # band-gradient reductions (read lambda and u: 16 B per row) and the loss
+    # (read u and target, write the gradient: 24 B per row)
     segments = -(-T // every)
-    step_bytes = (24.0 * segments + 40.0 * T + 24.0) * n * m
+    step_bytes = (32.0 * segments + 32.0 * T + 24.0) * n * m
     return {
         "roofline": {"bound": "hbm", "achieved": step_bytes * k / t64 / 1e9, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": step_bytes * k / t64 / 1e9 / PEAK_HBM_GBS,

@@ -15,17 +15,51 @@ on chip, and the recomputation of a segment one launch of the same kernel
 that also stores every intermediate state.  A fused launch of k steps, a
 trajectory launch and k single-step launches agree bitwise (same kernel
 arithmetic and decomposition), so the recomputed states equal the forward's.
+The adjoint recursion lam_t = A^{-T} lam_{t+1} is stepped the same way: one
+trajectory launch per segment on the factor of A^T (its bands are A's bands
+transposed), after which the segment's band gradients reduce lam_t against
+u_t.
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from .solver import Factor, mse_loss_grad
 
 
+def _host_bands(bands):
+    return [b.detach().to("cpu", torch.float64).numpy() for b in bands]
+
+
 def _factor_from(bands, kind: str, cyclic: bool) -> Factor:
-    host = [b.detach().to("cpu", torch.float64).numpy() for b in bands]
+    host = _host_bands(bands)
     return Factor.tri(*host, cyclic=cyclic) if kind == "tri" else Factor.penta(*host, cyclic=cyclic)
+
+
+def _transposed_bands(host):
+    """Bands of A^T for a non-periodic band matrix A given by its host bands
+    (row i of A holds band q at column i + q - K): band q of A^T at row i is
+    band 2K - q of A at row i + q - K; entries outside the matrix are 0."""
+    nb = len(host)
+    K = nb // 2
+    n = host[0].shape[0]
+    out = []
+    for q in range(nb):
+        src = np.asarray(host[nb - 1 - q], dtype=np.float64)
+        sh = q - K
+        t = np.zeros(n)
+        if sh >= 0:
+            t[:n - sh] = src[sh:]
+        else:
+            t[-sh:] = src[:n + sh]
+        out.append(t)
+    return out
+
+
+def _transposed_factor(host) -> Factor:
+    t = _transposed_bands(host)
+    return Factor.tri(*t) if len(t) == 3 else Factor.penta(*t)
 
 
 _SIDE_STREAMS: dict = {}
@@ -105,7 +139,9 @@ class BandedRollout(torch.autograd.Function):
     def forward(ctx, u0, steps, checkpoint_every, precision, *bands):
         if steps < 1 or checkpoint_every < 1:
             raise ValueError("steps and checkpoint_every must be >= 1")
-        f = _factor_from(bands, _kind(len(bands)), False)
+        _kind(len(bands))
+        host = _host_bands(bands)
+        f = Factor.tri(*host) if len(host) == 3 else Factor.penta(*host)
         u = u0.detach().contiguous()
         checkpoints = [u]
         t = 0
@@ -117,6 +153,7 @@ class BandedRollout(torch.autograd.Function):
                 checkpoints.append(u)
         ctx.factor, ctx.steps, ctx.every, ctx.precision = f, steps, checkpoint_every, precision
         ctx.band_devices = [b.device for b in bands]
+        ctx.host_bands = host
         ctx.checkpoints = checkpoints
         return u
 
@@ -145,6 +182,9 @@ class BandedRollout(torch.autograd.Function):
                 return [ctx.checkpoints[i]] + _trajectory(f, ctx.checkpoints[i],
                                                           min(s + every, steps) - s, prec)
 
+        # FP64: the adjoints of a segment as one trajectory on A^T
+        ft = _transposed_factor(ctx.host_bands) if prec == "f64" else None
+
         # segments [s, e): states u_s .. u_e; checkpoint i holds u_{i*every}
         last = len(ctx.checkpoints) - 1
         pending = recompute(last)
@@ -156,6 +196,19 @@ class BandedRollout(torch.autograd.Function):
             for u in states:
                 u.record_stream(main)
             pending = recompute(i - 1) if i > 0 else None
+            if ft is not None:
+                # lams[j] = lam_{e-j} = A^{-T} lam_{e-j+1}, lam_{e+1} = g
+                lams = list(ft.cn_trajectory(g, _identity(ft), e - s).unbind(0))
+                side.wait_stream(main)
+                with torch.cuda.stream(side):
+                    for j, lam in enumerate(lams):
+                        f.band_grad(lam, states[e - s - j], gb)
+                for j, lam in enumerate(lams):
+                    lam.record_stream(side)
+                    states[e - s - j].record_stream(side)
+                g = lams[-1]
+                del states
+                continue
             for t in range(e, s, -1):          # u_t = A^{-1} u_{t-1}
                 lam = f.adjoint(g, precision=prec)
                 side.wait_stream(main)
@@ -166,7 +219,7 @@ class BandedRollout(torch.autograd.Function):
                 g = lam
             del states
         main.wait_stream(side)
-        ctx.checkpoints = None
+        ctx.checkpoints = ctx.host_bands = None
         return (g, None, None, None, *[gb[q].to(d) for q, d in enumerate(ctx.band_devices)])
 
 

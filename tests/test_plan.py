@@ -91,3 +91,17 @@ def test_plan_argument_errors(L):
     assert L.bb_plan(h, 10, 0, 9, ctypes.byref(out), None, None, None) == -1
     assert L.bb_plan(h, 10, 0, 0, None, None, None, None) == 0
     L.bb_factor_destroy(h)
+
+
+@pytest.mark.parametrize("nb,n", [(3, 9), (5, 11), (5, 5), (3, 2)])
+def test_rollout_transposed_bands(nb, n):
+    """The rollout steps its adjoints with a factor of A^T built from A's
+    bands: the bands it builds give the dense transpose of A's matrix
+    (the entries a non-periodic factor ignores are random here)."""
+    from paper_2107_05395_amd.autograd import _transposed_bands
+    from tests.dense import penta_dense, tri_dense
+    g = np.random.default_rng(nb * 100 + n)
+    bands = [g.uniform(-1, 1, n) for _ in range(nb)]
+    dense = tri_dense if nb == 3 else penta_dense
+    At = dense(*_transposed_bands(bands))
+    assert np.array_equal(At, dense(*bands).T)
