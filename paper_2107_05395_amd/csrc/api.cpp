@@ -103,6 +103,21 @@ int solve_chunk(int64_t n, int64_t m, bb_precision p)
 // The refinement kernel keeps it (penta n = 1024 with FP32 right-hand sides:
 // 1.46 vs 1.56 ms without).
 // BANDBATCH_LOCKSTEP=0/1 overrides (tuning).
+// Grid shape.  Persistent grids (at most one wave of resident workgroups,
+// each walking its XCD's share of the groups) serve the kernels that stage
+// a coefficient table in LDS, once per workgroup.  The scalar-coefficient
+// stepper stages nothing and runs one workgroup per group in launch order
+// (measured, CH n = 256, m = 2^20, one step per launch: 0.855 vs 0.953 ms;
+// the LDS kernels lose: tri FP32+refine n = 512, m = 2^20 2.64 vs 2.04 ms,
+// penta n = 1024 FP64 1.04 vs 0.99 ms).  BANDBATCH_GRID_LINEAR=0/1 forces
+// persistent / one-per-group grids everywhere (tuning; the launcher reads the
+// same variable for the LDS kernels).  Returns -1 when unset.
+int grid_linear()
+{
+    const char *env = std::getenv("BANDBATCH_GRID_LINEAR");
+    return env ? (std::atoi(env) != 0) : -1;
+}
+
 int lockstep_for(bool split)
 {
     if (const char *env = std::getenv("BANDBATCH_LOCKSTEP")) return std::atoi(env) != 0;
@@ -208,6 +223,7 @@ bb::SweepGeom step_geom(int64_t n, int64_t m, int64_t ld, const StepPlan &pl)
     const int S = (bb::kWave << g.log2Q) / pl.P;
     g.groups = (m + S - 1) / S;
     g.lockstep = lockstep_for(g.log2Q > 0);
+    g.linear = grid_linear() < 0 ? pl.scalar : grid_linear();
     return g;
 }
 
@@ -381,6 +397,7 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
     const int S = (bb::kWave << g.log2Q) / P;
     g.groups = (m + S - 1) / S;
     g.lockstep = lockstep_for(g.log2Q > 0 && op == bb::Op::Solve);
+    g.linear = grid_linear() > 0;
     hipError_t e = bb::launch_sweep(f.K, f.cyclic, op, f32 && p == BB_F32, tab.ptr, tab.elems,
                                     (const double *)band.ptr, band.elems, dir.cor.q, corners, g,
                                     in, out, (hipStream_t)stream);
@@ -617,6 +634,9 @@ bb_status ch_steps(bb_factor fh, const double *c_in, double *c_out, int64_t m, i
     bb::DeviceTable tab;
     bb::SweepGeom g;
     if ((st = stepper_setup(f, dev, m, ld, &pl, &tab, &g)) != BB_OK) return st;
+    // with the statistic the persistent grid measured faster (coarsening
+    // n = 256, m = 2^20, 2000 steps per launch: 0.209 vs 0.226 ms per step)
+    if (samples > 0 && grid_linear() < 0) g.linear = 0;
     hipError_t e = bb::launch_ch((const double *)tab.ptr, tab.elems, f.primal.cor.q, g, pl.scalar,
                                  alpha, steps, c_in, c_out, (hipStream_t)stream, every, samples,
                                  (double *)workspace, lbar);

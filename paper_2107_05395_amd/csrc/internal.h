@@ -103,6 +103,7 @@ struct SweepGeom {
     int64_t groups; // ceil(m / S): groups of S systems (one wave each, or 2^log2Q waves when split)
     int lockstep;   // workgroup barrier at the start of every persistent-loop iteration
     int log2Q;      // waves per system group (0: a group is one wave)
+    int linear = 0; // one workgroup per block of groups, in launch order (no persistent loop)
 };
 
 // Split groups of up to 4 waves, or 8 when the kernel runs two waves per SIMD

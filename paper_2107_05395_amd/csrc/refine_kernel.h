@@ -39,7 +39,7 @@ void refine_kernel(
     const int left = has_left ? lane - lg.S : lane;
     const int right = has_right ? lane + lg.S : lane;
     const int exact = FULL || g.exact;
-    const GroupRange gr = group_range(g.groups, QL);
+    const GroupRange gr = group_range(g.groups, QL, g.linear);
 
     for (int64_t blk = gr.first; blk < gr.end; blk += gr.stride) {
         const int64_t grp = begin_block(gr, blk, g.lockstep);

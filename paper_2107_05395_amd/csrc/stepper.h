@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kMaxBlockThreads) void step_kernel(const double *__
     const int left = has_left ? lane - lg.S : lane;
     const int right = has_right ? lane + lg.S : lane;
     const int exact = FULL || g.exact;
-    const GroupRange gr = group_range(g.groups);
+    const GroupRange gr = group_range(g.groups, 0, STATS ? 0 : g.linear);
 
     for (int64_t blk = gr.first; blk < gr.end; blk += gr.stride) {
         const int64_t grp = begin_block(gr, blk, g.lockstep);
@@ -188,7 +188,10 @@ void step_kernel_split(const double *__restrict__ table, int64_t table_elems, Cy
     const int lft = (has_left ? lg.j - 1 : lg.j) * lg.S + lg.sl;
     const int rgt = (has_right ? lg.j + 1 : lg.j) * lg.S + lg.sl;
     const int first = lg.sl, last = (lg.P - 1) * lg.S + lg.sl;
-    const GroupRange gr = group_range(g.groups, QL);
+    // STATS launches are persistent unless forced (the mapping code costs the
+    // statistic kernel its third wave per SIMD); the persistent mapping also
+    // serves a forced one-per-group grid
+    const GroupRange gr = group_range(g.groups, QL, STATS ? 0 : g.linear);
 
     for (int64_t blk = gr.first; blk < gr.end; blk += gr.stride) {
         const int64_t grp = begin_block(gr, blk, g.lockstep);
@@ -266,7 +269,10 @@ constexpr size_t split_step_lds(int QL, int R)
 // decomposition, log2Q <= 3), with the coefficients through the scalar cache
 // when `scalar` (then log2Q == log2P and C is 16, 32 or 64); `scalar` with
 // g.log2Q == g.log2P == 0 runs one-chunk systems the same way.  Otherwise the
-// LDS kernel with one wave per group.  TRAJ: every step's state, see
+// LDS kernel with one wave per group.  The scalar kernel's grid follows
+// g.linear (it stages no table, so one workgroup per group costs nothing);
+// the LDS kernels stage the table once per workgroup and stay persistent
+// unless BANDBATCH_GRID_LINEAR asks otherwise.  TRAJ: every step's state, see
 // step_kernel.
 template <class Rhs, int K, bool CYC, bool STATS = false, bool TRAJ = false>
 hipError_t launch_stepper(const double *table, int64_t table_elems, const CyclicQ &q,
@@ -282,10 +288,10 @@ hipError_t launch_stepper(const double *table, int64_t table_elems, const Cyclic
 #define BB_SCALAR(CC)                                                                                    \
         case CC:                                                                                         \
             switch (g.log2Q) {                                                                           \
-            case 0: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 0, true, STATS, TRAJ>, xl, g.groups, 1, s, table, table_elems, q, g, rhs, steps, st, in, out); \
-            case 1: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 1, true, STATS, TRAJ>, xl, g.groups, 2, s, table, table_elems, q, g, rhs, steps, st, in, out); \
-            case 2: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 2, true, STATS, TRAJ>, xl, g.groups, 4, s, table, table_elems, q, g, rhs, steps, st, in, out); \
-            default: return launch_grid_split(step_kernel_split<Rhs, K, CYC, CC, 3, true, STATS, TRAJ>, xl, g.groups, 8, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            case 0: return launch_grid_mode(step_kernel_split<Rhs, K, CYC, CC, 0, true, STATS, TRAJ>, xl, g.groups, 1, g.linear, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            case 1: return launch_grid_mode(step_kernel_split<Rhs, K, CYC, CC, 1, true, STATS, TRAJ>, xl, g.groups, 2, g.linear, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            case 2: return launch_grid_mode(step_kernel_split<Rhs, K, CYC, CC, 2, true, STATS, TRAJ>, xl, g.groups, 4, g.linear, s, table, table_elems, q, g, rhs, steps, st, in, out); \
+            default: return launch_grid_mode(step_kernel_split<Rhs, K, CYC, CC, 3, true, STATS, TRAJ>, xl, g.groups, 8, g.linear, s, table, table_elems, q, g, rhs, steps, st, in, out); \
             }
         switch (g.C) {
             BB_SCALAR(16)

@@ -416,13 +416,19 @@ struct GroupRange {
     int W, wave;
 };
 
-__device__ __forceinline__ GroupRange group_range(int64_t groups, int log2Q = 0)
+__device__ __forceinline__ GroupRange group_range(int64_t groups, int log2Q = 0, int linear = 0)
 {
     constexpr int kXcd = 8;
     GroupRange r;
     r.W = (blockDim.x / kWave) >> log2Q;     // groups per workgroup
     r.wave = (threadIdx.x / kWave) >> log2Q; // this wave's group in the workgroup
     const int64_t blocks = (groups + r.W - 1) / r.W;
+    if (linear) {   // the host launched one workgroup per block of groups
+        r.first = blockIdx.x;
+        r.end = r.first < blocks ? r.first + 1 : r.first;
+        r.stride = 1;
+        return r;
+    }
     const int xcd = blockIdx.x % kXcd;
     const int64_t per_xcd = (blocks + kXcd - 1) / kXcd;
     const int64_t base = (int64_t)xcd * per_xcd;
@@ -566,9 +572,20 @@ int cu_count()
 // Persistent-style launch: as many workgroups as can be resident at once
 // (rounded to a multiple of the 8 XCDs), each looping over groups of systems.
 // split_waves > 0: a split group of that many waves is the whole workgroup.
+// BANDBATCH_GRID_LINEAR=1: non-persistent grids for the kernels launched
+// through launch_grid_split (tuning); the host sets SweepGeom::linear to match.
+inline bool grid_linear()
+{
+    const char *env = std::getenv("BANDBATCH_GRID_LINEAR");
+    return env && std::atoi(env) != 0;
+}
+
+// linear: one workgroup per block of groups (the kernel's SweepGeom::linear
+// must be set); otherwise a persistent grid of at most one wave of resident
+// workgroups, each walking the blocks of its XCD's share (group_range).
 template <typename... KArgs, typename... Args>
-hipError_t launch_grid_split(void (*kern)(KArgs...), size_t lds, int64_t groups, int split_waves,
-                             hipStream_t s, Args... args)
+hipError_t launch_grid_mode(void (*kern)(KArgs...), size_t lds, int64_t groups, int split_waves,
+                            bool linear, hipStream_t s, Args... args)
 {
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,
@@ -595,10 +612,18 @@ hipError_t launch_grid_split(void (*kern)(KArgs...), size_t lds, int64_t groups,
     int64_t need = (groups + groups_per_block - 1) / groups_per_block;
     int64_t cap = (int64_t)cu_count() * per_cu;
     int64_t blocks = need < cap ? need : cap;
+    if (linear) blocks = need;
     blocks = ((blocks + 7) / 8) * 8;   // multiple of the XCD count, see group_range
     if (blocks < 8) blocks = 8;
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), lds, s, args...);
     return hipGetLastError();
+}
+
+template <typename... KArgs, typename... Args>
+hipError_t launch_grid_split(void (*kern)(KArgs...), size_t lds, int64_t groups, int split_waves,
+                             hipStream_t s, Args... args)
+{
+    return launch_grid_mode(kern, lds, groups, split_waves, grid_linear(), s, args...);
 }
 
 template <typename... KArgs, typename... Args>

@@ -26,7 +26,7 @@ void sweep_kernel(const T *__restrict__ table, int64_t table_elems, CyclicQ cq, 
 
     const LaneGeom lg = lane_geom(g.log2P, QL);
     const int row0 = lg.j * C;
-    const GroupRange gr = group_range(g.groups, QL);
+    const GroupRange gr = group_range(g.groups, QL, g.linear);
     for (int64_t b = gr.first; b < gr.end; b += gr.stride) {
         const int64_t grp = begin_block(gr, b, g.lockstep);
         if (grp >= g.groups) continue;

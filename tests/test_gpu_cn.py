@@ -238,3 +238,18 @@ def test_cn_trajectory_strided_and_identity_stencil():
         assert rel_err(host(tc[s]), u) < 1e-12, s
     with pytest.raises(ValueError):
         f.cn_trajectory(dev(c0h), ident, 0)
+
+
+@pytest.mark.parametrize("kind,n,m", [("tri", 256, 5000), ("penta", 512, 3000), ("tri", 1024, 3000)])
+def test_cn_grid_shapes_agree_bitwise(kind, n, m, monkeypatch):
+    """The scalar-coefficient stepper runs one workgroup per group by
+    default, the LDS kernels a persistent grid; forcing either grid shape
+    everywhere changes which workgroup runs a group, never its arithmetic."""
+    bands, w = _problem(kind, n, 0.7)
+    f = _factor(kind, bands, True)
+    c0 = dev(inputs.uniform_batch(n, m, seed=97))
+    ref = host(f.cn_step(c0, w, steps=4))
+    for v in ("0", "1"):
+        monkeypatch.setenv("BANDBATCH_GRID_LINEAR", v)
+        assert np.array_equal(host(f.cn_step(c0, w, steps=4)), ref), v
+        assert np.array_equal(host(f.cn_trajectory(c0, w, 4)[-1]), ref), v

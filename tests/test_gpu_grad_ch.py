@@ -238,3 +238,22 @@ def test_ch_domain_size_statistic_without_samples():
     out, lbar = f.ch_step_stats(dev(c0), alpha, steps=2, every=5)
     assert lbar.numel() == 0
     assert rel_err(host(out), oracle.ch_step(c0, sigma, alpha, steps=2)) < 1e-12
+
+
+def test_ch_grid_shapes_agree_bitwise(monkeypatch):
+    """The Cahn-Hilliard steps and the domain-size statistic are the same
+    bitwise on the default grids (one workgroup per group for the plain
+    scalar-kernel steps, persistent with the statistic) and on either grid
+    shape forced: the partial sums belong to groups, not to workgroups."""
+    n, m = 256, 4000
+    f, sigma, alpha = _ch(n)
+    c0 = dev(inputs.uniform_batch(n, m, seed=98, lo=-0.1, hi=0.1))
+    assert f.plan(m, stepper=True)["scalar"]
+    out, lbar = f.ch_step_stats(c0, alpha, steps=12, every=3)
+    ref_out, ref_lbar = host(out), host(lbar)
+    assert np.array_equal(host(f.ch_step(c0, alpha, steps=12)), ref_out)
+    for v in ("0", "1"):
+        monkeypatch.setenv("BANDBATCH_GRID_LINEAR", v)
+        out, lbar = f.ch_step_stats(c0, alpha, steps=12, every=3)
+        assert np.array_equal(host(out), ref_out) and np.array_equal(host(lbar), ref_lbar), v
+        assert np.array_equal(host(f.ch_step(c0, alpha, steps=12)), ref_out), v
