@@ -137,10 +137,16 @@ def bench_tri(args, torch):
     ref32 = oracle.tri_solve(*bands, rhs_host[:, cols32].astype(np.float32).astype(np.float64))
     err32 = rel_err_cols(x[:, torch.from_numpy(cols32).cuda()].cpu().numpy(), ref32)
     del rhs32
-    # a plain device-to-device copy of the same array: the achievable HBM rate
-    # for one read + one write stream on this part (context for the roofline)
+    # torch's device-to-device copy of the same array, one read + one write
+    # stream (context for the roofline; not the fastest copy on this part)
     ct, _ = time_launches(lambda: x.copy_(rhs), 10, 2, torch)
     copy_gbs = algo_bytes * 10 / ct / 1e9
+    # the fastest plain copy found on this part: one contiguous 16 KB tile per
+    # workgroup (bb_copy_tiles), the sweep's HBM reference
+    from paper_2107_05395_amd.solver import copy_tiles
+    tt, _ = time_launches(lambda: copy_tiles(rhs, x), 10, 2, torch)
+    assert torch.equal(x, rhs)
+    tile_gbs = algo_bytes * 10 / tt / 1e9
     # small batches are bound by launch latency: the same solves replayed
     # from a HIP graph (captured after the eager calls uploaded the tables)
     graph = None
@@ -184,7 +190,7 @@ def bench_tri(args, torch):
                    "rel_err_vs_oracle": err32, "hbm_gbs_algorithmic": 12.0 * n * m * k / t32 / 1e9,
                    "note": "FP32 right-hand sides (the same draws rounded), double solution; "
                            "oracle on the rounded values"},
-        "copy_gbs": copy_gbs,
+        "copy_gbs": copy_gbs, "tile_copy_gbs": tile_gbs,
         "hip_graph": graph,
         "thread_per_system_design": {"ms_per_step": 1e3 * pt, "value": m / pt,
                                      "hbm_gbs_algorithmic": algo_bytes / pt / 1e9},
@@ -194,8 +200,9 @@ def bench_tri(args, torch):
                      "traffic": traffic,
                      "kernel": "sweep_kernel<double,1,%d,false,full>" % f.chunk(),
                      "algorithmic_bytes_per_launch": algo_bytes,
-                     "copy_ceiling_gbs": copy_gbs,
-                     "frac_of_copy": algo_bytes / per_launch / 1e9 / copy_gbs},
+                     "torch_copy_gbs": copy_gbs,
+                     "tile_copy_gbs": tile_gbs,
+                     "frac_of_tile_copy": algo_bytes / per_launch / 1e9 / tile_gbs},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_tri(bands, n, seed + 100, args.cpu_seconds)

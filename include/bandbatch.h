@@ -262,6 +262,16 @@ bb_status bb_cn_step(bb_factor f, const double *w, const double *c_in, double *c
 bb_status bb_cn_trajectory(bb_factor f, const double *w, const double *c_in, double *traj,
                            int64_t m, int64_t ld, int64_t steps, void *stream);
 
+/* ---------------------------------------------------------------- measurement
+ * A measurement utility, not part of the method: copy `bytes` from src to
+ * dst (device, 16-byte aligned, not overlapping; bytes a multiple of 16) with
+ * each workgroup moving one contiguous 16 KB tile, its loads issued before
+ * its stores -- the fastest plain read + write stream found on this part,
+ * which benchmarks time beside the sweeps as their HBM reference.  bytes = 0
+ * does nothing (the pointers may then be NULL).
+ * Errors: BB_ERR_ARG (NULL, alignment, size, overlap), BB_ERR_HIP. */
+bb_status bb_copy_tiles(const void *src, void *dst, int64_t bytes, void *stream);
+
 /* ---------------------------------------------------------------- loss
  * Mean-squared-error loss of a batch against a target and its gradient:
  *   grad[i,k] = 2 (u[i,k] - target[i,k]) / (n m),

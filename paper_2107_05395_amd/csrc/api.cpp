@@ -3,6 +3,7 @@
 // lazy upload of the factor's coefficient tables, kernel dispatch.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -745,6 +746,21 @@ bb_status bb_cn_trajectory(bb_factor fh, const double *w, const double *c_in, do
                            int64_t m, int64_t ld, int64_t steps, void *stream)
 {
     return cn_steps(fh, w, c_in, traj, m, ld, steps, true, stream);
+}
+
+bb_status bb_copy_tiles(const void *src, void *dst, int64_t bytes, void *stream)
+{
+    if (bytes < 0 || bytes % 16) return fail(BB_ERR_ARG, "bytes must be a non-negative multiple of 16");
+    if (bytes == 0) { g_last_error.clear(); return BB_OK; }
+    if (!src || !dst) return fail(BB_ERR_ARG, "NULL pointer");
+    if (((uintptr_t)src | (uintptr_t)dst) % 16) return fail(BB_ERR_ARG, "pointers must be 16-byte aligned");
+    const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+    if (bytes > 0 && a < b + (uintptr_t)bytes && b < a + (uintptr_t)bytes)
+        return fail(BB_ERR_ARG, "source and destination overlap");
+    hipError_t e = bb::launch_copy_tiles(src, dst, bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "copy launch");
+    g_last_error.clear();
+    return BB_OK;
 }
 
 size_t bb_mse_workspace_bytes(int64_t n, int64_t m)

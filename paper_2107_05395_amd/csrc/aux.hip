@@ -214,7 +214,40 @@ __global__ __launch_bounds__(256) void tri_thread_per_system(const double *__res
     }
 }
 
+// Streaming reference for the roofline (not part of the method): each
+// workgroup of 256 threads copies one contiguous 16 KB tile, four 16-byte
+// loads per thread issued before its four stores.
+typedef double copy_vec __attribute__((ext_vector_type(2)));
+constexpr int kCopyPerThread = 4;
+
+__global__ __launch_bounds__(256) void copy_tiles(const copy_vec *__restrict__ in,
+                                                  copy_vec *__restrict__ out, int64_t n2)
+{
+    const int64_t base = (int64_t)blockIdx.x * 256 * kCopyPerThread + threadIdx.x;
+    copy_vec v[kCopyPerThread];
+#pragma unroll
+    for (int u = 0; u < kCopyPerThread; ++u) {
+        const int64_t i = base + (int64_t)u * 256;
+        if (i < n2) v[u] = in[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyPerThread; ++u) {
+        const int64_t i = base + (int64_t)u * 256;
+        if (i < n2) out[i] = v[u];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_copy_tiles(const void *src, void *dst, int64_t bytes, hipStream_t s)
+{
+    const int64_t n2 = bytes / 16;
+    const int64_t blocks = (n2 + 256 * kCopyPerThread - 1) / (256 * kCopyPerThread);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_tiles, dim3((unsigned)blocks), dim3(256), 0, s, (const copy_vec *)src,
+                       (copy_vec *)dst, n2);
+    return hipGetLastError();
+}
 
 // k-blocks per wave: enough waves (about 8192, four per SIMD on 256 CUs) to
 // keep HBM busy, few enough partial sums that the fold stays short.

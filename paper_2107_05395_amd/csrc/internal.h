@@ -190,6 +190,10 @@ hipError_t launch_cn_penta(bool cyclic, const double *table, int64_t table_elems
                            int64_t steps, int64_t traj_stride, const double *in, double *out,
                            hipStream_t stream);
 
+// Copy of `bytes` (a multiple of 16) in contiguous 16 KB tiles per workgroup:
+// the streaming reference the sweeps' HBM rate is compared with.
+hipError_t launch_copy_tiles(const void *src, void *dst, int64_t bytes, hipStream_t stream);
+
 // The paper's thread-per-system mapping (Appendix A), kept as a measured
 // baseline design: forward intermediate written to and re-read from `x`.
 hipError_t launch_tri_thread_per_system(const double *rhat, const double *aprime,

@@ -285,8 +285,22 @@ def mse_loss_grad(u: torch.Tensor, target: torch.Tensor, grad: torch.Tensor | No
     return loss, grad
 
 
+def copy_tiles(src: torch.Tensor, dst: torch.Tensor) -> torch.Tensor:
+    """dst <- src through bb_copy_tiles (the streaming reference of the
+    benchmarks); both contiguous device tensors of the same size in bytes."""
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous device tensors")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst differ in size")
+    with torch.cuda.device(src.device):
+        check(lib().bb_copy_tiles(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                  nbytes, _stream_ptr(src)))
+    return dst
+
+
 def max_n() -> int:
     return int(lib().bb_max_n())
 
 
-__all__ = ["Factor", "BandBatchError", "mse_loss_grad", "max_n", "KINDS"]
+__all__ = ["Factor", "BandBatchError", "mse_loss_grad", "copy_tiles", "max_n", "KINDS"]
