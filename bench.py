@@ -236,7 +236,7 @@ def bench_penta(args, torch):
     del rhs32
     k = args.steps
     per = out["f64"][0] / k
-    return {
+    line = {
         "metric": "systems solved/s", "value": m * k / out["f64"][0], "unit": "systems/s",
         "n_gpus": 1, "steps": k, "warmup": args.warmup, "ms_per_step": 1e3 * per,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -252,55 +252,118 @@ def bench_penta(args, torch):
                      "unit": "GB/s", "frac": algo_bytes / per / 1e9 / PEAK_HBM_GBS,
                      "traffic": measured_traffic(args.workload, "f64", "sweep")},
     }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_penta(bands, n, seed + 100, args.cpu_seconds)
+    return line
+
+
+def cpu_baseline_penta(bands, n, seed, budget_s):
+    """The oracle on the host cores on bounded blocks of the same workload."""
+    import oracle
+    from paper_2107_05395_amd import inputs
+    m_s = 1 << 14
+    rhs = inputs.sine_mode_batch(n, m_s, seed=seed)
+    calls, t0 = 0, time.perf_counter()
+    while True:
+        oracle.penta_solve(*bands, rhs)
+        calls += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": calls * m_s / el, "unit": "systems/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d x oracle.penta_solve on %d systems of the same workload (n=%d), %.1f s"
+                      % (calls, m_s, n, el)}
 
 
 def bench_ch(args, torch):
+    """The configured Cahn-Hilliard ensemble: all of its steps (5000) from the
+    seeded start, in launches of --ch-fuse fused steps (state on chip), then
+    the same start in one launch per step for a sample of steps (the state
+    through HBM each step).  The final state of at least 2^12 runs, sampled
+    evenly over the batch, is compared with the oracle run over the same 5000
+    steps; that oracle run on the host cores is also the cpu_baseline."""
     from paper_2107_05395_amd import Factor, inputs
+    import oracle
     spec = dict(inputs.WORKLOADS[args.workload])
-    n, m, seed = spec["n"], spec["m"], spec["seed"]
-    sigma, alpha = inputs.ch_parameters(n=n, gamma=spec["gamma"], dt=spec["dt"])
-    f = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
+    n, m, seed, T = spec["n"], spec["m"], spec["seed"], spec["steps"]
+    L, gamma, dt = 2.0 * np.pi, spec["gamma"], spec["dt"]
+    f = Factor.cahn_hilliard(n, L, gamma, dt)
     f.upload()
     c_host = inputs.uniform_batch(n, m, seed=seed, lo=-0.1, hi=0.1)
-    c = torch.from_numpy(c_host).cuda()
-    out = torch.empty_like(c)
-    steps_per_launch = args.ch_fuse
-    launches = max(1, args.steps // steps_per_launch)
-    t, _ = time_launches(lambda: f.ch_step(c, alpha, steps=steps_per_launch, out=out), launches,
-                         args.warmup, torch)
-    total_steps = launches * steps_per_launch
-    per_step = t / total_steps
-    algo_bytes_per_step = 16.0 * n * m
-    import oracle
-    cols = np.arange(0, m, m // 64)
-    ref = oracle.ch_step(c_host[:, cols], sigma, alpha, steps=steps_per_launch)
-    err = rel_err_cols(out[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref)
-    # Roofline: one step per launch streams the ensemble through HBM (16 B per
-    # row); fused steps keep it in registers and are bound by FP64 arithmetic.
-    # Algorithmic FP64 operations per row and step of the scheme (Section 5.1):
-    # N = C^3 - C (3), the stencil f = C + a(N_{i-1} - 2N_i + N_{i+1}) (5), the
-    # LR forward step with stored reciprocal (5), the back substitution (4)
-    # and the periodic rank-2 correction (4).
+    c0 = torch.from_numpy(c_host).cuda()
+    bufs = [c0.clone(), torch.empty_like(c0)]
+    fuse = max(1, min(args.ch_fuse, T))
+
+    def run_all():
+        bufs[0].copy_(c0)
+        done, cur = 0, 0
+        while done < T:
+            k = min(fuse, T - done)
+            f.ch_step(bufs[cur], f.alpha, steps=k, out=bufs[1 - cur])
+            cur, done = 1 - cur, done + k
+        return bufs[cur]
+
+    f.ch_step(c0, f.alpha, steps=2, out=bufs[1])        # warm-up (tables, code)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    final = run_all()
+    stop.record()
+    torch.cuda.synchronize()
+    secs = start.elapsed_time(stop) / 1e3
+    per_step = secs / T
+    # one launch per step: 200 steps from the same start (HBM-bound)
+    single = 200
+    tp, _ = time_launches(lambda: f.ch_step(bufs[0], f.alpha, steps=1, out=bufs[1]), single, 3,
+                          torch)
+    final = run_all()                                    # the timed trajectory's result again
+    torch.cuda.synchronize()
+    # parity over the full trajectory on >= 2^12 sampled runs
+    samp = max(1 << 12, args.ch_sample)
+    cols = np.unique(np.r_[np.linspace(0, m - 1, samp).astype(np.int64), m - 1])
+    sigma, alpha = oracle.ch_coefficients(gamma, L / n, dt)
+    t0 = time.perf_counter()
+    ref = oracle.ch_step(c_host[:, cols], sigma, alpha, steps=T)
+    cpu_s = time.perf_counter() - t0
+    got = final[:, torch.from_numpy(cols).cuda()].cpu().numpy()
+    num = np.linalg.norm(got - ref, axis=0)
+    errs = num / np.linalg.norm(ref, axis=0)
+    flag = 1e-10
+    outliers = [{"run": int(cols[j]), "rel_err": float(errs[j])}
+                for j in np.argsort(-errs)[:8] if errs[j] > flag]
+    # Roofline of the fused launches: FP64 arithmetic.  Algorithmic
+    # operations per row and step of the scheme (Section 5.1): N = C^3 - C
+    # (3), the stencil f = C + a(N_{i-1} - 2N_i + N_{i+1}) (5), the LR forward
+    # step with stored reciprocal (5), the back substitution (4) and the
+    # periodic rank-2 correction (4).
     flops_row_step = 21.0
-    if steps_per_launch == 1:
-        ach = algo_bytes_per_step / per_step / 1e9
-        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": None}
-    else:
-        ach = flops_row_step * n * m / per_step / 1e12
-        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
-                "note": "algorithmic FP64 operations of the scheme, 21 per row and step"}
-    return {
-        "metric": "system-steps/s", "value": m * total_steps / t, "unit": "system-steps/s",
-        "n_gpus": 1, "steps": total_steps, "warmup": args.warmup, "ms_per_step": 1e3 * per_step,
+    ach = flops_row_step * n * m / per_step / 1e12
+    line = {
+        "metric": "system-steps/s", "value": m * T / secs, "unit": "system-steps/s",
+        "n_gpus": 1, "steps": T, "warmup": 1, "ms_per_step": 1e3 * per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded uniform[-0.1,0.1) initial states)",
-        "config": {"workload": args.workload, "n": n, "m": m, "steps_per_launch": steps_per_launch},
-        "rel_err_vs_oracle": err,
-        "hbm_equivalent_gbs": algo_bytes_per_step / per_step / 1e9,
-        "roofline": roof,
+        "config": {"workload": args.workload, "n": n, "m": m, "L": L, "gamma": gamma, "dt": dt,
+                   "steps": T, "steps_per_launch": fuse},
+        "trajectory_check": {"runs": int(len(cols)), "steps": T,
+                             "max_rel_err_vs_oracle": float(errs.max()),
+                             "median_rel_err_vs_oracle": float(np.median(errs)),
+                             "flag_above": flag, "outliers": outliers},
+        "one_step_per_launch": {"ms_per_step": 1e3 * tp / single,
+                                "hbm_gbs_algorithmic": 16.0 * n * m * single / tp / 1e9,
+                                "frac_of_hbm_peak": 16.0 * n * m * single / tp / 1e9 / PEAK_HBM_GBS},
+        "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
+                     "note": "fused launches; algorithmic FP64 operations of the scheme, "
+                             "21 per row and step"},
+        "cpu_baseline": {"value": len(cols) * T / cpu_s, "unit": "system-steps/s",
+                         "cores": oracle.num_threads(), "kind": "oracle",
+                         "sample": "oracle.ch_step over all %d steps on the %d sampled runs "
+                                   "(n=%d) of the trajectory check, %.1f s"
+                                   % (T, len(cols), n, cpu_s)},
     }
+    return line
 
 
 # The paper's own times for 1000 steps on the same grid (Tesla V100; Section
@@ -428,13 +491,14 @@ def bench_ch_coarsening(args, torch):
     dx = L / n
     dt = 0.1 * dx
     steps = int(round(T / dt))
-    sigma, alpha = inputs.ch_parameters(n=n, length=L, gamma=gamma, dt=dt)
-    f = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
+    f = Factor.cahn_hilliard(n, L, gamma, dt)
     f.upload()
+    alpha = f.alpha
+    sigma_o, alpha_o = oracle.ch_coefficients(gamma, dx, dt)
     # parity first: 256 runs, 20 steps, lbar at every step against the oracle
     c_small = inputs.uniform_batch(n, 256, seed=seed + 1, lo=-0.1, hi=0.1)
     _, lb_small = f.ch_step_stats(torch.from_numpy(c_small).cuda(), alpha, steps=20, every=1)
-    ref_small, _ = oracle.ch_coarsening(c_small, sigma, alpha, 20, 1)
+    ref_small, _ = oracle.ch_coarsening(c_small, sigma_o, alpha_o, 20, 1)
     err = float(np.max(np.abs(lb_small.cpu().numpy() - ref_small) / ref_small))
 
     c = torch.from_numpy(inputs.uniform_batch(n, m, seed=seed, lo=-0.1, hi=0.1)).cuda()
@@ -491,7 +555,7 @@ def bench_ch_coarsening(args, torch):
         cs = inputs.uniform_batch(n, m_s, seed=seed + 2, lo=-0.1, hi=0.1)
         done_s, t0 = 0, time.perf_counter()
         while time.perf_counter() - t0 < args.cpu_seconds:
-            cs = oracle.ch_step(cs, sigma, alpha, steps=10)
+            cs = oracle.ch_step(cs, sigma_o, alpha_o, steps=10)
             oracle.ch_domain_size(cs)
             done_s += 10
         el = time.perf_counter() - t0
@@ -517,23 +581,24 @@ def bench_ch_forced(args, torch):
     dx = L / n
     dt = 0.1 * dx
     steps = int(round(T / dt))
-    sigma, alpha = inputs.ch_parameters(n=n, length=L, gamma=gamma, dt=dt)
     f0 = np.repeat(np.linspace(spec["f0"][0], spec["f0"][1], G), G)
     mean = np.tile(np.linspace(spec["mean"][0], spec["mean"][1], G), G)
-    beta, amp, kdx = oracle.ch_forced_parameters(dt, dx, np.full(m, spec["v"]), f0,
-                                                 np.full(m, spec["k"]))
-    f = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
+    v, kw = np.full(m, spec["v"]), np.full(m, spec["k"])
+    f = Factor.cahn_hilliard(n, L, gamma, dt)
     f.upload()
     c_host = mean + inputs.uniform_batch(n, m, seed=seed, lo=-0.1, hi=0.1)
-    # parity first: 64 sampled runs, 20 steps, against the oracle
+    # parity first: 64 sampled runs, 20 steps, against the oracle (its own
+    # coefficients and mapping of v, f0, k)
+    sigma_o, alpha_o = oracle.ch_coefficients(gamma, dx, dt)
+    beta, amp, kdx = oracle.ch_forced_parameters(dt, dx, v, f0, kw)
     cols = np.unique(np.r_[np.linspace(0, m - 1, 64).astype(np.int64), m - 1])
-    ref = oracle.ch_forced_step(c_host[:, cols], sigma, alpha, beta[cols], amp[cols], kdx[cols],
-                                steps=20)
+    ref = oracle.ch_forced_step(c_host[:, cols], sigma_o, alpha_o, beta[cols], amp[cols],
+                                kdx[cols], steps=20)
     dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    pb, pa, pk = dv(beta), dv(amp), dv(kdx)
+    pv, pf, pk = dv(v), dv(f0), dv(kw)
     c = dv(c_host)
     nxt = torch.empty_like(c)
-    f.ch_forced_step(c, alpha, pb, pa, pk, steps=20, out=nxt)
+    f.ch_forced_step(c, dt, dx, pv, pf, pk, steps=20, out=nxt)
     err = rel_err_cols(nxt[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref)
     chunk = 2000
     torch.cuda.synchronize()
@@ -542,7 +607,7 @@ def bench_ch_forced(args, torch):
     done = 0
     while done < steps:
         k = min(chunk, steps - done)
-        f.ch_forced_step(c, alpha, pb, pa, pk, steps=k, out=nxt)
+        f.ch_forced_step(c, dt, dx, pv, pf, pk, steps=k, out=nxt)
         c, nxt = nxt, c
         done += k
     stop.record()
@@ -577,7 +642,8 @@ def bench_ch_forced(args, torch):
         cs = c_host[:, :m_s].copy()
         done_s, t0 = 0, time.perf_counter()
         while time.perf_counter() - t0 < args.cpu_seconds:
-            cs = oracle.ch_forced_step(cs, sigma, alpha, beta[:m_s], amp[:m_s], kdx[:m_s], steps=5)
+            cs = oracle.ch_forced_step(cs, sigma_o, alpha_o, beta[:m_s], amp[:m_s], kdx[:m_s],
+                                       steps=5)
             done_s += 5
         el = time.perf_counter() - t0
         line["cpu_baseline"] = {"value": done_s * m_s / el, "unit": "system-steps/s",
@@ -611,8 +677,10 @@ def bench_adjoint(args, torch):
 
     out = {}
     import oracle
-    cols = np.unique(np.r_[np.linspace(0, m - 1, 62).astype(np.int64), 0, m - 1])
+    cols = np.unique(np.r_[np.linspace(0, m - 1, 254).astype(np.int64), 0, m - 1])
+    t_cpu = time.perf_counter()
     _, _, du0_ref = oracle.diffusion_loss_and_grads(D0, r, u0_host[:, cols], y_host[:, cols], T)
+    t_cpu = time.perf_counter() - t_cpu
     du0_ref *= len(cols) / m          # the loss is a mean over all n*m entries
     for prec in ("f64", "f32r"):
         t, _ = time_launches(lambda: step(prec), args.steps, args.warmup, torch)
@@ -644,6 +712,11 @@ def bench_adjoint(args, torch):
         "du0_rel_err_vs_oracle": out["f64"][1],
         "f32r": {"value": m * T * k / out["f32r"][0], "ms_per_step": 1e3 * out["f32r"][0] / k,
                  "du0_rel_err_vs_oracle": out["f32r"][1]},
+        "cpu_baseline": {"value": len(cols) * T / t_cpu, "unit": "system-steps/s (forward + backward)",
+                         "cores": oracle.num_threads(), "kind": "oracle",
+                         "sample": "oracle.diffusion_loss_and_grads (T=%d forward solves, T adjoint "
+                                   "solves and band gradients) on %d of the m systems (n=%d), "
+                                   "%.1f s" % (T, len(cols), n, t_cpu)},
     }
 
 
@@ -675,10 +748,9 @@ def probe(torch):
     torch.cuda.synchronize()
     del rhs, x
     n, m = 256, 1 << 20
-    sigma, alpha = inputs.ch_parameters(n=n)
     c = torch.rand(n, m, dtype=torch.float64, device="cuda").mul_(0.2).sub_(0.1)
-    h = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
-    h.ch_step(c, alpha, steps=10)
+    h = Factor.cahn_hilliard(n, 2.0 * np.pi, 0.01, 1e-3)
+    h.ch_step(c, h.alpha, steps=10)
     torch.cuda.synchronize()
     del c
     n, m = 1024, 1 << 16
@@ -698,7 +770,9 @@ def main():
     ap.add_argument("--workload", default="diffusion_n512_m1048576")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--ch-fuse", type=int, default=1, help="CH steps per kernel launch")
+    ap.add_argument("--ch-fuse", type=int, default=1000, help="CH steps per kernel launch")
+    ap.add_argument("--ch-sample", type=int, default=1 << 12,
+                    help="runs of the CH ensemble checked against the oracle after all steps")
     ap.add_argument("--probe", action="store_true",
                     help="one dispatch of each kernel (for rocprofv3 counter runs); no timing")
     args = ap.parse_args()

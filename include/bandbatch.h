@@ -215,21 +215,32 @@ bb_status bb_ch_step_stats(bb_factor f, const double *c_in, double *c_out, int64
  * (the forced flow-pattern section, numerical scheme):
  *     C^{n+1} + dt gamma d4 C^{n+1} = C^n + dt [d2 (C^3 - C)^n + v dC^n/deta
  *                                              + f0 k cos(k eta)],
- * i.e. bb_ch_step's right-hand side plus, for run k,
- *     beta[k] W_i(C) + amp[k] cos(kdx[k] i),
- * with W_i dx times the fifth-order Hamilton-Jacobi WENO derivative of the
- * run's state at row i, upwinded for dC/dt = v dC/deta (right-biased
- * differences when beta > 0, left-biased when beta < 0), and eta_i = i dx.
- * Per-run parameters: beta = dt v / dx, amp = dt f0 k, kdx = k dx.
- * `f` must be the cyclic penta factor of the Cahn-Hilliard LHS (bb_ch_step).
- * beta, amp, kdx: device, m doubles each.  c_in, c_out: device double,
- * interleaved, same ld; in place allowed.  All `steps` steps run inside one
- * kernel with the state on chip.
- * Errors: BB_ERR_ARG (not a cyclic penta factor, NULL parameters, sizes),
- * BB_ERR_HIP. */
+ * with the second difference of bb_ch_step (alpha = dt / dx^2), the advection
+ * term dt v dC/deta taken as (dt v / dx) W_i(C), W_i dx times the fifth-order
+ * Hamilton-Jacobi WENO derivative of the run's state at row i, upwinded for
+ * dC/dt = v dC/deta (right-biased differences when v > 0, left-biased when
+ * v < 0), and the forcing at eta_i = i dx.
+ * Per run k: speed v[k], forcing amplitude f0[k] and wavenumber k[k] (device,
+ * m doubles each); dt and dx are shared.  `f` must be the cyclic penta factor
+ * of the Cahn-Hilliard LHS for the same dt and dx (bb_factor_ch).
+ * c_in, c_out: device double, interleaved, same ld; in place allowed.  All
+ * `steps` steps run inside one kernel with the state on chip.
+ * Errors: BB_ERR_ARG (not a cyclic penta factor, NULL parameters, dt or dx not
+ * finite and positive, sizes), BB_ERR_HIP. */
 bb_status bb_ch_forced_step(bb_factor f, const double *c_in, double *c_out, int64_t m, int64_t ld,
-                            double alpha, const double *beta, const double *amp,
-                            const double *kdx, int64_t steps, void *stream);
+                            double dt, double dx, const double *v, const double *f0,
+                            const double *k, int64_t steps, void *stream);
+
+/* The semi-implicit Cahn-Hilliard scheme of Section 5.1 on n periodic grid
+ * points of a domain of length L (dx = L / n): factorise its left-hand side,
+ * the cyclic pentadiagonal matrix with a = e = sigma, b = d = -4 sigma,
+ * c = 1 + 6 sigma, sigma = gamma dt / dx^4 (the implicit fourth difference),
+ * and return sigma and alpha = dt / dx^2 (the explicit second difference of
+ * C^3 - C, the alpha of bb_ch_step).  sigma, alpha: host, may be NULL.
+ * Errors: BB_ERR_ARG (n < 5, length, gamma or dt not finite and positive),
+ * BB_ERR_UNSUPPORTED (n above the pentadiagonal limit), BB_ERR_OOM. */
+bb_status bb_factor_ch(int64_t n, double length, double gamma, double dt, bb_factor *out,
+                       double *sigma, double *alpha);
 
 /* ---------------------------------------------------------------- Crank-Nicolson
  * `steps` Crank-Nicolson steps of m systems (Section 3 benchmark problem:

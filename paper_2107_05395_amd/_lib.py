@@ -50,7 +50,10 @@ SIGNATURES = {
     "bb_cn_trajectory": (_S, [_FACTOR, _P, _P, _P, _I64, _I64, _I64, _P]),
     "bb_copy_tiles": (_S, [_P, _P, _I64, _P]),
     "bb_ch_stats_workspace_bytes": (ctypes.c_size_t, [_FACTOR, _I64, _I64]),
-    "bb_ch_forced_step": (_S, [_FACTOR, _P, _P, _I64, _I64, ctypes.c_double, _P, _P, _P, _I64, _P]),
+    "bb_ch_forced_step": (_S, [_FACTOR, _P, _P, _I64, _I64, ctypes.c_double, ctypes.c_double,
+                               _P, _P, _P, _I64, _P]),
+    "bb_factor_ch": (_S, [_I64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                          ctypes.POINTER(_FACTOR), _D, _D]),
     "bb_ch_step_stats": (_S, [_FACTOR, _P, _P, _I64, _I64, ctypes.c_double, _I64, _I64, _P, _P,
                               ctypes.c_size_t, _P]),
     "bb_mse_workspace_bytes": (ctypes.c_size_t, [_I64, _I64]),

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/bandbatch.h"
 #include "factor.h"
@@ -670,16 +671,20 @@ bb_status bb_ch_step_stats(bb_factor fh, const double *c_in, double *c_out, int6
 }
 
 bb_status bb_ch_forced_step(bb_factor fh, const double *c_in, double *c_out, int64_t m,
-                            int64_t ld, double alpha, const double *beta, const double *amp,
-                            const double *kdx, int64_t steps, void *stream)
+                            int64_t ld, double dt, double dx, const double *v, const double *f0,
+                            const double *k, int64_t steps, void *stream)
 {
     bb_status st = check_batch(fh, c_in, c_out, m, ld);
     if (st != BB_OK) return st;
     bb::Factor &f = fh->f;
     if (f.kind != bb::kPentaCyclic) return fail(BB_ERR_ARG, "needs a cyclic pentadiagonal factor");
     if (steps < 1) return fail(BB_ERR_ARG, "steps < 1");
-    if (!std::isfinite(alpha)) return fail(BB_ERR_ARG, "alpha is not finite");
-    if (m > 0 && (!beta || !amp || !kdx)) return fail(BB_ERR_ARG, "parameter pointer is NULL");
+    if (!(dt > 0.0) || !(dx > 0.0) || !std::isfinite(dt) || !std::isfinite(dx))
+        return fail(BB_ERR_ARG, "dt and dx must be finite and positive");
+    // the scheme's explicit second difference: dt d2 N ~ (dt / dx^2) (N_{i-1} - 2 N_i + N_{i+1})
+    const double alpha = dt / (dx * dx);
+    if (!std::isfinite(alpha)) return fail(BB_ERR_ARG, "dt / dx^2 is not finite");
+    if (m > 0 && (!v || !f0 || !k)) return fail(BB_ERR_ARG, "parameter pointer is NULL");
     if (m == 0) { g_last_error.clear(); return BB_OK; }
     int dev;
     if ((st = current_device(&dev)) != BB_OK) return st;
@@ -688,10 +693,33 @@ bb_status bb_ch_forced_step(bb_factor fh, const double *c_in, double *c_out, int
     bb::SweepGeom g;
     if ((st = stepper_setup(f, dev, m, ld, &pl, &tab, &g)) != BB_OK) return st;
     hipError_t e = bb::launch_ch_forced((const double *)tab.ptr, tab.elems, f.primal.cor.q, g,
-                                        pl.scalar, alpha, beta, amp, kdx, steps, c_in, c_out,
+                                        pl.scalar, alpha, dt, dx, v, f0, k, steps, c_in, c_out,
                                         (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "forced Cahn-Hilliard launch");
     g_last_error.clear();
+    return BB_OK;
+}
+
+bb_status bb_factor_ch(int64_t n, double length, double gamma, double dt, bb_factor *out,
+                       double *sigma, double *alpha)
+{
+    if (!out) return fail(BB_ERR_ARG, "out is NULL");
+    if (n < 5) return fail(BB_ERR_ARG, "n must be at least 5");
+    if (!(length > 0.0) || !(gamma > 0.0) || !(dt > 0.0) || !std::isfinite(length) ||
+        !std::isfinite(gamma) || !std::isfinite(dt))
+        return fail(BB_ERR_ARG, "length, gamma and dt must be finite and positive");
+    // n periodic points on [0, L): dx = L / n; implicit hyperdiffusion
+    // dt gamma d4 C ~ sigma (C_{i-2} - 4 C_{i-1} + 6 C_i - 4 C_{i+1} + C_{i+2})
+    const double dx = length / (double)n;
+    const double dx2 = dx * dx;
+    const double s = gamma * dt / (dx2 * dx2);
+    const double a = dt / dx2;
+    if (!std::isfinite(s) || !std::isfinite(a)) return fail(BB_ERR_ARG, "coefficients overflow");
+    std::vector<double> e(n, s), d(n, -4.0 * s), c(n, 1.0 + 6.0 * s);
+    bb_status st = make(bb::kPentaCyclic, e.data(), d.data(), c.data(), d.data(), e.data(), n, out);
+    if (st != BB_OK) return st;
+    if (sigma) *sigma = s;
+    if (alpha) *alpha = a;
     return BB_OK;
 }
 

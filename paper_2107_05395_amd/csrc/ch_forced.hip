@@ -40,21 +40,26 @@ __device__ __forceinline__ double weno5(double v1, double v2, double v3, double 
 }
 
 // f_i = C_i + alpha (N_{i-1} - 2 N_i + N_{i+1}) + beta W_i(C) + amp cos(kdx i),
-// N = C^3 - C, periodic; beta = dt v / dx, amp = dt f0 k, kdx = k dx per run,
-// W upwinded for dC/dt = v dC/deta (beta > 0: right-biased differences).
+// N = C^3 - C, periodic, W upwinded for dC/dt = v dC/deta (beta > 0:
+// right-biased differences).  The scheme's per-run coefficients follow from
+// the physical parameters of run k when its group is loaded: the advection
+// term dt v dC/deta with the WENO derivative W/dx gives beta = dt v / dx, the
+// forcing dt f0 k cos(k eta) at eta_i = i dx gives amp = dt f0 k and
+// kdx = k dx.
 struct ForcedChRhs {
     static constexpr int R = 3;
-    double alpha;
-    const double *beta, *amp, *kdx;   // device, one per run
+    double alpha, dt, dx;
+    const double *v, *f0, *k;   // device, one per run
     struct State {
         double beta, amp, c0, s0, cd, sd;   // cos, sin of kdx * row0 and of kdx
     };
-    __device__ State lane_state(int64_t k, int row0) const
+    __device__ State lane_state(int64_t run, int row0) const
     {
         State st;
-        st.beta = beta[k];
-        st.amp = amp[k];
-        const double kd = kdx[k];
+        const double kr = k[run];
+        st.beta = dt * v[run] / dx;
+        st.amp = dt * f0[run] * kr;
+        const double kd = kr * dx;
         sincos(kd * (double)row0, &st.s0, &st.c0);
         sincos(kd, &st.sd, &st.cd);
         return st;
@@ -124,15 +129,17 @@ struct ForcedChRhs {
 }  // namespace
 
 hipError_t launch_ch_forced(const double *table, int64_t table_elems, const CyclicQ &q,
-                            const SweepGeom &g, bool scalar, double alpha, const double *beta,
-                            const double *amp, const double *kdx, int64_t steps,
+                            const SweepGeom &g, bool scalar, double alpha, double dt, double dx,
+                            const double *v, const double *f0, const double *k, int64_t steps,
                             const double *in, double *out, hipStream_t s)
 {
     ForcedChRhs r;
     r.alpha = alpha;
-    r.beta = beta;
-    r.amp = amp;
-    r.kdx = kdx;
+    r.dt = dt;
+    r.dx = dx;
+    r.v = v;
+    r.f0 = f0;
+    r.k = k;
     return launch_stepper<ForcedChRhs, 2, true>(table, table_elems, q, g, scalar, r, steps, in,
                                                 out, s);
 }

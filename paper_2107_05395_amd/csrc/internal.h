@@ -171,11 +171,12 @@ hipError_t launch_ch(const double *table, int64_t table_elems, const CyclicQ &q,
                      int64_t samples = 0, double *partial = nullptr, double *lbar = nullptr);
 
 // Forced Cahn-Hilliard steps in the frame of the travelling wave
-// (ch_forced.hip): per run k, beta[k] = dt v / dx, amp[k] = dt f0 k,
-// kdx[k] = k dx (device arrays of m doubles); scalar / log2Q as for launch_ch.
+// (ch_forced.hip): per run, the speed v[k], forcing amplitude f0[k] and
+// wavenumber k[k] (device arrays of m doubles); alpha = dt / dx^2; scalar /
+// log2Q as for launch_ch.
 hipError_t launch_ch_forced(const double *table, int64_t table_elems, const CyclicQ &q,
-                            const SweepGeom &g, bool scalar, double alpha, const double *beta,
-                            const double *amp, const double *kdx, int64_t steps,
+                            const SweepGeom &g, bool scalar, double alpha, double dt, double dx,
+                            const double *v, const double *f0, const double *k, int64_t steps,
                             const double *in, double *out, hipStream_t stream);
 
 // Crank-Nicolson steps x <- A^{-1} (B x) with B a constant (2K+1)-point

@@ -99,13 +99,6 @@ def random_dominant_penta(n: int, seed: int, margin: float = 1.0):
 
 # ---------------------------------------------------------------- workloads
 
-def ch_parameters(n: int = 256, length: float = 2.0 * math.pi, gamma: float = 0.01,
-                  dt: float = 1e-3):
-    """sigma = gamma dt / dx^4, alpha = dt / dx^2 with dx = L / n (Section 5.1)."""
-    dx = length / n
-    return gamma * dt / dx ** 4, dt / dx ** 2
-
-
 WORKLOADS = {
     # name: description; seeds are SEED_BASE + index
     "diffusion_n256_m1024": dict(kind="tri", n=256, m=1024, r=0.5, seed=SEED_BASE + 0),

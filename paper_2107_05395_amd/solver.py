@@ -73,6 +73,21 @@ class Factor:
     def penta(cls, a, b, c, d, e, cyclic: bool = False) -> "Factor":
         return cls._make("penta", (a, b, c, d, e), cyclic)
 
+    @classmethod
+    def cahn_hilliard(cls, n: int, length: float, gamma: float, dt: float) -> "Factor":
+        """The left-hand side of the semi-implicit Cahn-Hilliard scheme on n
+        periodic points of a domain of length `length` (bb_factor_ch).  The
+        factor carries the scheme's scalars: .sigma, .alpha (dt/dx^2, the
+        argument of ch_step), .dt and .dx."""
+        h = ctypes.c_void_p()
+        sigma, alpha = ctypes.c_double(), ctypes.c_double()
+        check(lib().bb_factor_ch(int(n), float(length), float(gamma), float(dt), ctypes.byref(h),
+                                 ctypes.byref(sigma), ctypes.byref(alpha)))
+        f = cls("penta_cyclic", None, int(n), h)
+        f.sigma, f.alpha, f.dt, f.dx, f.gamma = (sigma.value, alpha.value, float(dt),
+                                                 float(length) / int(n), float(gamma))
+        return f
+
     def __del__(self):
         h = getattr(self, "_handle", None)
         if h is not None and h.value:
@@ -203,14 +218,14 @@ class Factor:
                                          _stream_ptr(c)))
         return out, lbar[:samples]
 
-    def ch_forced_step(self, c: torch.Tensor, alpha: float, beta: torch.Tensor,
-                       amp: torch.Tensor, kdx: torch.Tensor, steps: int = 1,
+    def ch_forced_step(self, c: torch.Tensor, dt: float, dx: float, v: torch.Tensor,
+                       f0: torch.Tensor, k: torch.Tensor, steps: int = 1,
                        out: torch.Tensor | None = None) -> torch.Tensor:
-        """Forced Cahn-Hilliard steps in the frame of the travelling wave; per
-        run k: beta[k] = dt v / dx, amp[k] = dt f0 k, kdx[k] = k dx (float64
-        device tensors of m entries)."""
+        """Forced Cahn-Hilliard steps in the frame of the travelling wave
+        (bb_ch_forced_step); per run: speed v, forcing amplitude f0 and
+        wavenumber k (float64 device tensors of m entries); dt, dx shared."""
         m, ld = _batch_view(c, self.n, torch.float64, "c")
-        for name, t in (("beta", beta), ("amp", amp), ("kdx", kdx)):
+        for name, t in (("v", v), ("f0", f0), ("k", k)):
             if (t.dtype != torch.float64 or t.device != c.device or t.numel() != m
                     or not t.is_contiguous()):
                 raise ValueError("%s must be a contiguous float64 tensor of m entries on c's device" % name)
@@ -220,10 +235,10 @@ class Factor:
             raise ValueError("out must match c in shape and strides")
         with torch.cuda.device(c.device):
             check(lib().bb_ch_forced_step(self._handle, ctypes.c_void_p(c.data_ptr()),
-                                          ctypes.c_void_p(out.data_ptr()), m, ld, float(alpha),
-                                          ctypes.c_void_p(beta.data_ptr()),
-                                          ctypes.c_void_p(amp.data_ptr()),
-                                          ctypes.c_void_p(kdx.data_ptr()), int(steps),
+                                          ctypes.c_void_p(out.data_ptr()), m, ld, float(dt),
+                                          float(dx), ctypes.c_void_p(v.data_ptr()),
+                                          ctypes.c_void_p(f0.data_ptr()),
+                                          ctypes.c_void_p(k.data_ptr()), int(steps),
                                           _stream_ptr(c)))
         return out
 

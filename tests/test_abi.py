@@ -34,7 +34,7 @@ def test_header_declares_expected_entry_points():
     for must in ["bb_factor_shared_tri", "bb_factor_shared_penta", "bb_factor_shared_tri_cyclic",
                  "bb_factor_shared_penta_cyclic", "bb_solve_batch_tri", "bb_solve_batch_penta",
                  "bb_solve_batch_tri_adjoint", "bb_solve_batch_penta_adjoint", "bb_band_grad",
-                 "bb_ch_step", "bb_ch_step_stats", "bb_ch_forced_step", "bb_cn_step",
+                 "bb_ch_step", "bb_ch_step_stats", "bb_ch_forced_step", "bb_factor_ch", "bb_cn_step",
                  "bb_status_string", "bb_last_error_message"]:
         assert must in names
 
@@ -134,10 +134,14 @@ def test_solve_argument_checks_need_no_gpu(L):
     assert L.bb_ch_step_stats(hc, fake, fake, 4, 4, 1.0, 4, 1, fake, None, 1 << 20, None) == -1  # no workspace
     assert L.bb_ch_stats_workspace_bytes(hc, 4, 4) == 8 * 4             # one group of 4 runs, 4 samples
     assert L.bb_ch_step_stats(hc, fake, fake, 4, 4, 1.0, 4, 1, fake, fake, 8 * 4 - 1, None) == -1  # too small
-    assert L.bb_ch_forced_step(h, fake, fake, 4, 4, 1.0, fake, fake, fake, 1, None) == -1  # not cyclic penta
-    assert L.bb_ch_forced_step(hc, fake, fake, 4, 4, 1.0, None, fake, fake, 1, None) == -1  # no beta
-    assert L.bb_ch_forced_step(hc, fake, fake, 4, 4, 1.0, fake, fake, fake, 0, None) == -1  # steps < 1
-    assert L.bb_ch_forced_step(hc, None, None, 0, 1, 1.0, None, None, None, 1, None) == 0   # m = 0
+    F = L.bb_ch_forced_step
+    assert F(h, fake, fake, 4, 4, 0.1, 0.2, fake, fake, fake, 1, None) == -1    # not cyclic penta
+    assert F(hc, fake, fake, 4, 4, 0.1, 0.2, None, fake, fake, 1, None) == -1   # no v
+    assert F(hc, fake, fake, 4, 4, 0.1, 0.2, fake, fake, fake, 0, None) == -1   # steps < 1
+    assert F(hc, fake, fake, 4, 4, -0.1, 0.2, fake, fake, fake, 1, None) == -1  # dt <= 0
+    assert F(hc, fake, fake, 4, 4, 0.1, 0.0, fake, fake, fake, 1, None) == -1   # dx <= 0
+    assert F(hc, fake, fake, 4, 4, float("inf"), 0.2, fake, fake, fake, 1, None) == -1
+    assert F(hc, None, None, 0, 1, 0.1, 0.2, None, None, None, 1, None) == 0    # m = 0
     L.bb_factor_destroy(hc)
     assert L.bb_cn_step(h, None, fake, fake, 4, 4, 1, None) == -1           # no stencil
     assert L.bb_cn_step(h, bad, fake, fake, 4, 4, 1, None) == -1            # weight not finite
@@ -164,3 +168,32 @@ def test_workspace_sizes(L):
     assert L.bb_band_grad_workspace_bytes(h, 1000) >= 3 * n * 8
     assert L.bb_mse_workspace_bytes(n, 1000) >= 8
     L.bb_factor_destroy(h)
+
+
+def _golden_ch_rows():
+    path = os.path.join(ROOT, "tests", "golden", "ch_coefficients.txt")
+    with open(path) as fh:
+        return [tuple(float(x) for x in line.split()) for line in fh
+                if line.strip() and not line.startswith("#")]
+
+
+def test_cahn_hilliard_factor_coefficients(L):
+    """bb_factor_ch: the library's own sigma = gamma dt / dx^4 and
+    alpha = dt / dx^2 of the Section 5.1 scheme against the hand-evaluated
+    golden values; host only."""
+    for n, length, gamma, dt, s_ref, a_ref in _golden_ch_rows():
+        h = ctypes.c_void_p()
+        sigma, alpha = ctypes.c_double(), ctypes.c_double()
+        assert L.bb_factor_ch(int(n), length, gamma, dt, ctypes.byref(h), ctypes.byref(sigma),
+                              ctypes.byref(alpha)) == 0
+        assert abs(sigma.value - s_ref) < 5e-6 * s_ref and abs(alpha.value - a_ref) < 5e-6 * a_ref
+        nn, kind = ctypes.c_int64(), ctypes.c_int32()
+        assert L.bb_factor_info(h, ctypes.byref(nn), ctypes.byref(kind), None) == 0
+        assert (nn.value, kind.value) == (int(n), 3)
+        L.bb_factor_destroy(h)
+    h = ctypes.c_void_p()
+    assert L.bb_factor_ch(4, 1.0, 0.01, 1e-3, ctypes.byref(h), None, None) == -1       # n < 5
+    assert L.bb_factor_ch(64, -1.0, 0.01, 1e-3, ctypes.byref(h), None, None) == -1     # L <= 0
+    assert L.bb_factor_ch(64, 1.0, 0.0, 1e-3, ctypes.byref(h), None, None) == -1       # gamma <= 0
+    assert L.bb_factor_ch(64, 1.0, 0.01, float("nan"), ctypes.byref(h), None, None) == -1
+    assert L.bb_factor_ch(64, 1.0, 0.01, 1e-3, None, None, None) == -1

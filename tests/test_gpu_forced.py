@@ -23,11 +23,12 @@ def _lib_loaded():
 def _setup(n, m, seed, L=2 * math.pi):
     """Flow-pattern style batch: dt = 0.1 dx, gamma = 0.01; per run a speed
     v in [-1, 1] (some exactly 0), amplitude f0 in [0, 2], wavenumber k in
-    {1, 2, 3}, mean concentration in [0, 1.5] plus U[-0.1, 0.1)."""
+    {1, 2, 3}, mean concentration in [0, 1.5] plus U[-0.1, 0.1).  The GPU side
+    gets the physical parameters and the product's factor; the oracle side
+    maps them with its own coefficients."""
     from paper_2107_05395_amd import Factor
     dx = L / n
     dt = 0.1 * dx
-    sigma, alpha = inputs.ch_parameters(n=n, length=L, gamma=0.01, dt=dt)
     g = inputs.rng(seed)
     v = g.uniform(-1, 1, m)
     v[::7] = 0.0
@@ -35,9 +36,23 @@ def _setup(n, m, seed, L=2 * math.pi):
     k = g.integers(1, 4, m).astype(np.float64) * (2 * math.pi / L)
     mean = g.uniform(0, 1.5, m)
     c0 = mean + inputs.uniform_batch(n, m, seed=seed + 1, lo=-0.1, hi=0.1)
+    f = Factor.cahn_hilliard(n, L, 0.01, dt)
+    sigma, alpha = oracle.ch_coefficients(0.01, dx, dt)
     beta, amp, kdx = oracle.ch_forced_parameters(dt, dx, v, f0, k)
-    f = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
-    return f, sigma, alpha, c0, beta, amp, kdx
+    gpu = dict(dt=dt, dx=dx, v=dev(v), f0=dev(f0), k=dev(k))
+    ref = dict(sigma=sigma, alpha=alpha, beta=beta, amp=amp, kdx=kdx)
+    return f, c0, gpu, ref
+
+
+def _oracle_steps(c0, ref, steps, cols=None):
+    sel = slice(None) if cols is None else cols
+    return oracle.ch_forced_step(c0[:, sel], ref["sigma"], ref["alpha"], ref["beta"][sel],
+                                 ref["amp"][sel], ref["kdx"][sel], steps=steps)
+
+
+def _gpu_steps(f, c, gpu, steps, out=None):
+    return f.ch_forced_step(c, gpu["dt"], gpu["dx"], gpu["v"], gpu["f0"], gpu["k"], steps=steps,
+                            out=out)
 
 
 @pytest.mark.parametrize("n,m", [(256, 300), (512, 300), (64, 300), (1024, 300), (300, 200),
@@ -45,15 +60,14 @@ def _setup(n, m, seed, L=2 * math.pi):
                                  (64, 70000)])
 def test_forced_steps_match_oracle(n, m):
     say("forced", n, m)
-    f, sigma, alpha, c0, beta, amp, kdx = _setup(n, m, seed=n + m)
+    f, c0, gpu, ref = _setup(n, m, seed=n + m)
     steps = 5
     cols = np.unique(np.r_[np.linspace(0, m - 1, 300).astype(np.int64), m - 1])
-    ref = oracle.ch_forced_step(c0[:, cols], sigma, alpha, beta[cols], amp[cols], kdx[cols],
-                                steps=steps)
-    out = host(f.ch_forced_step(dev(c0), alpha, dev(beta), dev(amp), dev(kdx), steps=steps))
-    err = rel_err(out[:, cols], ref)
+    want = _oracle_steps(c0, ref, steps, cols)
+    out = host(_gpu_steps(f, dev(c0), gpu, steps))
+    err = rel_err(out[:, cols], want)
     say("  rel err", err)
-    assert err < 1e-11
+    assert err < 1e-12
 
 
 @pytest.mark.parametrize("n", [64, 256, 512, 1024])
@@ -62,43 +76,44 @@ def test_forced_kernel_variants_agree_bitwise(n, monkeypatch):
     the LDS one-wave group do the same arithmetic (64-row chunks forced)."""
     monkeypatch.setenv("BANDBATCH_MAX_CHUNK", "64")
     m = 3000
-    f, sigma, alpha, c0, beta, amp, kdx = _setup(n, m, seed=7 * n)
-    args = (dev(beta), dev(amp), dev(kdx))
+    f, c0, gpu, ref = _setup(n, m, seed=7 * n)
     t = dev(c0)
-    a = host(f.ch_forced_step(t, alpha, *args, steps=4))
+    a = host(_gpu_steps(f, t, gpu, 4))
     monkeypatch.setenv("BANDBATCH_CH_UNIFORM", "0")
-    assert np.array_equal(a, host(f.ch_forced_step(t, alpha, *args, steps=4)))
+    assert np.array_equal(a, host(_gpu_steps(f, t, gpu, 4)))
     monkeypatch.setenv("BANDBATCH_WAVES_PER_SYSTEM", "1")
-    assert np.array_equal(a, host(f.ch_forced_step(t, alpha, *args, steps=4)))
+    assert np.array_equal(a, host(_gpu_steps(f, t, gpu, 4)))
 
 
 @pytest.mark.parametrize("chunk", ["4", "8", "16", "32"])
 def test_forced_chunk_sizes_match_oracle(chunk, monkeypatch):
     monkeypatch.setenv("BANDBATCH_MAX_CHUNK", chunk)
     for n in (256, 250):
-        f, sigma, alpha, c0, beta, amp, kdx = _setup(n, 130, seed=11 + n)
-        ref = oracle.ch_forced_step(c0, sigma, alpha, beta, amp, kdx, steps=3)
-        out = host(f.ch_forced_step(dev(c0), alpha, dev(beta), dev(amp), dev(kdx), steps=3))
-        assert rel_err(out, ref) < 1e-11, (n, chunk)
+        f, c0, gpu, ref = _setup(n, 130, seed=11 + n)
+        want = _oracle_steps(c0, ref, 3)
+        out = host(_gpu_steps(f, dev(c0), gpu, 3))
+        assert rel_err(out, want) < 1e-12, (n, chunk)
 
 
 def test_forced_without_forcing_matches_plain_steps_and_in_place():
     n, m = 256, 500
-    f, sigma, alpha, c0, beta, amp, kdx = _setup(n, m, seed=3)
+    f, c0, gpu, ref = _setup(n, m, seed=3)
     z = torch.zeros(m, dtype=torch.float64, device="cuda")
     t = dev(c0)
-    a = host(f.ch_forced_step(t, alpha, z, z, dev(kdx), steps=6))
-    b = host(f.ch_step(t, alpha, steps=6))
+    a = host(f.ch_forced_step(t, gpu["dt"], gpu["dx"], z, z, gpu["k"], steps=6))
+    b = host(f.ch_step(t, f.alpha, steps=6))
     assert rel_err(a, b) < 1e-13
-    f.ch_forced_step(t, alpha, dev(beta), dev(amp), dev(kdx), steps=6, out=t)
-    ref = oracle.ch_forced_step(c0, sigma, alpha, beta, amp, kdx, steps=6)
-    assert rel_err(host(t), ref) < 1e-11
+    _gpu_steps(f, t, gpu, 6, out=t)
+    assert rel_err(host(t), _oracle_steps(c0, ref, 6)) < 1e-12
 
 
-def test_forced_rejects_bad_parameter_tensors():
-    f, sigma, alpha, c0, beta, amp, kdx = _setup(64, 10, seed=4)
+def test_forced_rejects_bad_parameters():
+    f, c0, gpu, ref = _setup(64, 10, seed=4)
     with pytest.raises(ValueError):
-        f.ch_forced_step(dev(c0), alpha, dev(beta[:5]), dev(amp), dev(kdx))
+        f.ch_forced_step(dev(c0), gpu["dt"], gpu["dx"], gpu["v"][:5], gpu["f0"], gpu["k"])
+    from paper_2107_05395_amd import BandBatchError
+    with pytest.raises(BandBatchError):
+        f.ch_forced_step(dev(c0), -1.0, gpu["dx"], gpu["v"], gpu["f0"], gpu["k"])
 
 
 def test_steppers_on_strided_batches():
@@ -106,19 +121,19 @@ def test_steppers_on_strided_batches():
     Cahn-Hilliard-with-statistic and the forced steps: the same results as
     on contiguous arrays, and the columns past m untouched."""
     n, m, extra = 256, 700, 37
-    f, sigma, alpha, c0, beta, amp, kdx = _setup(n, m, seed=21)
+    f, c0, gpu, ref = _setup(n, m, seed=21)
     wide = torch.zeros(n, m + extra, dtype=torch.float64, device="cuda")
     wide[:, :m] = dev(c0)
     wide[:, m:] = 7.0
     out_wide = torch.full_like(wide, 9.0)
     view, oview = wide[:, :m], out_wide[:, :m]
-    got = f.ch_forced_step(view, alpha, dev(beta), dev(amp), dev(kdx), steps=4, out=oview)
-    ref = f.ch_forced_step(dev(c0), alpha, dev(beta), dev(amp), dev(kdx), steps=4)
-    assert np.array_equal(host(got), host(ref))
+    got = _gpu_steps(f, view, gpu, 4, out=oview)
+    want = _gpu_steps(f, dev(c0), gpu, 4)
+    assert np.array_equal(host(got), host(want))
     assert torch.all(out_wide[:, m:] == 9.0) and torch.all(wide[:, m:] == 7.0)
     out_wide.fill_(9.0)
-    _, lb = f.ch_step_stats(view, alpha, steps=4, every=2, out=oview)
-    _, lb_ref = f.ch_step_stats(dev(c0), alpha, steps=4, every=2)
+    _, lb = f.ch_step_stats(view, f.alpha, steps=4, every=2, out=oview)
+    _, lb_ref = f.ch_step_stats(dev(c0), f.alpha, steps=4, every=2)
     assert np.array_equal(host(lb), host(lb_ref)) and torch.all(out_wide[:, m:] == 9.0)
     from paper_2107_05395_amd import Factor
     bands, w = inputs.cn_hyperdiffusion_problem(n, 0.5)

@@ -22,6 +22,8 @@ systems the oracle solves one by one, plus properties that hold at any size.
   * forced Cahn-Hilliard flow-pattern batch (768 x 768 runs, n=512): 20
     steps, sampled runs.
 """
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -114,12 +116,12 @@ def test_cahn_hilliard_n256_m2p20_sampled():
     from paper_2107_05395_amd import Factor
     spec = inputs.WORKLOADS["cahn_hilliard_n256_m1048576"]
     n, m = spec["n"], spec["m"]
-    sigma, alpha = inputs.ch_parameters(n=n, gamma=spec["gamma"], dt=spec["dt"])
+    sigma, alpha = oracle.ch_coefficients(spec["gamma"], 2 * math.pi / n, spec["dt"])
     c0 = inputs.uniform_batch(n, m, seed=spec["seed"], lo=-0.1, hi=0.1)
-    f = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
+    f = Factor.cahn_hilliard(n, 2 * math.pi, spec["gamma"], spec["dt"])
     t = torch.from_numpy(c0).cuda()
     steps = 10
-    out = f.ch_step(t, alpha, steps=steps)
+    out = f.ch_step(t, f.alpha, steps=steps)
     cols = sample_cols(m, 256)
     ref = oracle.ch_step(c0[:, cols], sigma, alpha, steps=steps)
     err = rel_err(cols_of(out, cols), ref)
@@ -214,16 +216,16 @@ def test_ch_coarsening_statistic_full_batch():
     spec = inputs.WORKLOADS["ch_coarsening_L2pi"]
     n, m, L, gamma = spec["n"], spec["m"], spec["length"], spec["gamma"]
     dt = 0.1 * L / n
-    sigma, alpha = inputs.ch_parameters(n=n, length=L, gamma=gamma, dt=dt)
-    f = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
+    sigma, alpha = oracle.ch_coefficients(gamma, L / n, dt)
+    f = Factor.cahn_hilliard(n, L, gamma, dt)
     c0 = inputs.uniform_batch(n, m, seed=spec["seed"], lo=-0.1, hi=0.1)
     steps = 4
     ref, ref_c = oracle.ch_coarsening(c0, sigma, alpha, steps, 1)
-    out, lbar = f.ch_step_stats(torch.from_numpy(c0).cuda(), alpha, steps=steps, every=1)
+    out, lbar = f.ch_step_stats(torch.from_numpy(c0).cuda(), f.alpha, steps=steps, every=1)
     lb = lbar.cpu().numpy()
     err = float(np.max(np.abs(lb - ref) / (ref - 1.0)))
     say("coarsening full batch lbar", lb, "rel err of lbar - 1", err)
-    assert err < 1e-11
+    assert err < 1e-12
     cols = sample_cols(m, 512, seed=6)
     assert rel_err(cols_of(out, cols), ref_c[:, cols]) < 1e-12
 
@@ -238,18 +240,18 @@ def test_forced_flowmap_batch_sampled():
     m = G * G
     dx = L / n
     dt = 0.1 * dx
-    sigma, alpha = inputs.ch_parameters(n=n, length=L, gamma=spec["gamma"], dt=dt)
+    sigma, alpha = oracle.ch_coefficients(spec["gamma"], dx, dt)
     f0 = np.repeat(np.linspace(spec["f0"][0], spec["f0"][1], G), G)
     mean = np.tile(np.linspace(spec["mean"][0], spec["mean"][1], G), G)
-    beta, amp, kdx = oracle.ch_forced_parameters(dt, dx, np.full(m, spec["v"]), f0,
-                                                 np.full(m, spec["k"]))
+    v, k = np.full(m, spec["v"]), np.full(m, spec["k"])
+    beta, amp, kdx = oracle.ch_forced_parameters(dt, dx, v, f0, k)
     c0 = mean + inputs.uniform_batch(n, m, seed=spec["seed"], lo=-0.1, hi=0.1)
     cols = sample_cols(m, 256, seed=7)
     ref = oracle.ch_forced_step(c0[:, cols], sigma, alpha, beta[cols], amp[cols], kdx[cols],
                                 steps=20)
-    f = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
+    f = Factor.cahn_hilliard(n, L, spec["gamma"], dt)
     dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    out = f.ch_forced_step(dv(c0), alpha, dv(beta), dv(amp), dv(kdx), steps=20)
+    out = f.ch_forced_step(dv(c0), dt, dx, dv(v), dv(f0), dv(k), steps=20)
     err = rel_err(cols_of(out, cols), ref)
     say("forced flow-map batch, 20 steps, rel err", err)
-    assert err < 1e-11
+    assert err < 1e-12

@@ -3,6 +3,8 @@ host synchronisation once a call's coefficient table exists), so a sequence
 of solves and fused steps can be captured in a HIP graph and replayed.  Each
 replay must reproduce the eager results bitwise, with eager work and
 synchronisations between the replays."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -20,8 +22,7 @@ def test_solves_and_steps_replay_in_a_graph():
     tri = Factor.tri(*inputs.diffusion_tri_bands(n, 1.0))
     pb, pw = inputs.cn_hyperdiffusion_problem(n, 0.8)
     penta = Factor.penta(*pb, cyclic=True)
-    sigma, alpha = inputs.ch_parameters(n=n)
-    ch = Factor.penta(*inputs.ch_penta_bands(n, sigma), cyclic=True)
+    ch = Factor.cahn_hilliard(n, 2 * math.pi, 0.01, 1e-3)
     rhs_h = inputs.uniform_batch(n, m, seed=81)
     rhs = dev(rhs_h)
     c0 = dev(inputs.uniform_batch(n, m, seed=82, lo=-0.1, hi=0.1))
@@ -32,7 +33,7 @@ def test_solves_and_steps_replay_in_a_graph():
         tri.solve(rhs, out=outs[1], precision="f32r")
         penta.solve(rhs, out=outs[2])
         penta.cn_step(rhs, pw, steps=5, out=outs[3])
-        ch.ch_step(c0, alpha, steps=3, out=outs[4])
+        ch.ch_step(c0, ch.alpha, steps=3, out=outs[4])
 
     work()                                     # eager: builds and uploads every table
     torch.cuda.synchronize()

@@ -1,5 +1,6 @@
 """Pins for the oracle's semi-implicit Cahn-Hilliard step (Section 5.1)."""
 import math
+import os
 
 import numpy as np
 
@@ -7,10 +8,15 @@ from paper_2107_05395_amd import inputs
 from tests.dense import penta_dense, rel_err
 
 
+def _coef(oracle, n, length=2 * math.pi, gamma=0.01, dt=1e-3):
+    """sigma, alpha of the oracle for n periodic points on a domain of `length`."""
+    return oracle.ch_coefficients(gamma, length / n, dt)
+
+
 def test_ch_step_vs_dense(oracle):
     """RHS built here by array slicing, LHS solved densely with LAPACK."""
     n, m = 24, 5
-    sigma, alpha = inputs.ch_parameters(n=n, length=2 * math.pi, gamma=0.01, dt=1e-3)
+    sigma, alpha = _coef(oracle, n)
     c0 = inputs.uniform_batch(n, m, seed=1, lo=-0.9, hi=0.9)
     nl = c0 ** 3 - c0
     f = c0 + alpha * (np.roll(nl, 1, axis=0) - 2 * nl + np.roll(nl, -1, axis=0))
@@ -23,7 +29,7 @@ def test_ch_mass_conserved(oracle):
     """Periodic boundaries conserve the mean (Section 5): the column sums of the
     LHS are all 1 and the second difference sums to zero."""
     n, m = 256, 64
-    sigma, alpha = inputs.ch_parameters()
+    sigma, alpha = _coef(oracle, 256)
     c = inputs.uniform_batch(n, m, seed=inputs.SEED_BASE + 3, lo=-0.1, hi=0.1)
     mass0 = c.sum(axis=0)
     c = oracle.ch_step(c, sigma, alpha, steps=50)
@@ -36,7 +42,7 @@ def test_ch_single_mode_linear_growth(oracle):
     s_k = 2 - 2 cos(k dx)."""
     n = 256
     dx = 2 * math.pi / n
-    sigma, alpha = inputs.ch_parameters()
+    sigma, alpha = _coef(oracle, 256)
     x = np.arange(n) * dx
     eps, steps = 1e-6, 200
     for k in (1, 5, 8, 20):
@@ -54,14 +60,14 @@ def test_ch_single_mode_linear_growth(oracle):
 
 def test_ch_constant_state_stays(oracle):
     n = 64
-    sigma, alpha = inputs.ch_parameters(n=n)
+    sigma, alpha = _coef(oracle, n)
     c = np.full((n, 3), 0.3)
     assert np.max(np.abs(oracle.ch_step(c, sigma, alpha, steps=5) - 0.3)) < 1e-14
 
 
 def test_ch_step_leaves_its_input_alone(oracle):
     n = 32
-    sigma, alpha = inputs.ch_parameters(n=n)
+    sigma, alpha = _coef(oracle, n)
     c = inputs.uniform_batch(n, 4, seed=5, lo=-0.1, hi=0.1)
     keep = c.copy()
     oracle.ch_step(c, sigma, alpha, steps=3)
@@ -102,7 +108,7 @@ def test_coarsening_samples_follow_the_steps(oracle):
     """lbar after every `every` steps is the mean of l over the runs of the
     state reached by that many single steps."""
     n, m = 32, 5
-    sigma, alpha = inputs.ch_parameters(n=n)
+    sigma, alpha = _coef(oracle, n)
     c0 = inputs.uniform_batch(n, m, seed=92, lo=-0.1, hi=0.1)
     lbar, cT = oracle.ch_coarsening(c0, sigma, alpha, steps=7, every=3)
     assert lbar.shape == (2,)
@@ -111,3 +117,52 @@ def test_coarsening_samples_follow_the_steps(oracle):
         c = oracle.ch_step(c, sigma, alpha, steps=s)
         assert abs(np.mean(oracle.ch_domain_size(c)) - want) < 1e-15 * want
     assert np.array_equal(cT, oracle.ch_step(c, sigma, alpha, steps=1))
+
+
+# ---------------------------------------------------------------- scheme coefficients
+
+def _golden_coefficients():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ch_coefficients.txt")
+    rows = []
+    with open(path) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                n, L, g, dt, s, a = line.split()
+                rows.append((int(n), float(L), float(g), float(dt), float(s), float(a)))
+    return rows
+
+
+def test_ch_coefficients_golden(oracle):
+    """sigma and alpha of the configured ensembles, quoted to 6 significant
+    digits in tests/golden/ch_coefficients.txt."""
+    rows = _golden_coefficients()
+    assert len(rows) == 3
+    for n, L, g, dt, s, a in rows:
+        sigma, alpha = oracle.ch_coefficients(g, L / n, dt)
+        assert abs(sigma - s) < 5e-6 * s and abs(alpha - a) < 5e-6 * a, (n, L, dt)
+
+
+def test_ch_step_growth_rate_is_that_of_the_equation(oracle):
+    """Against the PDE rather than the scheme: linearised about C = 0 the
+    Cahn-Hilliard equation C_t = d2(C^3 - C - gamma d2 C) grows the mode
+    cos(kx) at the rate k^2 - gamma k^4.  One step of tiny dt from a tiny
+    amplitude gives (G - 1)/dt, which must approach that rate at second order
+    in dx (the central differences of Section 5.1).  k = 12 sits past the
+    spinodal cut-off, so the gamma k^4 (sigma) term decides its sign; k = 1
+    and 3 are dominated by the k^2 (alpha) term."""
+    L, gamma, dt, eps = 2 * math.pi, 0.01, 1e-7, 1e-7
+    prev = None
+    for n in (256, 512, 1024):
+        dx = L / n
+        sigma, alpha = oracle.ch_coefficients(gamma, dx, dt)
+        x = np.arange(n) * dx
+        errs = []
+        for k in (1, 3, 8, 12):
+            mode = np.cos(k * x)
+            out = oracle.ch_step((eps * mode)[:, None], sigma, alpha)[:, 0]
+            rate = (np.dot(out, mode) / np.dot(eps * mode, mode) - 1.0) / dt
+            errs.append(abs(rate - (k ** 2 - gamma * k ** 4)) / k ** 2)
+        assert max(errs) < 2e-2, (n, errs)
+        if prev is not None:
+            assert all(e < 0.3 * p for e, p in zip(errs, prev)), (n, errs, prev)
+        prev = errs
