@@ -77,8 +77,13 @@ typedef struct bb_factor_s *bb_factor;
  *   Non-cyclic: a[0], a[1], b[0], d[n-1], e[n-2], e[n-1] are ignored.
  *   Cyclic (indices mod n): those six are the corners (Section 5.1 matrix).
  *
- * Sizes: 1 <= n <= bb_max_n() (tri) or 1024 (penta, whose larger coefficient tables
- * must also fit LDS); cyclic needs 3 <= n (tri) or 5 <= n (penta).
+ * Sizes: 1 <= n <= bb_max_n(); cyclic needs 3 <= n (tri) or 5 <= n (penta).
+ * Up to n = 2048 (tri) and 1024 (penta) every system of a batch is solved
+ * on chip in one launch (its coefficient table staged in LDS).  Longer
+ * ("long") systems are solved in three launches (a pass over every chunk of
+ * C rows, a scan along each system, a second pass) with the solution array
+ * as their scratch: FP64 only, out of place, one Cahn-Hilliard step per
+ * call, no fused Crank-Nicolson or forced steps (BB_ERR_UNSUPPORTED).
  * Errors: BB_ERR_ARG (null pointer, n out of range), BB_ERR_ZERO_PIVOT,
  *         BB_ERR_SINGULAR_CAPACITANCE (cyclic), BB_ERR_OOM.  *out is set only on BB_OK. */
 bb_status bb_factor_shared_tri(const double *a, const double *b, const double *c, int64_t n,
@@ -107,8 +112,8 @@ bb_status bb_factor_upload(bb_factor f, void *stream);
  * batches (small batches take shorter chunks).  Any out pointer may be NULL. */
 bb_status bb_factor_info(bb_factor f, int64_t *n, int32_t *kind, int32_t *chunk);
 
-/* Largest n the sweep kernels are built for (2048: the shared coefficient
- * tables are staged in LDS). */
+/* Largest n a factor may have (262144).  Above n = 2048 (tri) / 1024
+ * (penta) the solves take the three-launch path described with the factors. */
 int64_t bb_max_n(void);
 
 /* The decomposition a call with m systems takes, without running it: rows per
@@ -131,8 +136,12 @@ bb_status bb_plan(bb_factor f, int64_t m, int32_t what, bb_precision p, int32_t 
  * m >= 0 (m == 0 enqueues nothing), ld >= max(m, 1).
  * The tri entry point requires a tri factor (cyclic or not), the penta one a
  * penta factor; the _cyclic names additionally require a cyclic factor.
+ * Long systems (n above 2048 tri / 1024 penta): three launches, x is written
+ * as scratch before it receives the solution, so x must not overlap rhs;
+ * BB_F64 only.
  * Errors: BB_ERR_ARG (wrong factor kind, null pointer, m or ld out of range,
- * unknown precision, rhs == x with BB_F32_RHS_REFINE), BB_ERR_HIP, BB_ERR_OOM
+ * unknown precision, rhs == x with BB_F32_RHS_REFINE), BB_ERR_UNSUPPORTED
+ * (long system: another precision, or rhs == x), BB_ERR_HIP, BB_ERR_OOM
  * (first upload). */
 bb_status bb_solve_batch_tri(bb_factor f, const void *rhs, void *x, int64_t m, int64_t ld,
                              bb_precision p, void *stream);
@@ -187,7 +196,11 @@ bb_status bb_band_grad(bb_factor f, const double *lam, const double *x, int64_t 
  * sigma = gamma dt / dx^4).  All `steps` steps of a system run inside one
  * kernel with the state held on chip, reading c_in once and writing c_out once.
  * c_in, c_out: device double, interleaved, same ld.  steps >= 1.
- * Errors: BB_ERR_ARG (not a cyclic penta factor, sizes), BB_ERR_HIP. */
+ * Long systems (n > 1024): one step per call, in three launches that form the
+ * right-hand side from c_in and its neighbour rows wherever they read it;
+ * c_out must not overlap c_in.
+ * Errors: BB_ERR_ARG (not a cyclic penta factor, sizes), BB_ERR_UNSUPPORTED
+ * (long system with steps > 1 or c_out == c_in), BB_ERR_HIP. */
 bb_status bb_ch_step(bb_factor f, const double *c_in, double *c_out, int64_t m, int64_t ld,
                      double alpha, int64_t steps, void *stream);
 
@@ -238,7 +251,7 @@ bb_status bb_ch_forced_step(bb_factor f, const double *c_in, double *c_out, int6
  * and return sigma and alpha = dt / dx^2 (the explicit second difference of
  * C^3 - C, the alpha of bb_ch_step).  sigma, alpha: host, may be NULL.
  * Errors: BB_ERR_ARG (n < 5, length, gamma or dt not finite and positive),
- * BB_ERR_UNSUPPORTED (n above the pentadiagonal limit), BB_ERR_OOM. */
+ * BB_ERR_UNSUPPORTED (n above bb_max_n()), BB_ERR_OOM. */
 bb_status bb_factor_ch(int64_t n, double length, double gamma, double dt, bb_factor *out,
                        double *sigma, double *alpha);
 

@@ -229,6 +229,36 @@ bb::SweepGeom step_geom(int64_t n, int64_t m, int64_t ld, const StepPlan &pl)
     return g;
 }
 
+// Long systems: n above what one workgroup holds (tri 2048, penta 1024: the
+// one-launch kernels stage the whole coefficient table in LDS) go through the
+// three launches of long_core.h.
+bool is_long(const bb::Factor &f) { return f.n > (f.K == 1 ? bb::kMaxN : bb::kMaxNPenta); }
+
+// Rows per chunk of a long solve: 64 for large batches (fewer chunks, so less
+// scratch traffic and a shorter scan), 32 for small ones, whose time is the
+// latency of a chunk's passes and of the scan.  BANDBATCH_MAX_CHUNK = 16, 32
+// or 64 overrides (tuning).
+int long_chunk(int64_t m)
+{
+    if (const char *env = std::getenv("BANDBATCH_MAX_CHUNK")) {
+        const int v = std::atoi(env);
+        if (v == 16 || v == 32 || v == 64) return v;
+    }
+    return (m == 0 || m >= 4096) ? 64 : 32;
+}
+
+bb::LongGeom long_geom(const bb::Factor &f, int64_t m, int64_t ld, int C)
+{
+    bb::LongGeom g;
+    g.n = (int)f.n;
+    g.C = C;
+    g.P = (int)((f.n + C - 1) / C);
+    g.m = m;
+    g.ld = ld;
+    g.groups = (m + bb::kWave - 1) / bb::kWave;
+    return g;
+}
+
 // Decomposition, device table (the factor's own primal FP64 table for that
 // chunk size, shared with the solves) and launch geometry of a fused stepper.
 bb_status stepper_setup(bb::Factor &f, int dev, int64_t m, int64_t ld, StepPlan *pl,
@@ -242,10 +272,9 @@ bb_status make(int kind, const double *a, const double *b, const double *c, cons
     if (!a || !b || !c || (penta && (!d || !e))) return fail(BB_ERR_ARG, "band pointer is NULL");
     const int64_t nmin = kind == bb::kTriCyclic ? 3 : kind == bb::kPentaCyclic ? 5 : 1;
     if (n < nmin) return fail(BB_ERR_ARG, "n = " + std::to_string(n) + " is below the minimum " + std::to_string(nmin));
-    if (n > bb::kMaxN) return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(n) + " exceeds bb_max_n()");
-    if (penta && n > bb::kMaxNPenta)
-        return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(n) + " exceeds the pentadiagonal limit " +
-                                            std::to_string(bb::kMaxNPenta));
+    if (n > bb::kMaxNLong)
+        return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(n) + " exceeds bb_max_n() = " +
+                                            std::to_string(bb::kMaxNLong));
     bb_factor f = new (std::nothrow) bb_factor_s;
     if (!f) return fail(BB_ERR_OOM, "host allocation");
     const double *bands[5] = {a, b, c, d, e};
@@ -299,9 +328,24 @@ bb_status device_table(bb::Factor &f, std::map<Key, bb::DeviceTable> &cache, con
     return BB_OK;
 }
 
+// The table of a long solve: any number of chunks, read through the scalar
+// cache (key slot 4 = 2 keeps it apart from the one-launch tables).
+bb_status long_table(bb::Factor &f, int dev, bool adjoint, int C, bb::DeviceTable *tab)
+{
+    const int P = (int)((f.n + C - 1) / C);
+    const bb::Direction &dir = adjoint ? f.adjoint : f.primal;
+    return device_table(f, f.dev, std::make_tuple(dev, (int)adjoint, 0, C, 2), false,
+                        [&] { return bb::build_table(dir, f.K, f.cyclic, f.n, C, P); }, tab);
+}
+
 bb_status stepper_setup(bb::Factor &f, int dev, int64_t m, int64_t ld, StepPlan *pl,
                         bb::DeviceTable *tab, bb::SweepGeom *g)
 {
+    if (is_long(f))
+        return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(f.n) +
+                                             ": the fused steppers hold a system on chip (tri n <= " +
+                                             std::to_string(bb::kMaxN) + ", penta n <= " +
+                                             std::to_string(bb::kMaxNPenta) + ")");
     *pl = step_plan(f.n, m);
     const int C = pl->C, P = pl->P;
     bb_status st = device_table(f, f.dev, std::make_tuple(dev, 0, 0, C, 0), false,
@@ -334,9 +378,29 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
         return fail(BB_ERR_ARG, "unknown precision");
     if (p == BB_F32_RHS_REFINE && m > 0 && in == out)
         return fail(BB_ERR_ARG, "BB_F32_RHS_REFINE reads float and writes double: rhs and x must not overlap");
+    if (is_long(f) && p != BB_F64)
+        return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(f.n) +
+                                             " (long system): only BB_F64 is built for it");
+    if (is_long(f) && m > 0 && in == out)
+        return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(f.n) +
+                                             " (long system): x serves as scratch and must not "
+                                             "overlap rhs");
     if (m == 0) { g_last_error.clear(); return BB_OK; }
     int dev;
     if ((st = current_device(&dev)) != BB_OK) return st;
+
+    if (is_long(f)) {
+        const int C = long_chunk(m);
+        bb::DeviceTable tab;
+        if ((st = long_table(f, dev, adjoint, C, &tab)) != BB_OK) return st;
+        const bb::Direction &dir = adjoint ? f.adjoint : f.primal;
+        hipError_t e = bb::launch_long_solve(f.K, f.cyclic, (const double *)tab.ptr, dir.cor.q,
+                                             long_geom(f, m, ld, C), (const double *)in,
+                                             (double *)out, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "long-system launch");
+        g_last_error.clear();
+        return BB_OK;
+    }
 
     const int C = solve_chunk(f.n, m, p);
     const int P = bb::lanes_for(f.n, C);
@@ -451,6 +515,13 @@ bb_status bb_factor_upload(bb_factor fh, void *stream)
     int dev;
     bb_status st = current_device(&dev);
     if (st != BB_OK) return st;
+    if (is_long(f)) {
+        bb::DeviceTable t;
+        for (int adj = 0; adj < 2; ++adj)
+            if ((st = long_table(f, dev, adj != 0, long_chunk(0), &t)) != BB_OK) return st;
+        g_last_error.clear();
+        return BB_OK;
+    }
     for (bb_precision p : {BB_F64, BB_F32_REFINE}) {
         const int C = solve_chunk(f.n, 0, p);
         const int P = bb::lanes_for(f.n, C);
@@ -477,7 +548,14 @@ bb_status bb_plan(bb_factor fh, int64_t m, int32_t what, bb_precision p, int32_t
         return fail(BB_ERR_ARG, "unknown precision");
     const bb::Factor &f = fh->f;
     int C, P, log2Q, sc = 0;
-    if (what == 0) {
+    if (is_long(f)) {
+        // three launches, one chunk of 64 systems per wave, coefficients
+        // through the scalar cache
+        C = long_chunk(m);
+        P = (int)((f.n + C - 1) / C);
+        log2Q = 0;
+        sc = 1;
+    } else if (what == 0) {
         C = solve_chunk(f.n, m, p);
         P = bb::lanes_for(f.n, C);
         int log2P = 0;
@@ -505,11 +583,11 @@ bb_status bb_factor_info(bb_factor fh, int64_t *n, int32_t *kind, int32_t *chunk
     if (!fh) return fail(BB_ERR_ARG, "factor is NULL");
     if (n) *n = fh->f.n;
     if (kind) *kind = fh->f.kind;
-    if (chunk) *chunk = solve_chunk(fh->f.n, 0, BB_F64);
+    if (chunk) *chunk = is_long(fh->f) ? long_chunk(0) : solve_chunk(fh->f.n, 0, BB_F64);
     return BB_OK;
 }
 
-int64_t bb_max_n(void) { return bb::kMaxN; }
+int64_t bb_max_n(void) { return bb::kMaxNLong; }
 
 bb_status bb_solve_batch_tri(bb_factor f, const void *rhs, void *x, int64_t m, int64_t ld,
                              bb_precision p, void *stream)
@@ -621,6 +699,13 @@ bb_status ch_steps(bb_factor fh, const double *c_in, double *c_out, int64_t m, i
     if (!std::isfinite(alpha)) return fail(BB_ERR_ARG, "alpha is not finite");
     if (every < 1) return fail(BB_ERR_ARG, "every < 1");
     const int64_t samples = lbar ? steps / every : 0;
+    if (is_long(f) && (steps != 1 || samples > 0))
+        return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(f.n) +
+                                             " (long system): one step per call, without the "
+                                             "statistic");
+    if (is_long(f) && m > 0 && c_in == c_out)
+        return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(f.n) +
+                                             " (long system): c_out must not overlap c_in");
     if (m == 0) { g_last_error.clear(); return BB_OK; }
     if (samples > 0) {
         if (!workspace) return fail(BB_ERR_ARG, "workspace is NULL");
@@ -629,6 +714,17 @@ bb_status ch_steps(bb_factor fh, const double *c_in, double *c_out, int64_t m, i
     }
     int dev;
     if ((st = current_device(&dev)) != BB_OK) return st;
+    if (is_long(f)) {
+        const int C = long_chunk(m);
+        bb::DeviceTable tab;
+        if ((st = long_table(f, dev, false, C, &tab)) != BB_OK) return st;
+        hipError_t e = bb::launch_ch_long((const double *)tab.ptr, f.primal.cor.q,
+                                          long_geom(f, m, ld, C), alpha, c_in, c_out,
+                                          (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "long Cahn-Hilliard launch");
+        g_last_error.clear();
+        return BB_OK;
+    }
     // The fused steps are bound by arithmetic and coefficient reads, not HBM
     // (64 rows per lane, two waves per SIMD: 0.39 vs 0.52 ms per step at
     // n = 256, m = 2^20 against 128 rows per lane); see step_plan.

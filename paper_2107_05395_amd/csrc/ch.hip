@@ -1,5 +1,6 @@
 // ch.hip -- fused Cahn-Hilliard steps (Section 5.1) with the state kept in
 // registers: the right-hand-side policy of the fused stepper (stepper.h).
+#include "long_core.h"
 #include "stepper.h"
 
 namespace bb {
@@ -52,7 +53,36 @@ struct ChRhs {
     }
 };
 
-// lbar[s] = inv_m * sum over groups of partial[group][s], groups in order.
+// The Cahn-Hilliard right-hand side as the source of the long-system
+// launches: rows of the state plus the neighbour row on each side (indices
+// mod n), so no wrap term is needed beyond the halo.
+struct ChLongSrc {
+    const double *c;
+    double alpha;
+    template <int C>
+    __device__ __forceinline__ void full(double (&v)[C], int row0, int64_t k, int64_t ld,
+                                         int n) const
+    {
+        load_chunk<double, C, true>(v, c, row0, k, ld, n);
+        const int left = row0 > 0 ? row0 - 1 : n - 1;
+        const int right = row0 + C < n ? row0 + C : 0;
+        const double cl = c[(int64_t)left * ld + k], cr = c[(int64_t)right * ld + k];
+        ch_rhs<C, true>(v, cl, cr, 0.0, 0.0, alpha, 1, false, C);
+    }
+    // the last chunk: rows row0 .. n-1 (at least one, and row0 > 0)
+    template <int C>
+    __device__ __forceinline__ void tail(double (&v)[C], int row0, int64_t k, int64_t ld,
+                                         int n) const
+    {
+        load_chunk<double, C, false>(v, c, row0, k, ld, n);
+        const double cl = c[(int64_t)(row0 - 1) * ld + k], c0 = c[k];
+        ch_rhs<C, false>(v, cl, 0.0, c0, 0.0, alpha, 1, true, n - row0);
+    }
+};
+
+// lbar[s] = 1 + inv_m * sum over groups of partial[group][s], groups in
+// order; the partial sums hold l - 1 per run (about <C^2>, a few thousandths
+// early in a coarsening run), whose rounding the 1 would otherwise swamp.
 __global__ void stats_fold(const double *__restrict__ partial, int64_t groups, int64_t samples,
                            double inv_m, double *__restrict__ lbar)
 {
@@ -60,10 +90,16 @@ __global__ void stats_fold(const double *__restrict__ partial, int64_t groups, i
     if (s >= samples) return;
     double acc = 0.0;
     for (int64_t r = 0; r < groups; ++r) acc += partial[r * samples + s];
-    lbar[s] = acc * inv_m;
+    lbar[s] = fma(acc, inv_m, 1.0);
 }
 
 }  // namespace
+
+hipError_t launch_ch_long(const double *table, const CyclicQ &q, const LongGeom &g, double alpha,
+                          const double *c_in, double *c_out, hipStream_t s)
+{
+    return launch_long_k<2, true>(table, q, g, ChLongSrc{c_in, alpha}, c_out, s);
+}
 
 hipError_t launch_ch(const double *table, int64_t table_elems, const CyclicQ &q,
                      const SweepGeom &g, bool scalar, double alpha, int64_t steps,

@@ -85,7 +85,7 @@ constexpr int kChunkMaxCH = 64;       // fused Cahn-Hilliard steps: two waves pe
 constexpr int64_t kMaxN = 2048;
 constexpr int64_t kMaxNPenta = 1024;
 
-inline int num_arrays(int K, bool cyclic) { return 4 * K + 1 + (cyclic ? K : 0); }
+__host__ __device__ constexpr int num_arrays(int K, bool cyclic) { return 4 * K + 1 + (cyclic ? K : 0); }
 
 inline int64_t table_len(int K, bool cyclic, int C, int P)
 {
@@ -190,6 +190,23 @@ hipError_t launch_cn_penta(bool cyclic, const double *table, int64_t table_elems
                            const CyclicQ &q, const SweepGeom &g, bool scalar, const double *w,
                            int64_t steps, int64_t traj_stride, const double *in, double *out,
                            hipStream_t stream);
+
+// Long systems (long_core.h): n above what one workgroup's LDS table and
+// registers hold, solved in three launches (reduce, scan, solve) with the
+// solution array as their scratch; FP64 only, x must not overlap the input.
+struct LongGeom {
+    int n, C, P;        // rows, rows per chunk, chunks (P >= 2; chunk P-1 is the tail)
+    int64_t m, ld;      // systems, leading dimension
+    int64_t groups;     // groups of 64 systems
+};
+constexpr int64_t kMaxNLong = int64_t(1) << 18;
+hipError_t launch_long_solve(int K, bool cyclic, const double *table, const CyclicQ &q,
+                             const LongGeom &g, const double *rhs, double *x, hipStream_t stream);
+// One Cahn-Hilliard step (Section 5.1) of long periodic systems: the
+// right-hand side C + alpha d2(C^3 - C) is formed from c_in (with its
+// neighbour rows) wherever the launches read it; c_out must not overlap c_in.
+hipError_t launch_ch_long(const double *table, const CyclicQ &q, const LongGeom &g, double alpha,
+                          const double *c_in, double *c_out, hipStream_t stream);
 
 // Copy of `bytes` (a multiple of 16) in contiguous 16 KB tiles per workgroup:
 // the streaming reference the sweeps' HBM rate is compared with.

@@ -1,0 +1,343 @@
+// long_core.h -- batched solves of long systems, whose rows a workgroup
+// cannot hold at once: the chunked decomposition of internal.h spread over
+// three launches instead of one wave or workgroup per system group.
+//
+// A system of n rows is cut into P chunks of C rows; chunks 0 .. P-2 are full
+// and chunk P-1 (the tail) holds the remaining nr = n - (P-1) C rows (1 .. C).
+// The recurrences, coefficient table (internal.h layout, any P) and
+// chunk-boundary algebra are those of the one-launch sweep (sweep_core.h):
+//
+//   reduce (one wave per full chunk and group of 64 systems): the chunk's
+//          zero-history forward end state e_j and zero-future backward start
+//          state o_j (dot products with the table's weights), written to rows
+//          r0 .. r0+2K-1 of the solution array x, which serves as the scratch
+//          of the launch sequence;
+//   scan   (one lane per system): H_j (prefix over the full chunks,
+//          H_{j+1} = e_j + Mf_j H_j) written over e_j; the tail chunk solved
+//          in registers from its history H_{P-1}; then S_j = o_j + G_j H_j and
+//          the future F_j (suffix, F_{j-1} = S_j + Mb_j F_j, F_{P-2} = the
+//          tail's start state) written over o_j; for periodic systems the
+//          correction scalars c = Q (w_0, w_1, w_{n-2}, w_{n-1}) written to
+//          rows r0+2K .. r0+3K-1 of every full chunk; the tail's solution
+//          stored;
+//   solve  (one wave per full chunk and group): forward pass from H_j,
+//          backward pass from F_j with the correction fused, solution stored
+//          over the chunk (the reads of H_j, F_j and c come first).
+//
+// Every wave of reduce and solve works on one chunk of 64 systems, so each
+// row is one 512-byte coalesced access and every coefficient is the same for
+// the whole wave: the table is read through the scalar cache and may have
+// any size.  HBM traffic: the right-hand side read twice and the solution
+// written once (24 B per row in double) plus 2K doubles per chunk of
+// scratch, against 16 B for the one-launch sweep.  x must not overlap the
+// right-hand side.
+#pragma once
+
+#include "sweep_core.h"
+
+namespace bb {
+namespace {
+
+// Right-hand-side source of the plain solve: the rows of rhs.
+struct PlainSrc {
+    const double *rhs;
+    template <int C>
+    __device__ __forceinline__ void full(double (&v)[C], int row0, int64_t k, int64_t ld,
+                                         int n) const
+    {
+        load_chunk<double, C, true>(v, rhs, row0, k, ld, n);
+    }
+    template <int C>
+    __device__ __forceinline__ void tail(double (&v)[C], int row0, int64_t k, int64_t ld,
+                                         int n) const
+    {
+        load_chunk<double, C, false>(v, rhs, row0, k, ld, n);
+    }
+};
+
+template <int K, int C, bool CYC>
+using LongTable = LaneTable<typename FromScalar<double>::ptr>;
+
+template <int K, int C, bool CYC>
+__device__ __forceinline__ LongTable<K, C, CYC> long_table(const double *table, int P, int j)
+{
+    using Src = FromScalar<double>;
+    return lane_table<double, K, C, CYC>(Src::base((typename Src::ptr)table), P, j);
+}
+
+// Wave w of a reduce or solve launch: chunk j = w / groups (wave-uniform),
+// group w % groups, so neighbouring waves read neighbouring 512-byte
+// segments of the same rows.
+struct LongWave {
+    int j;
+    int64_t k;
+    bool valid;   // false: the wave has no chunk (grid rounding)
+};
+
+__device__ __forceinline__ LongWave long_wave(const LongGeom &g)
+{
+    LongWave lw;
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t total = (int64_t)(g.P - 1) * g.groups;
+    lw.valid = w < total;
+    const int64_t ww = lw.valid ? w : 0;
+    lw.j = __builtin_amdgcn_readfirstlane((int)(ww / g.groups));
+    lw.k = (ww % g.groups) * kWave + threadIdx.x % kWave;
+    return lw;
+}
+
+template <int K, int C, bool CYC, class Src>
+__global__ __launch_bounds__(256) void long_reduce(const double *__restrict__ table, LongGeom g,
+                                                   Src src, double *x)
+{
+    const LongWave lw = long_wave(g);
+    if (!lw.valid) return;   // whole waves
+    const bool kval = lw.k < g.m;
+    const int64_t kk = kval ? lw.k : g.m - 1;
+    const int row0 = lw.j * C;
+    double v[C];
+    src.template full<C>(v, row0, kk, g.ld, g.n);
+    const auto tb = long_table<K, C, CYC>(table, g.P, lw.j);
+    double e1 = 0.0, e2 = 0.0, o1 = 0.0, o2 = 0.0;
+    rows_up<C>([&](int t) {
+        e1 = fma(tb.wE1[t], v[t], e1);
+        o1 = fma(tb.wS1[t], v[t], o1);
+        if constexpr (K == 2) {
+            e2 = fma(tb.wE2[t], v[t], e2);
+            o2 = fma(tb.wS2[t], v[t], o2);
+        }
+    });
+    if (kval) {
+        double *p = x + (int64_t)row0 * g.ld + lw.k;
+        p[0] = e1;
+        if constexpr (K == 2) p[g.ld] = e2;
+        p[(int64_t)K * g.ld] = o1;
+        if constexpr (K == 2) p[(int64_t)(K + 1) * g.ld] = o2;
+    }
+}
+
+// Full chunks scanned per block: their scratch values are loaded together
+// before the dependent chain runs over them.
+constexpr int kScanBlock = 8;
+
+template <int K, int C, bool CYC, class Src>
+__global__ __launch_bounds__(256) void long_scan(const double *__restrict__ table, CyclicQ cq,
+                                                 LongGeom g, Src src, double *x)
+{
+    using SP = FromScalar<double>;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t kmax = g.groups * kWave;
+    if ((int64_t)blockIdx.x * blockDim.x >= kmax) return;   // whole workgroups past the batch
+    const bool kval = k < g.m;
+    const int64_t kk = kval ? k : g.m - 1;
+    const int64_t ld = g.ld;
+    const int full = g.P - 1;
+    const int na = num_arrays(K, CYC);
+    const int64_t L = (int64_t)g.P * (C + 1);
+    const typename SP::ptr tabs = SP::base((typename SP::ptr)table);
+    const typename SP::ptr Mf = tabs + na * L;
+    const typename SP::ptr Mb = Mf + (int64_t)g.P * K * K;
+    const typename SP::ptr Gm = Mb + (int64_t)g.P * K * K;
+
+    // forward scan: H_j over e_j, in blocks of loads issued together
+    double h1 = 0.0, h2 = 0.0;
+    for (int j0 = 0; j0 < full; j0 += kScanBlock) {
+        double a1[kScanBlock], a2[kScanBlock];
+#pragma unroll
+        for (int b = 0; b < kScanBlock; ++b) {
+            const int j = j0 + b < full ? j0 + b : full - 1;
+            const double *p = x + (int64_t)j * C * ld + kk;
+            a1[b] = p[0];
+            a2[b] = K == 2 ? p[ld] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < kScanBlock; ++b) {
+            if (j0 + b < full) {
+                double *p = x + (int64_t)(j0 + b) * C * ld + k;
+                if (kval) {
+                    p[0] = h1;
+                    if constexpr (K == 2) p[ld] = h2;
+                }
+                affine<double, K>(Mf + (j0 + b) * K * K, h1, h2, a1[b], a2[b]);
+            }
+        }
+    }
+
+    // the tail chunk, from its history (h1, h2): forward, then backward with
+    // zero future; rows past n hold 0 (zero coefficients)
+    const int trow0 = full * C;
+    const int nr = g.n - trow0;
+    double v[C];
+    src.template tail<C>(v, trow0, kk, ld, g.n);
+    double yn1, yn2;   // y_{n-1}, y_{n-2}
+    {
+        const auto tp = lane_table<double, K, C, CYC>(SP::base(tabs), g.P, full);
+        double y1 = h1, y2 = h2;
+        rows_up<C>([&](int t) {
+            double y = tp.s[t] * v[t];
+            if constexpr (K == 2) y = fma(tp.l2[t], y2, y);
+            y = fma(tp.l1[t], y1, y);
+            v[t] = y;
+            y2 = y1;
+            y1 = y;
+        });
+        yn1 = pick(v, nr - 1);
+        yn2 = nr >= 2 ? pick(v, nr - 2) : h1;
+        double x1 = 0.0, x2 = 0.0;
+        rows_down<C>([&](int t) {
+            double xx = v[t];
+            if constexpr (K == 2) xx = fma(tp.u2[t], x2, xx);
+            xx = fma(tp.u1[t], x1, xx);
+            x2 = x1;
+            x1 = xx;
+            v[t] = xx;
+        });
+    }
+
+    // backward scan: F_j over o_j, starting from the tail's start state
+    double f1 = v[0], f2 = K == 2 ? v[1] : 0.0;
+    for (int j1 = full - 1; j1 >= 0; j1 -= kScanBlock) {
+        double hh1[kScanBlock], hh2[kScanBlock], oo1[kScanBlock], oo2[kScanBlock];
+#pragma unroll
+        for (int b = 0; b < kScanBlock; ++b) {
+            const int j = j1 - b >= 0 ? j1 - b : 0;
+            const double *p = x + (int64_t)j * C * ld + kk;
+            hh1[b] = p[0];
+            hh2[b] = K == 2 ? p[ld] : 0.0;
+            oo1[b] = p[(int64_t)K * ld];
+            oo2[b] = K == 2 ? p[(int64_t)(K + 1) * ld] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < kScanBlock; ++b) {
+            const int j = j1 - b;
+            if (j >= 0) {
+                const auto G = Gm + j * K * K;
+                double s1, s2 = 0.0;
+                if constexpr (K == 1) {
+                    s1 = fma(G[0], hh1[b], oo1[b]);
+                } else {
+                    s1 = fma(G[1], hh2[b], fma(G[0], hh1[b], oo1[b]));
+                    s2 = fma(G[3], hh2[b], fma(G[2], hh1[b], oo2[b]));
+                }
+                if (kval) {
+                    double *p = x + (int64_t)j * C * ld + k;
+                    p[(int64_t)K * ld] = f1;
+                    if constexpr (K == 2) p[(int64_t)(K + 1) * ld] = f2;
+                }
+                affine<double, K>(Mb + j * K * K, f1, f2, s1, s2);
+            }
+        }
+    }
+
+    // periodic correction scalars from w_0, w_1 (start of chunk 0) and
+    // w_{n-2}, w_{n-1} (x_{n-1} = y_{n-1}, x_{n-2} = y_{n-2} - u1 y_{n-1})
+    double c0 = 0.0, c1 = 0.0;
+    if constexpr (CYC) {
+        const double rn1 = yn1;
+        const double rn2 = K == 2 ? fma(cq.u1_nm2, rn1, yn2) : 0.0;
+        correction_scalars<double, K>(cq, f1, f2, rn2, rn1, c0, c1);
+        if (kval) {
+            for (int j = 0; j < full; ++j) {
+                double *p = x + ((int64_t)j * C + 2 * K) * ld + k;
+                p[0] = c0;
+                if constexpr (K == 2) p[ld] = c1;
+            }
+        }
+        const auto tp = lane_table<double, K, C, CYC>(SP::base(tabs), g.P, full);
+        rows_up<C>([&](int t) {
+            double xx = fma(tp.z0[t], c0, v[t]);
+            if constexpr (K == 2) xx = fma(tp.z1[t], c1, xx);
+            v[t] = xx;
+        });
+    }
+    if (kval) store_chunk<double, C, false>(v, x, trow0, k, ld, g.n);
+}
+
+template <int K, int C, bool CYC, class Src>
+__global__ __launch_bounds__(256) void long_solve(const double *__restrict__ table, LongGeom g,
+                                                  Src src, double *x)
+{
+    const LongWave lw = long_wave(g);
+    if (!lw.valid) return;
+    const bool kval = lw.k < g.m;
+    const int64_t kk = kval ? lw.k : g.m - 1;
+    const int row0 = lw.j * C;
+    const int64_t ld = g.ld;
+    // scratch of this chunk: H (rows 0..K-1), F (K..2K-1), c (2K..3K-1)
+    const double *p = x + (int64_t)row0 * ld + kk;
+    const double h1 = p[0], h2 = K == 2 ? p[ld] : 0.0;
+    const double f1 = p[(int64_t)K * ld], f2 = K == 2 ? p[(int64_t)(K + 1) * ld] : 0.0;
+    double c0 = 0.0, c1 = 0.0;
+    if constexpr (CYC) {
+        c0 = p[(int64_t)2 * K * ld];
+        if constexpr (K == 2) c1 = p[(int64_t)(2 * K + 1) * ld];
+    }
+    double v[C];
+    src.template full<C>(v, row0, kk, ld, g.n);
+    __builtin_amdgcn_sched_barrier(0);
+    {
+        const auto tp = long_table<K, C, CYC>(table, g.P, lw.j);
+        double y1 = h1, y2 = h2;
+        rows_up<C>([&](int t) {
+            double y = tp.s[t] * v[t];
+            if constexpr (K == 2) y = fma(tp.l2[t], y2, y);
+            y = fma(tp.l1[t], y1, y);
+            v[t] = y;
+            y2 = y1;
+            y1 = y;
+        });
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+        const auto tp = long_table<K, C, CYC>(table, g.P, lw.j);
+        double x1 = f1, x2 = f2;
+        rows_down<C>([&](int t) {
+            double xx = v[t];
+            if constexpr (K == 2) xx = fma(tp.u2[t], x2, xx);
+            xx = fma(tp.u1[t], x1, xx);
+            x2 = x1;
+            x1 = xx;
+            if constexpr (CYC) {
+                xx = fma(tp.z0[t], c0, xx);
+                if constexpr (K == 2) xx = fma(tp.z1[t], c1, xx);
+            }
+            v[t] = xx;
+        });
+    }
+    if (kval) store_chunk<double, C, true>(v, x, row0, lw.k, ld, g.n);
+}
+
+template <int K, int C, bool CYC, class Src>
+hipError_t launch_long_c(const double *table, const CyclicQ &q, const LongGeom &g, const Src &src,
+                         double *x, hipStream_t s)
+{
+    constexpr int threads = 256;
+    const int64_t waves = (int64_t)(g.P - 1) * g.groups;
+    const int64_t blocks = (waves * kWave + threads - 1) / threads;
+    const int64_t sblocks = (g.groups * kWave + threads - 1) / threads;
+    hipLaunchKernelGGL((long_reduce<K, C, CYC, Src>), dim3((unsigned)blocks), dim3(threads), 0, s,
+                       table, g, src, x);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((long_scan<K, C, CYC, Src>), dim3((unsigned)sblocks), dim3(threads), 0, s,
+                       table, q, g, src, x);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((long_solve<K, C, CYC, Src>), dim3((unsigned)blocks), dim3(threads), 0, s,
+                       table, g, src, x);
+    return hipGetLastError();
+}
+
+template <int K, bool CYC, class Src>
+hipError_t launch_long_k(const double *table, const CyclicQ &q, const LongGeom &g, const Src &src,
+                         double *x, hipStream_t s)
+{
+    switch (g.C) {
+    case 16: return launch_long_c<K, 16, CYC>(table, q, g, src, x, s);
+    case 32: return launch_long_c<K, 32, CYC>(table, q, g, src, x, s);
+    case 64: return launch_long_c<K, 64, CYC>(table, q, g, src, x, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+}  // namespace bb

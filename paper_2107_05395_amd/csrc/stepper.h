@@ -132,7 +132,10 @@ __global__ __launch_bounds__(kMaxBlockThreads) void step_kernel(const double *__
                 const double ss = chunk_sum_sq<C>(c);
                 double tot = 0.0;
                 for (int i = 0; i < lg.P; ++i) tot += shfl(ss, i * lg.S + lg.sl);
-                const double ell = kval ? 1.0 / (1.0 - tot * st.inv_n) : 0.0;
+                // l - 1 = <C^2> / (1 - <C^2>): summed without the 1 of every run,
+                // so the ensemble sum keeps the digits that l - 1 carries
+                const double msq = tot * st.inv_n;
+                const double ell = kval ? msq / (1.0 - msq) : 0.0;
                 const double sum = block_sum(ell, lg.S);   // the group: lanes 0 .. S-1
                 if (lane == 0) st.partial[grp * st.samples + (step + 1) / st.every - 1] = sum;
             }
@@ -242,7 +245,8 @@ void step_kernel_split(const double *__restrict__ table, int64_t table_elems, Cy
                 if (threadIdx.x < kWave) {
                     double tot = 0.0;
                     for (int i = 0; i < lg.P; ++i) tot += xs[i * lg.S + lg.sl];
-                    const double ell = kval ? 1.0 / (1.0 - tot * st.inv_n) : 0.0;
+                    const double msq = tot * st.inv_n;   // l - 1, as above
+                    const double ell = kval ? msq / (1.0 - msq) : 0.0;
                     const double sum = block_sum(ell, lg.S);
                     if (threadIdx.x == 0)
                         st.partial[grp * st.samples + (step + 1) / st.every - 1] = sum;

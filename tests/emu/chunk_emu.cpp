@@ -122,3 +122,131 @@ extern "C" int emu_solve(int kind, const double *a, const double *b, const doubl
     for (int64_t i = 0; i < n; ++i) x[i] = v[i / C][i % C];
     return 0;
 }
+
+// The three-launch decomposition of long systems (long_core.h), replayed for
+// one system in double: the solution array x doubles as the scratch of the
+// launches exactly as on the device (e, o, then H, F and the periodic
+// correction scalars in the first 3K rows of every full chunk).
+extern "C" int emu_solve_long(int kind, const double *a, const double *b, const double *c,
+                              const double *d, const double *e, int64_t n, int adjoint, int C,
+                              const double *f, double *x)
+{
+    bb::Factor F;
+    std::string err;
+    const double *bands[5] = {a, b, c, d, e};
+    int st = bb::make_factor(kind, bands, n, F, err);
+    if (st) return st;
+    const int K = F.K;
+    const int P = (int)((n + C - 1) / C);
+    if (P < 2 || C < 3 * K) return -100;
+    const int full = P - 1;
+    const bb::Direction &dir = adjoint ? F.adjoint : F.primal;
+    const std::vector<double> tab = bb::build_table(dir, K, F.cyclic, n, C, P);
+    const int64_t L = (int64_t)P * (C + 1);
+    const int na = bb::num_arrays(K, F.cyclic);
+    auto arr = [&](int q, int j, int t) { return tab[(size_t)(q * L + (int64_t)j * (C + 1) + t)]; };
+    const double *Mf = tab.data() + na * L, *Mb = Mf + P * K * K, *G = Mb + P * K * K;
+    const int qE = 0, qS = K, qs = 2 * K, ql = 2 * K + 1, qu = 3 * K + 1, qz = 4 * K + 1;
+    auto affine = [&](const double *M, double &y1, double &y2, double a1, double a2) {
+        if (K == 1) {
+            y1 = M[0] * y1 + a1;
+        } else {
+            const double n1 = M[0] * y1 + M[1] * y2 + a1, n2 = M[2] * y1 + M[3] * y2 + a2;
+            y1 = n1;
+            y2 = n2;
+        }
+    };
+    auto fwd = [&](std::vector<double> &v, int j, double h1, double h2) {
+        for (int t = 0; t < C; ++t) {
+            double y = arr(qs, j, t) * v[t];
+            if (K == 2) y += arr(ql + 1, j, t) * h2;
+            y += arr(ql, j, t) * h1;
+            v[t] = y;
+            h2 = h1;
+            h1 = y;
+        }
+    };
+    auto bwd = [&](std::vector<double> &v, int j, double g1, double g2, double c0, double c1) {
+        for (int t = C - 1; t >= 0; --t) {
+            double xx = v[t];
+            if (K == 2) xx += arr(qu + 1, j, t) * g2;
+            xx += arr(qu, j, t) * g1;
+            g2 = g1;
+            g1 = xx;
+            if (F.cyclic) xx += arr(qz, j, t) * c0 + (K == 2 ? arr(qz + 1, j, t) * c1 : 0.0);
+            v[t] = xx;
+        }
+    };
+    // reduce
+    for (int j = 0; j < full; ++j) {
+        double e1 = 0, e2 = 0, o1 = 0, o2 = 0;
+        for (int t = 0; t < C; ++t) {
+            const double v = f[j * C + t];
+            e1 += arr(qE, j, t) * v;
+            o1 += arr(qS, j, t) * v;
+            if (K == 2) {
+                e2 += arr(qE + 1, j, t) * v;
+                o2 += arr(qS + 1, j, t) * v;
+            }
+        }
+        x[j * C] = e1;
+        if (K == 2) x[j * C + 1] = e2;
+        x[j * C + K] = o1;
+        if (K == 2) x[j * C + K + 1] = o2;
+    }
+    // scan
+    double h1 = 0, h2 = 0;
+    for (int j = 0; j < full; ++j) {
+        const double a1 = x[j * C], a2 = K == 2 ? x[j * C + 1] : 0.0;
+        x[j * C] = h1;
+        if (K == 2) x[j * C + 1] = h2;
+        affine(Mf + j * K * K, h1, h2, a1, a2);
+    }
+    const int64_t tr0 = (int64_t)full * C;
+    const int nr = (int)(n - tr0);
+    std::vector<double> v(C, 0.0);
+    for (int t = 0; t < nr; ++t) v[t] = f[tr0 + t];
+    fwd(v, full, h1, h2);
+    const double yn1 = v[nr - 1], yn2 = nr >= 2 ? v[nr - 2] : h1;
+    bwd(v, full, 0.0, 0.0, 0.0, 0.0);
+    double f1 = v[0], f2 = K == 2 ? v[1] : 0.0;
+    for (int j = full - 1; j >= 0; --j) {
+        const double *g = G + j * K * K;
+        const double hh1 = x[j * C], hh2 = K == 2 ? x[j * C + 1] : 0.0;
+        const double s1 = x[j * C + K] + g[0] * hh1 + (K == 2 ? g[1] * hh2 : 0.0);
+        const double s2 = K == 2 ? x[j * C + K + 1] + g[2] * hh1 + g[3] * hh2 : 0.0;
+        x[j * C + K] = f1;
+        if (K == 2) x[j * C + K + 1] = f2;
+        affine(Mb + j * K * K, f1, f2, s1, s2);
+    }
+    double c0 = 0.0, c1 = 0.0;
+    if (F.cyclic) {
+        const bb::CyclicQ &q = dir.cor.q;
+        const double rn1 = yn1, rn2 = K == 2 ? q.u1_nm2 * rn1 + yn2 : 0.0;
+        if (K == 1) {
+            c0 = q.q[0][0] * f1 + q.q[0][1] * rn1;
+        } else {
+            c0 = q.q[0][0] * f1 + q.q[0][1] * f2 + q.q[0][2] * rn2 + q.q[0][3] * rn1;
+            c1 = q.q[1][0] * f1 + q.q[1][1] * f2 + q.q[1][2] * rn2 + q.q[1][3] * rn1;
+        }
+        for (int j = 0; j < full; ++j) {
+            x[j * C + 2 * K] = c0;
+            if (K == 2) x[j * C + 2 * K + 1] = c1;
+        }
+        for (int t = 0; t < C; ++t)
+            v[t] += arr(qz, full, t) * c0 + (K == 2 ? arr(qz + 1, full, t) * c1 : 0.0);
+    }
+    for (int t = 0; t < nr; ++t) x[tr0 + t] = v[t];
+    // solve
+    for (int j = 0; j < full; ++j) {
+        const double H1 = x[j * C], H2 = K == 2 ? x[j * C + 1] : 0.0;
+        const double G1 = x[j * C + K], G2 = K == 2 ? x[j * C + K + 1] : 0.0;
+        const double C0 = F.cyclic ? x[j * C + 2 * K] : 0.0;
+        const double C1 = F.cyclic && K == 2 ? x[j * C + 2 * K + 1] : 0.0;
+        std::vector<double> w(f + j * C, f + (j + 1) * C);
+        fwd(w, j, H1, H2);
+        bwd(w, j, G1, G2, C0, C1);
+        for (int t = 0; t < C; ++t) x[j * C + t] = w[t];
+    }
+    return 0;
+}

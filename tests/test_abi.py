@@ -98,12 +98,40 @@ def test_size_limits(L):
     big = L.bb_max_n() + 1
     st, _ = _factor(L, "tri", (np.ones(big), np.full(big, 3.0), np.ones(big)), big)
     assert st == -6
-    # pentadiagonal tables are larger: n is limited to 1024
-    st, _ = _factor(L, "penta", [np.ones(1025)] * 2 + [np.full(1025, 9.0)] + [np.ones(1025)] * 2, 1025)
-    assert st == -6 and b"1024" in L.bb_last_error_message()
+    assert b"bb_max_n" in L.bb_last_error_message()
     st, h = _factor(L, "penta", [np.ones(1024)] * 2 + [np.full(1024, 9.0)] + [np.ones(1024)] * 2, 1024)
     assert st == 0
     L.bb_factor_destroy(h)
+
+
+def test_long_systems_host_checks(L):
+    """Above tri n = 2048 / penta n = 1024 the solves take the three-launch
+    long-system path: FP64 only, out of place; the fused steppers are not
+    built for it and the Cahn-Hilliard step takes one out-of-place step per
+    call.  All of it is checked on the host, before any device call."""
+    fake = ctypes.c_void_p(0x1000)
+    other = ctypes.c_void_p(0x2000)
+    n = 1025
+    st, hp = _factor(L, "penta", [np.ones(n)] * 2 + [np.full(n, 9.0)] + [np.ones(n)] * 2, n)
+    assert st == 0
+    chunk, lanes, waves, scalar = (ctypes.c_int32() for _ in range(4))
+    assert L.bb_plan(hp, 100000, 0, 0, ctypes.byref(chunk), ctypes.byref(lanes), ctypes.byref(waves),
+                     ctypes.byref(scalar)) == 0
+    assert chunk.value == 64 and lanes.value == 17 and waves.value == 1 and scalar.value == 1
+    for prec in (1, 2, 3):   # refinement and float precisions: not built for long systems
+        assert L.bb_solve_batch_penta(hp, fake, other, 4, 4, prec, None) == -6
+    assert L.bb_solve_batch_penta(hp, fake, fake, 4, 4, 0, None) == -6      # in place
+    assert L.bb_solve_batch_penta_adjoint(hp, fake, fake, 4, 4, 0, None) == -6
+    L.bb_factor_destroy(hp)
+    ch = ctypes.c_void_p()
+    sig, alp = ctypes.c_double(), ctypes.c_double()
+    assert L.bb_factor_ch(4096, 2 * np.pi, 0.01, 1e-4, ctypes.byref(ch), ctypes.byref(sig),
+                          ctypes.byref(alp)) == 0
+    assert L.bb_ch_step(ch, fake, other, 4, 4, alp, 2, None) == -6          # one step per call
+    assert L.bb_ch_step(ch, fake, fake, 4, 4, alp, 1, None) == -6           # in place
+    ws = ctypes.c_void_p(0x3000)
+    assert L.bb_ch_step_stats(ch, fake, other, 4, 4, alp, 1, 1, ws, ws, 1 << 20, None) == -6
+    L.bb_factor_destroy(ch)
     h = ctypes.c_void_p()
     assert L.bb_factor_shared_tri(None, None, None, 4, ctypes.byref(h)) == -1
     one = np.ones(4)

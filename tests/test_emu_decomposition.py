@@ -36,16 +36,17 @@ def emu():
     lib = ctypes.CDLL(LIB)
     P = ctypes.POINTER(ctypes.c_double)
     lib.emu_solve.argtypes = [ctypes.c_int] + [P] * 5 + [ctypes.c_int64, ctypes.c_int, ctypes.c_int, P, P]
+    lib.emu_solve_long.argtypes = lib.emu_solve.argtypes
     return lib
 
 
-def run(emu, kind_id, bands, n, adjoint, C, f):
+def run(emu, kind_id, bands, n, adjoint, C, f, entry="emu_solve"):
     bands = [np.ascontiguousarray(b, dtype=np.float64) for b in bands] + [np.zeros(n)] * (5 - len(bands))
     f = np.ascontiguousarray(f, dtype=np.float64)
     x = np.empty(n)
     P = ctypes.POINTER(ctypes.c_double)
-    st = emu.emu_solve(kind_id, *(b.ctypes.data_as(P) for b in bands), n, adjoint, C,
-                       f.ctypes.data_as(P), x.ctypes.data_as(P))
+    st = getattr(emu, entry)(kind_id, *(b.ctypes.data_as(P) for b in bands), n, adjoint, C,
+                             f.ctypes.data_as(P), x.ctypes.data_as(P))
     assert st == 0, st
     return x
 
@@ -66,6 +67,30 @@ def test_chunked_decomposition_matches_oracle(emu, oracle, kind, adjoint, n, C):
     bands = inputs.random_dominant_penta(n, seed=n + C) if penta else inputs.random_dominant_tri(n, seed=n + C)
     f = inputs.uniform_batch(n, 1, seed=7 * n + C)[:, 0]
     x = run(emu, kind_id, bands, n, adjoint, C, f)
+    if penta:
+        ref = (oracle.penta_adjoint if adjoint else oracle.penta_solve)(*bands, f[:, None], cyclic=cyclic)[:, 0]
+    else:
+        ref = (oracle.tri_adjoint if adjoint else oracle.tri_solve)(*bands, f[:, None], cyclic=cyclic)[:, 0]
+    assert np.linalg.norm(x - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+LONG_CASES = [(n, C) for n in (17, 33, 48, 100, 257, 1000, 1025, 4097) for C in (16, 32, 64)
+              if (n + C - 1) // C >= 2]
+
+
+@pytest.mark.parametrize("kind", ["tri", "tri_cyclic", "penta", "penta_cyclic"])
+@pytest.mark.parametrize("adjoint", [0, 1])
+@pytest.mark.parametrize("n,C", LONG_CASES)
+def test_long_system_launches_match_oracle(emu, oracle, kind, adjoint, n, C):
+    """The reduce / scan / solve sequence of long systems, with the solution
+    array as scratch, replayed from the library's tables: any number of
+    chunks, a tail of 1 .. C rows."""
+    cyclic = kind.endswith("cyclic")
+    penta = kind.startswith("penta")
+    kind_id = {"tri": 0, "tri_cyclic": 1, "penta": 2, "penta_cyclic": 3}[kind]
+    bands = inputs.random_dominant_penta(n, seed=n + C) if penta else inputs.random_dominant_tri(n, seed=n + C)
+    f = inputs.uniform_batch(n, 1, seed=11 * n + C)[:, 0]
+    x = run(emu, kind_id, bands, n, adjoint, C, f, entry="emu_solve_long")
     if penta:
         ref = (oracle.penta_adjoint if adjoint else oracle.penta_solve)(*bands, f[:, None], cyclic=cyclic)[:, 0]
     else:

@@ -30,7 +30,7 @@ import torch
 
 import oracle
 from paper_2107_05395_amd import inputs
-from tests.gpu_util import rel_err, say
+from tests.gpu_util import fp64_tol, lbar_tol, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -224,8 +224,9 @@ def test_ch_coarsening_statistic_full_batch():
     out, lbar = f.ch_step_stats(torch.from_numpy(c0).cuda(), f.alpha, steps=steps, every=1)
     lb = lbar.cpu().numpy()
     err = float(np.max(np.abs(lb - ref) / (ref - 1.0)))
-    say("coarsening full batch lbar", lb, "rel err of lbar - 1", err)
-    assert err < 1e-12
+    tol = lbar_tol(1.0 + 16.0 * sigma, steps, c0, ref)
+    say("coarsening full batch lbar", lb, "rel err of lbar - 1", err, "tol", tol)
+    assert err < tol
     cols = sample_cols(m, 512, seed=6)
     assert rel_err(cols_of(out, cols), ref_c[:, cols]) < 1e-12
 
@@ -253,5 +254,6 @@ def test_forced_flowmap_batch_sampled():
     dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     out = f.ch_forced_step(dv(c0), dt, dx, dv(v), dv(f0), dv(k), steps=20)
     err = rel_err(cols_of(out, cols), ref)
-    say("forced flow-map batch, 20 steps, rel err", err)
-    assert err < 1e-12
+    tol = fp64_tol(1.0 + 16.0 * sigma, 20)
+    say("forced flow-map batch, 20 steps, rel err", err, "tol", tol)
+    assert err < tol

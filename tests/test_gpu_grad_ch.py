@@ -9,7 +9,7 @@ import torch
 
 import oracle
 from paper_2107_05395_amd import inputs
-from tests.gpu_util import dev, host, rel_err, say
+from tests.gpu_util import dev, fp64_tol, host, lbar_tol, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -181,7 +181,7 @@ def test_ch_uniform_chunks_match_lds_kernel(n, monkeypatch):
     monkeypatch.setenv("BANDBATCH_CH_UNIFORM", "0")
     lds = host(f.ch_step(dev(c0), f.alpha, steps=steps))
     say("ch uniform vs lds", n, float(np.max(np.abs(uni - lds))), rel_err(uni, ref))
-    assert rel_err(uni, ref) < 1e-12
+    assert rel_err(uni, ref) < fp64_tol(1.0 + 16.0 * sigma, steps)
     assert np.array_equal(uni, lds)
 
 
@@ -204,13 +204,14 @@ def test_ch_domain_size_statistic_matches_oracle(n, m):
     assert lb.shape == (3,)
     # relative to lbar - 1 = <C^2> / (1 - <C^2>), the part the state decides
     err = float(np.max(np.abs(lb - ref_lbar) / (ref_lbar - 1.0)))
-    say("  lbar", lb, "rel err of lbar - 1", err)
-    assert err < 1e-12
+    tol = lbar_tol(1.0 + 16.0 * sigma, steps, c0, ref_lbar)
+    say("  lbar", lb, "rel err of lbar - 1", err, "tol", tol)
+    assert err < tol
     # The hyperdiffusion smooths the U[-0.5, 0.5) start to a tenth of its norm
     # within a few steps, while the rounding of the explicit right-hand side
     # (about eps alpha |C^3 - C|) reaches the low modes, which the solve passes
     # undamped, at the scale of the start: bound the error against that scale.
-    assert np.max(np.abs(host(out) - ref_c)) < 2e-12 * np.max(np.abs(c0))
+    assert np.max(np.abs(host(out) - ref_c)) < fp64_tol(1.0 + 16.0 * sigma, steps) * np.max(np.abs(c0))
     assert np.array_equal(host(out), host(f.ch_step(t, f.alpha, steps=steps)))
     _, lbar2 = f.ch_step_stats(t, f.alpha, steps=steps, every=every)
     assert np.array_equal(host(lbar2), lb)
@@ -232,8 +233,9 @@ def test_ch_domain_size_statistic_kernel_variants(monkeypatch):
             monkeypatch.setenv(k, v)
         _, lbar = f.ch_step_stats(t, f.alpha, steps=steps, every=every)
         err = float(np.max(np.abs(host(lbar) - ref) / (ref - 1.0)))
-        say("  variant", env, "rel err of lbar - 1", err)
-        assert err < 1e-12
+        tol = lbar_tol(1.0 + 16.0 * sigma, steps, c0, ref)
+        say("  variant", env, "rel err of lbar - 1", err, "tol", tol)
+        assert err < tol
 
 
 def test_ch_domain_size_statistic_without_samples():
