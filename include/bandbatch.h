@@ -187,6 +187,25 @@ size_t bb_band_grad_workspace_bytes(bb_factor f, int64_t m);
 bb_status bb_band_grad(bb_factor f, const double *lam, const double *x, int64_t m, int64_t ld,
                        double *grad_bands, void *workspace, size_t workspace_bytes, void *stream);
 
+/* bb_band_grad for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * gradients, accumulated (+=) into grad_bands, with the batch's partial sums
+ * kept in a device array of the library instead of a caller workspace.  The
+ * array holds bb_band_grad_scratch_bytes() bytes (4 MiB) per device, is made
+ * when the library is loaded and lives until the process ends; the call
+ * allocates nothing and needs no factor upload.  The batch is cut into at
+ * most as many partial groups as fit the array, so the sum order (fixed, and
+ * bitwise reproducible from call to call) can differ from bb_band_grad's; the
+ * two agree to rounding.  Every call on a device shares that device's array:
+ * calls that overlap in time on one device (several streams or host threads)
+ * race and must be serialised by the caller.
+ * Errors: as bb_band_grad; BB_ERR_UNSUPPORTED when (2K+1) * n doubles exceed
+ * the array (n above 174762 for tri, 104857 for penta: beyond every size the
+ * solves support). */
+bb_status bb_band_grad_noalloc(bb_factor f, const double *lam, const double *x, int64_t m,
+                               int64_t ld, double *grad_bands, void *stream);
+int64_t bb_band_grad_scratch_bytes(void);
+
 /* ---------------------------------------------------------------- Cahn-Hilliard
  * `steps` semi-implicit Cahn-Hilliard steps (Section 5.1) of m periodic
  * systems:  C^{n+1} + dt gamma d4 C^{n+1} = C^n + dt d2 (C^3 - C)^n, i.e.

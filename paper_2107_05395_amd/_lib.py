@@ -45,6 +45,8 @@ SIGNATURES = {
     "bb_solve_batch_tri_thread_per_system": (_S, [_FACTOR, _P, _P, _I64, _I64, _P]),
     "bb_band_grad_workspace_bytes": (ctypes.c_size_t, [_FACTOR, _I64]),
     "bb_band_grad": (_S, [_FACTOR, _P, _P, _I64, _I64, _P, _P, ctypes.c_size_t, _P]),
+    "bb_band_grad_noalloc": (_S, [_FACTOR, _P, _P, _I64, _I64, _P, _P]),
+    "bb_band_grad_scratch_bytes": (_I64, []),
     "bb_ch_step": (_S, [_FACTOR, _P, _P, _I64, _I64, ctypes.c_double, _I64, _P]),
     "bb_cn_step": (_S, [_FACTOR, _P, _P, _P, _I64, _I64, _I64, _P]),
     "bb_cn_trajectory": (_S, [_FACTOR, _P, _P, _P, _I64, _I64, _I64, _P]),

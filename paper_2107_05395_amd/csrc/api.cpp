@@ -676,6 +676,27 @@ bb_status bb_band_grad(bb_factor fh, const double *lam, const double *x, int64_t
     return BB_OK;
 }
 
+bb_status bb_band_grad_noalloc(bb_factor fh, const double *lam, const double *x, int64_t m,
+                               int64_t ld, double *grad_bands, void *stream)
+{
+    bb_status st = check_batch(fh, lam, x, m, ld);
+    if (st != BB_OK) return st;
+    if (!grad_bands) return fail(BB_ERR_ARG, "grad_bands is NULL");
+    const bb::Factor &f = fh->f;
+    const int nb = 2 * f.K + 1;
+    if ((size_t)nb * (size_t)f.n * sizeof(double) > bb::kGradScratchBytes)
+        return fail(BB_ERR_UNSUPPORTED, "bands x n exceed the library's band-gradient scratch (" +
+                                            std::to_string(bb::kGradScratchBytes) + " bytes)");
+    if (m == 0) { g_last_error.clear(); return BB_OK; }
+    hipError_t e = bb::launch_band_grad_scratch(nb, f.cyclic, (int)f.n, m, ld, lam, x, grad_bands,
+                                                (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "band-gradient launch (library scratch)");
+    g_last_error.clear();
+    return BB_OK;
+}
+
+int64_t bb_band_grad_scratch_bytes(void) { return (int64_t)bb::kGradScratchBytes; }
+
 namespace {
 
 // One row of `samples` partial sums per group of systems of the stepper.

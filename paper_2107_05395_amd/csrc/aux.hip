@@ -3,9 +3,19 @@
 //   * mean-squared-error loss and gradient
 //   * the paper's thread-per-system tridiagonal sweep (Appendix A batched
 //     sweep), kept as the measured baseline design
+#include <mutex>
+
 #include "internal.h"
 
 namespace bb {
+
+// Device memory of the allocation-free band gradient: the partial sums of
+// its groups of systems.  One copy per device, alive until the process ends.
+// Host code never uses this name as an address (on the host it is only a
+// stand-in for the symbol): band_grad_scratch_ptr() asks the runtime for the
+// device address once per device.
+static __device__ __align__(256) double scratch[kGradScratchBytes / sizeof(double)];
+
 namespace {
 
 constexpr int kGradR = 4;          // systems per lane in the band-gradient kernel
@@ -267,16 +277,17 @@ size_t band_grad_workspace(int nb, int n, int64_t m)
     return (size_t)groups * nb * n * sizeof(double);
 }
 
-hipError_t launch_band_grad(int nb, bool cyclic, int n, int64_t m, int64_t ld, const double *lam,
-                            const double *x, double *grad, void *ws, hipStream_t s)
+namespace {
+
+hipError_t band_grad_launch(int nb, bool cyclic, int n, int64_t m, int64_t ld, const double *lam,
+                            const double *x, double *grad, double *part, int64_t kpw,
+                            hipStream_t s)
 {
     const int64_t kblocks = (m + kGradSys - 1) / kGradSys;
-    const int64_t kpw = band_grad_kpw(n, m);
     const int64_t groups = (kblocks + kpw - 1) / kpw;
     const int strips = (n + kGradRows - 1) / kGradRows;
     const int waves = 256 / kWave;
     dim3 grid((unsigned)groups, (unsigned)((strips + waves - 1) / waves));
-    double *part = (double *)ws;
     if (nb == 3)
         hipLaunchKernelGGL(band_grad_partial<3>, grid, dim3(256), 0, s, n, (int)cyclic, m, ld, kpw,
                            lam, x, part);
@@ -289,6 +300,54 @@ hipError_t launch_band_grad(int nb, bool cyclic, int n, int64_t m, int64_t ld, c
     hipLaunchKernelGGL(band_grad_fold, dim3((unsigned)((total + kWave - 1) / kWave)),
                        dim3(kFoldSubs * kWave), 0, s, total, groups, (const double *)part, grad);
     return hipGetLastError();
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device (each device holds its own copy at its own address).
+constexpr int kMaxDevices = 64;
+hipError_t band_grad_scratch_ptr(double **out)
+{
+    static std::mutex mu;
+    static double *ptr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[dev] = (double *)p;
+    }
+    *out = ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_band_grad(int nb, bool cyclic, int n, int64_t m, int64_t ld, const double *lam,
+                            const double *x, double *grad, void *ws, hipStream_t s)
+{
+    return band_grad_launch(nb, cyclic, n, m, ld, lam, x, grad, (double *)ws, band_grad_kpw(n, m),
+                            s);
+}
+
+// Every entry of the partial sums that the fold reads is written by
+// band_grad_partial in the same call, so nothing in the array needs clearing.
+hipError_t launch_band_grad_scratch(int nb, bool cyclic, int n, int64_t m, int64_t ld,
+                                    const double *lam, const double *x, double *grad,
+                                    hipStream_t s)
+{
+    const int64_t cap = (int64_t)(kGradScratchBytes / sizeof(double)) / ((int64_t)nb * n);
+    if (cap < 1) return hipErrorInvalidValue;   // the host checks nb * n first
+    const int64_t kblocks = (m + kGradSys - 1) / kGradSys;
+    int64_t kpw = band_grad_kpw(n, m);
+    if ((kblocks + kpw - 1) / kpw > cap) kpw = (kblocks + cap - 1) / cap;
+    double *part = nullptr;
+    hipError_t e = band_grad_scratch_ptr(&part);
+    if (e != hipSuccess) return e;
+    return band_grad_launch(nb, cyclic, n, m, ld, lam, x, grad, part, kpw, s);
 }
 
 size_t mse_workspace(int64_t n, int64_t m)

@@ -224,6 +224,15 @@ size_t band_grad_workspace(int nb, int n, int64_t m);
 hipError_t launch_band_grad(int nb, bool cyclic, int n, int64_t m, int64_t ld, const double *lam,
                             const double *x, double *grad, void *ws, hipStream_t stream);
 
+// The same reduction with the partial sums in the library's own device array
+// (`scratch` in aux.hip, kGradScratchBytes per device, held until the process
+// ends): k-blocks per wave raised until the partial sums fit.  No allocation;
+// calls that overlap on one device race on the array.
+constexpr size_t kGradScratchBytes = (size_t)4 << 20;
+hipError_t launch_band_grad_scratch(int nb, bool cyclic, int n, int64_t m, int64_t ld,
+                                    const double *lam, const double *x, double *grad,
+                                    hipStream_t stream);
+
 size_t mse_workspace(int64_t n, int64_t m);
 hipError_t launch_mse(const double *u, const double *target, double *grad, double *loss, int n,
                       int64_t m, int64_t ld, void *ws, hipStream_t stream);

@@ -182,6 +182,21 @@ class Factor:
                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(lam)))
         return grad
 
+    def band_grad_noalloc(self, lam: torch.Tensor, x: torch.Tensor,
+                          grad: torch.Tensor) -> torch.Tensor:
+        """band_grad into a caller-given grad (+=) with the library's own
+        device scratch: nothing is allocated (bb_band_grad_noalloc)."""
+        m, ld = _batch_view(lam, self.n, torch.float64, "lam")
+        if _batch_view(x, self.n, torch.float64, "x") != (m, ld):
+            raise ValueError("x must match lam in shape and strides")
+        if grad.shape != (self.nbands, self.n) or grad.dtype != torch.float64 or not grad.is_contiguous():
+            raise ValueError("grad must be a contiguous (nbands, n) float64 tensor")
+        with torch.cuda.device(lam.device):
+            check(lib().bb_band_grad_noalloc(self._handle, ctypes.c_void_p(lam.data_ptr()),
+                                             ctypes.c_void_p(x.data_ptr()), m, ld,
+                                             ctypes.c_void_p(grad.data_ptr()), _stream_ptr(lam)))
+        return grad
+
     def ch_step(self, c: torch.Tensor, alpha: float, steps: int = 1,
                 out: torch.Tensor | None = None) -> torch.Tensor:
         """`steps` semi-implicit Cahn-Hilliard steps (cyclic penta factor of the LHS)."""

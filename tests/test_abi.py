@@ -178,6 +178,10 @@ def test_solve_argument_checks_need_no_gpu(L):
     assert L.bb_cn_step(h, w3, None, None, 0, 1, 1, None) == 0              # m = 0: nothing to do
     assert L.bb_solve_batch_tri(h, None, None, 0, 1, 0, None) == 0         # m = 0: nothing to do
     assert L.bb_band_grad(h, fake, fake, 4, 4, None, None, 0, None) == -1
+    assert L.bb_band_grad_noalloc(h, fake, fake, 4, 4, None, None) == -1   # no gradient
+    assert L.bb_band_grad_noalloc(h, fake, fake, 8, 4, fake, None) == -1   # ld < m
+    assert L.bb_band_grad_noalloc(None, fake, fake, 4, 4, fake, None) == -1
+    assert L.bb_band_grad_noalloc(h, None, None, 0, 1, fake, None) == 0     # m = 0
     assert L.bb_solve_batch_tri_thread_per_system(hp, fake, fake, 4, 4, None) == -1
     L.bb_factor_destroy(h)
     L.bb_factor_destroy(hp)
@@ -195,6 +199,7 @@ def test_workspace_sizes(L):
     assert L.bb_band_grad_workspace_bytes(h, 0) == 0
     assert L.bb_band_grad_workspace_bytes(h, 1000) >= 3 * n * 8
     assert L.bb_mse_workspace_bytes(n, 1000) >= 8
+    assert L.bb_band_grad_scratch_bytes() == 4 << 20
     L.bb_factor_destroy(h)
 
 
