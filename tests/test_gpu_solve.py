@@ -281,3 +281,61 @@ def test_workgroup_shape_and_lockstep_do_not_change_results(monkeypatch):
             outs.append(host(f.solve(t)))
     assert rel_err(outs[0], oracle_solve("penta", bands, rhs, True)) < F64_TOL
     assert all(np.array_equal(o, outs[0]) for o in outs[1:])
+
+
+# ---------------------------------------------------------------- hard matrices
+def _dense(kind, bands, n, cyclic):
+    A = np.zeros((n, n))
+    K = 1 if kind == "tri" else 2
+    for q, band in enumerate(bands):
+        off = q - K
+        for i in range(n):
+            j = i + off
+            if cyclic:
+                A[i, j % n] += band[i]
+            elif 0 <= j < n:
+                A[i, j] = band[i]
+    return A
+
+
+def _hard(name, n, seed):
+    """Matrices near the edge of what an LU without pivoting handles:
+    weakly diagonally dominant random bands (margin 1e-3, non-symmetric),
+    and implicit Euler diffusion with r = 1000 (kappa about 4000)."""
+    if name == "weak_tri":
+        return "tri", inputs.random_dominant_tri(n, seed, margin=1e-3)
+    if name == "weak_penta":
+        return "penta", inputs.random_dominant_penta(n, seed, margin=1e-3)
+    if name == "diffusion_r1000":
+        return "tri", inputs.diffusion_tri_bands(n, 1000.0)
+    assert name == "hyperdiffusion_r1000"
+    return "penta", inputs.hyperdiffusion_penta_bands(n, 1000.0)
+
+
+@pytest.mark.parametrize("name,n", [("weak_tri", 2048), ("weak_penta", 1024),
+                                    ("diffusion_r1000", 2048), ("hyperdiffusion_r1000", 1024)])
+@pytest.mark.parametrize("cyclic", [False, True])
+def test_hard_matrices(name, n, cyclic, monkeypatch):
+    """64-row chunks (the decomposition whose chunk-transfer weights decay
+    slowest on these matrices), FP64 and FP32 + refinement.  Tolerances from
+    the arithmetic: FP64 max(1e-12, 2 kappa u); one refinement step leaves
+    about (kappa u32)^2 + kappa u of the first solve's error, taken with a
+    factor 4."""
+    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", "64")
+    kind, bands = _hard(name, n, seed=n + 17)
+    from paper_2107_05395_amd import Factor
+    f = Factor.tri(*bands, cyclic=cyclic) if kind == "tri" else Factor.penta(*bands, cyclic=cyclic)
+    assert f.plan(300)["chunk"] == 64
+    kappa = float(np.linalg.cond(_dense(kind, bands, n, cyclic)))
+    rhs = inputs.uniform_batch(n, 300, seed=n + 18)
+    ref = oracle_solve(kind, bands, rhs, cyclic)
+    u, u32 = 2.0 ** -53, 2.0 ** -24
+    tol64 = max(F64_TOL, 2.0 * kappa * u)
+    tol32r = max(F32R_TOL, 4.0 * ((kappa * u32) ** 2 + kappa * u))
+    e64 = rel_err(host(f.solve(dev(rhs))), ref)
+    e32 = rel_err(host(f.solve(dev(rhs), precision="f32r")), ref)
+    say("hard", name, n, cyclic, "kappa %.3g" % kappa, "f64", e64, tol64, "f32r", e32, tol32r)
+    assert e64 < tol64
+    assert e32 < tol32r
+    lam = host(f.adjoint(dev(rhs)))
+    assert rel_err(lam, oracle_adjoint(kind, bands, rhs, cyclic)) < tol64
