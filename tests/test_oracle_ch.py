@@ -166,3 +166,25 @@ def test_ch_step_growth_rate_is_that_of_the_equation(oracle):
         if prev is not None:
             assert all(e < 0.3 * p for e, p in zip(errs, prev)), (n, errs, prev)
         prev = errs
+
+
+def test_ch_scheme_converges_at_second_order(oracle):
+    """Section 5.2: from eps cos(5x), eps = 1e-6, L = 2 pi, gamma = 0.01 and
+    dt = 0.1 dx, the scheme is second order in space while the spatial error
+    dominates.  Every N stops at the same T = 204 dt_128 (past saturation),
+    and E_N = max |C_N - C_2N| on the shared points gives log2(E_N/E_2N)
+    near 2 for N = 128, 256, 512 (the paper's Table 3 prints 2.04 .. 2.00 for
+    N = 256 .. 2048).  A dropped or mis-scaled term of the scheme changes the
+    limit the runs converge to, not the order, so this pins the consistency
+    of the discretisation rather than its coefficients (other tests do)."""
+    L, gamma, eps = 2 * math.pi, 0.01, 1e-6
+    finals = {}
+    for n in (128, 256, 512, 1024):
+        dx = L / n
+        sigma, alpha = oracle.ch_coefficients(gamma, dx, 0.1 * dx)
+        c = (eps * np.cos(5 * np.arange(n) * dx))[:, None]
+        finals[n] = oracle.ch_step(c, sigma, alpha, steps=204 * n // 128)[:, 0]
+    assert np.max(np.abs(finals[1024])) > 0.5   # saturated, not still linear
+    E = {n: np.max(np.abs(finals[n] - finals[2 * n][::2])) for n in (128, 256, 512)}
+    orders = [np.log2(E[n] / E[2 * n]) for n in (128, 256)]
+    assert all(1.9 < p < 2.2 for p in orders), (E, orders)
