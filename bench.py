@@ -722,7 +722,8 @@ def bench_adjoint(args, torch):
 
 def probe(torch):
     """One dispatch of each kernel of interest, for rocprofv3 counter runs:
-    a plain copy of known size (4 GiB read + 4 GiB written), the FP64 and
+    a plain copy of known size (4 GiB read + 4 GiB written), the library's
+    16 KB-tile copy of the same array, the FP64 and
     FP32+refine sweeps and the thread-per-system design on the bench workload,
     the FP64 pentadiagonal sweep on the hyperdiffusion workload, one launch
     of 10 fused Cahn-Hilliard steps on the n=256, m=2^20 ensemble, and one
@@ -732,6 +733,9 @@ def probe(torch):
     rhs = torch.rand(n, m, dtype=torch.float64, device="cuda")
     x = torch.empty_like(rhs)
     x.copy_(rhs)
+    torch.cuda.synchronize()
+    from paper_2107_05395_amd.solver import copy_tiles
+    copy_tiles(rhs, x)
     torch.cuda.synchronize()
     f = Factor.tri(*inputs.diffusion_tri_bands(n, 1.0))
     for prec in ("f64", "f32r"):
@@ -760,6 +764,155 @@ def probe(torch):
     cn.cn_step(c, w, steps=1, out=torch.empty_like(c))
     torch.cuda.synchronize()
     print(json.dumps({"probe": "done"}), flush=True)
+
+
+# Table 3 of the paper (Section 5.2, N_x, E_N, log2(E_N / E_2N)), as printed;
+# context only: the paper does not define E_N or give the end time.
+PAPER_TABLE3 = [(128, 0.0310, 3.7932), (256, 0.0022, 2.0376), (512, 5.45e-4, 2.0089),
+                (1024, 1.35e-4, 2.0022), (2048, 3.38e-5, 2.0005), (4096, 8.45e-6, 0.8947),
+                (8192, 4.54e-6, None)]
+
+
+def bench_ch_convergence(args, torch):
+    """The Section 5.2 convergence study of the Cahn-Hilliard scheme: one run
+    per N from eps cos(5x) to the same end time T with dt = 0.1 dx, and the
+    self-convergence error E_N = max_i |C_N(x_i, T) - C_2N(x_i, T)| over the
+    N points the two grids share, with the observed order log2(E_N / E_2N).
+    N <= 1024 run fused on chip, longer systems one three-launch step per
+    call.  The oracle repeats the runs up to N = 1024 on the host (its E_N and
+    final states are compared with the GPU's)."""
+    from paper_2107_05395_amd import Factor, inputs
+    import oracle
+    spec = dict(inputs.WORKLOADS[args.workload])
+    L, gamma, eps, mode, s128 = (spec["length"], spec["gamma"], spec["eps"], spec["mode"],
+                                 spec["steps128"])
+    ns = list(spec["ns"]) + [2 * spec["ns"][-1]]
+    finals, times, steps_of = {}, {}, {}
+    total_steps = 0
+    for n in ns:
+        dx = L / n
+        dt = 0.1 * dx
+        steps = s128 * n // 128
+        f = Factor.cahn_hilliard(n, L, gamma, dt)
+        x = np.arange(n) * dx
+        c0 = torch.from_numpy((eps * np.cos(mode * x))[:, None].copy()).cuda()
+        f.ch_run(c0, f.alpha, 2)                              # warm-up (tables, code)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = f.ch_run(c0, f.alpha, steps)
+        torch.cuda.synchronize()
+        times[n] = time.perf_counter() - t0
+        finals[n] = out[:, 0].cpu().numpy()
+        steps_of[n] = steps
+        total_steps += steps
+    table = []
+    for n in spec["ns"]:
+        e = float(np.max(np.abs(finals[n] - finals[2 * n][::2])))
+        table.append({"N": n, "E_N": e, "steps": steps_of[n], "gpu_s": times[n]})
+    for i in range(len(table) - 1):
+        table[i]["order"] = float(np.log2(table[i]["E_N"] / table[i + 1]["E_N"]))
+    # the oracle on the same runs up to N = 1024 (and its 2N references)
+    t0 = time.perf_counter()
+    ref_finals = {}
+    for n in [n for n in ns if n <= 2048]:
+        dx = L / n
+        sigma, alpha = oracle.ch_coefficients(gamma, dx, 0.1 * dx)
+        c = (eps * np.cos(mode * np.arange(n) * dx))[:, None]
+        ref_finals[n] = oracle.ch_step(c, sigma, alpha, steps=steps_of[n])[:, 0]
+    cpu_s = time.perf_counter() - t0
+    cpu_steps = sum(steps_of[n] for n in ref_finals)
+    checks = []
+    for row in table:
+        n = row["N"]
+        if n in ref_finals and 2 * n in ref_finals:
+            e_ref = float(np.max(np.abs(ref_finals[n] - ref_finals[2 * n][::2])))
+            row["E_N_oracle"] = e_ref
+            checks.append({"N": n, "max_abs_diff_vs_oracle":
+                           float(np.max(np.abs(finals[n] - ref_finals[n])))})
+    gpu_total = sum(times.values())
+    return {
+        "metric": "system-steps/s", "value": total_steps / gpu_total, "unit": "system-steps/s",
+        "n_gpus": 1, "steps": total_steps, "warmup": 1, "ms_per_step": 1e3 * gpu_total / total_steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (the cosine initial state of Section 5.2)",
+        "config": {"workload": args.workload, "ns": ns, "L": L, "gamma": gamma, "eps": eps,
+                   "mode": mode, "dt": "0.1 dx", "T": s128 * 0.1 * L / 128},
+        "table": table, "state_checks": checks,
+        "paper_table3": [{"N": a, "E_N": b, "order": c} for a, b, c in PAPER_TABLE3],
+        "roofline": None,
+        "cpu_baseline": {"value": cpu_steps / cpu_s, "unit": "system-steps/s", "cores": 1,
+                         "kind": "oracle",
+                         "sample": "oracle.ch_step over the runs N = %s (one system each, one "
+                                   "thread), %.1f s" % (sorted(ref_finals), cpu_s)},
+    }
+
+
+def bench_long(args, torch):
+    """Long systems (tri and penta beyond one launch's on-chip limit), FP64:
+    every (n, m) point times eager solves and solves replayed from a HIP graph
+    (small batches are bound by latency), periodic penta as well; the oracle
+    solves the same batch on the host cores (sampled systems for large m)."""
+    from paper_2107_05395_amd import Factor, inputs
+    import oracle
+    spec = dict(inputs.WORKLOADS[args.workload])
+    points = []
+    for n in spec["ns"]:
+        for m in spec["ms"]:
+            for kind, cyclic in (("tri", False), ("penta", True)):
+                bands = (inputs.diffusion_tri_bands(n, 1.0) if kind == "tri"
+                         else inputs.hyperdiffusion_penta_bands(n, 0.25))
+                f = Factor.tri(*bands) if kind == "tri" else Factor.penta(*bands, cyclic=cyclic)
+                rhs_host = inputs.uniform_batch(n, m, seed=spec["seed"] + n + m)
+                rhs = torch.from_numpy(rhs_host).cuda()
+                x = torch.empty_like(rhs)
+                reps = args.steps
+                t, _ = time_launches(lambda: f.solve(rhs, out=x), reps, args.warmup, torch)
+                graph_ms = None
+                if m * n <= (1 << 22):
+                    g = torch.cuda.CUDAGraph()
+                    side = torch.cuda.Stream()
+                    side.wait_stream(torch.cuda.current_stream())
+                    with torch.cuda.stream(side):
+                        with torch.cuda.graph(g, stream=side):
+                            for _ in range(20):
+                                f.solve(rhs, out=x)
+                    torch.cuda.current_stream().wait_stream(side)
+                    gt, _ = time_launches(g.replay, 5, 1, torch)
+                    graph_ms = 1e3 * gt / (5 * 20)
+                    del g
+                cols = np.unique(np.linspace(0, m - 1, min(m, 64)).astype(np.int64))
+                solve = oracle.tri_solve if kind == "tri" else oracle.penta_solve
+                t0 = time.perf_counter()
+                ref = solve(*bands, rhs_host[:, cols], cyclic=cyclic)
+                cpu_s = (time.perf_counter() - t0) / len(cols) * m
+                got = x[:, torch.from_numpy(cols).cuda()].cpu().numpy()
+                pl = f.plan(m)
+                points.append({"kind": kind + ("_cyclic" if cyclic else ""), "n": n, "m": m,
+                               "chunk": pl["chunk"], "chunks": pl["lanes"],
+                               "ms_per_solve": 1e3 * t / reps, "graph_ms_per_solve": graph_ms,
+                               "hbm_gbs_algorithmic": 16.0 * n * m * reps / t / 1e9,
+                               "oracle_ms_per_solve": 1e3 * cpu_s,
+                               "rel_err_vs_oracle": rel_err_cols(got, ref)})
+                del rhs, x
+    big = max(points, key=lambda p: p["n"] * p["m"])
+    ach = big["hbm_gbs_algorithmic"]
+    return {
+        "metric": "systems solved/s", "value": big["m"] / (big["ms_per_solve"] / 1e3),
+        "unit": "systems/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": big["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded uniform[-1,1) right-hand sides)",
+        "config": {"workload": args.workload, "ns": list(spec["ns"]), "ms": list(spec["ms"]),
+                   "matrices": "tri (-1, 3, -1); periodic penta (0.25, -1, 2.5, -1, 0.25)"},
+        "points": points,
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": ach / PEAK_HBM_GBS, "traffic": None,
+                     "note": "largest point (%s n=%d m=%d), algorithmic 16 B per row; the three "
+                             "launches move 24 B per row" % (big["kind"], big["n"], big["m"])},
+        "cpu_baseline": {"value": big["m"] / (big["oracle_ms_per_solve"] / 1e3),
+                         "unit": "systems/s", "cores": oracle.num_threads(), "kind": "oracle",
+                         "sample": "oracle solves of %d sampled systems per point, scaled to m"
+                                   % 64},
+    }
 
 
 def main():
@@ -805,6 +958,10 @@ def main():
         line = bench_ch_coarsening(args, torch)
     elif kind == "ch_forced":
         line = bench_ch_forced(args, torch)
+    elif kind == "ch_convergence":
+        line = bench_ch_convergence(args, torch)
+    elif kind == "long":
+        line = bench_long(args, torch)
     else:
         sys.exit("workload %s is not a bench workload" % args.workload)
     line["device"] = torch.cuda.get_device_name(0)

@@ -100,11 +100,13 @@ bb_status bb_factor_shared_penta_cyclic(const double *a, const double *b, const 
 bb_status bb_factor_destroy(bb_factor f);
 
 /* Copy the factor's coefficient tables for large batches to the current
- * device now, ordered on `stream`, instead of on the first solve.  A call
- * whose decomposition differs (a small batch: fewer than 2^16 lanes of 64-row
- * chunks; the fused steppers) builds its own table on first use.  That first
- * call allocates device memory; make it before capturing the calls in a HIP
- * graph. */
+ * device now, instead of on the first solve.  The copy is synchronous: the
+ * tables are on the device when the call returns, and `stream` is not used
+ * (kept so that the call can later be made asynchronous without an ABI
+ * change).  A call whose decomposition differs (a small batch: fewer than
+ * 2^16 lanes of 64-row chunks; the fused steppers) builds its own table on
+ * first use.  That first call allocates device memory; make it before
+ * capturing the calls in a HIP graph. */
 bb_status bb_factor_upload(bb_factor f, void *stream);
 
 /* Matrix size, kind (0 tri, 1 tri cyclic, 2 penta, 3 penta cyclic) and the
@@ -305,6 +307,17 @@ bb_status bb_cn_step(bb_factor f, const double *w, const double *c_in, double *c
 bb_status bb_cn_trajectory(bb_factor f, const double *w, const double *c_in, double *traj,
                            int64_t m, int64_t ld, int64_t steps, void *stream);
 
+/* The adjoint recursion of `steps` implicit steps, lam_{s+1} = A^{-T} lam_s
+ * (s = 0 .. steps-1, lam_0 = g), with the same shared factor as the solves
+ * (A^T = U^T L^T, the transposed solve of bb_solve_batch_*_adjoint), in one
+ * launch of the fused stepper with the state on chip: lam_{s+1} goes to
+ * traj + s * n * ld.  This is the backward pass of a rollout
+ * u_{t+1} = A^{-1} u_t: for a loss of u_T, lam_s = dL/du_{T-s}.  Reads g once
+ * and writes each state once.  Same sizes, layouts and errors as
+ * bb_cn_trajectory (g, traj: device double; traj must not overlap g). */
+bb_status bb_adjoint_trajectory(bb_factor f, const double *g, double *traj, int64_t m,
+                                int64_t ld, int64_t steps, void *stream);
+
 /* ---------------------------------------------------------------- measurement
  * A measurement utility, not part of the method: copy `bytes` from src to
  * dst (device, 16-byte aligned, not overlapping; bytes a multiple of 16) with
@@ -326,6 +339,24 @@ size_t bb_mse_workspace_bytes(int64_t n, int64_t m);
 bb_status bb_mse_loss_grad(const double *u, const double *target, double *grad, double *loss_dev,
                            int64_t n, int64_t m, int64_t ld, void *workspace,
                            size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------- tuning
+ * Process-wide overrides of the decomposition choices, for measurement and
+ * tests; results never depend on them beyond rounding (on max_chunk) and not
+ * at all on the others.  value -1 restores the automatic choice.
+ *   "max_chunk"         rows per lane, power of two 4 .. 128 (long systems: 16,
+ *                       32 or 64; other values leave them automatic)
+ *   "waves_per_system"  waves per split system group: 1, 2, 4 or 8 where valid
+ *   "waves_per_block"   waves per workgroup of unsplit sweeps: 1, 2 or 4
+ *   "lockstep"          0 / 1: a workgroup barrier at every persistent iteration
+ *   "ch_uniform"        0: the fused steppers never read coefficients through
+ *                       the scalar cache
+ *   "grid_linear"       0 / 1: persistent grids / one workgroup per group
+ * The settings are read when a call enqueues its launches; change them only
+ * between calls.  Errors: BB_ERR_ARG (unknown name, invalid value). */
+bb_status bb_set_tuning(const char *name, int64_t value);
+/* The current value of a setting (-1: automatic), or -2 for an unknown name. */
+int64_t bb_get_tuning(const char *name);
 
 /* ---------------------------------------------------------------- errors */
 const char *bb_status_string(bb_status s);

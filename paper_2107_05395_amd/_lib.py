@@ -50,6 +50,7 @@ SIGNATURES = {
     "bb_ch_step": (_S, [_FACTOR, _P, _P, _I64, _I64, ctypes.c_double, _I64, _P]),
     "bb_cn_step": (_S, [_FACTOR, _P, _P, _P, _I64, _I64, _I64, _P]),
     "bb_cn_trajectory": (_S, [_FACTOR, _P, _P, _P, _I64, _I64, _I64, _P]),
+    "bb_adjoint_trajectory": (_S, [_FACTOR, _P, _P, _I64, _I64, _I64, _P]),
     "bb_copy_tiles": (_S, [_P, _P, _I64, _P]),
     "bb_ch_stats_workspace_bytes": (ctypes.c_size_t, [_FACTOR, _I64, _I64]),
     "bb_ch_forced_step": (_S, [_FACTOR, _P, _P, _I64, _I64, ctypes.c_double, ctypes.c_double,
@@ -60,6 +61,8 @@ SIGNATURES = {
                               ctypes.c_size_t, _P]),
     "bb_mse_workspace_bytes": (ctypes.c_size_t, [_I64, _I64]),
     "bb_mse_loss_grad": (_S, [_P, _P, _P, _P, _I64, _I64, _I64, _P, ctypes.c_size_t, _P]),
+    "bb_set_tuning": (_S, [ctypes.c_char_p, _I64]),
+    "bb_get_tuning": (_I64, [ctypes.c_char_p]),
     "bb_status_string": (ctypes.c_char_p, [_S]),
     "bb_last_error_message": (ctypes.c_char_p, []),
 }

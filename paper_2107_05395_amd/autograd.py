@@ -16,13 +16,12 @@ that also stores every intermediate state.  A fused launch of k steps, a
 trajectory launch and k single-step launches agree bitwise (same kernel
 arithmetic and decomposition), so the recomputed states equal the forward's.
 The adjoint recursion lam_t = A^{-T} lam_{t+1} is stepped the same way: one
-trajectory launch per segment on the factor of A^T (its bands are A's bands
-transposed), after which the segment's band gradients reduce lam_t against
-u_t.
+launch per segment of the same kernel on the factor's transposed solve
+(bb_adjoint_trajectory), after which the segment's band gradients reduce
+lam_t against u_t.
 """
 from __future__ import annotations
 
-import numpy as np
 import torch
 
 from .solver import Factor, mse_loss_grad
@@ -35,31 +34,6 @@ def _host_bands(bands):
 def _factor_from(bands, kind: str, cyclic: bool) -> Factor:
     host = _host_bands(bands)
     return Factor.tri(*host, cyclic=cyclic) if kind == "tri" else Factor.penta(*host, cyclic=cyclic)
-
-
-def _transposed_bands(host):
-    """Bands of A^T for a non-periodic band matrix A given by its host bands
-    (row i of A holds band q at column i + q - K): band q of A^T at row i is
-    band 2K - q of A at row i + q - K; entries outside the matrix are 0."""
-    nb = len(host)
-    K = nb // 2
-    n = host[0].shape[0]
-    out = []
-    for q in range(nb):
-        src = np.asarray(host[nb - 1 - q], dtype=np.float64)
-        sh = q - K
-        t = np.zeros(n)
-        if sh >= 0:
-            t[:n - sh] = src[sh:]
-        else:
-            t[-sh:] = src[:n + sh]
-        out.append(t)
-    return out
-
-
-def _transposed_factor(host) -> Factor:
-    t = _transposed_bands(host)
-    return Factor.tri(*t) if len(t) == 3 else Factor.penta(*t)
 
 
 _SIDE_STREAMS: dict = {}
@@ -153,7 +127,6 @@ class BandedRollout(torch.autograd.Function):
                 checkpoints.append(u)
         ctx.factor, ctx.steps, ctx.every, ctx.precision = f, steps, checkpoint_every, precision
         ctx.band_devices = [b.device for b in bands]
-        ctx.host_bands = host
         ctx.checkpoints = checkpoints
         return u
 
@@ -182,8 +155,9 @@ class BandedRollout(torch.autograd.Function):
                 return [ctx.checkpoints[i]] + _trajectory(f, ctx.checkpoints[i],
                                                           min(s + every, steps) - s, prec)
 
-        # FP64: the adjoints of a segment as one trajectory on A^T
-        ft = _transposed_factor(ctx.host_bands) if prec == "f64" else None
+        # FP64: the adjoints of a segment as one trajectory of transposed
+        # solves with the factor's own A^T = U^T L^T
+        traj = prec == "f64"
 
         # segments [s, e): states u_s .. u_e; checkpoint i holds u_{i*every}
         last = len(ctx.checkpoints) - 1
@@ -196,9 +170,9 @@ class BandedRollout(torch.autograd.Function):
             for u in states:
                 u.record_stream(main)
             pending = recompute(i - 1) if i > 0 else None
-            if ft is not None:
+            if traj:
                 # lams[j] = lam_{e-j} = A^{-T} lam_{e-j+1}, lam_{e+1} = g
-                lams = list(ft.cn_trajectory(g, _identity(ft), e - s).unbind(0))
+                lams = list(f.adjoint_trajectory(g, e - s).unbind(0))
                 side.wait_stream(main)
                 with torch.cuda.stream(side):
                     for j, lam in enumerate(lams):
@@ -219,7 +193,7 @@ class BandedRollout(torch.autograd.Function):
                 g = lam
             del states
         main.wait_stream(side)
-        ctx.checkpoints = ctx.host_bands = None
+        ctx.checkpoints = None
         return (g, None, None, None, *[gb[q].to(d) for q, d in enumerate(ctx.band_devices)])
 
 

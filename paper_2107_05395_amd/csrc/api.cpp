@@ -2,6 +2,7 @@
 // include/bandbatch.h): argument checks, choice of the sweep decomposition,
 // lazy upload of the factor's coefficient tables, kernel dispatch.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -42,17 +43,30 @@ bb_status hip_fail(hipError_t e, const char *where)
     return fail(BB_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+// Tuning overrides (bb_set_tuning), read at each call; -1 = automatic.
+std::atomic<int64_t> g_tuning[bb::kTuneCount] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
+const char *const kTuneNames[bb::kTuneCount] = {"max_chunk", "waves_per_system", "waves_per_block",
+                                                "lockstep", "ch_uniform", "grid_linear"};
+
+bool tune_valid(int key, int64_t v)
+{
+    if (v == -1) return true;
+    switch (key) {
+    case bb::kTuneMaxChunk: return v >= bb::kChunkMin && v <= bb::kChunkMax && (v & (v - 1)) == 0;
+    case bb::kTuneWavesPerSystem: return v == 1 || v == 2 || v == 4 || v == 8;
+    case bb::kTuneWavesPerBlock: return v == 1 || v == 2 || v == 4;
+    default: return v == 0 || v == 1;
+    }
+}
+
 // Upper bound on rows per lane.  The sweeps hold C rows of the right-hand side
 // per lane in registers; the refinement kernel holds the double input, the
 // float first solution and the float correction at once, so it gets half.
-// BANDBATCH_MAX_CHUNK lowers the bound (tuning).
+// Tuning max_chunk lowers the bound.
 int max_chunk(bb_precision p)
 {
     int c = bb::kChunkMax;
-    if (const char *env = std::getenv("BANDBATCH_MAX_CHUNK")) {
-        const int v = std::atoi(env);
-        if (v >= bb::kChunkMin && v <= bb::kChunkMax && (v & (v - 1)) == 0) c = v;
-    }
+    if (bb::tuning(bb::kTuneMaxChunk) > 0) c = (int)bb::tuning(bb::kTuneMaxChunk);
     if ((p == BB_F32_REFINE || p == BB_F32_RHS_REFINE) && c > bb::kChunkMaxRefine) c = bb::kChunkMaxRefine;
     return c;
 }
@@ -85,11 +99,11 @@ int latency_chunk(int64_t n, int64_t m, int C)
 // 3406; penta n = 1024 4269 vs 3949; ragged tri n = 1000 3992 vs 3701,
 // n = 2000 3635 vs 3200, penta n = 1000 3994 vs 3328.  Systems of 64 rows or
 // fewer take one lane; small batches follow latency_chunk.
-// BANDBATCH_MAX_CHUNK overrides (tuning).
+// Tuning max_chunk overrides.
 int solve_chunk(int64_t n, int64_t m, bb_precision p)
 {
     const int cmax = max_chunk(p);
-    if (std::getenv("BANDBATCH_MAX_CHUNK")) return bb::choose_chunk(n, cmax);
+    if (bb::tuning(bb::kTuneMaxChunk) > 0) return bb::choose_chunk(n, cmax);
     const int C = bb::choose_chunk(n, std::min(cmax, 64));
     return m > 0 ? latency_chunk(n, m, C) : C;
 }
@@ -104,25 +118,21 @@ int solve_chunk(int64_t n, int64_t m, bb_precision p)
 // costs (measured tri n = 1024, m = 2^16: 0.267 vs 0.293 ms), so it is off.
 // The refinement kernel keeps it (penta n = 1024 with FP32 right-hand sides:
 // 1.46 vs 1.56 ms without).
-// BANDBATCH_LOCKSTEP=0/1 overrides (tuning).
+// Tuning lockstep = 0/1 overrides.
 // Grid shape.  Persistent grids (at most one wave of resident workgroups,
 // each walking its XCD's share of the groups) serve the kernels that stage
 // a coefficient table in LDS, once per workgroup.  The scalar-coefficient
 // stepper stages nothing and runs one workgroup per group in launch order
 // (measured, CH n = 256, m = 2^20, one step per launch: 0.855 vs 0.953 ms;
 // the LDS kernels lose: tri FP32+refine n = 512, m = 2^20 2.64 vs 2.04 ms,
-// penta n = 1024 FP64 1.04 vs 0.99 ms).  BANDBATCH_GRID_LINEAR=0/1 forces
+// penta n = 1024 FP64 1.04 vs 0.99 ms).  Tuning grid_linear = 0/1 forces
 // persistent / one-per-group grids everywhere (tuning; the launcher reads the
-// same variable for the LDS kernels).  Returns -1 when unset.
-int grid_linear()
-{
-    const char *env = std::getenv("BANDBATCH_GRID_LINEAR");
-    return env ? (std::atoi(env) != 0) : -1;
-}
+// same setting for the LDS kernels).  Returns -1 when unset.
+int grid_linear() { return (int)bb::tuning(bb::kTuneGridLinear); }
 
 int lockstep_for(bool split)
 {
-    if (const char *env = std::getenv("BANDBATCH_LOCKSTEP")) return std::atoi(env) != 0;
+    if (bb::tuning(bb::kTuneLockstep) >= 0) return (int)bb::tuning(bb::kTuneLockstep);
     return split ? 0 : 1;
 }
 
@@ -135,12 +145,12 @@ int lockstep_for(bool split)
 // with FP32 right-hand sides (two waves per SIMD for tri) with 4-wave groups
 // from P = 4 (tri n = 512: 1.59 vs 1.80 ms at Q = 2).  P <= 4 otherwise keeps
 // one wave.
-// BANDBATCH_WAVES_PER_SYSTEM = 1, 2, 4 or 8 forces the group size where it
-// is valid (tuning); anything else keeps the automatic choice.
+// Tuning waves_per_system = 1, 2, 4 or 8 forces the group size where it is
+// valid; otherwise the automatic choice stands.
 int split_log2(int log2P, int C, int n, bb::Op op)
 {
     const bool refine = op != bb::Op::Solve;
-    if (C < (refine ? 32 : 64) || (refine && ((int64_t)C << log2P) != n)) return 0;
+    if (C < 32 || (refine && ((int64_t)C << log2P) != n)) return 0;
     const int lmax = bb::max_log2q(C, refine);
     int l = 0;
     if (op == bb::Op::RefineF32Rhs)   // float input: fewer registers, 4-wave groups from P = 4
@@ -149,13 +159,13 @@ int split_log2(int log2P, int C, int n, bb::Op op)
         l = log2P > 2 ? log2P - 2 : 0;
     else if (C > 64)
         l = log2P >= 3 ? 2 : 0;
-    else
+    else if (C == 64)
         l = log2P >= 4 ? 3 : log2P == 3 ? 2 : 0;
     if (l > lmax) l = lmax;
-    if (const char *env = std::getenv("BANDBATCH_WAVES_PER_SYSTEM")) {
-        const int q = std::atoi(env);
-        const int fl = q == 1 ? 0 : q == 2 ? 1 : q == 4 ? 2 : q == 8 ? 3 : -1;
-        if (fl >= 0 && fl <= log2P && fl <= lmax) l = fl;
+    if (bb::tuning(bb::kTuneWavesPerSystem) > 0) {
+        const int64_t q = bb::tuning(bb::kTuneWavesPerSystem);
+        const int fl = q == 1 ? 0 : q == 2 ? 1 : q == 4 ? 2 : 3;
+        if (fl <= log2P && fl <= lmax) l = fl;
     }
     return l;
 }
@@ -171,12 +181,12 @@ struct StepPlan {
 // chunk per wave with scalar coefficients up to 8 chunks, else the LDS table
 // with 32 systems per group (4 waves at P = 8, 8 waves from P = 16; n = 1024,
 // m = 2^16: 0.063 vs 0.096 ms per tri step over one wave per group).
-// BANDBATCH_MAX_CHUNK, BANDBATCH_CH_UNIFORM=0 (no scalar kernel) and
-// BANDBATCH_WAVES_PER_SYSTEM=1/2/4/8 override (tuning, testing).
+// Tuning max_chunk, ch_uniform = 0 (no scalar kernel) and waves_per_system =
+// 1/2/4/8 override (tuning, testing).
 StepPlan step_plan(int64_t n, int64_t m)
 {
     int C = bb::choose_chunk(n, std::min(max_chunk(BB_F64), bb::kChunkMaxCH));
-    if (!std::getenv("BANDBATCH_MAX_CHUNK")) {
+    if (bb::tuning(bb::kTuneMaxChunk) < 0) {
         const int64_t lanes64 = m * bb::lanes_for(n, C);
         C = latency_chunk(n, m, C);
         // Fewer than two waves per SIMD at 64 rows: 32-row chunks (still one
@@ -195,19 +205,16 @@ StepPlan step_plan(int64_t n, int64_t m)
     pl.log2P = 0;
     while ((1 << pl.log2P) < pl.P) ++pl.log2P;
     const bool full = (int64_t)C * pl.P == n;
-    const char *uni = std::getenv("BANDBATCH_CH_UNIFORM");
-    pl.scalar = full && C >= 16 && pl.log2P <= 3 && !(uni && std::atoi(uni) == 0);
+    pl.scalar = full && C >= 16 && pl.log2P <= 3 && bb::tuning(bb::kTuneChUniform) != 0;
     pl.log2Q = 0;
     if (pl.scalar)
         pl.log2Q = pl.log2P;
     else if (full && C >= 32 && pl.log2P >= 3)
         pl.log2Q = pl.log2P >= 4 ? 3 : 2;
-    if (const char *env = std::getenv("BANDBATCH_WAVES_PER_SYSTEM")) {
-        if (!pl.scalar && full && C >= 32) {
-            const int q = std::atoi(env);
-            const int fl = q == 1 ? 0 : q == 2 ? 1 : q == 4 ? 2 : q == 8 ? 3 : -1;
-            if (fl >= 0 && fl <= pl.log2P) pl.log2Q = fl;
-        }
+    if (bb::tuning(bb::kTuneWavesPerSystem) > 0 && !pl.scalar && full && C >= 32) {
+        const int64_t q = bb::tuning(bb::kTuneWavesPerSystem);
+        const int fl = q == 1 ? 0 : q == 2 ? 1 : q == 4 ? 2 : 3;
+        if (fl <= pl.log2P) pl.log2Q = fl;
     }
     return pl;
 }
@@ -236,14 +243,12 @@ bool is_long(const bb::Factor &f) { return f.n > (f.K == 1 ? bb::kMaxN : bb::kMa
 
 // Rows per chunk of a long solve: 64 for large batches (fewer chunks, so less
 // scratch traffic and a shorter scan), 32 for small ones, whose time is the
-// latency of a chunk's passes and of the scan.  BANDBATCH_MAX_CHUNK = 16, 32
-// or 64 overrides (tuning).
+// latency of a chunk's passes and of the scan.  Tuning max_chunk = 16, 32 or
+// 64 overrides.
 int long_chunk(int64_t m)
 {
-    if (const char *env = std::getenv("BANDBATCH_MAX_CHUNK")) {
-        const int v = std::atoi(env);
-        if (v == 16 || v == 32 || v == 64) return v;
-    }
+    const int64_t v = bb::tuning(bb::kTuneMaxChunk);
+    if (v == 16 || v == 32 || v == 64) return (int)v;
     return (m == 0 || m >= 4096) ? 64 : 32;
 }
 
@@ -262,7 +267,7 @@ bb::LongGeom long_geom(const bb::Factor &f, int64_t m, int64_t ld, int C)
 // Decomposition, device table (the factor's own primal FP64 table for that
 // chunk size, shared with the solves) and launch geometry of a fused stepper.
 bb_status stepper_setup(bb::Factor &f, int dev, int64_t m, int64_t ld, StepPlan *pl,
-                        bb::DeviceTable *tab, bb::SweepGeom *g);
+                        bb::DeviceTable *tab, bb::SweepGeom *g, bool adjoint = false);
 
 bb_status make(int kind, const double *a, const double *b, const double *c, const double *d,
                const double *e, int64_t n, bb_factor *out)
@@ -339,7 +344,7 @@ bb_status long_table(bb::Factor &f, int dev, bool adjoint, int C, bb::DeviceTabl
 }
 
 bb_status stepper_setup(bb::Factor &f, int dev, int64_t m, int64_t ld, StepPlan *pl,
-                        bb::DeviceTable *tab, bb::SweepGeom *g)
+                        bb::DeviceTable *tab, bb::SweepGeom *g, bool adjoint)
 {
     if (is_long(f))
         return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(f.n) +
@@ -348,8 +353,10 @@ bb_status stepper_setup(bb::Factor &f, int dev, int64_t m, int64_t ld, StepPlan 
                                              std::to_string(bb::kMaxNPenta) + ")");
     *pl = step_plan(f.n, m);
     const int C = pl->C, P = pl->P;
-    bb_status st = device_table(f, f.dev, std::make_tuple(dev, 0, 0, C, 0), false,
-                                [&] { return bb::build_table(f.primal, f.K, f.cyclic, f.n, C, P); },
+    // the same table as a solve (or adjoint solve) with this chunk size
+    const bb::Direction &dir = adjoint ? f.adjoint : f.primal;
+    bb_status st = device_table(f, f.dev, std::make_tuple(dev, (int)adjoint, 0, C, 0), false,
+                                [&] { return bb::build_table(dir, f.K, f.cyclic, f.n, C, P); },
                                 tab);
     if (st != BB_OK) return st;
     *g = step_geom(f.n, m, ld, *pl);
@@ -474,7 +481,31 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
 
 }  // namespace
 
+int64_t bb::tuning(bb::TuneKey key) { return g_tuning[key].load(std::memory_order_relaxed); }
+
 extern "C" {
+
+bb_status bb_set_tuning(const char *name, int64_t value)
+{
+    if (!name) return fail(BB_ERR_ARG, "name is NULL");
+    for (int k = 0; k < bb::kTuneCount; ++k)
+        if (std::strcmp(name, kTuneNames[k]) == 0) {
+            if (!tune_valid(k, value))
+                return fail(BB_ERR_ARG, "value " + std::to_string(value) + " is not valid for " + name);
+            g_tuning[k].store(value, std::memory_order_relaxed);
+            g_last_error.clear();
+            return BB_OK;
+        }
+    return fail(BB_ERR_ARG, std::string("unknown tuning name: ") + name);
+}
+
+int64_t bb_get_tuning(const char *name)
+{
+    if (name)
+        for (int k = 0; k < bb::kTuneCount; ++k)
+            if (std::strcmp(name, kTuneNames[k]) == 0) return g_tuning[k].load(std::memory_order_relaxed);
+    return -2;
+}
 
 bb_status bb_factor_shared_tri(const double *a, const double *b, const double *c, int64_t n,
                                bb_factor *out)
@@ -847,7 +878,7 @@ namespace {
 // Fused Crank-Nicolson steps; traj: store every step's state (step s at
 // out + s * n * ld) rather than only the last.
 bb_status cn_steps(bb_factor fh, const double *w, const double *c_in, double *out, int64_t m,
-                   int64_t ld, int64_t steps, bool traj, void *stream)
+                   int64_t ld, int64_t steps, bool traj, void *stream, bool adjoint = false)
 {
     bb_status st = check_batch(fh, c_in, out, m, ld);
     if (st != BB_OK) return st;
@@ -864,14 +895,15 @@ bb_status cn_steps(bb_factor fh, const double *w, const double *c_in, double *ou
     StepPlan pl;
     bb::DeviceTable tab;
     bb::SweepGeom g;
-    if ((st = stepper_setup(f, dev, m, ld, &pl, &tab, &g)) != BB_OK) return st;
+    if ((st = stepper_setup(f, dev, m, ld, &pl, &tab, &g, adjoint)) != BB_OK) return st;
     double wk[5] = {0, 0, 0, 0, 0};
     for (int d = 0; d <= 2 * f.K; ++d) wk[d] = w[d];
+    const bb::CyclicQ &q = adjoint ? f.adjoint.cor.q : f.primal.cor.q;
     hipError_t e = f.K == 1
-        ? bb::launch_cn_tri(f.cyclic, (const double *)tab.ptr, tab.elems, f.primal.cor.q, g,
-                            pl.scalar, wk, steps, stride, c_in, out, (hipStream_t)stream)
-        : bb::launch_cn_penta(f.cyclic, (const double *)tab.ptr, tab.elems, f.primal.cor.q, g,
-                              pl.scalar, wk, steps, stride, c_in, out, (hipStream_t)stream);
+        ? bb::launch_cn_tri(f.cyclic, (const double *)tab.ptr, tab.elems, q, g, pl.scalar, wk,
+                            steps, stride, c_in, out, (hipStream_t)stream)
+        : bb::launch_cn_penta(f.cyclic, (const double *)tab.ptr, tab.elems, q, g, pl.scalar, wk,
+                              steps, stride, c_in, out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "Crank-Nicolson launch");
     g_last_error.clear();
     return BB_OK;
@@ -891,6 +923,15 @@ bb_status bb_cn_trajectory(bb_factor fh, const double *w, const double *c_in, do
                            int64_t m, int64_t ld, int64_t steps, void *stream)
 {
     return cn_steps(fh, w, c_in, traj, m, ld, steps, true, stream);
+}
+
+bb_status bb_adjoint_trajectory(bb_factor fh, const double *g, double *traj, int64_t m,
+                                int64_t ld, int64_t steps, void *stream)
+{
+    if (!fh) return fail(BB_ERR_ARG, "factor is NULL");
+    double id[5] = {0, 0, 0, 0, 0};
+    id[fh->f.K] = 1.0;   // the identity stencil: every step is a plain transposed solve
+    return cn_steps(fh, id, g, traj, m, ld, steps, true, stream, true);
 }
 
 bb_status bb_copy_tiles(const void *src, void *dst, int64_t bytes, void *stream)

@@ -117,6 +117,19 @@ __host__ __device__ constexpr int64_t split_exchange_len(int log2Q) { return 8LL
 // ... and of a fourth phase: rows 0, 1, n-2, n-1 of every (chunk, slot).
 __host__ __device__ constexpr int64_t split_ends_len(int log2Q) { return 4LL * kWave << log2Q; }
 
+// Tuning overrides of the automatic decomposition choices (measurement and
+// tests), process-wide, set through bb_set_tuning; -1 means automatic.
+enum TuneKey : int {
+    kTuneMaxChunk = 0,       // rows per lane: power of two 4 .. 128
+    kTuneWavesPerSystem,     // split-group width 1, 2, 4 or 8 where valid
+    kTuneWavesPerBlock,      // waves per workgroup of unsplit sweeps: 1, 2 or 4
+    kTuneLockstep,           // 0 / 1: workgroup barrier per persistent iteration
+    kTuneChUniform,          // 0: no scalar-coefficient stepper kernel
+    kTuneGridLinear,         // 0 / 1: persistent or one-workgroup-per-group grids
+    kTuneCount
+};
+int64_t tuning(TuneKey key);   // api.cpp
+
 struct CyclicQ {
     double q[2][4];   // K x 2K, uses q[0][0..1] for K = 1
     double u1_nm2;    // -u1 of row n-2 (x_{n-2} = y_{n-2} - u1 y_{n-1} at the last chunk)

@@ -276,7 +276,7 @@ constexpr size_t split_step_lds(int QL, int R)
 // LDS kernel with one wave per group.  The scalar kernel's grid follows
 // g.linear (it stages no table, so one workgroup per group costs nothing);
 // the LDS kernels stage the table once per workgroup and stay persistent
-// unless BANDBATCH_GRID_LINEAR asks otherwise.  TRAJ: every step's state, see
+// unless tuning grid_linear asks otherwise.  TRAJ: every step's state, see
 // step_kernel.
 template <class Rhs, int K, bool CYC, bool STATS = false, bool TRAJ = false>
 hipError_t launch_stepper(const double *table, int64_t table_elems, const CyclicQ &q,

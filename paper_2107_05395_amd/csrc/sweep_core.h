@@ -16,8 +16,6 @@
 // from LDS (staged once per workgroup) or through the scalar cache.
 #pragma once
 
-#include <cstdlib>
-
 #include "internal.h"
 
 namespace bb {
@@ -572,13 +570,9 @@ int cu_count()
 // Persistent-style launch: as many workgroups as can be resident at once
 // (rounded to a multiple of the 8 XCDs), each looping over groups of systems.
 // split_waves > 0: a split group of that many waves is the whole workgroup.
-// BANDBATCH_GRID_LINEAR=1: non-persistent grids for the kernels launched
-// through launch_grid_split (tuning); the host sets SweepGeom::linear to match.
-inline bool grid_linear()
-{
-    const char *env = std::getenv("BANDBATCH_GRID_LINEAR");
-    return env && std::atoi(env) != 0;
-}
+// Tuning grid_linear = 1: non-persistent grids for the kernels launched
+// through launch_grid_split; the host sets SweepGeom::linear to match.
+inline bool grid_linear() { return tuning(kTuneGridLinear) == 1; }
 
 // linear: one workgroup per block of groups (the kernel's SweepGeom::linear
 // must be set); otherwise a persistent grid of at most one wave of resident
@@ -593,12 +587,9 @@ hipError_t launch_grid_mode(void (*kern)(KArgs...), size_t lds, int64_t groups, 
         if (e != hipSuccess) return e;
     }
     // waves per workgroup: the workgroup is the unit that moves in step (see
-    // begin_block); BANDBATCH_WAVES_PER_BLOCK (1, 2 or 4) overrides (tuning)
+    // begin_block); tuning waves_per_block (1, 2 or 4) overrides
     int waves_per_block = kBlockThreads / kWave;
-    if (const char *env = std::getenv("BANDBATCH_WAVES_PER_BLOCK")) {
-        const int w = std::atoi(env);
-        if (w == 1 || w == 2 || w == 4) waves_per_block = w;
-    }
+    if (tuning(kTuneWavesPerBlock) > 0) waves_per_block = (int)tuning(kTuneWavesPerBlock);
     int groups_per_block = waves_per_block;
     if (split_waves > 0) {
         waves_per_block = split_waves;

@@ -58,8 +58,8 @@ hipError_t sweep_c(const void *table, int64_t table_elems, const CyclicQ &q, con
                    const void *in, void *out, hipStream_t stream)
 {
     if (g.log2Q > 0) {
-        // split groups: 64 or 128 rows per lane only
-        if constexpr (C >= 64) {
+        // split groups: 32, 64 or 128 rows per lane
+        if constexpr (C >= 32) {
             if (g.log2Q > max_log2q(C, false) || g.log2Q > g.log2P) return hipErrorInvalidValue;
             if (g.log2Q == 1) return sweep_split<T, K, CYC, C, 1>(table, table_elems, q, g, in, out, stream);
             if (g.log2Q == 2) return sweep_split<T, K, CYC, C, 2>(table, table_elems, q, g, in, out, stream);

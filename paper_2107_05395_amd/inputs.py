@@ -122,6 +122,18 @@ WORKLOADS = {
     "ch_forced_flowmap_v05": dict(kind="ch_forced", n=512, length=2.0 * math.pi, grid=768,
                                   v=0.5, k=1.0, f0=(0.0, 2.0), mean=(0.0, 1.5), gamma=0.01,
                                   T=50.0, seed=SEED_BASE + 9),
+    # Section 5.2 convergence study: C(x, 0) = eps cos(5x), eps = 1e-6,
+    # L = 2 pi, gamma = 0.01, dt = 0.1 dx, one run per N = 128 .. 8192 and
+    # the N = 16384 reference of E_8192; every N stops at the same time,
+    # T = 204 dt_128 (about 1.0014, after the mode has grown to saturation),
+    # i.e. 204 N / 128 steps
+    "ch_convergence_1d": dict(kind="ch_convergence", ns=(128, 256, 512, 1024, 2048, 4096, 8192),
+                              length=2.0 * math.pi, gamma=0.01, eps=1e-6, mode=5, steps128=204),
+    # long systems (beyond one launch's on-chip limit), small batches where
+    # the paper hands the work to the CPU, and one large batch
+    "long_small_batch": dict(kind="long", ns=(4096, 8192, 16384), ms=(1, 8, 64),
+                             seed=SEED_BASE + 10),
+    "long_tri_n8192_m65536": dict(kind="long", ns=(8192,), ms=(1 << 16,), seed=SEED_BASE + 11),
     # Crank-Nicolson time stepping on the grid of the paper's benchmark tables
     # (1000 steps; n = 64, 256, 1024; m = 2^6, 2^12, 2^16); the step size is
     # not printed; sigma = 1 is taken here (it does not change the work)

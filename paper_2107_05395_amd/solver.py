@@ -211,6 +211,28 @@ class Factor:
                                    int(steps), _stream_ptr(c)))
         return out
 
+    @property
+    def long(self) -> bool:
+        """True when n is above what one launch holds on chip (tri 2048,
+        penta 1024): solves go through three launches, out of place, and the
+        Cahn-Hilliard step takes one step per call."""
+        return self.n > (2048 if self.nbands == 3 else 1024)
+
+    def ch_run(self, c: torch.Tensor, alpha: float, steps: int) -> torch.Tensor:
+        """`steps` Cahn-Hilliard steps from c (left unchanged) into a new
+        tensor: one fused call, or for long systems one call per step
+        alternating between two buffers (the step of a long system is out of
+        place)."""
+        if not self.long:
+            return self.ch_step(c, alpha, steps=steps)
+        a, b = torch.empty_like(c), torch.empty_like(c)
+        src = c
+        for s in range(int(steps)):
+            dst = a if s % 2 == 0 else b
+            self.ch_step(src, alpha, steps=1, out=dst)
+            src = dst
+        return src if steps > 0 else c.clone()
+
     def ch_step_stats(self, c: torch.Tensor, alpha: float, steps: int, every: int = 1,
                       out: torch.Tensor | None = None):
         """Cahn-Hilliard steps plus the ensemble-mean typical domain size
@@ -295,6 +317,38 @@ class Factor:
         return traj
 
 
+    def adjoint_trajectory(self, g: torch.Tensor, steps: int) -> torch.Tensor:
+        """lam_{s+1} = A^{-T} lam_s from lam_0 = g for s < steps, as a
+        (steps, n, m) tensor (bb_adjoint_trajectory): the adjoints of a
+        rollout of implicit steps, with the factor's own transposed solve."""
+        m, ld = _batch_view(g, self.n, torch.float64, "g")
+        if steps < 1:
+            raise ValueError("steps must be >= 1")
+        traj = torch.empty((steps, self.n, ld), dtype=torch.float64, device=g.device)[:, :, :m]
+        with torch.cuda.device(g.device):
+            check(lib().bb_adjoint_trajectory(self._handle, ctypes.c_void_p(g.data_ptr()),
+                                              ctypes.c_void_p(traj.data_ptr()), m, ld, int(steps),
+                                              _stream_ptr(g)))
+        return traj
+
+
+TUNING_NAMES = ("max_chunk", "waves_per_system", "waves_per_block", "lockstep", "ch_uniform",
+                "grid_linear")
+
+
+def set_tuning(name: str, value: int | None) -> None:
+    """Process-wide override of a decomposition choice (bb_set_tuning); None
+    restores the automatic choice."""
+    check(lib().bb_set_tuning(name.encode(), -1 if value is None else int(value)))
+
+
+def get_tuning(name: str) -> int | None:
+    v = lib().bb_get_tuning(name.encode())
+    if v == -2:
+        raise ValueError("unknown tuning name %r" % name)
+    return None if v == -1 else int(v)
+
+
 def mse_loss_grad(u: torch.Tensor, target: torch.Tensor, grad: torch.Tensor | None = None):
     """(loss as a 0-d device tensor, dloss/du) for loss = mean((u - target)^2)."""
     n = u.shape[0]
@@ -333,4 +387,5 @@ def max_n() -> int:
     return int(lib().bb_max_n())
 
 
-__all__ = ["Factor", "BandBatchError", "mse_loss_grad", "copy_tiles", "max_n", "KINDS"]
+__all__ = ["Factor", "BandBatchError", "mse_loss_grad", "copy_tiles", "max_n", "KINDS",
+           "set_tuning", "get_tuning"]

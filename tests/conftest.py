@@ -25,3 +25,24 @@ def oracle():
     import oracle as o
     o.build()
     return o
+
+
+class _Tuning:
+    """Library tuning overrides for one test (bb_set_tuning); every setting is
+    restored to automatic when the test ends."""
+
+    def set(self, name, value):
+        from paper_2107_05395_amd.solver import set_tuning
+        set_tuning(name, None if value is None else int(value))
+
+    def reset(self):
+        from paper_2107_05395_amd.solver import TUNING_NAMES, set_tuning
+        for n in TUNING_NAMES:
+            set_tuning(n, None)
+
+
+@pytest.fixture
+def tuning():
+    t = _Tuning()
+    yield t
+    t.reset()

@@ -230,3 +230,19 @@ def test_cahn_hilliard_factor_coefficients(L):
     assert L.bb_factor_ch(64, 1.0, 0.0, 1e-3, ctypes.byref(h), None, None) == -1       # gamma <= 0
     assert L.bb_factor_ch(64, 1.0, 0.01, float("nan"), ctypes.byref(h), None, None) == -1
     assert L.bb_factor_ch(64, 1.0, 0.01, 1e-3, None, None, None) == -1
+
+
+def test_tuning_settings(L):
+    """bb_set_tuning / bb_get_tuning: known names and valid values only, -1
+    restores the automatic choice; host only."""
+    for name, good, bad in [(b"max_chunk", 32, 48), (b"waves_per_system", 4, 3),
+                            (b"waves_per_block", 2, 8), (b"lockstep", 0, 2),
+                            (b"ch_uniform", 0, 5), (b"grid_linear", 1, -3)]:
+        assert L.bb_get_tuning(name) == -1
+        assert L.bb_set_tuning(name, good) == 0 and L.bb_get_tuning(name) == good
+        assert L.bb_set_tuning(name, bad) == -1 and L.bb_get_tuning(name) == good
+        assert L.bb_set_tuning(name, -1) == 0 and L.bb_get_tuning(name) == -1
+    assert L.bb_set_tuning(b"no_such_knob", 1) == -1
+    assert b"unknown" in L.bb_last_error_message()
+    assert L.bb_get_tuning(b"no_such_knob") == -2
+    assert L.bb_set_tuning(None, 1) == -1

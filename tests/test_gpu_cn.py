@@ -55,10 +55,10 @@ def test_cn_steps_match_oracle(kind, cyclic, n):
 
 @pytest.mark.parametrize("kind", ["tri", "penta"])
 @pytest.mark.parametrize("chunk", ["4", "8", "16", "32"])
-def test_cn_chunk_sizes_match_oracle(kind, chunk, monkeypatch):
+def test_cn_chunk_sizes_match_oracle(kind, chunk, tuning):
     """Every chunk size the stepper is built for, full (n = 256) and ragged
     (n = 250) decompositions, against the oracle."""
-    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", chunk)
+    tuning.set("max_chunk", chunk)
     for n in (256, 250):
         bands, w = _problem(kind, n, 1.3)
         f = _factor(kind, bands, True)
@@ -70,7 +70,7 @@ def test_cn_chunk_sizes_match_oracle(kind, chunk, monkeypatch):
 @pytest.mark.parametrize("kind,n", [("tri", 64), ("tri", 256), ("tri", 512), ("tri", 1024),
                                     ("tri", 2048), ("penta", 64), ("penta", 256), ("penta", 512),
                                     ("penta", 1024)])
-def test_cn_kernel_variants_agree_bitwise(kind, n, monkeypatch):
+def test_cn_kernel_variants_agree_bitwise(kind, n, tuning):
     """One chunk per wave with scalar coefficients, a group split over several
     waves with the table in LDS, and one wave per group with the table in LDS
     do the same arithmetic in the same order: bitwise equal results, at a
@@ -87,23 +87,23 @@ def test_cn_kernel_variants_agree_bitwise(kind, n, monkeypatch):
     cols = np.r_[np.arange(0, m, 997), m - 5:m]
     ref = oracle.cn_step(bands, w, np.ascontiguousarray(c0h[:, cols]), steps=steps)
     assert rel_err(a[:, cols], ref) < 1e-12
-    monkeypatch.setenv("BANDBATCH_CH_UNIFORM", "0")
+    tuning.set("ch_uniform", "0")
     b = host(f.cn_step(c0, w, steps=steps))
     assert np.array_equal(a, b)
-    monkeypatch.setenv("BANDBATCH_WAVES_PER_SYSTEM", "1")
+    tuning.set("waves_per_system", "1")
     b = host(f.cn_step(c0, w, steps=steps))
     assert np.array_equal(a, b)
     for q in ("2", "4", "8"):
         if (1 << {"2": 1, "4": 2, "8": 3}[q]) <= n // 64:
-            monkeypatch.setenv("BANDBATCH_WAVES_PER_SYSTEM", q)
+            tuning.set("waves_per_system", q)
             assert np.array_equal(a, host(f.cn_step(c0, w, steps=steps))), q
 
 
 @pytest.mark.parametrize("kind", ["tri", "penta"])
-def test_cn_split_groups_with_32_row_chunks(kind, monkeypatch):
+def test_cn_split_groups_with_32_row_chunks(kind, tuning):
     """32-row chunks split over 2, 4 and 8 waves (LDS table) equal one wave per
     group, bitwise, and match the oracle."""
-    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", "32")
+    tuning.set("max_chunk", "32")
     n, m = 1024, 5000
     bands, w = _problem(kind, n, 1.1)
     f = _factor(kind, bands, True)
@@ -112,7 +112,7 @@ def test_cn_split_groups_with_32_row_chunks(kind, monkeypatch):
     a = host(f.cn_step(c0, w, steps=4))
     assert rel_err(a, oracle.cn_step(bands, w, c0h, steps=4)) < 1e-12
     for q in ("1", "2", "4", "8"):
-        monkeypatch.setenv("BANDBATCH_WAVES_PER_SYSTEM", q)
+        tuning.set("waves_per_system", q)
         assert np.array_equal(a, host(f.cn_step(c0, w, steps=4))), q
 
 
@@ -170,7 +170,7 @@ def test_cn_rejects_wrong_stencil_length():
 
 @pytest.mark.parametrize("kind,n", [("tri", 64), ("tri", 128), ("tri", 256), ("penta", 64),
                                     ("penta", 256)])
-def test_cn_short_chunk_scalar_kernel_matches_lds(kind, n, monkeypatch):
+def test_cn_short_chunk_scalar_kernel_matches_lds(kind, n, tuning):
     """Small batches take 16- or 32-row chunks; when they tile n into at most
     eight the scalar-coefficient kernel runs them: bitwise what the LDS
     kernel gives, and the oracle's result."""
@@ -183,7 +183,7 @@ def test_cn_short_chunk_scalar_kernel_matches_lds(kind, n, monkeypatch):
     assert pl["scalar"] and pl["chunk"] in (16, 32), pl
     a = host(f.cn_step(c0, w, steps=7))
     assert rel_err(a, oracle.cn_step(bands, w, c0h, steps=7)) < 1e-12
-    monkeypatch.setenv("BANDBATCH_CH_UNIFORM", "0")
+    tuning.set("ch_uniform", "0")
     assert not f.plan(m, stepper=True)["scalar"]
     assert np.array_equal(a, host(f.cn_step(c0, w, steps=7)))
 
@@ -241,7 +241,7 @@ def test_cn_trajectory_strided_and_identity_stencil():
 
 
 @pytest.mark.parametrize("kind,n,m", [("tri", 256, 5000), ("penta", 512, 3000), ("tri", 1024, 3000)])
-def test_cn_grid_shapes_agree_bitwise(kind, n, m, monkeypatch):
+def test_cn_grid_shapes_agree_bitwise(kind, n, m, tuning):
     """The scalar-coefficient stepper runs one workgroup per group by
     default, the LDS kernels a persistent grid; forcing either grid shape
     everywhere changes which workgroup runs a group, never its arithmetic."""
@@ -250,6 +250,29 @@ def test_cn_grid_shapes_agree_bitwise(kind, n, m, monkeypatch):
     c0 = dev(inputs.uniform_batch(n, m, seed=97))
     ref = host(f.cn_step(c0, w, steps=4))
     for v in ("0", "1"):
-        monkeypatch.setenv("BANDBATCH_GRID_LINEAR", v)
+        tuning.set("grid_linear", v)
         assert np.array_equal(host(f.cn_step(c0, w, steps=4)), ref), v
         assert np.array_equal(host(f.cn_trajectory(c0, w, 4)[-1]), ref), v
+
+
+@pytest.mark.parametrize("kind,cyclic,n,m", [("tri", False, 1024, 3000), ("tri", True, 512, 700),
+                                             ("penta", False, 1024, 2000), ("penta", True, 256, 5000),
+                                             ("tri", False, 64, 70000), ("penta", True, 7, 33)])
+def test_adjoint_trajectory_is_repeated_transposed_solves(kind, cyclic, n, m):
+    """bb_adjoint_trajectory: lam_{s+1} = A^{-T} lam_s with the factor's own
+    transposed solve, every state against the oracle's transposed solves
+    (row-dependent, non-symmetric bands)."""
+    say("adjoint trajectory", kind, cyclic, n, m)
+    from paper_2107_05395_amd import Factor
+    bands = (inputs.random_dominant_tri(n, seed=n) if kind == "tri"
+             else inputs.random_dominant_penta(n, seed=n))
+    f = Factor.tri(*bands, cyclic=cyclic) if kind == "tri" else Factor.penta(*bands, cyclic=cyclic)
+    gh = inputs.uniform_batch(n, m, seed=7 * n + m)
+    steps = 5
+    traj = f.adjoint_trajectory(dev(gh), steps)
+    assert traj.shape == (steps, n, m)
+    lam = gh
+    adj = oracle.tri_adjoint if kind == "tri" else oracle.penta_adjoint
+    for s in range(steps):
+        lam = adj(*bands, lam, cyclic=cyclic)
+        assert rel_err(host(traj[s]), lam) < 1e-12, s

@@ -75,23 +75,23 @@ def test_forced_steps_match_oracle(n, m):
 
 
 @pytest.mark.parametrize("n", [64, 256, 512, 1024])
-def test_forced_kernel_variants_agree_bitwise(n, monkeypatch):
+def test_forced_kernel_variants_agree_bitwise(n, tuning):
     """Scalar coefficients with one chunk per wave, the LDS split group and
     the LDS one-wave group do the same arithmetic (64-row chunks forced)."""
-    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", "64")
+    tuning.set("max_chunk", "64")
     m = 3000
     f, c0, gpu, ref = _setup(n, m, seed=7 * n)
     t = dev(c0)
     a = host(_gpu_steps(f, t, gpu, 4))
-    monkeypatch.setenv("BANDBATCH_CH_UNIFORM", "0")
+    tuning.set("ch_uniform", "0")
     assert np.array_equal(a, host(_gpu_steps(f, t, gpu, 4)))
-    monkeypatch.setenv("BANDBATCH_WAVES_PER_SYSTEM", "1")
+    tuning.set("waves_per_system", "1")
     assert np.array_equal(a, host(_gpu_steps(f, t, gpu, 4)))
 
 
 @pytest.mark.parametrize("chunk", ["4", "8", "16", "32"])
-def test_forced_chunk_sizes_match_oracle(chunk, monkeypatch):
-    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", chunk)
+def test_forced_chunk_sizes_match_oracle(chunk, tuning):
+    tuning.set("max_chunk", chunk)
     for n in (256, 250):
         f, c0, gpu, ref = _setup(n, 130, seed=11 + n)
         want = _oracle_steps(c0, ref, 3)

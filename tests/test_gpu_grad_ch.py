@@ -168,17 +168,17 @@ def test_ch_in_place():
 
 
 @pytest.mark.parametrize("n", [128, 256, 512])
-def test_ch_uniform_chunks_match_lds_kernel(n, monkeypatch):
+def test_ch_uniform_chunks_match_lds_kernel(n, tuning):
     """With one 64-row chunk per wave the CH kernel reads its coefficients
     through the scalar cache; the arithmetic is the same as the LDS kernel's,
     so the two agree bitwise, and both match the oracle."""
-    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", "64")   # a small batch would take shorter chunks
+    tuning.set("max_chunk", "64")   # a small batch would take shorter chunks
     f, sigma, alpha = _ch(n)
     m, steps = 1000, 7
     c0 = inputs.uniform_batch(n, m, seed=23 + n, lo=-0.1, hi=0.1)
     ref = oracle.ch_step(c0, sigma, alpha, steps=steps)
     uni = host(f.ch_step(dev(c0), f.alpha, steps=steps))
-    monkeypatch.setenv("BANDBATCH_CH_UNIFORM", "0")
+    tuning.set("ch_uniform", "0")
     lds = host(f.ch_step(dev(c0), f.alpha, steps=steps))
     say("ch uniform vs lds", n, float(np.max(np.abs(uni - lds))), rel_err(uni, ref))
     assert rel_err(uni, ref) < fp64_tol(1.0 + 16.0 * sigma, steps)
@@ -217,7 +217,7 @@ def test_ch_domain_size_statistic_matches_oracle(n, m):
     assert np.array_equal(host(lbar2), lb)
 
 
-def test_ch_domain_size_statistic_kernel_variants(monkeypatch):
+def test_ch_domain_size_statistic_kernel_variants(tuning):
     """Scalar-coefficient, LDS split and LDS one-wave kernels group the runs
     differently, so their sums round differently, but each matches the
     oracle (130 samples, one per step)."""
@@ -226,11 +226,11 @@ def test_ch_domain_size_statistic_kernel_variants(monkeypatch):
     c0 = inputs.uniform_batch(n, m, seed=95, lo=-0.5, hi=0.5)
     ref, _ = oracle.ch_coarsening(c0, sigma, alpha, steps, every)
     t = dev(c0)
-    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", "64")
-    for env in ({}, {"BANDBATCH_CH_UNIFORM": "0"},
-                {"BANDBATCH_CH_UNIFORM": "0", "BANDBATCH_WAVES_PER_SYSTEM": "1"}):
+    tuning.set("max_chunk", "64")
+    for env in ({}, {"ch_uniform": "0"},
+                {"ch_uniform": "0", "waves_per_system": "1"}):
         for k, v in env.items():
-            monkeypatch.setenv(k, v)
+            tuning.set(k, v)
         _, lbar = f.ch_step_stats(t, f.alpha, steps=steps, every=every)
         err = float(np.max(np.abs(host(lbar) - ref) / (ref - 1.0)))
         tol = lbar_tol(1.0 + 16.0 * sigma, steps, c0, ref)
@@ -247,7 +247,7 @@ def test_ch_domain_size_statistic_without_samples():
     assert rel_err(host(out), oracle.ch_step(c0, sigma, alpha, steps=2)) < 1e-12
 
 
-def test_ch_grid_shapes_agree_bitwise(monkeypatch):
+def test_ch_grid_shapes_agree_bitwise(tuning):
     """The Cahn-Hilliard steps and the domain-size statistic are the same
     bitwise on the default grids (one workgroup per group for the plain
     scalar-kernel steps, persistent with the statistic) and on either grid
@@ -260,7 +260,7 @@ def test_ch_grid_shapes_agree_bitwise(monkeypatch):
     ref_out, ref_lbar = host(out), host(lbar)
     assert np.array_equal(host(f.ch_step(c0, f.alpha, steps=12)), ref_out)
     for v in ("0", "1"):
-        monkeypatch.setenv("BANDBATCH_GRID_LINEAR", v)
+        tuning.set("grid_linear", v)
         out, lbar = f.ch_step_stats(c0, f.alpha, steps=12, every=3)
         assert np.array_equal(host(out), ref_out) and np.array_equal(host(lbar), ref_lbar), v
         assert np.array_equal(host(f.ch_step(c0, f.alpha, steps=12)), ref_out), v

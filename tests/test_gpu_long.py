@@ -60,8 +60,8 @@ def test_long_solves_match_oracle(kind, n, m, cyclic, adjoint):
 
 @pytest.mark.parametrize("chunk", ["16", "32", "64"])
 @pytest.mark.parametrize("kind,n", [("tri", 4097), ("penta", 2050), ("penta", 2048)])
-def test_long_chunk_sizes(chunk, kind, n, monkeypatch):
-    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", chunk)
+def test_long_chunk_sizes(chunk, kind, n, tuning):
+    tuning.set("max_chunk", chunk)
     for cyclic in (False, True):
         f, bands = _make(kind, n, seed=n + int(chunk), cyclic=cyclic)
         assert f.plan(100)["chunk"] == int(chunk)

@@ -214,14 +214,14 @@ def test_factor_on_the_oracle_matrices_of_every_config():
                                            ("penta", 600, True), ("penta", 1000, False),
                                            ("tri", 1536, True)])
 @pytest.mark.parametrize("rows", [64, 128, 32])
-def test_split_groups_match_single_wave_groups(kind, n, cyclic, rows, monkeypatch):
+def test_split_groups_match_single_wave_groups(kind, n, cyclic, rows, tuning):
     """A system group spread over 2, 4 or 8 waves (boundary states exchanged
     through LDS) computes exactly what a one-wave group computes: same
     operations in the same order, so the results are bitwise equal.  Solve,
     adjoint, plain FP32 and FP32 + refinement; 64 rows per lane (the default
     for large batches), 128 rows and 32 rows (refinement groups of up to 8
     waves; a width a kernel cannot run falls back to the automatic one)."""
-    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", str(rows))
+    tuning.set("max_chunk", str(rows))
     f, bands = make(kind, n, seed=17 * n, cyclic=cyclic)
     m = 1000                                   # not a multiple of any group width
     rhs = inputs.uniform_batch(n, m, seed=6000 + n)
@@ -229,7 +229,7 @@ def test_split_groups_match_single_wave_groups(kind, n, cyclic, rows, monkeypatc
     t = dev(rhs)
     got = {}
     for q in (1, 2, 4, 8):
-        monkeypatch.setenv("BANDBATCH_WAVES_PER_SYSTEM", str(q))
+        tuning.set("waves_per_system", str(q))
         say("split", kind, n, cyclic, "waves per system", q)
         got[q] = host(f.solve(t))
         assert rel_err(got[q], ref) < F64_TOL
@@ -239,7 +239,7 @@ def test_split_groups_match_single_wave_groups(kind, n, cyclic, rows, monkeypatc
         assert rel_err(x32, ref) < F32_TOL
         got[("r", q)] = host(f.solve(t, precision="f32r"))
         assert rel_err(got[("r", q)], ref) < F32R_TOL
-    monkeypatch.setenv("BANDBATCH_WAVES_PER_SYSTEM", "2")
+    tuning.set("waves_per_system", "2")
     assert np.array_equal(host(f.solve(t, precision="f32r")), got[("r", 2)])   # repeatable
     for q in (2, 4):
         say("  max |f32r diff| q=1 vs q=%d" % q, np.max(np.abs(got[("r", 1)] - got[("r", q)])))
@@ -250,7 +250,7 @@ def test_split_groups_match_single_wave_groups(kind, n, cyclic, rows, monkeypatc
 
 @pytest.mark.parametrize("n,m,rows", [(256, 1024, 32), (64, 4096, 16), (1024, 64, 32),
                                       (2048, 256, 64)])
-def test_small_batches_take_short_chunks(n, m, rows, monkeypatch):
+def test_small_batches_take_short_chunks(n, m, rows, tuning):
     """With fewer than 2^16 lanes of 64-row chunks the solve takes the
     latency rule's chunk (the power of two >= 2 sqrt(n), at most 32, at most
     32 chunks per system): bitwise what forcing that chunk gives, and within
@@ -261,11 +261,11 @@ def test_small_batches_take_short_chunks(n, m, rows, monkeypatch):
     t = dev(rhs)
     auto = host(f.solve(t))
     assert rel_err(auto, oracle_solve("tri", bands, rhs, False)) < F64_TOL
-    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", str(rows))
+    tuning.set("max_chunk", str(rows))
     assert np.array_equal(auto, host(f.solve(t)))
 
 
-def test_workgroup_shape_and_lockstep_do_not_change_results(monkeypatch):
+def test_workgroup_shape_and_lockstep_do_not_change_results(tuning):
     """Waves per workgroup and the lockstep barrier only change which waves run
     together, not the arithmetic: bitwise equal results (ragged n, so the
     groups are one wave each)."""
@@ -276,8 +276,8 @@ def test_workgroup_shape_and_lockstep_do_not_change_results(monkeypatch):
     outs = []
     for w in ("1", "2", "4"):
         for lock in ("0", "1"):
-            monkeypatch.setenv("BANDBATCH_WAVES_PER_BLOCK", w)
-            monkeypatch.setenv("BANDBATCH_LOCKSTEP", lock)
+            tuning.set("waves_per_block", w)
+            tuning.set("lockstep", lock)
             outs.append(host(f.solve(t)))
     assert rel_err(outs[0], oracle_solve("penta", bands, rhs, True)) < F64_TOL
     assert all(np.array_equal(o, outs[0]) for o in outs[1:])
@@ -315,13 +315,13 @@ def _hard(name, n, seed):
 @pytest.mark.parametrize("name,n", [("weak_tri", 2048), ("weak_penta", 1024),
                                     ("diffusion_r1000", 2048), ("hyperdiffusion_r1000", 1024)])
 @pytest.mark.parametrize("cyclic", [False, True])
-def test_hard_matrices(name, n, cyclic, monkeypatch):
+def test_hard_matrices(name, n, cyclic, tuning):
     """64-row chunks (the decomposition whose chunk-transfer weights decay
     slowest on these matrices), FP64 and FP32 + refinement.  Tolerances from
     the arithmetic: FP64 max(1e-12, 2 kappa u); one refinement step leaves
     about (kappa u32)^2 + kappa u of the first solve's error, taken with a
     factor 4."""
-    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", "64")
+    tuning.set("max_chunk", "64")
     kind, bands = _hard(name, n, seed=n + 17)
     from paper_2107_05395_amd import Factor
     f = Factor.tri(*bands, cyclic=cyclic) if kind == "tri" else Factor.penta(*bands, cyclic=cyclic)

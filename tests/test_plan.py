@@ -70,14 +70,14 @@ def test_plan_rules(L, kind, n, m, what, prec, want):
     L.bb_factor_destroy(h)
 
 
-def test_plan_follows_tuning_variables(L, monkeypatch):
+def test_plan_follows_tuning_variables(L, tuning):
     h = _factor(L, "penta_cyclic", 256)
-    monkeypatch.setenv("BANDBATCH_MAX_CHUNK", "32")
+    tuning.set("max_chunk", "32")
     assert plan(L, h, 1 << 20, 0, 0)[:2] == (32, 8)
-    monkeypatch.delenv("BANDBATCH_MAX_CHUNK")
-    monkeypatch.setenv("BANDBATCH_CH_UNIFORM", "0")
+    tuning.set("max_chunk", None)
+    tuning.set("ch_uniform", "0")
     assert plan(L, h, 1 << 20, 1, 0) == (64, 4, 1, 0)
-    monkeypatch.setenv("BANDBATCH_WAVES_PER_SYSTEM", "2")
+    tuning.set("waves_per_system", "2")
     assert plan(L, h, 1 << 20, 1, 0) == (64, 4, 2, 0)
     L.bb_factor_destroy(h)
 
@@ -91,17 +91,3 @@ def test_plan_argument_errors(L):
     assert L.bb_plan(h, 10, 0, 9, ctypes.byref(out), None, None, None) == -1
     assert L.bb_plan(h, 10, 0, 0, None, None, None, None) == 0
     L.bb_factor_destroy(h)
-
-
-@pytest.mark.parametrize("nb,n", [(3, 9), (5, 11), (5, 5), (3, 2)])
-def test_rollout_transposed_bands(nb, n):
-    """The rollout steps its adjoints with a factor of A^T built from A's
-    bands: the bands it builds give the dense transpose of A's matrix
-    (the entries a non-periodic factor ignores are random here)."""
-    from paper_2107_05395_amd.autograd import _transposed_bands
-    from tests.dense import penta_dense, tri_dense
-    g = np.random.default_rng(nb * 100 + n)
-    bands = [g.uniform(-1, 1, n) for _ in range(nb)]
-    dense = tri_dense if nb == 3 else penta_dense
-    At = dense(*_transposed_bands(bands))
-    assert np.array_equal(At, dense(*bands).T)
