@@ -147,6 +147,14 @@ def bench_tri(args, torch):
     tt, _ = time_launches(lambda: copy_tiles(rhs, x), 10, 2, torch)
     assert torch.equal(x, rhs)
     tile_gbs = algo_bytes * 10 / tt / 1e9
+    # the same bytes moved with the sweep's own access pattern (bb_copy_rows:
+    # 64 rows of two 256-byte segments per wave, loads before stores): the
+    # ceiling of that pattern on this part
+    from paper_2107_05395_amd.solver import copy_rows
+    x.zero_()
+    rt, _ = time_launches(lambda: copy_rows(rhs, x), 10, 2, torch)
+    assert torch.equal(x, rhs)
+    rows_gbs = algo_bytes * 10 / rt / 1e9
     # small batches are bound by launch latency: the same solves replayed
     # from a HIP graph (captured after the eager calls uploaded the tables)
     graph = None
@@ -202,7 +210,10 @@ def bench_tri(args, torch):
                      "algorithmic_bytes_per_launch": algo_bytes,
                      "torch_copy_gbs": copy_gbs,
                      "tile_copy_gbs": tile_gbs,
-                     "frac_of_tile_copy": algo_bytes / per_launch / 1e9 / tile_gbs},
+                     "frac_of_tile_copy": algo_bytes / per_launch / 1e9 / tile_gbs,
+                     "pattern_copy_gbs": rows_gbs,
+                     "frac_of_pattern_copy": algo_bytes / per_launch / 1e9 / rows_gbs,
+                     "pattern_copy_frac_of_peak": rows_gbs / PEAK_HBM_GBS},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_tri(bands, n, seed + 100, args.cpu_seconds)
@@ -234,6 +245,18 @@ def bench_penta(args, torch):
     ref32 = oracle.penta_solve(*bands, rhs_host[:, cols].astype(np.float32).astype(np.float64))
     out["f32rhs"] = (t, rel_err_cols(x[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref32))
     del rhs32
+    # the same batch in arrays with a leading dimension of m + 32 (rows no
+    # longer a power of two apart; the library takes any ld >= m)
+    pad = 32
+    rp = torch.empty(n, m + pad, dtype=torch.float64, device="cuda")[:, :m]
+    xp = torch.empty(n, m + pad, dtype=torch.float64, device="cuda")[:, :m]
+    rp.copy_(rhs)
+    tpad, _ = time_launches(lambda: f.solve(rp, out=xp), args.steps, args.warmup, torch)
+    err_pad = rel_err_cols(xp[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref)
+    del rp, xp
+    from paper_2107_05395_amd.solver import copy_rows
+    rt, _ = time_launches(lambda: copy_rows(rhs, x), 10, 2, torch)
+    rows_gbs = algo_bytes * 10 / rt / 1e9
     k = args.steps
     per = out["f64"][0] / k
     line = {
@@ -248,9 +271,14 @@ def bench_penta(args, torch):
         "f32rhs": {"value": m * k / out["f32rhs"][0], "rel_err_vs_oracle": out["f32rhs"][1],
                    "ms_per_step": 1e3 * out["f32rhs"][0] / k,
                    "hbm_gbs_algorithmic": 12.0 * n * m * k / out["f32rhs"][0] / 1e9},
+        "padded_ld": {"ld": m + pad, "ms_per_step": 1e3 * tpad / k, "value": m * k / tpad,
+                      "hbm_gbs_algorithmic": algo_bytes * k / tpad / 1e9,
+                      "rel_err_vs_oracle": err_pad},
         "roofline": {"bound": "hbm", "achieved": algo_bytes / per / 1e9, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": algo_bytes / per / 1e9 / PEAK_HBM_GBS,
-                     "traffic": measured_traffic(args.workload, "f64", "sweep")},
+                     "traffic": measured_traffic(args.workload, "f64", "sweep"),
+                     "pattern_copy_gbs": rows_gbs,
+                     "frac_of_pattern_copy": algo_bytes / per / 1e9 / rows_gbs},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_penta(bands, n, seed + 100, args.cpu_seconds)

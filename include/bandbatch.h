@@ -328,6 +328,17 @@ bb_status bb_adjoint_trajectory(bb_factor f, const double *g, double *traj, int6
  * Errors: BB_ERR_ARG (NULL, alignment, size, overlap), BB_ERR_HIP. */
 bb_status bb_copy_tiles(const void *src, void *dst, int64_t bytes, void *stream);
 
+/* A measurement utility, not part of the method: copy the interleaved n x m
+ * double array src (element (i,k) at [i*ld + k]) to dst with the access
+ * pattern of the FP64 sweeps -- every wave moves 64 rows of two 32-system
+ * segments 64 rows apart (256 contiguous bytes per segment and row), all its
+ * loads issued before its stores -- the ceiling that pattern sets on a solve
+ * that reads b and writes x once.  n a multiple of 128, m of 32, ld >= m;
+ * src and dst must not overlap (n * ld doubles each).
+ * Errors: BB_ERR_ARG, BB_ERR_HIP. */
+bb_status bb_copy_rows(const double *src, double *dst, int64_t n, int64_t m, int64_t ld,
+                       void *stream);
+
 /* ---------------------------------------------------------------- loss
  * Mean-squared-error loss of a batch against a target and its gradient:
  *   grad[i,k] = 2 (u[i,k] - target[i,k]) / (n m),

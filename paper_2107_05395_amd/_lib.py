@@ -52,6 +52,7 @@ SIGNATURES = {
     "bb_cn_trajectory": (_S, [_FACTOR, _P, _P, _P, _I64, _I64, _I64, _P]),
     "bb_adjoint_trajectory": (_S, [_FACTOR, _P, _P, _I64, _I64, _I64, _P]),
     "bb_copy_tiles": (_S, [_P, _P, _I64, _P]),
+    "bb_copy_rows": (_S, [_P, _P, _I64, _I64, _I64, _P]),
     "bb_ch_stats_workspace_bytes": (ctypes.c_size_t, [_FACTOR, _I64, _I64]),
     "bb_ch_forced_step": (_S, [_FACTOR, _P, _P, _I64, _I64, ctypes.c_double, ctypes.c_double,
                                _P, _P, _P, _I64, _P]),

@@ -934,6 +934,23 @@ bb_status bb_adjoint_trajectory(bb_factor fh, const double *g, double *traj, int
     return cn_steps(fh, id, g, traj, m, ld, steps, true, stream, true);
 }
 
+bb_status bb_copy_rows(const double *src, double *dst, int64_t n, int64_t m, int64_t ld,
+                       void *stream)
+{
+    if (n < 0 || m < 0 || n % 128 || m % 32 || n > bb::kMaxNLong)
+        return fail(BB_ERR_ARG, "n must be a multiple of 128 and m of 32");
+    if (ld < m || ld > (int64_t(1) << 40)) return fail(BB_ERR_ARG, "ld out of range");
+    if (n == 0 || m == 0) { g_last_error.clear(); return BB_OK; }
+    if (!src || !dst) return fail(BB_ERR_ARG, "NULL pointer");
+    const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+    const uintptr_t bytes = (uintptr_t)(n * ld) * sizeof(double);
+    if (a < b + bytes && b < a + bytes) return fail(BB_ERR_ARG, "source and destination overlap");
+    hipError_t e = bb::launch_copy_rows(src, dst, (int)n, m, ld, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "copy launch");
+    g_last_error.clear();
+    return BB_OK;
+}
+
 bb_status bb_copy_tiles(const void *src, void *dst, int64_t bytes, void *stream)
 {
     if (bytes < 0 || bytes % 16) return fail(BB_ERR_ARG, "bytes must be a non-negative multiple of 16");

@@ -247,7 +247,46 @@ __global__ __launch_bounds__(256) void copy_tiles(const copy_vec *__restrict__ i
     }
 }
 
+// Streaming reference with the access pattern of the FP64 sweeps (not part
+// of the method): an interleaved n x m array copied by waves that each move
+// 64 rows of two 32-system segments 64 rows apart -- one 8-byte load per
+// lane per row, 256-byte segments, every load issued before any store --
+// like a 64-row-chunk sweep wave holding two chunks of 32 systems.
+constexpr int kRowsPerLane = 64, kSegSystems = 32;
+
+__global__ __launch_bounds__(256) void copy_rows(const double *__restrict__ in,
+                                                 double *__restrict__ out, int n, int64_t ld,
+                                                 int64_t m)
+{
+    const int lane = threadIdx.x % kWave;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t cblocks = m / kSegSystems;
+    const int64_t rblocks = n / (2 * kRowsPerLane);
+    if (wave >= cblocks * rblocks) return;
+    const int64_t cb = wave % cblocks;   // neighbouring waves: neighbouring segments
+    const int64_t rb = wave / cblocks;
+    const int64_t col = cb * kSegSystems + lane % kSegSystems;
+    const int64_t row0 = rb * 2 * kRowsPerLane + (lane / kSegSystems) * kRowsPerLane;
+    const double *p = in + row0 * ld + col;
+    double *q = out + row0 * ld + col;
+    double v[kRowsPerLane];
+#pragma unroll
+    for (int t = 0; t < kRowsPerLane; ++t) v[t] = p[(int64_t)t * ld];
+#pragma unroll
+    for (int t = 0; t < kRowsPerLane; ++t) q[(int64_t)t * ld] = v[t];
+}
+
 }  // namespace
+
+hipError_t launch_copy_rows(const double *src, double *dst, int n, int64_t m, int64_t ld,
+                            hipStream_t s)
+{
+    const int64_t waves = (m / kSegSystems) * (n / (2 * kRowsPerLane));
+    const int64_t blocks = (waves * kWave + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_rows, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n, ld, m);
+    return hipGetLastError();
+}
 
 hipError_t launch_copy_tiles(const void *src, void *dst, int64_t bytes, hipStream_t s)
 {

@@ -224,6 +224,11 @@ hipError_t launch_ch_long(const double *table, const CyclicQ &q, const LongGeom 
 // Copy of `bytes` (a multiple of 16) in contiguous 16 KB tiles per workgroup:
 // the streaming reference the sweeps' HBM rate is compared with.
 hipError_t launch_copy_tiles(const void *src, void *dst, int64_t bytes, hipStream_t stream);
+// Copy of an interleaved n x m double array (n a multiple of 128, m of 32)
+// with the access pattern of the 64-row-chunk sweeps: their own streaming
+// reference.
+hipError_t launch_copy_rows(const double *src, double *dst, int n, int64_t m, int64_t ld,
+                            hipStream_t stream);
 
 // The paper's thread-per-system mapping (Appendix A), kept as a measured
 // baseline design: forward intermediate written to and re-read from `x`.

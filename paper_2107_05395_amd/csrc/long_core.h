@@ -307,6 +307,237 @@ __global__ __launch_bounds__(256) void long_solve(const double *__restrict__ tab
     if (kval) store_chunk<double, C, true>(v, x, row0, lw.k, ld, g.n);
 }
 
+// ---------------------------------------------------------------- small batches
+// The scan with one wave per system: lane l owns full chunks
+// [l * cpl, (l + 1) * cpl), composes their affine maps, the wave scans the
+// 64 compositions (shuffles, log2(64) steps), and each lane re-walks its
+// chunks with its exact history / future.  Every scratch value is loaded at
+// once, so the chain over the chunks costs a few round trips instead of one
+// per block of chunks; used when the batch is too small for the
+// lane-per-system scan to fill the device.  Same scratch protocol and results
+// (up to the rounding of the composition order) as long_scan.
+constexpr int kWaveScanMax = 8;       // full chunks per lane at most
+constexpr int64_t kWaveScanBatch = 256;  // systems up to which the wave scan is used
+
+// y <- M y + e composed as maps: (M, c) after (Ma, ca) is (M Ma, M ca + c)
+template <int K>
+struct Affine {
+    double m[4], c[2];
+    __device__ __forceinline__ void identity()
+    {
+        m[0] = 1.0; m[1] = 0.0; m[2] = 0.0; m[3] = 1.0;
+        c[0] = 0.0; c[1] = 0.0;
+    }
+    // this <- this after a (apply a first)
+    __device__ __forceinline__ void after(const Affine &a)
+    {
+        if constexpr (K == 1) {
+            c[0] = fma(m[0], a.c[0], c[0]);
+            m[0] = m[0] * a.m[0];
+        } else {
+            const double c0 = fma(m[1], a.c[1], fma(m[0], a.c[0], c[0]));
+            const double c1 = fma(m[3], a.c[1], fma(m[2], a.c[0], c[1]));
+            const double m0 = fma(m[1], a.m[2], m[0] * a.m[0]);
+            const double m1 = fma(m[1], a.m[3], m[0] * a.m[1]);
+            const double m2 = fma(m[3], a.m[2], m[2] * a.m[0]);
+            const double m3 = fma(m[3], a.m[3], m[2] * a.m[1]);
+            c[0] = c0; c[1] = c1;
+            m[0] = m0; m[1] = m1; m[2] = m2; m[3] = m3;
+        }
+    }
+    // this <- (M, e) after this, M a table matrix (row-major K x K)
+    template <typename Ptr>
+    __device__ __forceinline__ void then(Ptr M, double e1, double e2)
+    {
+        Affine t;
+        t.m[0] = M[0];
+        if constexpr (K == 2) { t.m[1] = M[1]; t.m[2] = M[2]; t.m[3] = M[3]; }
+        t.c[0] = e1;
+        t.c[1] = e2;
+        t.after(*this);
+        *this = t;
+    }
+    __device__ __forceinline__ Affine shfl_from(int src) const
+    {
+        Affine r;
+        r.c[0] = __shfl(c[0], src, kWave);
+        r.m[0] = __shfl(m[0], src, kWave);
+        if constexpr (K == 2) {
+            r.c[1] = __shfl(c[1], src, kWave);
+            r.m[1] = __shfl(m[1], src, kWave);
+            r.m[2] = __shfl(m[2], src, kWave);
+            r.m[3] = __shfl(m[3], src, kWave);
+        } else {
+            r.c[1] = 0.0; r.m[1] = 0.0; r.m[2] = 0.0; r.m[3] = 1.0;
+        }
+        return r;
+    }
+};
+
+template <int K, int C, bool CYC, class Src>
+__global__ __launch_bounds__(64) void long_scan_wave(const double *__restrict__ table, CyclicQ cq,
+                                                     LongGeom g, Src src, double *x)
+{
+    using SP = FromScalar<double>;
+    const int64_t k = blockIdx.x;   // one system per workgroup of one wave
+    if (k >= g.m) return;
+    const int lane = threadIdx.x;
+    const int64_t ld = g.ld;
+    const int full = g.P - 1;
+    const int cpl = (full + kWave - 1) / kWave;   // <= kWaveScanMax (host checks)
+    const int j0 = lane * cpl;
+    const int nb = j0 < full ? (full - j0 < cpl ? full - j0 : cpl) : 0;
+    const int na = num_arrays(K, CYC);
+    const int64_t L = (int64_t)g.P * (C + 1);
+    const typename SP::ptr tabs = SP::base((typename SP::ptr)table);
+    const typename SP::ptr Mf = tabs + na * L;
+    const typename SP::ptr Mb = Mf + (int64_t)g.P * K * K;
+    const typename SP::ptr Gm = Mb + (int64_t)g.P * K * K;
+
+    // every scratch value of this lane's chunks, and the tail's rows
+    double e1[kWaveScanMax], e2[kWaveScanMax], o1[kWaveScanMax], o2[kWaveScanMax];
+#pragma unroll
+    for (int b = 0; b < kWaveScanMax; ++b) {
+        const int j = b < nb ? j0 + b : 0;
+        const double *p = x + (int64_t)j * C * ld + k;
+        e1[b] = b < nb ? p[0] : 0.0;
+        e2[b] = (K == 2 && b < nb) ? p[ld] : 0.0;
+        o1[b] = b < nb ? p[(int64_t)K * ld] : 0.0;
+        o2[b] = (K == 2 && b < nb) ? p[(int64_t)(K + 1) * ld] : 0.0;
+    }
+    const int trow0 = full * C;
+    const int nr = g.n - trow0;
+    double v[C];
+    src.template tail<C>(v, trow0, k, ld, g.n);
+
+    // forward: this lane's composition, the wave's exclusive scan, re-walk
+    Affine<K> a;
+    a.identity();
+    for (int b = 0; b < nb; ++b) {
+        const int j = j0 + b;
+        a.then(Mf + j * K * K, e1[b], e2[b]);
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const Affine<K> o = a.shfl_from(lane >= d ? lane - d : lane);
+        if (lane >= d) a.after(o);
+    }
+    const int prev = lane > 0 ? lane - 1 : 0;
+    double h1 = __shfl(a.c[0], prev, kWave), h2 = K == 2 ? __shfl(a.c[1], prev, kWave) : 0.0;
+    if (lane == 0) h1 = h2 = 0.0;
+    double hh1[kWaveScanMax], hh2[kWaveScanMax];
+#pragma unroll
+    for (int b = 0; b < kWaveScanMax; ++b) {
+        hh1[b] = h1;
+        hh2[b] = h2;
+        if (b < nb) {
+            double *p = x + (int64_t)(j0 + b) * C * ld + k;
+            p[0] = h1;
+            if constexpr (K == 2) p[ld] = h2;
+            const auto M = Mf + (j0 + b) * K * K;
+            affine<double, K>(M, h1, h2, e1[b], e2[b]);
+        }
+    }
+    // history of the tail: the inclusive composition of the last lane
+    const double th1 = __shfl(a.c[0], kWave - 1, kWave);
+    const double th2 = K == 2 ? __shfl(a.c[1], kWave - 1, kWave) : 0.0;
+
+    // the tail, as in long_scan (every lane, identical)
+    double yn1, yn2;
+    {
+        const auto tp = lane_table<double, K, C, CYC>(SP::base(tabs), g.P, full);
+        double y1 = th1, y2 = th2;
+        rows_up<C>([&](int t) {
+            double y = tp.s[t] * v[t];
+            if constexpr (K == 2) y = fma(tp.l2[t], y2, y);
+            y = fma(tp.l1[t], y1, y);
+            v[t] = y;
+            y2 = y1;
+            y1 = y;
+        });
+        yn1 = pick(v, nr - 1);
+        yn2 = nr >= 2 ? pick(v, nr - 2) : th1;
+        double x1 = 0.0, x2 = 0.0;
+        rows_down<C>([&](int t) {
+            double xx = v[t];
+            if constexpr (K == 2) xx = fma(tp.u2[t], x2, xx);
+            xx = fma(tp.u1[t], x1, xx);
+            x2 = x1;
+            x1 = xx;
+            v[t] = xx;
+        });
+    }
+
+    // backward: S_j, this lane's composition (last chunk first), the wave's
+    // exclusive scan from the top lane down, re-walk
+    double s1[kWaveScanMax], s2[kWaveScanMax];
+    Affine<K> bk;
+    bk.identity();
+#pragma unroll
+    for (int b = kWaveScanMax - 1; b >= 0; --b) {
+        s1[b] = 0.0;
+        s2[b] = 0.0;
+        if (b < nb) {
+            const auto G = Gm + (j0 + b) * K * K;
+            if constexpr (K == 1) {
+                s1[b] = fma(G[0], hh1[b], o1[b]);
+            } else {
+                s1[b] = fma(G[1], hh2[b], fma(G[0], hh1[b], o1[b]));
+                s2[b] = fma(G[3], hh2[b], fma(G[2], hh1[b], o2[b]));
+            }
+            bk.then(Mb + (j0 + b) * K * K, s1[b], s2[b]);
+        }
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const Affine<K> o = bk.shfl_from(lane + d < kWave ? lane + d : lane);
+        if (lane + d < kWave) bk.after(o);
+    }
+    // F entering this lane's last chunk: the lanes above applied to the
+    // tail's start state
+    const double ts1 = v[0], ts2 = K == 2 ? v[1] : 0.0;
+    const int nxt = lane + 1 < kWave ? lane + 1 : lane;
+    Affine<K> up = bk.shfl_from(nxt);
+    double f1 = ts1, f2 = ts2;
+    if (lane + 1 < kWave) {
+        if constexpr (K == 1) {
+            f1 = fma(up.m[0], ts1, up.c[0]);
+        } else {
+            f1 = fma(up.m[1], ts2, fma(up.m[0], ts1, up.c[0]));
+            f2 = fma(up.m[3], ts2, fma(up.m[2], ts1, up.c[1]));
+        }
+    }
+#pragma unroll
+    for (int b = kWaveScanMax - 1; b >= 0; --b) {
+        if (b < nb) {
+            double *p = x + (int64_t)(j0 + b) * C * ld + k;
+            p[(int64_t)K * ld] = f1;
+            if constexpr (K == 2) p[(int64_t)(K + 1) * ld] = f2;
+            affine<double, K>(Mb + (j0 + b) * K * K, f1, f2, s1[b], s2[b]);
+        }
+    }
+    // (w_0, w_1): the start state of chunk 0, on lane 0
+    double c0 = 0.0, c1 = 0.0;
+    if constexpr (CYC) {
+        const double w0 = __shfl(f1, 0, kWave), w1 = K == 2 ? __shfl(f2, 0, kWave) : 0.0;
+        const double rn1 = yn1;
+        const double rn2 = K == 2 ? fma(cq.u1_nm2, rn1, yn2) : 0.0;
+        correction_scalars<double, K>(cq, w0, w1, rn2, rn1, c0, c1);
+        for (int b = 0; b < nb; ++b) {
+            double *p = x + ((int64_t)(j0 + b) * C + 2 * K) * ld + k;
+            p[0] = c0;
+            if constexpr (K == 2) p[ld] = c1;
+        }
+        const auto tp = lane_table<double, K, C, CYC>(SP::base(tabs), g.P, full);
+        rows_up<C>([&](int t) {
+            double xx = fma(tp.z0[t], c0, v[t]);
+            if constexpr (K == 2) xx = fma(tp.z1[t], c1, xx);
+            v[t] = xx;
+        });
+    }
+    if (lane == 0) store_chunk<double, C, false>(v, x, trow0, k, ld, g.n);
+}
+
 template <int K, int C, bool CYC, class Src>
 hipError_t launch_long_c(const double *table, const CyclicQ &q, const LongGeom &g, const Src &src,
                          double *x, hipStream_t s)
@@ -319,6 +550,9 @@ hipError_t launch_long_c(const double *table, const CyclicQ &q, const LongGeom &
                        table, g, src, x);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // The wave-per-system scan (long_scan_wave) is not launched: its first
+    // GPU run faulted on a periodic pentadiagonal batch (n = 1025, m = 65)
+    // and the cause has not been found; every batch takes the lane scan.
     hipLaunchKernelGGL((long_scan<K, C, CYC, Src>), dim3((unsigned)sblocks), dim3(threads), 0, s,
                        table, q, g, src, x);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -383,6 +383,20 @@ def copy_tiles(src: torch.Tensor, dst: torch.Tensor) -> torch.Tensor:
     return dst
 
 
+def copy_rows(src: torch.Tensor, dst: torch.Tensor) -> torch.Tensor:
+    """dst <- src (n, m) float64 batches of the same strides through
+    bb_copy_rows: the copy with the FP64 sweeps' access pattern, their
+    streaming ceiling (n a multiple of 128, m of 32)."""
+    n = src.shape[0]
+    m, ld = _batch_view(src, n, torch.float64, "src")
+    if _batch_view(dst, n, torch.float64, "dst") != (m, ld):
+        raise ValueError("dst must match src in shape and strides")
+    with torch.cuda.device(src.device):
+        check(lib().bb_copy_rows(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                 n, m, ld, _stream_ptr(src)))
+    return dst
+
+
 def max_n() -> int:
     return int(lib().bb_max_n())
 

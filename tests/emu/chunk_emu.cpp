@@ -6,6 +6,7 @@
 // chunks, the forward and backward passes and the periodic correction.  A
 // CPU test compares the result with the oracle, so the table construction
 // and the decomposition are checked without a GPU.
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -246,6 +247,209 @@ extern "C" int emu_solve_long(int kind, const double *a, const double *b, const 
         std::vector<double> w(f + j * C, f + (j + 1) * C);
         fwd(w, j, H1, H2);
         bwd(w, j, G1, G2, C0, C1);
+        for (int t = 0; t < C; ++t) x[j * C + t] = w[t];
+    }
+    return 0;
+}
+
+// The small-batch scan of long systems (long_scan_wave): lane l composes the
+// affine maps of its full chunks, the 64 lanes scan the compositions
+// (Kogge-Stone, forward and from the top lane down), and each lane re-walks
+// its chunks; reduce and solve as in emu_solve_long.  Compared with the
+// oracle, this checks the composition order and the exclusive scans.
+namespace {
+struct Aff {
+    double m[4], c[2];
+};
+Aff aff_id() { return Aff{{1, 0, 0, 1}, {0, 0}}; }
+// r = x after a (apply a first)
+Aff aff_after(const Aff &x, const Aff &a, int K)
+{
+    Aff r;
+    if (K == 1) {
+        r = aff_id();
+        r.c[0] = x.m[0] * a.c[0] + x.c[0];
+        r.m[0] = x.m[0] * a.m[0];
+        return r;
+    }
+    r.c[0] = x.m[0] * a.c[0] + x.m[1] * a.c[1] + x.c[0];
+    r.c[1] = x.m[2] * a.c[0] + x.m[3] * a.c[1] + x.c[1];
+    r.m[0] = x.m[0] * a.m[0] + x.m[1] * a.m[2];
+    r.m[1] = x.m[0] * a.m[1] + x.m[1] * a.m[3];
+    r.m[2] = x.m[2] * a.m[0] + x.m[3] * a.m[2];
+    r.m[3] = x.m[2] * a.m[1] + x.m[3] * a.m[3];
+    return r;
+}
+Aff aff_of(const double *M, double e1, double e2, int K)
+{
+    Aff t = aff_id();
+    t.m[0] = M[0];
+    if (K == 2) { t.m[1] = M[1]; t.m[2] = M[2]; t.m[3] = M[3]; }
+    t.c[0] = e1;
+    t.c[1] = e2;
+    return t;
+}
+}  // namespace
+
+extern "C" int emu_solve_long_wave(int kind, const double *a, const double *b, const double *c,
+                                   const double *d, const double *e, int64_t n, int adjoint, int C,
+                                   const double *f, double *x)
+{
+    bb::Factor F;
+    std::string err;
+    const double *bands[5] = {a, b, c, d, e};
+    int st = bb::make_factor(kind, bands, n, F, err);
+    if (st) return st;
+    const int K = F.K, W = 64;
+    const int P = (int)((n + C - 1) / C);
+    const int full = P - 1;
+    const int cpl = (full + W - 1) / W;
+    if (P < 2 || C < 3 * K || cpl > 8) return -100;
+    const bb::Direction &dir = adjoint ? F.adjoint : F.primal;
+    const std::vector<double> tab = bb::build_table(dir, K, F.cyclic, n, C, P);
+    const int64_t L = (int64_t)P * (C + 1);
+    const int na = bb::num_arrays(K, F.cyclic);
+    auto arr = [&](int q, int j, int t) { return tab[(size_t)(q * L + (int64_t)j * (C + 1) + t)]; };
+    const double *Mf = tab.data() + na * L, *Mb = Mf + P * K * K, *G = Mb + P * K * K;
+    const int qE = 0, qS = K, qs = 2 * K, ql = 2 * K + 1, qu = 3 * K + 1, qz = 4 * K + 1;
+    // reduce
+    std::vector<double> e1(full), e2(full), o1(full), o2(full);
+    for (int j = 0; j < full; ++j) {
+        double s1 = 0, s2 = 0, t1 = 0, t2 = 0;
+        for (int t = 0; t < C; ++t) {
+            const double v = f[j * C + t];
+            s1 += arr(qE, j, t) * v;
+            t1 += arr(qS, j, t) * v;
+            if (K == 2) {
+                s2 += arr(qE + 1, j, t) * v;
+                t2 += arr(qS + 1, j, t) * v;
+            }
+        }
+        e1[j] = s1; e2[j] = s2; o1[j] = t1; o2[j] = t2;
+    }
+    auto lo = [&](int l) { return std::min(l * cpl, full); };
+    auto hi = [&](int l) { return std::min((l + 1) * cpl, full); };
+    // forward: compositions, inclusive scan, exclusive history per lane
+    std::vector<Aff> A(W);
+    for (int l = 0; l < W; ++l) {
+        A[l] = aff_id();
+        for (int j = lo(l); j < hi(l); ++j) A[l] = aff_after(aff_of(Mf + j * K * K, e1[j], e2[j], K), A[l], K);
+    }
+    for (int dd = 1; dd < W; dd <<= 1) {
+        std::vector<Aff> B = A;
+        for (int l = dd; l < W; ++l) B[l] = aff_after(A[l], A[l - dd], K);
+        A = B;
+    }
+    std::vector<double> H1(full), H2(full);
+    for (int l = 0; l < W; ++l) {
+        double h1 = l ? A[l - 1].c[0] : 0.0, h2 = l ? A[l - 1].c[1] : 0.0;
+        for (int j = lo(l); j < hi(l); ++j) {
+            H1[j] = h1; H2[j] = h2;
+            const double *M = Mf + j * K * K;
+            if (K == 1) {
+                h1 = M[0] * h1 + e1[j];
+            } else {
+                const double n1 = M[0] * h1 + M[1] * h2 + e1[j], n2 = M[2] * h1 + M[3] * h2 + e2[j];
+                h1 = n1; h2 = n2;
+            }
+        }
+    }
+    const double th1 = A[W - 1].c[0], th2 = A[W - 1].c[1];
+    // the tail
+    const int64_t tr0 = (int64_t)full * C;
+    const int nr = (int)(n - tr0);
+    std::vector<double> v(C, 0.0);
+    for (int t = 0; t < nr; ++t) v[t] = f[tr0 + t];
+    {
+        double y1 = th1, y2 = th2;
+        for (int t = 0; t < C; ++t) {
+            double y = arr(qs, full, t) * v[t];
+            if (K == 2) y += arr(ql + 1, full, t) * y2;
+            y += arr(ql, full, t) * y1;
+            v[t] = y; y2 = y1; y1 = y;
+        }
+    }
+    const double yn1 = v[nr - 1], yn2 = nr >= 2 ? v[nr - 2] : th1;
+    {
+        double x1 = 0, x2 = 0;
+        for (int t = C - 1; t >= 0; --t) {
+            double xx = v[t];
+            if (K == 2) xx += arr(qu + 1, full, t) * x2;
+            xx += arr(qu, full, t) * x1;
+            x2 = x1; x1 = xx; v[t] = xx;
+        }
+    }
+    // backward: S_j, compositions from the last chunk, scan from the top lane
+    std::vector<double> S1(full), S2(full);
+    for (int j = 0; j < full; ++j) {
+        const double *g = G + j * K * K;
+        S1[j] = o1[j] + g[0] * H1[j] + (K == 2 ? g[1] * H2[j] : 0.0);
+        S2[j] = K == 2 ? o2[j] + g[2] * H1[j] + g[3] * H2[j] : 0.0;
+    }
+    std::vector<Aff> U(W);
+    for (int l = 0; l < W; ++l) {
+        U[l] = aff_id();
+        for (int j = hi(l) - 1; j >= lo(l); --j) U[l] = aff_after(aff_of(Mb + j * K * K, S1[j], S2[j], K), U[l], K);
+    }
+    for (int dd = 1; dd < W; dd <<= 1) {
+        std::vector<Aff> B = U;
+        for (int l = 0; l + dd < W; ++l) B[l] = aff_after(U[l], U[l + dd], K);
+        U = B;
+    }
+    std::vector<double> F1(full), F2(full);
+    double w0 = 0, w1 = 0;
+    for (int l = 0; l < W; ++l) {
+        double f1 = v[0], f2 = K == 2 ? v[1] : 0.0;
+        if (l + 1 < W) {
+            const Aff &u = U[l + 1];
+            const double n1 = u.m[0] * v[0] + (K == 2 ? u.m[1] * v[1] : 0.0) + u.c[0];
+            const double n2 = K == 2 ? u.m[2] * v[0] + u.m[3] * v[1] + u.c[1] : 0.0;
+            f1 = n1; f2 = n2;
+        }
+        for (int j = hi(l) - 1; j >= lo(l); --j) {
+            F1[j] = f1; F2[j] = f2;
+            const double *M = Mb + j * K * K;
+            if (K == 1) {
+                f1 = M[0] * f1 + S1[j];
+            } else {
+                const double n1 = M[0] * f1 + M[1] * f2 + S1[j], n2 = M[2] * f1 + M[3] * f2 + S2[j];
+                f1 = n1; f2 = n2;
+            }
+        }
+        if (l == 0) { w0 = f1; w1 = f2; }
+    }
+    double c0 = 0, c1 = 0;
+    if (F.cyclic) {
+        const bb::CyclicQ &q = dir.cor.q;
+        const double rn1 = yn1, rn2 = K == 2 ? q.u1_nm2 * rn1 + yn2 : 0.0;
+        if (K == 1) {
+            c0 = q.q[0][0] * w0 + q.q[0][1] * rn1;
+        } else {
+            c0 = q.q[0][0] * w0 + q.q[0][1] * w1 + q.q[0][2] * rn2 + q.q[0][3] * rn1;
+            c1 = q.q[1][0] * w0 + q.q[1][1] * w1 + q.q[1][2] * rn2 + q.q[1][3] * rn1;
+        }
+        for (int t = 0; t < C; ++t) v[t] += arr(qz, full, t) * c0 + (K == 2 ? arr(qz + 1, full, t) * c1 : 0.0);
+    }
+    for (int t = 0; t < nr; ++t) x[tr0 + t] = v[t];
+    // solve the full chunks
+    for (int j = 0; j < full; ++j) {
+        std::vector<double> w(f + j * C, f + (j + 1) * C);
+        double y1 = H1[j], y2 = H2[j];
+        for (int t = 0; t < C; ++t) {
+            double y = arr(qs, j, t) * w[t];
+            if (K == 2) y += arr(ql + 1, j, t) * y2;
+            y += arr(ql, j, t) * y1;
+            w[t] = y; y2 = y1; y1 = y;
+        }
+        double g1 = F1[j], g2 = F2[j];
+        for (int t = C - 1; t >= 0; --t) {
+            double xx = w[t];
+            if (K == 2) xx += arr(qu + 1, j, t) * g2;
+            xx += arr(qu, j, t) * g1;
+            g2 = g1; g1 = xx;
+            if (F.cyclic) xx += arr(qz, j, t) * c0 + (K == 2 ? arr(qz + 1, j, t) * c1 : 0.0);
+            w[t] = xx;
+        }
         for (int t = 0; t < C; ++t) x[j * C + t] = w[t];
     }
     return 0;
