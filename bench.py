@@ -33,7 +33,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 KERNEL_SOURCES = ("sweep_core.h", "sweep_kernel.h", "sweep.hip", "sweep_f32.hip", "refine_kernel.h",
                   "refine.hip", "refine_f32rhs.hip", "stepper.h", "ch.hip", "ch_forced.hip",
-                  "cn_stencil.h", "cn_tri.hip", "cn_penta.hip", "internal.h")
+                  "cn_stencil.h", "cn_tri.hip", "cn_penta.hip", "long_core.h", "long_sweep.hip",
+                  "internal.h")
 # the device sources behind each kernel whose HBM traffic is recorded
 KERNEL_FAMILIES = {
     "sweep": ("sweep_core.h", "sweep_kernel.h", "sweep.hip", "internal.h"),
@@ -41,6 +42,7 @@ KERNEL_FAMILIES = {
     "stepper_cn": ("sweep_core.h", "stepper.h", "cn_stencil.h", "cn_tri.hip", "internal.h"),
     "stepper_ch": ("sweep_core.h", "stepper.h", "ch.hip", "internal.h"),
     "stepper_forced": ("sweep_core.h", "stepper.h", "ch_forced.hip", "internal.h"),
+    "long": ("sweep_core.h", "long_core.h", "long_sweep.hip", "internal.h"),
 }
 
 
@@ -751,9 +753,11 @@ def bench_adjoint(args, torch):
 def probe(torch):
     """One dispatch of each kernel of interest, for rocprofv3 counter runs:
     a plain copy of known size (4 GiB read + 4 GiB written), the library's
-    16 KB-tile copy of the same array, the FP64 and
-    FP32+refine sweeps and the thread-per-system design on the bench workload,
-    the FP64 pentadiagonal sweep on the hyperdiffusion workload, one launch
+    16 KB-tile copy of the same array, the FP64 and FP32+refine sweeps, the
+    thread-per-system design and the sweep-pattern copy on the bench
+    workload, the FP64 and FP32+refine pentadiagonal sweeps on the
+    hyperdiffusion workload, the three launches of a long tridiagonal solve
+    (n = 8192, m = 2^16), one launch
     of 10 fused Cahn-Hilliard steps on the n=256, m=2^20 ensemble, and one
     Crank-Nicolson diffusion step (n=1024, m=2^16, periodic)."""
     from paper_2107_05395_amd import Factor, inputs
@@ -771,12 +775,23 @@ def probe(torch):
         torch.cuda.synchronize()
     f.solve_thread_per_system(rhs, out=x)
     torch.cuda.synchronize()
+    from paper_2107_05395_amd.solver import copy_rows
+    copy_rows(rhs, x)
+    torch.cuda.synchronize()
     del rhs, x
     n, m = 1024, 1 << 18
     rhs = torch.rand(n, m, dtype=torch.float64, device="cuda")
     x = torch.empty_like(rhs)
     g = Factor.penta(*inputs.hyperdiffusion_penta_bands(n, 0.25))
-    g.solve(rhs, out=x)
+    for prec in ("f64", "f32r"):
+        g.solve(rhs, out=x, precision=prec)
+        torch.cuda.synchronize()
+    del rhs, x
+    # a long system: tri n = 8192, m = 2^16 (reduce, scan, solve)
+    n, m = 8192, 1 << 16
+    rhs = torch.rand(n, m, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(rhs)
+    Factor.tri(*inputs.diffusion_tri_bands(n, 1.0)).solve(rhs, out=x)
     torch.cuda.synchronize()
     del rhs, x
     n, m = 256, 1 << 20
@@ -922,7 +937,8 @@ def bench_long(args, torch):
                                "oracle_ms_per_solve": 1e3 * cpu_s,
                                "rel_err_vs_oracle": rel_err_cols(got, ref)})
                 del rhs, x
-    big = max(points, key=lambda p: p["n"] * p["m"])
+    # the largest tridiagonal point (the one whose counters are recorded)
+    big = max(points, key=lambda p: (p["n"] * p["m"], p["kind"] == "tri"))
     ach = big["hbm_gbs_algorithmic"]
     return {
         "metric": "systems solved/s", "value": big["m"] / (big["ms_per_solve"] / 1e3),
@@ -933,9 +949,11 @@ def bench_long(args, torch):
                    "matrices": "tri (-1, 3, -1); periodic penta (0.25, -1, 2.5, -1, 0.25)"},
         "points": points,
         "roofline": {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": ach / PEAK_HBM_GBS, "traffic": None,
+                     "frac": ach / PEAK_HBM_GBS,
+                     "traffic": measured_traffic(args.workload, "f64", "long"),
                      "note": "largest point (%s n=%d m=%d), algorithmic 16 B per row; the three "
-                             "launches move 24 B per row" % (big["kind"], big["n"], big["m"])},
+                             "launches move 24 B per row (traffic: bytes of all three)"
+                             % (big["kind"], big["n"], big["m"])},
         "cpu_baseline": {"value": big["m"] / (big["oracle_ms_per_solve"] / 1e3),
                          "unit": "systems/s", "cores": oracle.num_threads(), "kind": "oracle",
                          "sample": "oracle solves of %d sampled systems per point, scaled to m"
