@@ -814,21 +814,27 @@ def probe(torch):
 PAPER_TABLE3 = [(128, 0.0310, 3.7932), (256, 0.0022, 2.0376), (512, 5.45e-4, 2.0089),
                 (1024, 1.35e-4, 2.0022), (2048, 3.38e-5, 2.0005), (4096, 8.45e-6, 0.8947),
                 (8192, 4.54e-6, None)]
+# the forced scheme's study (k = 1, v = 0.5, f0 = 1), as printed
+PAPER_TABLE4 = [(256, 0.0013, 2.8363), (512, 1.8e-4, 1.9869), (1024, 4.54e-5, 2.0086),
+                (2048, 1.13e-5, 1.9673), (4096, 2.88e-5, None)]
 
 
 def bench_ch_convergence(args, torch):
-    """The Section 5.2 convergence study of the Cahn-Hilliard scheme: one run
-    per N from eps cos(5x) to the same end time T with dt = 0.1 dx, and the
+    """The Section 5.2 convergence study of the Cahn-Hilliard scheme, or the
+    same study of the forced scheme in the travelling frame: one run per N
+    from eps cos(5x) to the same end time T with dt = 0.1 dx, and the
     self-convergence error E_N = max_i |C_N(x_i, T) - C_2N(x_i, T)| over the
     N points the two grids share, with the observed order log2(E_N / E_2N).
     N <= 1024 run fused on chip, longer systems one three-launch step per
-    call.  The oracle repeats the runs up to N = 1024 on the host (its E_N and
-    final states are compared with the GPU's)."""
+    call.  The oracle repeats the runs up to N = 2048 (or the workload's
+    limit) on the host; its E_N and final states are compared with the
+    GPU's."""
     from paper_2107_05395_amd import Factor, inputs
     import oracle
     spec = dict(inputs.WORKLOADS[args.workload])
     L, gamma, eps, mode, s128 = (spec["length"], spec["gamma"], spec["eps"], spec["mode"],
                                  spec["steps128"])
+    forced = spec.get("forced")
     ns = list(spec["ns"]) + [2 * spec["ns"][-1]]
     finals, times, steps_of = {}, {}, {}
     total_steps = 0
@@ -839,29 +845,43 @@ def bench_ch_convergence(args, torch):
         f = Factor.cahn_hilliard(n, L, gamma, dt)
         x = np.arange(n) * dx
         c0 = torch.from_numpy((eps * np.cos(mode * x))[:, None].copy()).cuda()
-        f.ch_run(c0, f.alpha, 2)                              # warm-up (tables, code)
+        if forced:
+            par = [torch.full((1,), forced[key], dtype=torch.float64, device="cuda")
+                   for key in ("v", "f0", "k")]
+            run = lambda s: f.ch_forced_run(c0, dt, dx, *par, s)
+        else:
+            run = lambda s: f.ch_run(c0, f.alpha, s)
+        run(2)                                   # warm-up (tables, code)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out = f.ch_run(c0, f.alpha, steps)
+        out = run(steps)
         torch.cuda.synchronize()
         times[n] = time.perf_counter() - t0
         finals[n] = out[:, 0].cpu().numpy()
         steps_of[n] = steps
         total_steps += steps
+        print("N = %d: %d steps in %.2f s" % (n, steps, times[n]), file=sys.stderr, flush=True)
     table = []
     for n in spec["ns"]:
         e = float(np.max(np.abs(finals[n] - finals[2 * n][::2])))
         table.append({"N": n, "E_N": e, "steps": steps_of[n], "gpu_s": times[n]})
     for i in range(len(table) - 1):
         table[i]["order"] = float(np.log2(table[i]["E_N"] / table[i + 1]["E_N"]))
-    # the oracle on the same runs up to N = 1024 (and its 2N references)
+    # the oracle on the same runs up to N = 2048 (or the workload's limit)
     t0 = time.perf_counter()
     ref_finals = {}
-    for n in [n for n in ns if n <= 2048]:
+    for n in [n for n in ns if n <= spec.get("oracle_max_n", 2048)]:
         dx = L / n
         sigma, alpha = oracle.ch_coefficients(gamma, dx, 0.1 * dx)
         c = (eps * np.cos(mode * np.arange(n) * dx))[:, None]
-        ref_finals[n] = oracle.ch_step(c, sigma, alpha, steps=steps_of[n])[:, 0]
+        if forced:
+            beta, amp, kdx = oracle.ch_forced_parameters(
+                0.1 * dx, dx, np.array([forced["v"]]), np.array([forced["f0"]]),
+                np.array([forced["k"]]))
+            ref_finals[n] = oracle.ch_forced_step(c, sigma, alpha, beta, amp, kdx,
+                                                  steps=steps_of[n])[:, 0]
+        else:
+            ref_finals[n] = oracle.ch_step(c, sigma, alpha, steps=steps_of[n])[:, 0]
     cpu_s = time.perf_counter() - t0
     cpu_steps = sum(steps_of[n] for n in ref_finals)
     checks = []
@@ -870,22 +890,25 @@ def bench_ch_convergence(args, torch):
         if n in ref_finals and 2 * n in ref_finals:
             e_ref = float(np.max(np.abs(ref_finals[n] - ref_finals[2 * n][::2])))
             row["E_N_oracle"] = e_ref
+        if n in ref_finals:
             checks.append({"N": n, "max_abs_diff_vs_oracle":
                            float(np.max(np.abs(finals[n] - ref_finals[n])))})
     gpu_total = sum(times.values())
+    paper = PAPER_TABLE4 if forced else PAPER_TABLE3
     return {
         "metric": "system-steps/s", "value": total_steps / gpu_total, "unit": "system-steps/s",
         "n_gpus": 1, "steps": total_steps, "warmup": 1, "ms_per_step": 1e3 * gpu_total / total_steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (the cosine initial state of Section 5.2)",
         "config": {"workload": args.workload, "ns": ns, "L": L, "gamma": gamma, "eps": eps,
-                   "mode": mode, "dt": "0.1 dx", "T": s128 * 0.1 * L / 128},
+                   "mode": mode, "dt": "0.1 dx", "T": s128 * 0.1 * L / 128,
+                   "forced": forced},
         "table": table, "state_checks": checks,
-        "paper_table3": [{"N": a, "E_N": b, "order": c} for a, b, c in PAPER_TABLE3],
+        "paper_table": [{"N": a, "E_N": b, "order": c} for a, b, c in paper],
         "roofline": None,
         "cpu_baseline": {"value": cpu_steps / cpu_s, "unit": "system-steps/s", "cores": 1,
                          "kind": "oracle",
-                         "sample": "oracle.ch_step over the runs N = %s (one system each, one "
+                         "sample": "the oracle's steps over the runs N = %s (one system each, one "
                                    "thread), %.1f s" % (sorted(ref_finals), cpu_s)},
     }
 
@@ -961,6 +984,55 @@ def bench_long(args, torch):
     }
 
 
+def bench_batch_sweep(args, torch):
+    """The FP64 tridiagonal sweep of one matrix over batch sizes (the row
+    stride of the interleaved layout is 8 m bytes), each point beside the
+    sweep-pattern copy and the 16 KB-tile copy of the same n x m array: how
+    the streaming rate of the sweep and of its access pattern depend on the
+    stride.  With --steps 1 --warmup 0 every kernel runs once per point (for
+    counter runs)."""
+    from paper_2107_05395_amd import Factor, inputs
+    from paper_2107_05395_amd.solver import copy_rows, copy_tiles
+    import oracle
+    spec = dict(inputs.WORKLOADS[args.workload])
+    n = spec["n"]
+    bands = inputs.diffusion_tri_bands(n, spec["r"])
+    f = Factor.tri(*bands)
+    points = []
+    for m in spec["ms"]:
+        rhs_host = inputs.uniform_batch(n, m, seed=spec["seed"] + m)
+        rhs = torch.from_numpy(rhs_host).cuda()
+        x = torch.empty_like(rhs)
+        gb = 16.0 * n * m / 1e9
+        t_sweep, _ = time_launches(lambda: f.solve(rhs, out=x), args.steps, args.warmup, torch)
+        cols = np.unique(np.linspace(0, m - 1, 64).astype(np.int64))
+        err = rel_err_cols(x[:, torch.from_numpy(cols).cuda()].cpu().numpy(),
+                           oracle.tri_solve(*bands, rhs_host[:, cols]))
+        t_rows, _ = time_launches(lambda: copy_rows(rhs, x), args.steps, args.warmup, torch)
+        t_tiles, _ = time_launches(lambda: copy_tiles(rhs, x), args.steps, args.warmup, torch)
+        points.append({"m": m, "row_stride_kib": 8 * m // 1024,
+                       "sweep_ms": 1e3 * t_sweep / args.steps,
+                       "sweep_gbs": gb * args.steps / t_sweep,
+                       "pattern_copy_gbs": gb * args.steps / t_rows,
+                       "tile_copy_gbs": gb * args.steps / t_tiles,
+                       "rel_err_vs_oracle": err})
+        del rhs, x
+    big = max(points, key=lambda p: p["m"])
+    return {
+        "metric": "systems solved/s", "value": big["m"] / (big["sweep_ms"] / 1e3),
+        "unit": "systems/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": big["sweep_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded uniform[-1,1) right-hand sides)",
+        "config": {"workload": args.workload, "n": n, "ms": list(spec["ms"]),
+                   "matrix": "tridiagonal (-r, 1+2r, -r), r = %g" % spec["r"]},
+        "points": points,
+        "roofline": {"bound": "hbm", "achieved": big["sweep_gbs"], "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": big["sweep_gbs"] / PEAK_HBM_GBS, "traffic": None,
+                     "note": "largest batch; algorithmic 16 B per row"},
+        "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -1008,6 +1080,8 @@ def main():
         line = bench_ch_convergence(args, torch)
     elif kind == "long":
         line = bench_long(args, torch)
+    elif kind == "batch_sweep":
+        line = bench_batch_sweep(args, torch)
     else:
         sys.exit("workload %s is not a bench workload" % args.workload)
     line["device"] = torch.cuda.get_device_name(0)

@@ -82,8 +82,8 @@ typedef struct bb_factor_s *bb_factor;
  * on chip in one launch (its coefficient table staged in LDS).  Longer
  * ("long") systems are solved in three launches (a pass over every chunk of
  * C rows, a scan along each system, a second pass) with the solution array
- * as their scratch: FP64 only, out of place, one Cahn-Hilliard step per
- * call, no fused Crank-Nicolson or forced steps (BB_ERR_UNSUPPORTED).
+ * as their scratch: FP64 only, out of place, one (forced) Cahn-Hilliard step
+ * per call, no fused Crank-Nicolson steps (BB_ERR_UNSUPPORTED).
  * Errors: BB_ERR_ARG (null pointer, n out of range), BB_ERR_ZERO_PIVOT,
  *         BB_ERR_SINGULAR_CAPACITANCE (cyclic), BB_ERR_OOM.  *out is set only on BB_OK. */
 bb_status bb_factor_shared_tri(const double *a, const double *b, const double *c, int64_t n,
@@ -258,9 +258,12 @@ bb_status bb_ch_step_stats(bb_factor f, const double *c_in, double *c_out, int64
  * m doubles each); dt and dx are shared.  `f` must be the cyclic penta factor
  * of the Cahn-Hilliard LHS for the same dt and dx (bb_factor_ch).
  * c_in, c_out: device double, interleaved, same ld; in place allowed.  All
- * `steps` steps run inside one kernel with the state on chip.
+ * `steps` steps run inside one kernel with the state on chip.  Long systems
+ * (n > 1024): one step per call in the three long-system launches, the
+ * right-hand side formed inside them from c_in; out of place.
  * Errors: BB_ERR_ARG (not a cyclic penta factor, NULL parameters, dt or dx not
- * finite and positive, sizes), BB_ERR_HIP. */
+ * finite and positive, sizes), BB_ERR_UNSUPPORTED (long system with
+ * steps != 1 or c_out == c_in), BB_ERR_HIP. */
 bb_status bb_ch_forced_step(bb_factor f, const double *c_in, double *c_out, int64_t m, int64_t ld,
                             double dt, double dx, const double *v, const double *f0,
                             const double *k, int64_t steps, void *stream);

@@ -343,14 +343,18 @@ bb_status long_table(bb::Factor &f, int dev, bool adjoint, int C, bb::DeviceTabl
                         [&] { return bb::build_table(dir, f.K, f.cyclic, f.n, C, P); }, tab);
 }
 
+bb_status stepper_too_long(const bb::Factor &f)
+{
+    return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(f.n) +
+                                        ": the fused steppers hold a system on chip (tri n <= " +
+                                        std::to_string(bb::kMaxN) + ", penta n <= " +
+                                        std::to_string(bb::kMaxNPenta) + ")");
+}
+
 bb_status stepper_setup(bb::Factor &f, int dev, int64_t m, int64_t ld, StepPlan *pl,
                         bb::DeviceTable *tab, bb::SweepGeom *g, bool adjoint)
 {
-    if (is_long(f))
-        return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(f.n) +
-                                             ": the fused steppers hold a system on chip (tri n <= " +
-                                             std::to_string(bb::kMaxN) + ", penta n <= " +
-                                             std::to_string(bb::kMaxNPenta) + ")");
+    if (is_long(f)) return stepper_too_long(f);
     *pl = step_plan(f.n, m);
     const int C = pl->C, P = pl->P;
     // the same table as a solve (or adjoint solve) with this chunk size
@@ -833,9 +837,26 @@ bb_status bb_ch_forced_step(bb_factor fh, const double *c_in, double *c_out, int
     const double alpha = dt / (dx * dx);
     if (!std::isfinite(alpha)) return fail(BB_ERR_ARG, "dt / dx^2 is not finite");
     if (m > 0 && (!v || !f0 || !k)) return fail(BB_ERR_ARG, "parameter pointer is NULL");
+    if (is_long(f) && steps != 1)
+        return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(f.n) +
+                                             " (long system): one step per call");
+    if (is_long(f) && m > 0 && c_in == c_out)
+        return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(f.n) +
+                                             " (long system): c_out must not overlap c_in");
     if (m == 0) { g_last_error.clear(); return BB_OK; }
     int dev;
     if ((st = current_device(&dev)) != BB_OK) return st;
+    if (is_long(f)) {
+        const int C = long_chunk(m);
+        bb::DeviceTable tab;
+        if ((st = long_table(f, dev, false, C, &tab)) != BB_OK) return st;
+        hipError_t e = bb::launch_ch_forced_long((const double *)tab.ptr, f.primal.cor.q,
+                                                 long_geom(f, m, ld, C), alpha, dt, dx, v, f0, k,
+                                                 c_in, c_out, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "long forced Cahn-Hilliard launch");
+        g_last_error.clear();
+        return BB_OK;
+    }
     StepPlan pl;
     bb::DeviceTable tab;
     bb::SweepGeom g;
@@ -889,6 +910,7 @@ bb_status cn_steps(bb_factor fh, const double *w, const double *c_in, double *ou
     if (steps < 1) return fail(BB_ERR_ARG, "steps < 1");
     const int64_t stride = traj ? f.n * ld : 0;
     if (traj && steps > (int64_t(1) << 62) / stride) return fail(BB_ERR_ARG, "steps * n * ld overflows");
+    if (is_long(f)) return stepper_too_long(f);
     if (m == 0) { g_last_error.clear(); return BB_OK; }
     int dev;
     if ((st = current_device(&dev)) != BB_OK) return st;

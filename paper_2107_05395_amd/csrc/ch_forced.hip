@@ -6,6 +6,7 @@
 // forcing.  A right-hand-side policy of the fused stepper (stepper.h).
 #include <cmath>
 
+#include "long_core.h"
 #include "stepper.h"
 
 namespace bb {
@@ -126,7 +127,66 @@ struct ForcedChRhs {
     }
 };
 
+// The forced right-hand side as the source of the long-system launches
+// (one step per call): a chunk's rows and the three rows on each side of it,
+// indices mod n, read from the state before the step.  The halo takes the
+// place of the wrap rows, so the policy sees every chunk as an inner one.
+struct ForcedLongSrc {
+    ForcedChRhs rhs;
+    const double *c;
+    __device__ __forceinline__ double row(int i, int64_t k, int64_t ld, int n) const
+    {
+        i = i < 0 ? i + n : (i >= n ? i - n : i);
+        return c[(int64_t)i * ld + k];
+    }
+    template <int C>
+    __device__ __forceinline__ void full(double (&v)[C], int row0, int64_t k, int64_t ld,
+                                         int n) const
+    {
+        load_chunk<double, C, true>(v, c, row0, k, ld, n);
+        Halo h{};
+        h.l1 = row(row0 - 1, k, ld, n);
+        h.l2 = row(row0 - 2, k, ld, n);
+        h.l3 = row(row0 - 3, k, ld, n);
+        h.r1 = row(row0 + C, k, ld, n);
+        h.r2 = row(row0 + C + 1, k, ld, n);
+        h.r3 = row(row0 + C + 2, k, ld, n);
+        rhs.template operator()<C, true>(v, h, 1, false, C, rhs.lane_state(k, row0));
+    }
+    // the last chunk: rows row0 .. n-1 (row0 >= C >= 16); past row n-1 come
+    // rows 0, 1, 2
+    template <int C>
+    __device__ __forceinline__ void tail(double (&v)[C], int row0, int64_t k, int64_t ld,
+                                         int n) const
+    {
+        load_chunk<double, C, false>(v, c, row0, k, ld, n);
+        Halo h{};
+        h.l1 = row(row0 - 1, k, ld, n);
+        h.l2 = row(row0 - 2, k, ld, n);
+        h.l3 = row(row0 - 3, k, ld, n);
+        h.e0 = c[k];
+        h.e1 = c[ld + k];
+        h.e2 = c[2 * ld + k];
+        rhs.template operator()<C, false>(v, h, 1, false, n - row0, rhs.lane_state(k, row0));
+    }
+};
+
 }  // namespace
+
+hipError_t launch_ch_forced_long(const double *table, const CyclicQ &q, const LongGeom &g,
+                                 double alpha, double dt, double dx, const double *v,
+                                 const double *f0, const double *k, const double *in, double *out,
+                                 hipStream_t s)
+{
+    ForcedChRhs r;
+    r.alpha = alpha;
+    r.dt = dt;
+    r.dx = dx;
+    r.v = v;
+    r.f0 = f0;
+    r.k = k;
+    return launch_long_k<2, true>(table, q, g, ForcedLongSrc{r, in}, out, s);
+}
 
 hipError_t launch_ch_forced(const double *table, int64_t table_elems, const CyclicQ &q,
                             const SweepGeom &g, bool scalar, double alpha, double dt, double dx,

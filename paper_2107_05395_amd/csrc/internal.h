@@ -220,6 +220,14 @@ hipError_t launch_long_solve(int K, bool cyclic, const double *table, const Cycl
 // neighbour rows) wherever the launches read it; c_out must not overlap c_in.
 hipError_t launch_ch_long(const double *table, const CyclicQ &q, const LongGeom &g, double alpha,
                           const double *c_in, double *c_out, hipStream_t stream);
+// One forced Cahn-Hilliard step of long periodic systems (the travelling-wave
+// scheme: the Section 5.1 right-hand side plus per-run WENO advection and
+// forcing), the right-hand side formed from c_in like launch_ch_long's;
+// v, f0, k: device, one per run; c_out must not overlap c_in.
+hipError_t launch_ch_forced_long(const double *table, const CyclicQ &q, const LongGeom &g,
+                                 double alpha, double dt, double dx, const double *v,
+                                 const double *f0, const double *k, const double *c_in,
+                                 double *c_out, hipStream_t stream);
 
 // Copy of `bytes` (a multiple of 16) in contiguous 16 KB tiles per workgroup:
 // the streaming reference the sweeps' HBM rate is compared with.

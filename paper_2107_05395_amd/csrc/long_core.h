@@ -116,10 +116,56 @@ __global__ __launch_bounds__(256) void long_reduce(const double *__restrict__ ta
     }
 }
 
-// Full chunks scanned per block: their scratch values are loaded together
-// before the dependent chain runs over them.
-constexpr int kScanBlock = 8;
+// Full chunks per block of the scan.  The chain over a system's chunks is
+// bound by load latency, so everything a block needs is loaded before the
+// chain runs over it: each chunk's scratch values (per lane) and the block's
+// chunk matrices, which are the same for every system -- one vector load
+// spreads them over the wave's lanes and the chain reads them back with
+// readlane (a scalar load per chunk would put one round trip per chunk into
+// the chain).  SB K x K matrices fill at most the 64 lanes.
+template <int K>
+constexpr int scan_block() { return K == 1 ? 32 : 16; }
 
+// the double held by lane l of the wave (l wave-uniform)
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// M_j = mats[(j0 + b) K^2 ..] for b = 0 .. SB-1, lane b K^2 + q holding
+// element q of chunk j0 + b (clamped to the last full chunk).
+template <int K, int SB>
+__device__ __forceinline__ double load_block_mats(const double *mats, int j0, int full, int lane)
+{
+    const int b = lane / (K * K) < SB ? lane / (K * K) : SB - 1;
+    const int j = j0 + b < full ? j0 + b : full - 1;
+    return mats[(int64_t)j * K * K + lane % (K * K)];
+}
+
+// y <- e + M_b y with M_b the matrix of chunk b of the block in `mats`.
+template <int K>
+__device__ __forceinline__ void affine_lanes(double mats, int b, double &y1, double &y2,
+                                             double e1, double e2)
+{
+    if constexpr (K == 1) {
+        y1 = fma(lane_value(mats, b), y1, e1);
+    } else {
+        const double m0 = lane_value(mats, 4 * b), m1 = lane_value(mats, 4 * b + 1);
+        const double m2 = lane_value(mats, 4 * b + 2), m3 = lane_value(mats, 4 * b + 3);
+        const double n1 = fma(m1, y2, fma(m0, y1, e1));
+        const double n2 = fma(m3, y2, fma(m2, y1, e2));
+        y1 = n1;
+        y2 = n2;
+    }
+}
+
+// One lane per system (k): the forward scan over the full chunks, the tail
+// chunk, the backward scan and the periodic correction scalars, reading and
+// writing the scratch rows of x.  Every lane of a launched wave runs (lanes
+// past m on system m-1, storing nothing), so readlane sees loaded values.
 template <int K, int C, bool CYC, class Src>
 __global__ __launch_bounds__(256) void long_scan(const double *__restrict__ table, CyclicQ cq,
                                                  LongGeom g, Src src, double *x)
@@ -130,47 +176,51 @@ __global__ __launch_bounds__(256) void long_scan(const double *__restrict__ tabl
     if ((int64_t)blockIdx.x * blockDim.x >= kmax) return;   // whole workgroups past the batch
     const bool kval = k < g.m;
     const int64_t kk = kval ? k : g.m - 1;
+    const int lane = threadIdx.x % kWave;
     const int64_t ld = g.ld;
     const int full = g.P - 1;
     const int na = num_arrays(K, CYC);
     const int64_t L = (int64_t)g.P * (C + 1);
     const typename SP::ptr tabs = SP::base((typename SP::ptr)table);
-    const typename SP::ptr Mf = tabs + na * L;
-    const typename SP::ptr Mb = Mf + (int64_t)g.P * K * K;
-    const typename SP::ptr Gm = Mb + (int64_t)g.P * K * K;
+    // the chunk matrices, read with vector loads
+    const double *Mf = table + opaque_v(0) + na * L;
+    const double *Mb = Mf + (int64_t)g.P * K * K;
+    const double *Gm = Mb + (int64_t)g.P * K * K;
+    constexpr int SB = scan_block<K>();
 
-    // forward scan: H_j over e_j, in blocks of loads issued together
+    // forward: H_j written over e_j
     double h1 = 0.0, h2 = 0.0;
-    for (int j0 = 0; j0 < full; j0 += kScanBlock) {
-        double a1[kScanBlock], a2[kScanBlock];
+    for (int j0 = 0; j0 < full; j0 += SB) {
+        double a1[SB], a2[SB];
+        const double mats = load_block_mats<K, SB>(Mf, j0, full, lane);
 #pragma unroll
-        for (int b = 0; b < kScanBlock; ++b) {
+        for (int b = 0; b < SB; ++b) {
             const int j = j0 + b < full ? j0 + b : full - 1;
             const double *p = x + (int64_t)j * C * ld + kk;
             a1[b] = p[0];
             a2[b] = K == 2 ? p[ld] : 0.0;
         }
 #pragma unroll
-        for (int b = 0; b < kScanBlock; ++b) {
+        for (int b = 0; b < SB; ++b) {
             if (j0 + b < full) {
                 double *p = x + (int64_t)(j0 + b) * C * ld + k;
                 if (kval) {
                     p[0] = h1;
                     if constexpr (K == 2) p[ld] = h2;
                 }
-                affine<double, K>(Mf + (j0 + b) * K * K, h1, h2, a1[b], a2[b]);
+                affine_lanes<K>(mats, b, h1, h2, a1[b], a2[b]);
             }
         }
     }
 
-    // the tail chunk, from its history (h1, h2): forward, then backward with
-    // zero future; rows past n hold 0 (zero coefficients)
+    // the tail chunk from its history, stored (uncorrected if periodic); its
+    // rows are not scratch rows of any full chunk
     const int trow0 = full * C;
     const int nr = g.n - trow0;
-    double v[C];
-    src.template tail<C>(v, trow0, kk, ld, g.n);
-    double yn1, yn2;   // y_{n-1}, y_{n-2}
+    double yn1, yn2, f1, f2;   // y_{n-1}, y_{n-2}; the tail's start state
     {
+        double v[C];
+        src.template tail<C>(v, trow0, kk, ld, g.n);
         const auto tp = lane_table<double, K, C, CYC>(SP::base(tabs), g.P, full);
         double y1 = h1, y2 = h2;
         rows_up<C>([&](int t) {
@@ -192,14 +242,21 @@ __global__ __launch_bounds__(256) void long_scan(const double *__restrict__ tabl
             x1 = xx;
             v[t] = xx;
         });
+        f1 = v[0];
+        f2 = K == 2 ? v[1] : 0.0;
+        if (kval) store_chunk<double, C, false>(v, x, trow0, k, ld, g.n);
     }
 
-    // backward scan: F_j over o_j, starting from the tail's start state
-    double f1 = v[0], f2 = K == 2 ? v[1] : 0.0;
-    for (int j1 = full - 1; j1 >= 0; j1 -= kScanBlock) {
-        double hh1[kScanBlock], hh2[kScanBlock], oo1[kScanBlock], oo2[kScanBlock];
+    // backward: S_j = o_j + G_j H_j, F_j written over o_j
+    for (int j1 = full - 1; j1 >= 0; j1 -= SB) {
+        // chunks j1, j1-1, .. j1-SB+1 are entries SB-1 .. 0 of the block
+        // starting at j1 - SB + 1 (clamped at 0 by the loads)
+        const int jb = j1 - SB + 1;
+        double hh1[SB], hh2[SB], oo1[SB], oo2[SB];
+        const double gms = load_block_mats<K, SB>(Gm, jb < 0 ? 0 : jb, full, lane);
+        const double mbs = load_block_mats<K, SB>(Mb, jb < 0 ? 0 : jb, full, lane);
 #pragma unroll
-        for (int b = 0; b < kScanBlock; ++b) {
+        for (int b = 0; b < SB; ++b) {
             const int j = j1 - b >= 0 ? j1 - b : 0;
             const double *p = x + (int64_t)j * C * ld + kk;
             hh1[b] = p[0];
@@ -208,33 +265,33 @@ __global__ __launch_bounds__(256) void long_scan(const double *__restrict__ tabl
             oo2[b] = K == 2 ? p[(int64_t)(K + 1) * ld] : 0.0;
         }
 #pragma unroll
-        for (int b = 0; b < kScanBlock; ++b) {
+        for (int b = 0; b < SB; ++b) {
             const int j = j1 - b;
             if (j >= 0) {
-                const auto G = Gm + j * K * K;
+                const int e = j - (jb < 0 ? 0 : jb);   // entry of chunk j in the block
                 double s1, s2 = 0.0;
                 if constexpr (K == 1) {
-                    s1 = fma(G[0], hh1[b], oo1[b]);
+                    s1 = fma(lane_value(gms, e), hh1[b], oo1[b]);
                 } else {
-                    s1 = fma(G[1], hh2[b], fma(G[0], hh1[b], oo1[b]));
-                    s2 = fma(G[3], hh2[b], fma(G[2], hh1[b], oo2[b]));
+                    const double g0 = lane_value(gms, 4 * e), g1 = lane_value(gms, 4 * e + 1);
+                    const double g2 = lane_value(gms, 4 * e + 2), g3 = lane_value(gms, 4 * e + 3);
+                    s1 = fma(g1, hh2[b], fma(g0, hh1[b], oo1[b]));
+                    s2 = fma(g3, hh2[b], fma(g2, hh1[b], oo2[b]));
                 }
                 if (kval) {
                     double *p = x + (int64_t)j * C * ld + k;
                     p[(int64_t)K * ld] = f1;
                     if constexpr (K == 2) p[(int64_t)(K + 1) * ld] = f2;
                 }
-                affine<double, K>(Mb + j * K * K, f1, f2, s1, s2);
+                affine_lanes<K>(mbs, e, f1, f2, s1, s2);
             }
         }
     }
 
-    // periodic correction scalars from w_0, w_1 (start of chunk 0) and
-    // w_{n-2}, w_{n-1} (x_{n-1} = y_{n-1}, x_{n-2} = y_{n-2} - u1 y_{n-1})
-    double c0 = 0.0, c1 = 0.0;
     if constexpr (CYC) {
         const double rn1 = yn1;
         const double rn2 = K == 2 ? fma(cq.u1_nm2, rn1, yn2) : 0.0;
+        double c0 = 0.0, c1 = 0.0;
         correction_scalars<double, K>(cq, f1, f2, rn2, rn1, c0, c1);
         if (kval) {
             for (int j = 0; j < full; ++j) {
@@ -242,15 +299,18 @@ __global__ __launch_bounds__(256) void long_scan(const double *__restrict__ tabl
                 p[0] = c0;
                 if constexpr (K == 2) p[ld] = c1;
             }
+            // the tail again, corrected (this lane stored it above)
+            double v[C];
+            load_chunk<double, C, false>(v, x, trow0, k, ld, g.n);
+            const auto tp = lane_table<double, K, C, CYC>(SP::base(tabs), g.P, full);
+            rows_up<C>([&](int t) {
+                double xx = fma(tp.z0[t], c0, v[t]);
+                if constexpr (K == 2) xx = fma(tp.z1[t], c1, xx);
+                v[t] = xx;
+            });
+            store_chunk<double, C, false>(v, x, trow0, k, ld, g.n);
         }
-        const auto tp = lane_table<double, K, C, CYC>(SP::base(tabs), g.P, full);
-        rows_up<C>([&](int t) {
-            double xx = fma(tp.z0[t], c0, v[t]);
-            if constexpr (K == 2) xx = fma(tp.z1[t], c1, xx);
-            v[t] = xx;
-        });
     }
-    if (kval) store_chunk<double, C, false>(v, x, trow0, k, ld, g.n);
 }
 
 template <int K, int C, bool CYC, class Src>

@@ -129,11 +129,23 @@ WORKLOADS = {
     # i.e. 204 N / 128 steps
     "ch_convergence_1d": dict(kind="ch_convergence", ns=(128, 256, 512, 1024, 2048, 4096, 8192),
                               length=2.0 * math.pi, gamma=0.01, eps=1e-6, mode=5, steps128=204),
+    # the same study of the forced scheme in the travelling frame (k = 1,
+    # v = 0.5, f0 = 1), run to T = 50 (10200 steps at N = 128), the horizon
+    # of the flow-pattern runs, where the travelling-frame state has settled
+    "ch_forced_convergence_1d": dict(kind="ch_convergence", ns=(256, 512, 1024, 2048, 4096),
+                                     length=2.0 * math.pi, gamma=0.01, eps=1e-6, mode=5,
+                                     steps128=10200, forced=dict(v=0.5, f0=1.0, k=1.0),
+                                     oracle_max_n=1024),
     # long systems (beyond one launch's on-chip limit), small batches where
     # the paper hands the work to the CPU, and one large batch
     "long_small_batch": dict(kind="long", ns=(4096, 8192, 16384), ms=(1, 8, 64),
                              seed=SEED_BASE + 10),
     "long_tri_n8192_m65536": dict(kind="long", ns=(8192,), ms=(1 << 16,), seed=SEED_BASE + 11),
+    # the FP64 tridiagonal sweep of the bench matrix (n = 512) over batch sizes
+    # 2^16 .. 2^21, i.e. row strides of 512 KiB .. 16 MiB, beside the two
+    # reference copies of the same bytes
+    "tri_batch_sweep_n512": dict(kind="batch_sweep", n=512, ms=tuple(1 << e for e in range(16, 22)),
+                                 r=1.0, seed=SEED_BASE + 12),
     # Crank-Nicolson time stepping on the grid of the paper's benchmark tables
     # (1000 steps; n = 64, 256, 1024; m = 2^6, 2^12, 2^16); the step size is
     # not printed; sigma = 1 is taken here (it does not change the work)

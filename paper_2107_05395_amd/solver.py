@@ -215,7 +215,7 @@ class Factor:
     def long(self) -> bool:
         """True when n is above what one launch holds on chip (tri 2048,
         penta 1024): solves go through three launches, out of place, and the
-        Cahn-Hilliard step takes one step per call."""
+        (forced) Cahn-Hilliard step takes one step per call."""
         return self.n > (2048 if self.nbands == 3 else 1024)
 
     def ch_run(self, c: torch.Tensor, alpha: float, steps: int) -> torch.Tensor:
@@ -278,6 +278,21 @@ class Factor:
                                           ctypes.c_void_p(k.data_ptr()), int(steps),
                                           _stream_ptr(c)))
         return out
+
+    def ch_forced_run(self, c: torch.Tensor, dt: float, dx: float, v: torch.Tensor,
+                      f0: torch.Tensor, k: torch.Tensor, steps: int) -> torch.Tensor:
+        """`steps` forced Cahn-Hilliard steps from c (left unchanged) into a
+        new tensor: one fused call, or for long systems one call per step
+        alternating between two buffers."""
+        if not self.long:
+            return self.ch_forced_step(c, dt, dx, v, f0, k, steps=steps)
+        a, b = torch.empty_like(c), torch.empty_like(c)
+        src = c
+        for s in range(int(steps)):
+            dst = a if s % 2 == 0 else b
+            self.ch_forced_step(src, dt, dx, v, f0, k, steps=1, out=dst)
+            src = dst
+        return src if steps > 0 else c.clone()
 
     def cn_step(self, c: torch.Tensor, w, steps: int = 1,
                 out: torch.Tensor | None = None) -> torch.Tensor:

@@ -107,8 +107,8 @@ def test_size_limits(L):
 def test_long_systems_host_checks(L):
     """Above tri n = 2048 / penta n = 1024 the solves take the three-launch
     long-system path: FP64 only, out of place; the fused steppers are not
-    built for it and the Cahn-Hilliard step takes one out-of-place step per
-    call.  All of it is checked on the host, before any device call."""
+    built for it and the (forced) Cahn-Hilliard step takes one out-of-place
+    step per call.  All of it is checked on the host, before any device call."""
     fake = ctypes.c_void_p(0x1000)
     other = ctypes.c_void_p(0x2000)
     n = 1025
@@ -131,6 +131,11 @@ def test_long_systems_host_checks(L):
     assert L.bb_ch_step(ch, fake, fake, 4, 4, alp, 1, None) == -6           # in place
     ws = ctypes.c_void_p(0x3000)
     assert L.bb_ch_step_stats(ch, fake, other, 4, 4, alp, 1, 1, ws, ws, 1 << 20, None) == -6
+    dx = 2 * np.pi / 4096
+    assert L.bb_ch_forced_step(ch, fake, other, 4, 4, 1e-4, dx, ws, ws, ws, 2, None) == -6
+    assert L.bb_ch_forced_step(ch, fake, fake, 4, 4, 1e-4, dx, ws, ws, ws, 1, None) == -6
+    w5 = (ctypes.c_double * 5)(0.0, 0.0, 1.0, 0.0, 0.0)
+    assert L.bb_cn_step(ch, w5, fake, other, 4, 4, 1, None) == -6           # no long CN steps
     L.bb_factor_destroy(ch)
     h = ctypes.c_void_p()
     assert L.bb_factor_shared_tri(None, None, None, 4, ctypes.byref(h)) == -1

@@ -130,3 +130,53 @@ def test_long_cahn_hilliard_steps_match_oracle(n, m):
     tol = fp64_tol(1.0 + 16.0 * sigma, 2)
     say("long CH", n, m, err, "tol", tol)
     assert err < tol
+
+
+@pytest.mark.parametrize("n,m", [(2048, 100), (3001, 70), (4096, 64), (8192, 5)])
+def test_long_forced_steps_match_oracle(n, m):
+    """The forced travelling-wave step of long periodic systems (WENO
+    advection and forcing formed inside the launches from the state and three
+    halo rows on each side), per-run v of both signs and zero, f0 and k
+    varying, two steps ping-ponged, against the oracle's steps; dt = 0.1 dx."""
+    L, gamma = 2 * math.pi, 0.01
+    dx = L / n
+    dt = 0.1 * dx
+    g = inputs.rng(n + m)
+    v = g.uniform(-1, 1, m)
+    v[::5] = 0.0
+    f0 = g.uniform(0, 2, m)
+    k = g.integers(1, 4, m).astype(np.float64) * (2 * math.pi / L)
+    c0 = g.uniform(0, 1.5, m) + inputs.uniform_batch(n, m, seed=n + 2 * m, lo=-0.1, hi=0.1)
+    f = Factor.cahn_hilliard(n, L, gamma, dt)
+    assert f.long
+    a, b = dev(c0), torch.empty(n, m, dtype=torch.float64, device="cuda")
+    pv, pf, pk = dev(v), dev(f0), dev(k)
+    f.ch_forced_step(a, dt, dx, pv, pf, pk, out=b)
+    f.ch_forced_step(b, dt, dx, pv, pf, pk, out=a)
+    sigma, alpha = oracle.ch_coefficients(gamma, dx, dt)
+    beta, amp, kdx = oracle.ch_forced_parameters(dt, dx, v, f0, k)
+    ref = oracle.ch_forced_step(c0, sigma, alpha, beta, amp, kdx, steps=2)
+    err = rel_err(host(a), ref)
+    tol = fp64_tol(1.0 + 16.0 * sigma, 2)
+    say("long forced CH", n, m, err, "tol", tol)
+    assert err < tol
+
+
+def test_long_forced_run_alternates_buffers():
+    """Factor.ch_forced_run on a long system: several one-step calls, the
+    input left unchanged, the result equal to the same calls made by hand."""
+    n, m = 2050, 40
+    L = 2 * math.pi
+    dx = L / n
+    dt = 0.1 * dx
+    f = Factor.cahn_hilliard(n, L, 0.01, dt)
+    c0 = dev(0.5 + inputs.uniform_batch(n, m, seed=4, lo=-0.1, hi=0.1))
+    keep = c0.clone()
+    pv = torch.full((m,), 0.5, dtype=torch.float64, device="cuda")
+    pf = torch.full((m,), 1.0, dtype=torch.float64, device="cuda")
+    pk = torch.full((m,), 1.0, dtype=torch.float64, device="cuda")
+    out = f.ch_forced_run(c0, dt, dx, pv, pf, pk, steps=3)
+    x = c0
+    for _ in range(3):
+        x = f.ch_forced_step(x, dt, dx, pv, pf, pk, out=torch.empty_like(x))
+    assert torch.equal(out, x) and torch.equal(c0, keep)
