@@ -366,6 +366,8 @@ bb_status bb_mse_loss_grad(const double *u, const double *target, double *grad, 
  *   "ch_uniform"        0: the fused steppers never read coefficients through
  *                       the scalar cache
  *   "grid_linear"       0 / 1: persistent grids / one workgroup per group
+ *   "long_spread"       0 / 1: the scan of long systems with one lane per system
+ *                       / one wave per system (automatic: a wave for m <= 1024)
  * The settings are read when a call enqueues its launches; change them only
  * between calls.  Errors: BB_ERR_ARG (unknown name, invalid value). */
 bb_status bb_set_tuning(const char *name, int64_t value);

@@ -44,9 +44,10 @@ bb_status hip_fail(hipError_t e, const char *where)
 }
 
 // Tuning overrides (bb_set_tuning), read at each call; -1 = automatic.
-std::atomic<int64_t> g_tuning[bb::kTuneCount] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
+std::atomic<int64_t> g_tuning[bb::kTuneCount] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
 const char *const kTuneNames[bb::kTuneCount] = {"max_chunk", "waves_per_system", "waves_per_block",
-                                                "lockstep", "ch_uniform", "grid_linear"};
+                                                "lockstep", "ch_uniform", "grid_linear",
+                                                "long_spread"};
 
 bool tune_valid(int key, int64_t v)
 {
@@ -261,6 +262,11 @@ bb::LongGeom long_geom(const bb::Factor &f, int64_t m, int64_t ld, int C)
     g.m = m;
     g.ld = ld;
     g.groups = (m + bb::kWave - 1) / bb::kWave;
+    // the scan: one wave per system while that leaves the batch's waves on
+    // few enough SIMDs that they run at once (a chain over the chunks in
+    // each, 64 chunks per round trip to memory), else one lane per system
+    const int64_t sp = bb::tuning(bb::kTuneLongSpread);
+    g.spread = sp >= 0 ? sp == 1 : m <= bb::kSpreadMax;
     return g;
 }
 

@@ -126,6 +126,7 @@ enum TuneKey : int {
     kTuneLockstep,           // 0 / 1: workgroup barrier per persistent iteration
     kTuneChUniform,          // 0: no scalar-coefficient stepper kernel
     kTuneGridLinear,         // 0 / 1: persistent or one-workgroup-per-group grids
+    kTuneLongSpread,         // 0 / 1: long-system scan with one lane or one wave per system
     kTuneCount
 };
 int64_t tuning(TuneKey key);   // api.cpp
@@ -211,7 +212,9 @@ struct LongGeom {
     int n, C, P;        // rows, rows per chunk, chunks (P >= 2; chunk P-1 is the tail)
     int64_t m, ld;      // systems, leading dimension
     int64_t groups;     // groups of 64 systems
+    bool spread;        // scan with one wave per system (small batches, m <= kSpreadMax)
 };
+constexpr int64_t kSpreadMax = 1024;
 constexpr int64_t kMaxNLong = int64_t(1) << 18;
 hipError_t launch_long_solve(int K, bool cyclic, const double *table, const CyclicQ &q,
                              const LongGeom &g, const double *rhs, double *x, hipStream_t stream);

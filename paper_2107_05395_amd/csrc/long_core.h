@@ -368,145 +368,204 @@ __global__ __launch_bounds__(256) void long_solve(const double *__restrict__ tab
 }
 
 // ---------------------------------------------------------------- small batches
-// The scan with one wave per system: lane l owns full chunks
-// [l * cpl, (l + 1) * cpl), composes their affine maps, the wave scans the
-// 64 compositions (shuffles, log2(64) steps), and each lane re-walks its
-// chunks with its exact history / future.  Every scratch value is loaded at
-// once, so the chain over the chunks costs a few round trips instead of one
-// per block of chunks; used when the batch is too small for the
-// lane-per-system scan to fill the device.  Same scratch protocol and results
-// (up to the rounding of the composition order) as long_scan.
-constexpr int kWaveScanMax = 8;       // full chunks per lane at most
-constexpr int64_t kWaveScanBatch = 256;  // systems up to which the wave scan is used
+// The scan with one wave per system, for batches too small for the
+// lane-per-system scan to keep more than a few lanes busy.  The lanes load
+// the values of 64 consecutive full chunks at once (lane l: chunk j0 + l),
+// keep the loads of the next two such blocks in flight while the current one
+// is scanned, and run the chain over a block as a scan of the chunks' affine
+// maps across the wave (6 rounds instead of 64 dependent steps); lane l
+// stores the state entering its chunk.  The composition rounds differently
+// from the lane scan's step-by-step chain (to a few units in the last place
+// of the chunk-boundary states); each round trip to memory serves 64 chunks.
 
-// y <- M y + e composed as maps: (M, c) after (Ma, ca) is (M Ma, M ca + c)
+// one full chunk's scratch values and matrices, in the lane that holds it
 template <int K>
-struct Affine {
-    double m[4], c[2];
-    __device__ __forceinline__ void identity()
-    {
-        m[0] = 1.0; m[1] = 0.0; m[2] = 0.0; m[3] = 1.0;
-        c[0] = 0.0; c[1] = 0.0;
-    }
-    // this <- this after a (apply a first)
-    __device__ __forceinline__ void after(const Affine &a)
-    {
-        if constexpr (K == 1) {
-            c[0] = fma(m[0], a.c[0], c[0]);
-            m[0] = m[0] * a.m[0];
-        } else {
-            const double c0 = fma(m[1], a.c[1], fma(m[0], a.c[0], c[0]));
-            const double c1 = fma(m[3], a.c[1], fma(m[2], a.c[0], c[1]));
-            const double m0 = fma(m[1], a.m[2], m[0] * a.m[0]);
-            const double m1 = fma(m[1], a.m[3], m[0] * a.m[1]);
-            const double m2 = fma(m[3], a.m[2], m[2] * a.m[0]);
-            const double m3 = fma(m[3], a.m[3], m[2] * a.m[1]);
-            c[0] = c0; c[1] = c1;
-            m[0] = m0; m[1] = m1; m[2] = m2; m[3] = m3;
-        }
-    }
-    // this <- (M, e) after this, M a table matrix (row-major K x K)
-    template <typename Ptr>
-    __device__ __forceinline__ void then(Ptr M, double e1, double e2)
-    {
-        Affine t;
-        t.m[0] = M[0];
-        if constexpr (K == 2) { t.m[1] = M[1]; t.m[2] = M[2]; t.m[3] = M[3]; }
-        t.c[0] = e1;
-        t.c[1] = e2;
-        t.after(*this);
-        *this = t;
-    }
-    __device__ __forceinline__ Affine shfl_from(int src) const
-    {
-        Affine r;
-        r.c[0] = __shfl(c[0], src, kWave);
-        r.m[0] = __shfl(m[0], src, kWave);
-        if constexpr (K == 2) {
-            r.c[1] = __shfl(c[1], src, kWave);
-            r.m[1] = __shfl(m[1], src, kWave);
-            r.m[2] = __shfl(m[2], src, kWave);
-            r.m[3] = __shfl(m[3], src, kWave);
-        } else {
-            r.c[1] = 0.0; r.m[1] = 0.0; r.m[2] = 0.0; r.m[3] = 1.0;
-        }
-        return r;
-    }
+struct SpreadFwd {
+    double e1, e2, m[K * K];   // e_j; Mf_j
+};
+template <int K>
+struct SpreadBwd {
+    double s1, s2, m[K * K];   // S_j = o_j + G_j H_j; Mb_j
 };
 
+template <int K, int C>
+__device__ __forceinline__ SpreadFwd<K> spread_fwd(const double *x, const double *Mf, int j,
+                                                   int64_t k, int64_t ld)
+{
+    SpreadFwd<K> v;
+    const double *p = x + (int64_t)j * C * ld + k;
+    v.e1 = p[0];
+    v.e2 = K == 2 ? p[ld] : 0.0;
+#pragma unroll
+    for (int q = 0; q < K * K; ++q) v.m[q] = Mf[(int64_t)j * K * K + q];
+    return v;
+}
+
+template <int K, int C>
+__device__ __forceinline__ SpreadBwd<K> spread_bwd(const double *x, const double *Mb,
+                                                   const double *Gm, int j, int64_t k, int64_t ld)
+{
+    SpreadBwd<K> v;
+    const double *p = x + (int64_t)j * C * ld + k;
+    const double h1 = p[0], h2 = K == 2 ? p[ld] : 0.0;
+    const double o1 = p[(int64_t)K * ld], o2 = K == 2 ? p[(int64_t)(K + 1) * ld] : 0.0;
+    double g[K * K];
+#pragma unroll
+    for (int q = 0; q < K * K; ++q) {
+        g[q] = Gm[(int64_t)j * K * K + q];
+        v.m[q] = Mb[(int64_t)j * K * K + q];
+    }
+    if constexpr (K == 1) {
+        v.s1 = fma(g[0], h1, o1);
+        v.s2 = 0.0;
+    } else {
+        v.s1 = fma(g[1], h2, fma(g[0], h1, o1));
+        v.s2 = fma(g[3], h2, fma(g[2], h1, o2));
+    }
+    return v;
+}
+
+// The affine map y -> c + M y of one chunk.
+template <int K>
+struct ChunkMap {
+    double m[K * K], c[K];
+};
+
+template <int K>
+__device__ __forceinline__ ChunkMap<K> identity_map()
+{
+    ChunkMap<K> a;
+#pragma unroll
+    for (int q = 0; q < K * K; ++q) a.m[q] = (q % (K + 1) == 0) ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < K; ++q) a.c[q] = 0.0;
+    return a;
+}
+
+// a <- a after b (b applied first): c = c_a + M_a c_b, M = M_a M_b
+template <int K>
+__device__ __forceinline__ void compose_after(ChunkMap<K> &a, const ChunkMap<K> &b)
+{
+    if constexpr (K == 1) {
+        a.c[0] = fma(a.m[0], b.c[0], a.c[0]);
+        a.m[0] = a.m[0] * b.m[0];
+    } else {
+        const double c0 = fma(a.m[1], b.c[1], fma(a.m[0], b.c[0], a.c[0]));
+        const double c1 = fma(a.m[3], b.c[1], fma(a.m[2], b.c[0], a.c[1]));
+        const double m0 = fma(a.m[1], b.m[2], a.m[0] * b.m[0]);
+        const double m1 = fma(a.m[1], b.m[3], a.m[0] * b.m[1]);
+        const double m2 = fma(a.m[3], b.m[2], a.m[2] * b.m[0]);
+        const double m3 = fma(a.m[3], b.m[3], a.m[2] * b.m[1]);
+        a.c[0] = c0;
+        a.c[1] = c1;
+        a.m[0] = m0;
+        a.m[1] = m1;
+        a.m[2] = m2;
+        a.m[3] = m3;
+    }
+}
+
+template <int K>
+__device__ __forceinline__ ChunkMap<K> shfl_up_map(const ChunkMap<K> &a, int d)
+{
+    ChunkMap<K> b;
+#pragma unroll
+    for (int q = 0; q < K * K; ++q) b.m[q] = __shfl_up(a.m[q], d, kWave);
+#pragma unroll
+    for (int q = 0; q < K; ++q) b.c[q] = __shfl_up(a.c[q], d, kWave);
+    return b;
+}
+
+// The chain over one block: lane l holds the map of the l-th chunk in the
+// chain's order (the identity past the block's last chunk).  An inclusive
+// scan of the maps across the wave (log2(64) rounds of composition with the
+// lane d below) gives every lane the composition of the maps up to its own;
+// lane l's entering state is the composition up to lane l-1 applied to y,
+// and y leaves as the composition of all 64.
+template <int K>
+__device__ __forceinline__ void chain_block(ChunkMap<K> a, int lane, double &y1, double &y2,
+                                            double &my1, double &my2)
+{
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const ChunkMap<K> b = shfl_up_map<K>(a, d);
+        if (lane >= d) compose_after<K>(a, b);
+    }
+    ChunkMap<K> p = shfl_up_map<K>(a, 1);
+    if (lane == 0) p = identity_map<K>();
+    if constexpr (K == 1) {
+        my1 = fma(p.m[0], y1, p.c[0]);
+        my2 = 0.0;
+        y1 = fma(__shfl(a.m[0], kWave - 1, kWave), y1, __shfl(a.c[0], kWave - 1, kWave));
+    } else {
+        my1 = fma(p.m[1], y2, fma(p.m[0], y1, p.c[0]));
+        my2 = fma(p.m[3], y2, fma(p.m[2], y1, p.c[1]));
+        const double t0 = __shfl(a.m[0], kWave - 1, kWave), t1 = __shfl(a.m[1], kWave - 1, kWave);
+        const double t2 = __shfl(a.m[2], kWave - 1, kWave), t3 = __shfl(a.m[3], kWave - 1, kWave);
+        const double c0 = __shfl(a.c[0], kWave - 1, kWave), c1 = __shfl(a.c[1], kWave - 1, kWave);
+        const double n1 = fma(t1, y2, fma(t0, y1, c0));
+        const double n2 = fma(t3, y2, fma(t2, y1, c1));
+        y1 = n1;
+        y2 = n2;
+    }
+}
+
+// Grid: exactly m workgroups of one wave (system k = blockIdx.x).
 template <int K, int C, bool CYC, class Src>
-__global__ __launch_bounds__(64) void long_scan_wave(const double *__restrict__ table, CyclicQ cq,
-                                                     LongGeom g, Src src, double *x)
+__global__ __launch_bounds__(64) void long_scan_spread(const double *__restrict__ table, CyclicQ cq,
+                                                       LongGeom g, Src src, double *x)
 {
     using SP = FromScalar<double>;
-    const int64_t k = blockIdx.x;   // one system per workgroup of one wave
-    if (k >= g.m) return;
+    const int64_t k = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t ld = g.ld;
     const int full = g.P - 1;
-    const int cpl = (full + kWave - 1) / kWave;   // <= kWaveScanMax (host checks)
-    const int j0 = lane * cpl;
-    const int nb = j0 < full ? (full - j0 < cpl ? full - j0 : cpl) : 0;
     const int na = num_arrays(K, CYC);
     const int64_t L = (int64_t)g.P * (C + 1);
     const typename SP::ptr tabs = SP::base((typename SP::ptr)table);
-    const typename SP::ptr Mf = tabs + na * L;
-    const typename SP::ptr Mb = Mf + (int64_t)g.P * K * K;
-    const typename SP::ptr Gm = Mb + (int64_t)g.P * K * K;
+    const double *Mf = table + opaque_v(0) + na * L;
+    const double *Mb = Mf + (int64_t)g.P * K * K;
+    const double *Gm = Mb + (int64_t)g.P * K * K;
 
-    // every scratch value of this lane's chunks, and the tail's rows
-    double e1[kWaveScanMax], e2[kWaveScanMax], o1[kWaveScanMax], o2[kWaveScanMax];
+    // forward: H_j written over e_j; lane l of block j0 holds chunk j0 + l
+    // (clamped to the last full chunk for the loads past it)
+    double h1 = 0.0, h2 = 0.0;
+    auto fwd_at = [&](int j) { return spread_fwd<K, C>(x, Mf, j < full ? j : full - 1, k, ld); };
+    SpreadFwd<K> cur = fwd_at(lane), nxt = fwd_at(kWave + lane);
+    for (int j0 = 0; j0 < full; j0 += kWave) {
+        const int cnt = full - j0 < kWave ? full - j0 : kWave;
+        // two blocks in flight ahead of the chain
+        const SpreadFwd<K> nn = fwd_at(j0 + 2 * kWave + lane);
+        ChunkMap<K> a = identity_map<K>();
+        if (lane < cnt) {
 #pragma unroll
-    for (int b = 0; b < kWaveScanMax; ++b) {
-        const int j = b < nb ? j0 + b : 0;
-        const double *p = x + (int64_t)j * C * ld + k;
-        e1[b] = b < nb ? p[0] : 0.0;
-        e2[b] = (K == 2 && b < nb) ? p[ld] : 0.0;
-        o1[b] = b < nb ? p[(int64_t)K * ld] : 0.0;
-        o2[b] = (K == 2 && b < nb) ? p[(int64_t)(K + 1) * ld] : 0.0;
+            for (int q = 0; q < K * K; ++q) a.m[q] = cur.m[q];
+            a.c[0] = cur.e1;
+            if constexpr (K == 2) a.c[1] = cur.e2;
+        }
+        double my1, my2;
+        chain_block<K>(a, lane, h1, h2, my1, my2);
+        if (lane < cnt) {
+            double *p = x + (int64_t)(j0 + lane) * C * ld + k;
+            p[0] = my1;
+            if constexpr (K == 2) p[ld] = my2;
+        }
+        cur = nxt;
+        nxt = nn;
     }
+    // the H_j stored by one lane are read back by another below
+    __threadfence_block();
+
+    // the tail chunk (every lane the same; lane 0 stores it, uncorrected if
+    // periodic)
     const int trow0 = full * C;
     const int nr = g.n - trow0;
-    double v[C];
-    src.template tail<C>(v, trow0, k, ld, g.n);
-
-    // forward: this lane's composition, the wave's exclusive scan, re-walk
-    Affine<K> a;
-    a.identity();
-    for (int b = 0; b < nb; ++b) {
-        const int j = j0 + b;
-        a.then(Mf + j * K * K, e1[b], e2[b]);
-    }
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const Affine<K> o = a.shfl_from(lane >= d ? lane - d : lane);
-        if (lane >= d) a.after(o);
-    }
-    const int prev = lane > 0 ? lane - 1 : 0;
-    double h1 = __shfl(a.c[0], prev, kWave), h2 = K == 2 ? __shfl(a.c[1], prev, kWave) : 0.0;
-    if (lane == 0) h1 = h2 = 0.0;
-    double hh1[kWaveScanMax], hh2[kWaveScanMax];
-#pragma unroll
-    for (int b = 0; b < kWaveScanMax; ++b) {
-        hh1[b] = h1;
-        hh2[b] = h2;
-        if (b < nb) {
-            double *p = x + (int64_t)(j0 + b) * C * ld + k;
-            p[0] = h1;
-            if constexpr (K == 2) p[ld] = h2;
-            const auto M = Mf + (j0 + b) * K * K;
-            affine<double, K>(M, h1, h2, e1[b], e2[b]);
-        }
-    }
-    // history of the tail: the inclusive composition of the last lane
-    const double th1 = __shfl(a.c[0], kWave - 1, kWave);
-    const double th2 = K == 2 ? __shfl(a.c[1], kWave - 1, kWave) : 0.0;
-
-    // the tail, as in long_scan (every lane, identical)
-    double yn1, yn2;
+    double yn1, yn2, f1, f2;
     {
+        double v[C];
+        src.template tail<C>(v, trow0, k, ld, g.n);
         const auto tp = lane_table<double, K, C, CYC>(SP::base(tabs), g.P, full);
-        double y1 = th1, y2 = th2;
+        double y1 = h1, y2 = h2;
         rows_up<C>([&](int t) {
             double y = tp.s[t] * v[t];
             if constexpr (K == 2) y = fma(tp.l2[t], y2, y);
@@ -516,7 +575,7 @@ __global__ __launch_bounds__(64) void long_scan_wave(const double *__restrict__ 
             y1 = y;
         });
         yn1 = pick(v, nr - 1);
-        yn2 = nr >= 2 ? pick(v, nr - 2) : th1;
+        yn2 = nr >= 2 ? pick(v, nr - 2) : h1;
         double x1 = 0.0, x2 = 0.0;
         rows_down<C>([&](int t) {
             double xx = v[t];
@@ -526,76 +585,59 @@ __global__ __launch_bounds__(64) void long_scan_wave(const double *__restrict__ 
             x1 = xx;
             v[t] = xx;
         });
+        f1 = v[0];
+        f2 = K == 2 ? v[1] : 0.0;
+        if (lane == 0) store_chunk<double, C, false>(v, x, trow0, k, ld, g.n);
     }
 
-    // backward: S_j, this lane's composition (last chunk first), the wave's
-    // exclusive scan from the top lane down, re-walk
-    double s1[kWaveScanMax], s2[kWaveScanMax];
-    Affine<K> bk;
-    bk.identity();
+    // backward: F_j written over o_j; lane l of block jt holds chunk jt - l
+    // (clamped to chunk 0)
+    auto bwd_at = [&](int j) { return spread_bwd<K, C>(x, Mb, Gm, j >= 0 ? j : 0, k, ld); };
+    SpreadBwd<K> bcur = bwd_at(full - 1 - lane), bnxt = bwd_at(full - 1 - kWave - lane);
+    for (int jt = full - 1; jt >= 0; jt -= kWave) {
+        const int cnt = jt + 1 < kWave ? jt + 1 : kWave;
+        const SpreadBwd<K> bnn = bwd_at(jt - 2 * kWave - lane);
+        ChunkMap<K> a = identity_map<K>();
+        if (lane < cnt) {
 #pragma unroll
-    for (int b = kWaveScanMax - 1; b >= 0; --b) {
-        s1[b] = 0.0;
-        s2[b] = 0.0;
-        if (b < nb) {
-            const auto G = Gm + (j0 + b) * K * K;
-            if constexpr (K == 1) {
-                s1[b] = fma(G[0], hh1[b], o1[b]);
-            } else {
-                s1[b] = fma(G[1], hh2[b], fma(G[0], hh1[b], o1[b]));
-                s2[b] = fma(G[3], hh2[b], fma(G[2], hh1[b], o2[b]));
-            }
-            bk.then(Mb + (j0 + b) * K * K, s1[b], s2[b]);
+            for (int q = 0; q < K * K; ++q) a.m[q] = bcur.m[q];
+            a.c[0] = bcur.s1;
+            if constexpr (K == 2) a.c[1] = bcur.s2;
         }
-    }
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const Affine<K> o = bk.shfl_from(lane + d < kWave ? lane + d : lane);
-        if (lane + d < kWave) bk.after(o);
-    }
-    // F entering this lane's last chunk: the lanes above applied to the
-    // tail's start state
-    const double ts1 = v[0], ts2 = K == 2 ? v[1] : 0.0;
-    const int nxt = lane + 1 < kWave ? lane + 1 : lane;
-    Affine<K> up = bk.shfl_from(nxt);
-    double f1 = ts1, f2 = ts2;
-    if (lane + 1 < kWave) {
-        if constexpr (K == 1) {
-            f1 = fma(up.m[0], ts1, up.c[0]);
-        } else {
-            f1 = fma(up.m[1], ts2, fma(up.m[0], ts1, up.c[0]));
-            f2 = fma(up.m[3], ts2, fma(up.m[2], ts1, up.c[1]));
+        double my1, my2;
+        chain_block<K>(a, lane, f1, f2, my1, my2);
+        if (lane < cnt) {
+            double *p = x + (int64_t)(jt - lane) * C * ld + k;
+            p[(int64_t)K * ld] = my1;
+            if constexpr (K == 2) p[(int64_t)(K + 1) * ld] = my2;
         }
+        bcur = bnxt;
+        bnxt = bnn;
     }
-#pragma unroll
-    for (int b = kWaveScanMax - 1; b >= 0; --b) {
-        if (b < nb) {
-            double *p = x + (int64_t)(j0 + b) * C * ld + k;
-            p[(int64_t)K * ld] = f1;
-            if constexpr (K == 2) p[(int64_t)(K + 1) * ld] = f2;
-            affine<double, K>(Mb + (j0 + b) * K * K, f1, f2, s1[b], s2[b]);
-        }
-    }
-    // (w_0, w_1): the start state of chunk 0, on lane 0
-    double c0 = 0.0, c1 = 0.0;
+
     if constexpr (CYC) {
-        const double w0 = __shfl(f1, 0, kWave), w1 = K == 2 ? __shfl(f2, 0, kWave) : 0.0;
         const double rn1 = yn1;
         const double rn2 = K == 2 ? fma(cq.u1_nm2, rn1, yn2) : 0.0;
-        correction_scalars<double, K>(cq, w0, w1, rn2, rn1, c0, c1);
-        for (int b = 0; b < nb; ++b) {
-            double *p = x + ((int64_t)(j0 + b) * C + 2 * K) * ld + k;
+        double c0 = 0.0, c1 = 0.0;
+        correction_scalars<double, K>(cq, f1, f2, rn2, rn1, c0, c1);
+        for (int j = lane; j < full; j += kWave) {
+            double *p = x + ((int64_t)j * C + 2 * K) * ld + k;
             p[0] = c0;
             if constexpr (K == 2) p[ld] = c1;
         }
-        const auto tp = lane_table<double, K, C, CYC>(SP::base(tabs), g.P, full);
-        rows_up<C>([&](int t) {
-            double xx = fma(tp.z0[t], c0, v[t]);
-            if constexpr (K == 2) xx = fma(tp.z1[t], c1, xx);
-            v[t] = xx;
-        });
+        if (lane == 0) {
+            // the tail again, corrected (this lane stored it above)
+            double v[C];
+            load_chunk<double, C, false>(v, x, trow0, k, ld, g.n);
+            const auto tp = lane_table<double, K, C, CYC>(SP::base(tabs), g.P, full);
+            rows_up<C>([&](int t) {
+                double xx = fma(tp.z0[t], c0, v[t]);
+                if constexpr (K == 2) xx = fma(tp.z1[t], c1, xx);
+                v[t] = xx;
+            });
+            store_chunk<double, C, false>(v, x, trow0, k, ld, g.n);
+        }
     }
-    if (lane == 0) store_chunk<double, C, false>(v, x, trow0, k, ld, g.n);
 }
 
 template <int K, int C, bool CYC, class Src>
@@ -610,11 +652,12 @@ hipError_t launch_long_c(const double *table, const CyclicQ &q, const LongGeom &
                        table, g, src, x);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // The wave-per-system scan (long_scan_wave) is not launched: its first
-    // GPU run faulted on a periodic pentadiagonal batch (n = 1025, m = 65)
-    // and the cause has not been found; every batch takes the lane scan.
-    hipLaunchKernelGGL((long_scan<K, C, CYC, Src>), dim3((unsigned)sblocks), dim3(threads), 0, s,
-                       table, q, g, src, x);
+    if (g.spread)
+        hipLaunchKernelGGL((long_scan_spread<K, C, CYC, Src>), dim3((unsigned)g.m), dim3(kWave), 0,
+                           s, table, q, g, src, x);
+    else
+        hipLaunchKernelGGL((long_scan<K, C, CYC, Src>), dim3((unsigned)sblocks), dim3(threads), 0,
+                           s, table, q, g, src, x);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((long_solve<K, C, CYC, Src>), dim3((unsigned)blocks), dim3(threads), 0, s,
                        table, g, src, x);

@@ -138,7 +138,7 @@ WORKLOADS = {
                                      oracle_max_n=1024),
     # long systems (beyond one launch's on-chip limit), small batches where
     # the paper hands the work to the CPU, and one large batch
-    "long_small_batch": dict(kind="long", ns=(4096, 8192, 16384), ms=(1, 8, 64),
+    "long_small_batch": dict(kind="long", ns=(4096, 8192, 16384), ms=(1, 8, 64, 512),
                              seed=SEED_BASE + 10),
     "long_tri_n8192_m65536": dict(kind="long", ns=(8192,), ms=(1 << 16,), seed=SEED_BASE + 11),
     # the FP64 tridiagonal sweep of the bench matrix (n = 512) over batch sizes

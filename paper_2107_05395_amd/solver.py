@@ -348,7 +348,7 @@ class Factor:
 
 
 TUNING_NAMES = ("max_chunk", "waves_per_system", "waves_per_block", "lockstep", "ch_uniform",
-                "grid_linear")
+                "grid_linear", "long_spread")
 
 
 def set_tuning(name: str, value: int | None) -> None:

@@ -291,9 +291,15 @@ Aff aff_of(const double *M, double e1, double e2, int K)
 }
 }  // namespace
 
-extern "C" int emu_solve_long_wave(int kind, const double *a, const double *b, const double *c,
-                                   const double *d, const double *e, int64_t n, int adjoint, int C,
-                                   const double *f, double *x)
+// The small-batch scan of long systems: blocks of 64 full chunks in the
+// chain's order (forward from chunk 0, backward from the last full chunk),
+// each block's affine maps scanned across the 64 lanes (Hillis-Steele, the
+// identity past the block's last chunk), the state entering a chunk being
+// the composition up to the previous lane applied to the block's entering
+// state.
+extern "C" int emu_solve_long_spread(int kind, const double *a, const double *b, const double *c,
+                                     const double *d, const double *e, int64_t n, int adjoint,
+                                     int C, const double *f, double *x)
 {
     bb::Factor F;
     std::string err;
@@ -303,8 +309,7 @@ extern "C" int emu_solve_long_wave(int kind, const double *a, const double *b, c
     const int K = F.K, W = 64;
     const int P = (int)((n + C - 1) / C);
     const int full = P - 1;
-    const int cpl = (full + W - 1) / W;
-    if (P < 2 || C < 3 * K || cpl > 8) return -100;
+    if (P < 2 || C < 3 * K) return -100;
     const bb::Direction &dir = adjoint ? F.adjoint : F.primal;
     const std::vector<double> tab = bb::build_table(dir, K, F.cyclic, n, C, P);
     const int64_t L = (int64_t)P * (C + 1);
@@ -327,41 +332,44 @@ extern "C" int emu_solve_long_wave(int kind, const double *a, const double *b, c
         }
         e1[j] = s1; e2[j] = s2; o1[j] = t1; o2[j] = t2;
     }
-    auto lo = [&](int l) { return std::min(l * cpl, full); };
-    auto hi = [&](int l) { return std::min((l + 1) * cpl, full); };
-    // forward: compositions, inclusive scan, exclusive history per lane
-    std::vector<Aff> A(W);
-    for (int l = 0; l < W; ++l) {
-        A[l] = aff_id();
-        for (int j = lo(l); j < hi(l); ++j) A[l] = aff_after(aff_of(Mf + j * K * K, e1[j], e2[j], K), A[l], K);
-    }
-    for (int dd = 1; dd < W; dd <<= 1) {
-        std::vector<Aff> B = A;
-        for (int l = dd; l < W; ++l) B[l] = aff_after(A[l], A[l - dd], K);
-        A = B;
-    }
-    std::vector<double> H1(full), H2(full);
-    for (int l = 0; l < W; ++l) {
-        double h1 = l ? A[l - 1].c[0] : 0.0, h2 = l ? A[l - 1].c[1] : 0.0;
-        for (int j = lo(l); j < hi(l); ++j) {
-            H1[j] = h1; H2[j] = h2;
-            const double *M = Mf + j * K * K;
-            if (K == 1) {
-                h1 = M[0] * h1 + e1[j];
-            } else {
-                const double n1 = M[0] * h1 + M[1] * h2 + e1[j], n2 = M[2] * h1 + M[3] * h2 + e2[j];
-                h1 = n1; h2 = n2;
-            }
+    // one block: maps[l] for l < cnt, identity beyond; returns the entering
+    // state of every lane and advances (y1, y2) past the block
+    auto block = [&](std::vector<Aff> maps, int cnt, double &y1, double &y2,
+                     std::vector<double> &in1, std::vector<double> &in2) {
+        for (int l = cnt; l < W; ++l) maps[l] = aff_id();
+        for (int dd = 1; dd < W; dd <<= 1) {
+            std::vector<Aff> B = maps;
+            for (int l = dd; l < W; ++l) B[l] = aff_after(maps[l], maps[l - dd], K);
+            maps = B;
         }
+        in1.assign(W, 0.0);
+        in2.assign(W, 0.0);
+        for (int l = 0; l < W; ++l) {
+            const Aff p = l ? maps[l - 1] : aff_id();
+            in1[l] = p.m[0] * y1 + (K == 2 ? p.m[1] * y2 : 0.0) + p.c[0];
+            in2[l] = K == 2 ? p.m[2] * y1 + p.m[3] * y2 + p.c[1] : 0.0;
+        }
+        const Aff &t = maps[W - 1];
+        const double n1 = t.m[0] * y1 + (K == 2 ? t.m[1] * y2 : 0.0) + t.c[0];
+        const double n2 = K == 2 ? t.m[2] * y1 + t.m[3] * y2 + t.c[1] : 0.0;
+        y1 = n1; y2 = n2;
+    };
+    std::vector<double> H1(full), H2(full), in1, in2;
+    double h1 = 0.0, h2 = 0.0;
+    for (int j0 = 0; j0 < full; j0 += W) {
+        const int cnt = std::min(W, full - j0);
+        std::vector<Aff> maps(W, aff_id());
+        for (int l = 0; l < cnt; ++l) maps[l] = aff_of(Mf + (j0 + l) * K * K, e1[j0 + l], e2[j0 + l], K);
+        block(maps, cnt, h1, h2, in1, in2);
+        for (int l = 0; l < cnt; ++l) { H1[j0 + l] = in1[l]; H2[j0 + l] = in2[l]; }
     }
-    const double th1 = A[W - 1].c[0], th2 = A[W - 1].c[1];
     // the tail
     const int64_t tr0 = (int64_t)full * C;
     const int nr = (int)(n - tr0);
     std::vector<double> v(C, 0.0);
     for (int t = 0; t < nr; ++t) v[t] = f[tr0 + t];
     {
-        double y1 = th1, y2 = th2;
+        double y1 = h1, y2 = h2;
         for (int t = 0; t < C; ++t) {
             double y = arr(qs, full, t) * v[t];
             if (K == 2) y += arr(ql + 1, full, t) * y2;
@@ -369,7 +377,7 @@ extern "C" int emu_solve_long_wave(int kind, const double *a, const double *b, c
             v[t] = y; y2 = y1; y1 = y;
         }
     }
-    const double yn1 = v[nr - 1], yn2 = nr >= 2 ? v[nr - 2] : th1;
+    const double yn1 = v[nr - 1], yn2 = nr >= 2 ? v[nr - 2] : h1;
     {
         double x1 = 0, x2 = 0;
         for (int t = C - 1; t >= 0; --t) {
@@ -379,45 +387,23 @@ extern "C" int emu_solve_long_wave(int kind, const double *a, const double *b, c
             x2 = x1; x1 = xx; v[t] = xx;
         }
     }
-    // backward: S_j, compositions from the last chunk, scan from the top lane
-    std::vector<double> S1(full), S2(full);
-    for (int j = 0; j < full; ++j) {
-        const double *g = G + j * K * K;
-        S1[j] = o1[j] + g[0] * H1[j] + (K == 2 ? g[1] * H2[j] : 0.0);
-        S2[j] = K == 2 ? o2[j] + g[2] * H1[j] + g[3] * H2[j] : 0.0;
-    }
-    std::vector<Aff> U(W);
-    for (int l = 0; l < W; ++l) {
-        U[l] = aff_id();
-        for (int j = hi(l) - 1; j >= lo(l); --j) U[l] = aff_after(aff_of(Mb + j * K * K, S1[j], S2[j], K), U[l], K);
-    }
-    for (int dd = 1; dd < W; dd <<= 1) {
-        std::vector<Aff> B = U;
-        for (int l = 0; l + dd < W; ++l) B[l] = aff_after(U[l], U[l + dd], K);
-        U = B;
-    }
+    // backward: S_j, blocks from the last full chunk down
     std::vector<double> F1(full), F2(full);
-    double w0 = 0, w1 = 0;
-    for (int l = 0; l < W; ++l) {
-        double f1 = v[0], f2 = K == 2 ? v[1] : 0.0;
-        if (l + 1 < W) {
-            const Aff &u = U[l + 1];
-            const double n1 = u.m[0] * v[0] + (K == 2 ? u.m[1] * v[1] : 0.0) + u.c[0];
-            const double n2 = K == 2 ? u.m[2] * v[0] + u.m[3] * v[1] + u.c[1] : 0.0;
-            f1 = n1; f2 = n2;
+    double f1 = v[0], f2 = K == 2 ? v[1] : 0.0;
+    for (int jt = full - 1; jt >= 0; jt -= W) {
+        const int cnt = std::min(W, jt + 1);
+        std::vector<Aff> maps(W, aff_id());
+        for (int l = 0; l < cnt; ++l) {
+            const int j = jt - l;
+            const double *g = G + j * K * K;
+            const double s1 = o1[j] + g[0] * H1[j] + (K == 2 ? g[1] * H2[j] : 0.0);
+            const double s2 = K == 2 ? o2[j] + g[2] * H1[j] + g[3] * H2[j] : 0.0;
+            maps[l] = aff_of(Mb + j * K * K, s1, s2, K);
         }
-        for (int j = hi(l) - 1; j >= lo(l); --j) {
-            F1[j] = f1; F2[j] = f2;
-            const double *M = Mb + j * K * K;
-            if (K == 1) {
-                f1 = M[0] * f1 + S1[j];
-            } else {
-                const double n1 = M[0] * f1 + M[1] * f2 + S1[j], n2 = M[2] * f1 + M[3] * f2 + S2[j];
-                f1 = n1; f2 = n2;
-            }
-        }
-        if (l == 0) { w0 = f1; w1 = f2; }
+        block(maps, cnt, f1, f2, in1, in2);
+        for (int l = 0; l < cnt; ++l) { F1[jt - l] = in1[l]; F2[jt - l] = in2[l]; }
     }
+    const double w0 = f1, w1 = f2;
     double c0 = 0, c1 = 0;
     if (F.cyclic) {
         const bb::CyclicQ &q = dir.cor.q;

@@ -242,7 +242,8 @@ def test_tuning_settings(L):
     restores the automatic choice; host only."""
     for name, good, bad in [(b"max_chunk", 32, 48), (b"waves_per_system", 4, 3),
                             (b"waves_per_block", 2, 8), (b"lockstep", 0, 2),
-                            (b"ch_uniform", 0, 5), (b"grid_linear", 1, -3)]:
+                            (b"ch_uniform", 0, 5), (b"grid_linear", 1, -3),
+                            (b"long_spread", 1, 2)]:
         assert L.bb_get_tuning(name) == -1
         assert L.bb_set_tuning(name, good) == 0 and L.bb_get_tuning(name) == good
         assert L.bb_set_tuning(name, bad) == -1 and L.bb_get_tuning(name) == good

@@ -37,7 +37,7 @@ def emu():
     P = ctypes.POINTER(ctypes.c_double)
     lib.emu_solve.argtypes = [ctypes.c_int] + [P] * 5 + [ctypes.c_int64, ctypes.c_int, ctypes.c_int, P, P]
     lib.emu_solve_long.argtypes = lib.emu_solve.argtypes
-    lib.emu_solve_long_wave.argtypes = lib.emu_solve.argtypes
+    lib.emu_solve_long_spread.argtypes = lib.emu_solve.argtypes
     return lib
 
 
@@ -101,18 +101,19 @@ def test_long_system_launches_match_oracle(emu, oracle, kind, adjoint, n, C):
 
 @pytest.mark.parametrize("kind", ["tri", "tri_cyclic", "penta", "penta_cyclic"])
 @pytest.mark.parametrize("adjoint", [0, 1])
-@pytest.mark.parametrize("n,C", [(33, 16), (100, 16), (1000, 16), (2049, 16), (4097, 16),
-                                 (8192, 32), (16000, 32), (16384, 32), (9000, 64)])
-def test_long_system_wave_scan_matches_oracle(emu, oracle, kind, adjoint, n, C):
-    """The small-batch scan (64 lanes composing their chunks' maps, scanned
-    across the wave) replayed on the host against the oracle: chunks per
-    lane from 1 to 8, empty lanes, tails of 1 .. C rows."""
+@pytest.mark.parametrize("n,C", [(33, 16), (100, 16), (1000, 16), (1040, 16), (1041, 16),
+                                 (2049, 16), (4097, 16), (8192, 32), (16000, 32), (16384, 32),
+                                 (9000, 64)])
+def test_long_system_spread_scan_matches_oracle(emu, oracle, kind, adjoint, n, C):
+    """The small-batch scan (blocks of 64 chunks whose affine maps are scanned
+    across the wave) replayed on the host against the oracle: one to eight
+    blocks, a last block of 1 .. 64 chunks, tails of 1 .. C rows."""
     cyclic = kind.endswith("cyclic")
     penta = kind.startswith("penta")
     kind_id = {"tri": 0, "tri_cyclic": 1, "penta": 2, "penta_cyclic": 3}[kind]
     bands = inputs.random_dominant_penta(n, seed=n + C) if penta else inputs.random_dominant_tri(n, seed=n + C)
     f = inputs.uniform_batch(n, 1, seed=13 * n + C)[:, 0]
-    x = run(emu, kind_id, bands, n, adjoint, C, f, entry="emu_solve_long_wave")
+    x = run(emu, kind_id, bands, n, adjoint, C, f, entry="emu_solve_long_spread")
     if penta:
         ref = (oracle.penta_adjoint if adjoint else oracle.penta_solve)(*bands, f[:, None], cyclic=cyclic)[:, 0]
     else:

@@ -71,6 +71,29 @@ def test_long_chunk_sizes(chunk, kind, n, tuning):
         assert err < 1e-12
 
 
+@pytest.mark.parametrize("kind,n,m", [("tri", 2049, 1), ("tri", 8192, 65), ("tri", 5000, 300),
+                                      ("penta", 1025, 1), ("penta", 4096, 64), ("penta", 3001, 129)])
+@pytest.mark.parametrize("cyclic", [False, True])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_long_scan_variants_match(kind, n, m, cyclic, adjoint, tuning):
+    """The two scans of a long solve -- one lane per system stepping through
+    its chunks, and one wave per system scanning 64 chunks' affine maps at a
+    time -- each against the oracle, and against each other (they differ
+    only in how the chunk-boundary recurrences are rounded)."""
+    say("long scans", kind, n, m, cyclic, adjoint)
+    f, bands = _make(kind, n, seed=2 * n + m, cyclic=cyclic)
+    rhs = dev(inputs.uniform_batch(n, m, seed=5 * n + m))
+    ref = _oracle(kind, bands, host(rhs), cyclic, adjoint)
+    outs = []
+    for spread in (0, 1):
+        tuning.set("long_spread", spread)
+        outs.append(host(f.adjoint(rhs) if adjoint else f.solve(rhs)))
+        err = rel_err(outs[-1], ref)
+        say("  spread", spread, err)
+        assert err < 1e-12
+    assert rel_err(outs[0], outs[1]) < 1e-13
+
+
 def test_long_large_batch_sampled():
     """A batch of 2^16 + 5 systems (1 GiB per array at n = 2048 penta): the
     large-batch chunk size, every 64-system group and the batch tail, checked
