@@ -82,8 +82,9 @@ typedef struct bb_factor_s *bb_factor;
  * on chip in one launch (its coefficient table staged in LDS).  Longer
  * ("long") systems are solved in three launches (a pass over every chunk of
  * C rows, a scan along each system, a second pass) with the solution array
- * as their scratch: FP64 only, out of place, one (forced) Cahn-Hilliard step
- * per call, no fused Crank-Nicolson steps (BB_ERR_UNSUPPORTED).
+ * as their scratch: FP64 only, out of place, one (forced) Cahn-Hilliard or
+ * Crank-Nicolson step per call (trajectories: one such step per stored state);
+ * other requests return BB_ERR_UNSUPPORTED.
  * Errors: BB_ERR_ARG (null pointer, n out of range), BB_ERR_ZERO_PIVOT,
  *         BB_ERR_SINGULAR_CAPACITANCE (cyclic), BB_ERR_OOM.  *out is set only on BB_OK. */
 bb_status bb_factor_shared_tri(const double *a, const double *b, const double *c, int64_t n,
@@ -293,8 +294,11 @@ bb_status bb_factor_ch(int64_t n, double length, double gamma, double dt, bb_fac
  * one-launch-per-step form (one read and one write of the batch per step).
  * w: host, 2K+1 finite doubles, read before the call returns.
  * c_in, c_out: device double, interleaved, same ld; c_in == c_out is allowed
- * (in place), any other overlap is not.  steps >= 1.
- * Errors: BB_ERR_ARG (w NULL or not finite, steps, sizes), BB_ERR_HIP. */
+ * (in place), any other overlap is not.  steps >= 1.  Long systems: one step
+ * per call (three launches, the right-hand side formed inside them), out of
+ * place.
+ * Errors: BB_ERR_ARG (w NULL or not finite, steps, sizes), BB_ERR_UNSUPPORTED
+ * (long system with steps != 1 or c_out == c_in), BB_ERR_HIP. */
 bb_status bb_cn_step(bb_factor f, const double *w, const double *c_in, double *c_out, int64_t m,
                      int64_t ld, int64_t steps, void *stream);
 
@@ -305,7 +309,8 @@ bb_status bb_cn_step(bb_factor f, const double *w, const double *c_in, double *c
  * steps = 1 (same kernel and decomposition).  With w the identity (w[K] = 1,
  * the rest 0) this is a trajectory of implicit solves A u_{s+1} = u_s, which
  * the recomputation between checkpoints of a differentiated rollout uses.
- * traj: device double, steps * n * ld elements, not overlapping c_in.
+ * traj: device double, steps * n * ld elements, not overlapping c_in.  Long
+ * systems: one three-launch step per state, each from the state before it.
  * Errors: as bb_cn_step, and BB_ERR_ARG if steps * n * ld overflows. */
 bb_status bb_cn_trajectory(bb_factor f, const double *w, const double *c_in, double *traj,
                            int64_t m, int64_t ld, int64_t steps, void *stream);
@@ -316,8 +321,9 @@ bb_status bb_cn_trajectory(bb_factor f, const double *w, const double *c_in, dou
  * launch of the fused stepper with the state on chip: lam_{s+1} goes to
  * traj + s * n * ld.  This is the backward pass of a rollout
  * u_{t+1} = A^{-1} u_t: for a loss of u_T, lam_s = dL/du_{T-s}.  Reads g once
- * and writes each state once.  Same sizes, layouts and errors as
- * bb_cn_trajectory (g, traj: device double; traj must not overlap g). */
+ * and writes each state once (long systems: one three-launch transposed
+ * solve per state).  Same sizes, layouts and errors as bb_cn_trajectory
+ * (g, traj: device double; traj must not overlap g). */
 bb_status bb_adjoint_trajectory(bb_factor f, const double *g, double *traj, int64_t m,
                                 int64_t ld, int64_t steps, void *stream);
 

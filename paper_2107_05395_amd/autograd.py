@@ -98,7 +98,13 @@ def _trajectory(f: Factor, u, k: int, precision: str):
 
 def _advance(f: Factor, u, k: int, precision: str):
     """u_{t+k} from u_t: k solves u' = A^{-1} u.  FP64 runs them in one launch
-    of the fused stepper (A u' = I u); other precisions solve step by step."""
+    of the fused stepper (A u' = I u), or for long systems as k single steps
+    of the same form (the steps the backward trajectory recomputes); other
+    precisions solve step by step."""
+    if precision == "f64" and f.long:
+        for _ in range(k):
+            u = f.cn_step(u, _identity(f), steps=1)
+        return u
     if precision == "f64":
         return f.cn_step(u, _identity(f), steps=k)
     for _ in range(k):

@@ -916,10 +916,39 @@ bb_status cn_steps(bb_factor fh, const double *w, const double *c_in, double *ou
     if (steps < 1) return fail(BB_ERR_ARG, "steps < 1");
     const int64_t stride = traj ? f.n * ld : 0;
     if (traj && steps > (int64_t(1) << 62) / stride) return fail(BB_ERR_ARG, "steps * n * ld overflows");
-    if (is_long(f)) return stepper_too_long(f);
+    if (is_long(f) && !traj && steps != 1)
+        return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(f.n) +
+                                             " (long system): one step per call");
+    if (is_long(f) && m > 0 && !traj && c_in == out)
+        return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(f.n) +
+                                             " (long system): c_out must not overlap c_in");
     if (m == 0) { g_last_error.clear(); return BB_OK; }
     int dev;
     if ((st = current_device(&dev)) != BB_OK) return st;
+    if (is_long(f)) {
+        // one three-launch step per step, each out of place: a trajectory
+        // steps from each stored state to the next
+        const int C = long_chunk(m);
+        bb::DeviceTable tab;
+        if ((st = long_table(f, dev, adjoint, C, &tab)) != BB_OK) return st;
+        const bb::LongGeom lg = long_geom(f, m, ld, C);
+        const bb::CyclicQ &q = adjoint ? f.adjoint.cor.q : f.primal.cor.q;
+        double wk[5] = {0, 0, 0, 0, 0};
+        for (int d = 0; d <= 2 * f.K; ++d) wk[d] = w[d];
+        const double *src = c_in;
+        for (int64_t s = 0; s < steps; ++s) {
+            double *dst = out + s * stride;
+            hipError_t e = f.K == 1
+                ? bb::launch_cn_tri_long(f.cyclic, (const double *)tab.ptr, q, lg, wk, src, dst,
+                                         (hipStream_t)stream)
+                : bb::launch_cn_penta_long(f.cyclic, (const double *)tab.ptr, q, lg, wk, src, dst,
+                                           (hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(e, "long-system Crank-Nicolson launch");
+            src = dst;
+        }
+        g_last_error.clear();
+        return BB_OK;
+    }
     StepPlan pl;
     bb::DeviceTable tab;
     bb::SweepGeom g;
@@ -1004,7 +1033,7 @@ bb_status bb_mse_loss_grad(const double *u, const double *target, double *grad, 
                            int64_t n, int64_t m, int64_t ld, void *workspace,
                            size_t workspace_bytes, void *stream)
 {
-    if (n < 1 || n > bb::kMaxN || m < 1 || ld < m) return fail(BB_ERR_ARG, "bad n, m or ld");
+    if (n < 1 || n > bb::kMaxNLong || m < 1 || ld < m) return fail(BB_ERR_ARG, "bad n, m or ld");
     if (!u || !target || !grad || !loss_dev) return fail(BB_ERR_ARG, "device pointer is NULL");
     const size_t need = bb::mse_workspace(n, m);
     if (workspace_bytes < need || !workspace) return fail(BB_ERR_ARG, "workspace too small");

@@ -155,14 +155,16 @@ __global__ __launch_bounds__(kFoldSubs * kWave) void band_grad_fold(int64_t tota
 constexpr int kMseCols = 1024;   // systems per block (4 per thread)
 
 // One block per (row, 1024 systems): the block grid is (columns, n).
-__global__ __launch_bounds__(256) void mse_partial(int64_t m, int64_t ld, double scale,
+__global__ __launch_bounds__(256) void mse_partial(int64_t n, int64_t m, int64_t ld, double scale,
                                                    const double *u,
                                                    const double *__restrict__ y,
                                                    double *grad,
                                                    double *__restrict__ part)
 {
     __shared__ double red[256 / kWave];
-    const int row = blockIdx.y;
+    // rows over grid y and z (a grid dimension y holds at most 65535 blocks)
+    const int row = (int)(blockIdx.z * gridDim.y + blockIdx.y);
+    if (row >= (int)n) return;   // whole blocks
     double acc = 0.0;
 #pragma unroll
     for (int r = 0; r < kMseCols / 256; ++r) {
@@ -399,8 +401,9 @@ hipError_t launch_mse(const double *u, const double *target, double *grad, doubl
 {
     const int64_t cols = (m + kMseCols - 1) / kMseCols;
     const double scale = 1.0 / ((double)n * (double)m);
-    hipLaunchKernelGGL(mse_partial, dim3((unsigned)cols, (unsigned)n), dim3(256), 0, s, m, ld,
-                       scale, u, target, grad, (double *)ws);
+    const int ny = n < 32768 ? n : 32768;
+    hipLaunchKernelGGL(mse_partial, dim3((unsigned)cols, (unsigned)ny, (unsigned)((n + ny - 1) / ny)),
+                       dim3(256), 0, s, (int64_t)n, m, ld, scale, u, target, grad, (double *)ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(mse_fold, dim3(1), dim3(256), 0, s, (int64_t)n * cols, scale,

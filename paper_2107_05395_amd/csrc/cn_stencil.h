@@ -5,6 +5,7 @@
 // instantiate it.
 #pragma once
 
+#include "long_core.h"
 #include "stepper.h"
 
 namespace bb {
@@ -80,6 +81,69 @@ hipError_t launch_cn_kc(const double *table, int64_t table_elems, const CyclicQ 
     }
     return launch_stepper<StencilRhs<K, CYC>, K, CYC>(table, table_elems, q, g, scalar, r, steps, in,
                                                       out, s);
+}
+
+// The stencil as the source of the long-system launches (one step per call):
+// a chunk's rows and the K rows on each side of it, read from the state
+// before the step -- wrapped mod n (periodic) or zero outside the system.
+// The halo takes the place of the wrap rows, so the policy sees every chunk
+// as an inner one.
+template <int K, bool CYC>
+struct StencilLongSrc {
+    StencilRhs<K, CYC> rhs;
+    const double *c;
+    __device__ __forceinline__ double row(int i, int64_t k, int64_t ld, int n) const
+    {
+        if constexpr (CYC) {
+            i = i < 0 ? i + n : (i >= n ? i - n : i);
+        } else {
+            if (i < 0 || i >= n) return 0.0;
+        }
+        return c[(int64_t)i * ld + k];
+    }
+    template <int C>
+    __device__ __forceinline__ void full(double (&v)[C], int row0, int64_t k, int64_t ld,
+                                         int n) const
+    {
+        load_chunk<double, C, true>(v, c, row0, k, ld, n);
+        Halo h{};
+        h.l1 = row(row0 - 1, k, ld, n);
+        h.l2 = row(row0 - 2, k, ld, n);
+        h.r1 = row(row0 + C, k, ld, n);
+        h.r2 = row(row0 + C + 1, k, ld, n);
+        rhs.template operator()<C, true>(v, h, 1, false, C, typename StencilRhs<K, CYC>::State{});
+    }
+    // the last chunk: rows row0 .. n-1 (row0 >= C); past row n-1 come rows
+    // 0, 1 (periodic) or nothing
+    template <int C>
+    __device__ __forceinline__ void tail(double (&v)[C], int row0, int64_t k, int64_t ld,
+                                         int n) const
+    {
+        load_chunk<double, C, false>(v, c, row0, k, ld, n);
+        Halo h{};
+        h.l1 = row(row0 - 1, k, ld, n);
+        h.l2 = row(row0 - 2, k, ld, n);
+        if constexpr (CYC) {
+            h.e0 = c[k];
+            h.e1 = c[ld + k];
+        }
+        rhs.template operator()<C, false>(v, h, 1, false, n - row0,
+                                          typename StencilRhs<K, CYC>::State{});
+    }
+};
+
+template <int K>
+hipError_t launch_cn_long_k(bool cyclic, const double *table, const CyclicQ &q, const LongGeom &g,
+                            const double *w, const double *in, double *out, hipStream_t s)
+{
+    if (cyclic) {
+        StencilLongSrc<K, true> src{{}, in};
+        for (int d = 0; d <= 2 * K; ++d) src.rhs.w[d] = w[d];
+        return launch_long_k<K, true>(table, q, g, src, out, s);
+    }
+    StencilLongSrc<K, false> src{{}, in};
+    for (int d = 0; d <= 2 * K; ++d) src.rhs.w[d] = w[d];
+    return launch_long_k<K, false>(table, q, g, src, out, s);
 }
 
 template <int K>

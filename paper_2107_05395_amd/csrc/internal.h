@@ -231,6 +231,14 @@ hipError_t launch_ch_forced_long(const double *table, const CyclicQ &q, const Lo
                                  double alpha, double dt, double dx, const double *v,
                                  const double *f0, const double *k, const double *c_in,
                                  double *c_out, hipStream_t stream);
+// One Crank-Nicolson step of long systems (A c' = B c, B the stencil w of
+// 2K+1 weights, periodic when the factor is), the right-hand side formed
+// from c_in wherever the long-system launches read it; out must not overlap
+// in.
+hipError_t launch_cn_tri_long(bool cyclic, const double *table, const CyclicQ &q, const LongGeom &g,
+                              const double *w, const double *in, double *out, hipStream_t s);
+hipError_t launch_cn_penta_long(bool cyclic, const double *table, const CyclicQ &q, const LongGeom &g,
+                                const double *w, const double *in, double *out, hipStream_t s);
 
 // Copy of `bytes` (a multiple of 16) in contiguous 16 KB tiles per workgroup:
 // the streaming reference the sweeps' HBM rate is compared with.

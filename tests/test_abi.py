@@ -135,7 +135,8 @@ def test_long_systems_host_checks(L):
     assert L.bb_ch_forced_step(ch, fake, other, 4, 4, 1e-4, dx, ws, ws, ws, 2, None) == -6
     assert L.bb_ch_forced_step(ch, fake, fake, 4, 4, 1e-4, dx, ws, ws, ws, 1, None) == -6
     w5 = (ctypes.c_double * 5)(0.0, 0.0, 1.0, 0.0, 0.0)
-    assert L.bb_cn_step(ch, w5, fake, other, 4, 4, 1, None) == -6           # no long CN steps
+    assert L.bb_cn_step(ch, w5, fake, other, 4, 4, 2, None) == -6           # one CN step per call
+    assert L.bb_cn_step(ch, w5, fake, fake, 4, 4, 1, None) == -6            # in place
     L.bb_factor_destroy(ch)
     h = ctypes.c_void_p()
     assert L.bb_factor_shared_tri(None, None, None, 4, ctypes.byref(h)) == -1

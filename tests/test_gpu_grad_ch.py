@@ -43,9 +43,11 @@ def test_band_grad(kind, cyclic, n, m):
     assert np.max(np.abs(host(g2) - 2 * ref)) < 2e-13 * scale
 
 
-def test_mse_loss_grad():
+@pytest.mark.parametrize("n,m", [(333, 1234), (70001, 3)])
+def test_mse_loss_grad(n, m):
+    """Loss and gradient against numpy; 70001 rows take the grid's third
+    dimension (rows beyond one grid dimension's 65535 blocks)."""
     from paper_2107_05395_amd import mse_loss_grad
-    n, m = 333, 1234
     u = inputs.uniform_batch(n, m, seed=3)
     y = inputs.uniform_batch(n, m, seed=4)
     loss, grad = mse_loss_grad(dev(u), dev(y))
