@@ -89,6 +89,32 @@ def time_launches(fn, steps, warmup, torch):
     return start.elapsed_time(stop) / 1e3, wall
 
 
+def launch_stats(fn, reps, torch):
+    """Median, minimum and maximum of `reps` single launches, each bracketed
+    by its own pair of events on the current stream (ms)."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    torch.cuda.synchronize()
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in evs)
+    return {"median": ms[len(ms) // 2], "min": ms[0], "max": ms[-1], "launches": reps}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline_tri(bands, n, seed, budget_s):
     """The oracle as it stands on the host cores, on a bounded sample."""
     import oracle
@@ -183,6 +209,8 @@ def bench_tri(args, torch):
     t64 = results["f64"]["seconds"]
     per_launch = t64 / k
     traffic = measured_traffic(args.workload, "f64", "sweep")
+    # the same solve launch by launch: median and minimum over the repeats
+    stats = launch_stats(lambda: f.solve(rhs, out=x), k, torch)
     line = {
         "metric": "systems solved/s", "value": m * k / t64, "unit": "systems/s",
         "n_gpus": 1, "steps": k, "warmup": args.warmup, "ms_per_step": 1e3 * per_launch,
@@ -192,6 +220,7 @@ def bench_tri(args, torch):
                    "matrix": "tridiagonal (-r, 1+2r, -r), zero Dirichlet", "parallelism": "none"},
         "rel_err_vs_oracle": results["f64"]["err"],
         "hbm_gbs_algorithmic": algo_bytes / per_launch / 1e9,
+        "launch_ms": stats,
         "f32r": {"value": m * k / results["f32r"]["seconds"], "unit": "systems/s",
                  "ms_per_step": 1e3 * results["f32r"]["seconds"] / k,
                  "rel_err_vs_oracle": results["f32r"]["err"],
@@ -261,6 +290,7 @@ def bench_penta(args, torch):
     rows_gbs = algo_bytes * 10 / rt / 1e9
     k = args.steps
     per = out["f64"][0] / k
+    stats = launch_stats(lambda: f.solve(rhs, out=x), k, torch)
     line = {
         "metric": "systems solved/s", "value": m * k / out["f64"][0], "unit": "systems/s",
         "n_gpus": 1, "steps": k, "warmup": args.warmup, "ms_per_step": 1e3 * per,
@@ -268,6 +298,7 @@ def bench_penta(args, torch):
         "data": "synthetic (random-phase sums of 8 sine modes)",
         "config": {"workload": args.workload, "n": n, "m": m, "r": r},
         "rel_err_vs_oracle": out["f64"][1],
+        "launch_ms": stats,
         "f32r": {"value": m * k / out["f32r"][0], "rel_err_vs_oracle": out["f32r"][1],
                  "ms_per_step": 1e3 * out["f32r"][0] / k},
         "f32rhs": {"value": m * k / out["f32rhs"][0], "rel_err_vs_oracle": out["f32rhs"][1],
@@ -1085,6 +1116,8 @@ def main():
     else:
         sys.exit("workload %s is not a bench workload" % args.workload)
     line["device"] = torch.cuda.get_device_name(0)
+    if isinstance(line.get("cpu_baseline"), dict):
+        line["cpu_baseline"]["cpu_model"] = cpu_model()
     print(json.dumps(line), flush=True)
 
 
