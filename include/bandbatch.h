@@ -373,7 +373,7 @@ bb_status bb_mse_loss_grad(const double *u, const double *target, double *grad, 
  *                       the scalar cache
  *   "grid_linear"       0 / 1: persistent grids / one workgroup per group
  *   "long_spread"       0 / 1: the scan of long systems with one lane per system
- *                       / one wave per system (automatic: a wave for m <= 1024)
+ *                       / one wave per system (automatic: a wave for m < 4096)
  * The settings are read when a call enqueues its launches; change them only
  * between calls.  Errors: BB_ERR_ARG (unknown name, invalid value). */
 bb_status bb_set_tuning(const char *name, int64_t value);

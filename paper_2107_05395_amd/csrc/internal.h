@@ -214,7 +214,10 @@ struct LongGeom {
     int64_t groups;     // groups of 64 systems
     bool spread;        // scan with one wave per system (small batches, m <= kSpreadMax)
 };
-constexpr int64_t kSpreadMax = 1024;
+// One wave per system scans faster than one lane per system up to 2048 systems
+// (32-row chunks) and slower from 4096 on (64-row chunks): the same boundary
+// as the chunk size.
+constexpr int64_t kSpreadMax = 4095;
 constexpr int64_t kMaxNLong = int64_t(1) << 18;
 hipError_t launch_long_solve(int K, bool cyclic, const double *table, const CyclicQ &q,
                              const LongGeom &g, const double *rhs, double *x, hipStream_t stream);
