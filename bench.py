@@ -237,6 +237,7 @@ def bench_tri(args, torch):
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": algo_bytes / per_launch / 1e9 / PEAK_HBM_GBS,
                      "traffic": traffic,
+                     "counter_gbs": traffic / per_launch / 1e9 if traffic else None,
                      "kernel": "sweep_kernel<double,1,%d,false,full>" % f.chunk(),
                      "algorithmic_bytes_per_launch": algo_bytes,
                      "torch_copy_gbs": copy_gbs,
@@ -310,6 +311,8 @@ def bench_penta(args, torch):
         "roofline": {"bound": "hbm", "achieved": algo_bytes / per / 1e9, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": algo_bytes / per / 1e9 / PEAK_HBM_GBS,
                      "traffic": measured_traffic(args.workload, "f64", "sweep"),
+                     "counter_gbs": (measured_traffic(args.workload, "f64", "sweep") / per / 1e9
+                                     if measured_traffic(args.workload, "f64", "sweep") else None),
                      "pattern_copy_gbs": rows_gbs,
                      "frac_of_pattern_copy": algo_bytes / per / 1e9 / rows_gbs},
     }
