@@ -252,11 +252,8 @@ extern "C" int emu_solve_long(int kind, const double *a, const double *b, const 
     return 0;
 }
 
-// The small-batch scan of long systems (long_scan_wave): lane l composes the
-// affine maps of its full chunks, the 64 lanes scan the compositions
-// (Kogge-Stone, forward and from the top lane down), and each lane re-walks
-// its chunks; reduce and solve as in emu_solve_long.  Compared with the
-// oracle, this checks the composition order and the exclusive scans.
+// Affine maps y -> c + M y of the chunks, for the small-batch scan of long
+// systems below (long_scan_spread); reduce and solve as in emu_solve_long.
 namespace {
 struct Aff {
     double m[4], c[2];
