@@ -12,14 +12,15 @@
 //          state o_j (dot products with the table's weights), written to rows
 //          r0 .. r0+2K-1 of the solution array x, which serves as the scratch
 //          of the launch sequence;
-//   scan   (one lane per system): H_j (prefix over the full chunks,
+//   scan   (one lane per system, or one wave per system for small
+//          batches, long_scan_spread): H_j (prefix over the full chunks,
 //          H_{j+1} = e_j + Mf_j H_j) written over e_j; the tail chunk solved
 //          in registers from its history H_{P-1}; then S_j = o_j + G_j H_j and
 //          the future F_j (suffix, F_{j-1} = S_j + Mb_j F_j, F_{P-2} = the
 //          tail's start state) written over o_j; for periodic systems the
 //          correction scalars c = Q (w_0, w_1, w_{n-2}, w_{n-1}) written to
 //          rows r0+2K .. r0+3K-1 of every full chunk; the tail's solution
-//          stored;
+//          stored (and corrected, periodic);
 //   solve  (one wave per full chunk and group): forward pass from H_j,
 //          backward pass from F_j with the correction fused, solution stored
 //          over the chunk (the reads of H_j, F_j and c come first).
