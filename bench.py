@@ -279,9 +279,9 @@ def bench_penta(args, torch):
     del rhs32
     # the same batch in arrays with a leading dimension of m + 32 (rows no
     # longer a power of two apart; the library takes any ld >= m)
-    pad = 32
-    rp = torch.empty(n, m + pad, dtype=torch.float64, device="cuda")[:, :m]
-    xp = torch.empty(n, m + pad, dtype=torch.float64, device="cuda")[:, :m]
+    from paper_2107_05395_amd import empty_batch
+    rp, xp = empty_batch(n, m), empty_batch(n, m)
+    pad = rp.stride(0) - m
     rp.copy_(rhs)
     tpad, _ = time_launches(lambda: f.solve(rp, out=xp), args.steps, args.warmup, torch)
     err_pad = rel_err_cols(xp[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref)

@@ -14,7 +14,8 @@ from ._lib import BandBatchError  # noqa: F401  (no library load at import)
 
 
 def __getattr__(name):
-    if name in ("Factor", "mse_loss_grad", "max_n", "KINDS", "set_tuning", "get_tuning"):
+    if name in ("Factor", "mse_loss_grad", "max_n", "KINDS", "set_tuning", "get_tuning",
+                "empty_batch"):
         from . import solver
         return getattr(solver, name)
     if name in ("banded_solve", "banded_rollout", "mse_loss", "BandedSolve", "BandedRollout"):

@@ -91,3 +91,16 @@ def test_plan_argument_errors(L):
     assert L.bb_plan(h, 10, 0, 9, ctypes.byref(out), None, None, None) == -1
     assert L.bb_plan(h, 10, 0, 0, None, None, None, None) == 0
     L.bb_factor_destroy(h)
+
+
+def test_empty_batch_pads_rows_at_64k_strides():
+    """empty_batch: an (n, m) view with ld = m + 32 where the row's byte
+    stride is a multiple of 64 KiB, ld = m otherwise, or the padding asked for."""
+    import torch
+    from paper_2107_05395_amd import empty_batch
+    t = empty_batch(8, 1 << 18, device="cpu")
+    assert t.shape == (8, 1 << 18) and t.stride() == ((1 << 18) + 32, 1)
+    assert empty_batch(8, 1000, device="cpu").stride() == (1000, 1)
+    assert empty_batch(8, 8192, dtype=torch.float32, device="cpu").stride() == (8192, 1)
+    assert empty_batch(8, 16384, dtype=torch.float32, device="cpu").stride() == (16384 + 32, 1)
+    assert empty_batch(8, 100, device="cpu", pad=7).stride() == (107, 1)
