@@ -267,6 +267,7 @@ bb::LongGeom long_geom(const bb::Factor &f, int64_t m, int64_t ld, int C)
     // each, 64 chunks per round trip to memory), else one lane per system
     const int64_t sp = bb::tuning(bb::kTuneLongSpread);
     g.spread = sp >= 0 ? sp == 1 : m <= bb::kSpreadMax;
+    g.halves = m >= bb::kHalvesMin;
     return g;
 }
 

@@ -213,7 +213,9 @@ struct LongGeom {
     int64_t m, ld;      // systems, leading dimension
     int64_t groups;     // groups of 64 systems
     bool spread;        // scan with one wave per system (small batches, m <= kSpreadMax)
+    bool halves;        // reduce / solve waves on two 32-system segments (m >= kHalvesMin)
 };
+constexpr int64_t kHalvesMin = 8192;
 // One wave per system scans faster than one lane per system up to 2048 systems
 // (32-row chunks) and slower from 4096 on (64-row chunks): the same boundary
 // as the chunk size.

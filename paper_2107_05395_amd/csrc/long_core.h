@@ -25,10 +25,10 @@
 //          backward pass from F_j with the correction fused, solution stored
 //          over the chunk (the reads of H_j, F_j and c come first).
 //
-// Every wave of reduce and solve works on one chunk of 64 systems, so each
-// row is one 512-byte coalesced access and every coefficient is the same for
-// the whole wave: the table is read through the scalar cache and may have
-// any size.  HBM traffic: the right-hand side read twice and the solution
+// Every wave of reduce and solve works on one chunk of 64 systems (one
+// 512-byte segment per row, or two 256-byte ones for large batches), so
+// every coefficient is the same for the whole wave: the table is read
+// through the scalar cache and may have any size.  HBM traffic: the right-hand side read twice and the solution
 // written once (24 B per row in double) plus 2K doubles per chunk of
 // scratch, against 16 B for the one-launch sweep.  x must not overlap the
 // right-hand side.
@@ -66,9 +66,13 @@ __device__ __forceinline__ LongTable<K, C, CYC> long_table(const double *table, 
     return lane_table<double, K, C, CYC>(Src::base((typename Src::ptr)table), P, j);
 }
 
-// Wave w of a reduce or solve launch: chunk j = w / groups (wave-uniform),
-// group w % groups, so neighbouring waves read neighbouring 512-byte
-// segments of the same rows.
+// Wave w of a reduce or solve launch: chunk j = w / groups (wave-uniform)
+// and group w % groups of 64 systems, neighbouring waves on neighbouring
+// systems of the same rows.  With g.halves the 64 lanes of group p are
+// systems 32p .. 32p+31 and 32(groups + p) .. 32(groups + p)+31: two
+// 256-byte segments per row instead of one 512-byte one, which large batches
+// stream faster (tri n = 8192, m = 2^16: 2.37 against 2.86 ms per solve;
+// slower at m = 4096).
 struct LongWave {
     int j;
     int64_t k;
@@ -83,7 +87,13 @@ __device__ __forceinline__ LongWave long_wave(const LongGeom &g)
     lw.valid = w < total;
     const int64_t ww = lw.valid ? w : 0;
     lw.j = __builtin_amdgcn_readfirstlane((int)(ww / g.groups));
-    lw.k = (ww % g.groups) * kWave + threadIdx.x % kWave;
+    const int64_t grp = ww % g.groups;
+    const int lane = threadIdx.x % kWave;
+    if (g.halves)
+        lw.k = lane < kWave / 2 ? grp * (kWave / 2) + lane
+                                : (g.groups + grp) * (kWave / 2) + (lane - kWave / 2);
+    else
+        lw.k = grp * kWave + lane;
     return lw;
 }
 

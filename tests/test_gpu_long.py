@@ -134,7 +134,7 @@ def test_long_rejects_in_place_and_other_precisions():
         f.solve(t, precision="f32r")
 
 
-@pytest.mark.parametrize("n,m", [(2048, 100), (4096, 70), (8192, 3), (3000, 64)])
+@pytest.mark.parametrize("n,m", [(2048, 100), (4096, 70), (8192, 3), (3000, 64), (2048, 8195)])
 def test_long_cahn_hilliard_steps_match_oracle(n, m):
     """The Section 5.1 step of long periodic systems (right-hand side formed
     inside the launches from the state and its neighbour rows), two steps
@@ -206,7 +206,8 @@ def test_long_forced_run_alternates_buffers():
 
 
 @pytest.mark.parametrize("kind,n,m", [("tri", 2049, 70), ("tri", 5000, 3), ("penta", 1025, 65),
-                                      ("penta", 3001, 129), ("penta", 8192, 1)])
+                                      ("penta", 3001, 129), ("penta", 8192, 1),
+                                      ("tri", 2100, 8193)])
 @pytest.mark.parametrize("cyclic", [False, True])
 def test_long_cn_steps_match_oracle(kind, n, m, cyclic):
     """Crank-Nicolson steps A c' = B c of long systems (the stencil formed
