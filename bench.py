@@ -755,12 +755,14 @@ def bench_adjoint(args, torch):
     # algorithmic HBM bytes of one FP64 training step: the forward pass in
     # ceil(T/c) fused launches (read the checkpoint, write the next one or
     # u_T: 16 B per row each); per segment one trajectory launch recomputing
-    # the states and one stepping the adjoints on A^T (each reads its start
-    # once, 8 B per row, and writes every state, 8 B per row and step); T
-    # band-gradient reductions (read lambda and u: 16 B per row) and the loss
-    # (read u and target, write the gradient: 24 B per row)
+    # the states (read the checkpoint, write every state: 8 B per row and
+    # step) and one stepping the adjoints on A^T with the band gradients
+    # reduced as it goes (read the incoming adjoint and every state, write
+    # the outgoing adjoint); the loss (read u and target, write the
+    # gradient: 24 B per row).  The groups' partial sums of the band
+    # gradients (about 1.5 B per row and segment here) are not counted.
     segments = -(-T // every)
-    step_bytes = (32.0 * segments + 32.0 * T + 24.0) * n * m
+    step_bytes = (40.0 * segments + 16.0 * T + 24.0) * n * m
     return {
         "roofline": {"bound": "hbm", "achieved": step_bytes * k / t64 / 1e9, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": step_bytes * k / t64 / 1e9 / PEAK_HBM_GBS,

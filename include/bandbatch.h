@@ -327,6 +327,41 @@ bb_status bb_cn_trajectory(bb_factor f, const double *w, const double *c_in, dou
 bb_status bb_adjoint_trajectory(bb_factor f, const double *g, double *traj, int64_t m,
                                 int64_t ld, int64_t steps, void *stream);
 
+/* The backward pass over one stretch of a rollout u_t = A^{-1} u_{t-1}
+ * (t = 1 .. T, T = steps), adjoints and band gradients together: the adjoint
+ * recursion of bb_adjoint_trajectory, d_{t-1} = A^{-T} d_t from d_T = g
+ * (d_t = dL/du_t), fused with the reduction of bb_band_grad for every step,
+ *     grad_bands[band*n + i] += -sum_t sum_k d_{t-1}[i,k] u_t[i + band - nb/2, k]
+ * (the adjoint of each solve is A^{-T} d_t = d_{t-1}; nb = 3 or 5; entries
+ * outside a non-cyclic matrix receive nothing, cyclic column indices wrap mod
+ * n).  This is the FP64 backward of a checkpointed differentiable rollout
+ * (the adjoint recursion and its gradient with respect to the shared bands,
+ * the extension of the batched solves to gradients).  Outputs d_0 = dL/du_0 at lam.
+ * traj: the forward states u_1 .. u_T, state u_t at traj + (t-1) * n * ld
+ * (what bb_cn_trajectory writes from u_0 with the identity stencil); g, lam:
+ * interleaved n x ld, lam may be g, traj must not overlap lam.
+ * Where the fused steppers hold a system on chip in split groups or one chunk
+ * per wave (bb_adjoint_band_grad_fused), one kernel steps the adjoints with
+ * each chunk in registers and reduces d_{t-1} u_t over each group's systems
+ * after every step: it reads g and every u_t once and writes lam and the
+ * groups' partial sums once (no adjoint states in memory), then a
+ * fixed-order fold adds the groups into grad_bands.  Otherwise each step is a
+ * transposed solve into the workspace or lam followed by bb_band_grad's
+ * reduction.  The adjoints equal bb_adjoint_trajectory's bitwise; the band
+ * gradients sum in a fixed order (bitwise reproducible), which differs
+ * between the two paths, so they agree with bb_band_grad's to rounding.
+ * workspace: device scratch of at least
+ * bb_adjoint_band_grad_workspace_bytes(f, m, ld) bytes, caller-owned.
+ * Errors: BB_ERR_ARG (null pointer, sizes, steps < 1, workspace too small),
+ * BB_ERR_HIP, BB_ERR_OOM (first table upload). */
+bb_status bb_adjoint_band_grad(bb_factor f, const double *g, const double *traj, double *lam,
+                               int64_t m, int64_t ld, int64_t steps, double *grad_bands,
+                               void *workspace, size_t workspace_bytes, void *stream);
+size_t bb_adjoint_band_grad_workspace_bytes(bb_factor f, int64_t m, int64_t ld);
+/* 1 if bb_adjoint_band_grad with m systems runs the fused kernel, else 0
+ * (host only). */
+int32_t bb_adjoint_band_grad_fused(bb_factor f, int64_t m);
+
 /* ---------------------------------------------------------------- measurement
  * A measurement utility, not part of the method: copy `bytes` from src to
  * dst (device, 16-byte aligned, not overlapping; bytes a multiple of 16) with

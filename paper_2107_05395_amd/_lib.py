@@ -51,6 +51,10 @@ SIGNATURES = {
     "bb_cn_step": (_S, [_FACTOR, _P, _P, _P, _I64, _I64, _I64, _P]),
     "bb_cn_trajectory": (_S, [_FACTOR, _P, _P, _P, _I64, _I64, _I64, _P]),
     "bb_adjoint_trajectory": (_S, [_FACTOR, _P, _P, _I64, _I64, _I64, _P]),
+    "bb_adjoint_band_grad": (_S, [_FACTOR, _P, _P, _P, _I64, _I64, _I64, _P, _P, ctypes.c_size_t,
+                                  _P]),
+    "bb_adjoint_band_grad_workspace_bytes": (ctypes.c_size_t, [_FACTOR, _I64, _I64]),
+    "bb_adjoint_band_grad_fused": (ctypes.c_int32, [_FACTOR, _I64]),
     "bb_copy_tiles": (_S, [_P, _P, _I64, _P]),
     "bb_copy_rows": (_S, [_P, _P, _I64, _I64, _I64, _P]),
     "bb_ch_stats_workspace_bytes": (ctypes.c_size_t, [_FACTOR, _I64, _I64]),

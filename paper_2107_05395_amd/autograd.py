@@ -15,10 +15,10 @@ on chip, and the recomputation of a segment one launch of the same kernel
 that also stores every intermediate state.  A fused launch of k steps, a
 trajectory launch and k single-step launches agree bitwise (same kernel
 arithmetic and decomposition), so the recomputed states equal the forward's.
-The adjoint recursion lam_t = A^{-T} lam_{t+1} is stepped the same way: one
-launch per segment of the same kernel on the factor's transposed solve
-(bb_adjoint_trajectory), after which the segment's band gradients reduce
-lam_t against u_t.
+The adjoint recursion lam_t = A^{-T} lam_{t+1} is stepped the same way,
+one launch per segment on the factor's transposed solve, and the same launch
+reduces each adjoint against its recomputed state into the band gradients
+(bb_adjoint_band_grad): no adjoint state is written to memory.
 """
 from __future__ import annotations
 
@@ -141,12 +141,13 @@ class BandedRollout(torch.autograd.Function):
         f, steps, every, prec = ctx.factor, ctx.steps, ctx.every, ctx.precision
         g = g_out.contiguous()
         main = torch.cuda.current_stream(g.device)
-        # The band-gradient reductions depend only on lam_t and u_t, not on the
-        # next adjoint solve: they run on a second stream so they overlap the
-        # chain of solves; their order among themselves, and so the sums, stay
-        # fixed.  The states of the next segment (walking backwards) depend
-        # only on its checkpoint: they are recomputed on a third stream while
-        # the current segment's adjoints run.  All streams default priority.
+        # The states of the next segment (walking backwards) depend only on
+        # its checkpoint: they are recomputed on a second stream while the
+        # current segment's adjoints run.  Outside FP64 the band-gradient
+        # reductions, which depend only on lam_t and u_t and not on the next
+        # adjoint solve, run on a third stream beside the chain of solves;
+        # their order among themselves, and so the sums, stay fixed.  All
+        # streams default priority.
         side = _side_stream(g.device, 0)
         ahead = _side_stream(g.device, 1)
         side.wait_stream(main)
@@ -154,16 +155,20 @@ class BandedRollout(torch.autograd.Function):
         gb = torch.zeros(f.nbands, f.n, dtype=torch.float64, device=g.device)
         gb.record_stream(side)
 
-        def recompute(i):
-            # states u_s .. u_e of segment i from checkpoint i, on `ahead`
-            s = i * every
-            with torch.cuda.stream(ahead):
-                return [ctx.checkpoints[i]] + _trajectory(f, ctx.checkpoints[i],
-                                                          min(s + every, steps) - s, prec)
-
-        # FP64: the adjoints of a segment as one trajectory of transposed
-        # solves with the factor's own A^T = U^T L^T
+        # FP64: the adjoints of a segment and their band gradients in one
+        # call (bb_adjoint_band_grad: transposed solves with the factor's own
+        # A^T = U^T L^T, reduced against the recomputed states as they go)
         traj = prec == "f64"
+
+        def recompute(i):
+            # states of segment i from checkpoint i, on `ahead`: FP64 the
+            # (k, n, m) trajectory u_{s+1} .. u_e, else the list u_s .. u_e
+            s = i * every
+            k = min(s + every, steps) - s
+            with torch.cuda.stream(ahead):
+                if traj:
+                    return f.cn_trajectory(ctx.checkpoints[i], _identity(f), k)
+                return [ctx.checkpoints[i]] + _trajectory(f, ctx.checkpoints[i], k, prec)
 
         # segments [s, e): states u_s .. u_e; checkpoint i holds u_{i*every}
         last = len(ctx.checkpoints) - 1
@@ -173,20 +178,16 @@ class BandedRollout(torch.autograd.Function):
             e = min(s + every, steps)
             main.wait_stream(ahead)                 # this segment's states are ready
             states = pending
-            for u in states:
-                u.record_stream(main)
+            if traj:
+                states.record_stream(main)
+            else:
+                for u in states:
+                    u.record_stream(main)
             pending = recompute(i - 1) if i > 0 else None
             if traj:
-                # lams[j] = lam_{e-j} = A^{-T} lam_{e-j+1}, lam_{e+1} = g
-                lams = list(f.adjoint_trajectory(g, e - s).unbind(0))
-                side.wait_stream(main)
-                with torch.cuda.stream(side):
-                    for j, lam in enumerate(lams):
-                        f.band_grad(lam, states[e - s - j], gb)
-                for j, lam in enumerate(lams):
-                    lam.record_stream(side)
-                    states[e - s - j].record_stream(side)
-                g = lams[-1]
+                # d_{t-1} = A^{-T} d_t for t = e .. s+1 from d_e = g, with
+                # gb += -sum_t d_{t-1} u_t^T over the segment
+                g, _ = f.adjoint_band_grad(g, states, gb)
                 del states
                 continue
             for t in range(e, s, -1):          # u_t = A^{-1} u_{t-1}

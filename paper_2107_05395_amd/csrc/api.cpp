@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/bandbatch.h"
+#include "adjoint_grad.h"
 #include "factor.h"
 
 struct bb_factor_s {
@@ -990,6 +991,118 @@ bb_status bb_adjoint_trajectory(bb_factor fh, const double *g, double *traj, int
     double id[5] = {0, 0, 0, 0, 0};
     id[fh->f.K] = 1.0;   // the identity stencil: every step is a plain transposed solve
     return cn_steps(fh, id, g, traj, m, ld, steps, true, stream, true);
+}
+
+}  // extern "C"
+
+namespace {
+
+// How bb_adjoint_band_grad runs a batch: the fused kernel where it covers the
+// fused stepper's decomposition (and its LDS fits one workgroup), else one
+// transposed step and one band-gradient pass per step.  Host only.
+struct AdjGradPlan {
+    bool fused = false;
+    StepPlan pl{};
+    bb::SweepGeom g{};
+    size_t bytes = 0;   // workspace
+};
+
+constexpr size_t kLdsBytes = 160 * 1024;   // LDS of one CU (gfx950)
+
+AdjGradPlan adjoint_grad_plan(const bb::Factor &f, int64_t m, int64_t ld)
+{
+    AdjGradPlan a;
+    const int nb = 2 * f.K + 1;
+    if (!is_long(f) && m > 0) {
+        a.pl = step_plan(f.n, m);
+        a.g = step_geom(f.n, m, ld, a.pl);
+        if (bb::adjoint_grad_supported(f.K, a.g, a.pl.scalar)) {
+            const int64_t te = bb::table_len(f.K, f.cyclic, a.pl.C, a.pl.P);
+            a.fused = bb::adjoint_grad_lds(f.K, a.g, a.pl.scalar, te) <= kLdsBytes;
+        }
+    }
+    if (m <= 0) return a;
+    if (a.fused)
+        a.bytes = (size_t)a.g.groups * nb * f.n * sizeof(double);
+    else   // one adjoint state, then the band-gradient partial sums
+        a.bytes = (size_t)f.n * ld * sizeof(double) + bb::band_grad_workspace(nb, (int)f.n, m);
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t bb_adjoint_band_grad_fused(bb_factor f, int64_t m)
+{
+    if (!f || m <= 0) return 0;
+    return adjoint_grad_plan(f->f, m, m).fused ? 1 : 0;
+}
+
+size_t bb_adjoint_band_grad_workspace_bytes(bb_factor f, int64_t m, int64_t ld)
+{
+    if (!f || m <= 0 || ld < m) return 0;
+    return adjoint_grad_plan(f->f, m, ld).bytes;
+}
+
+bb_status bb_adjoint_band_grad(bb_factor fh, const double *g, const double *traj, double *lam,
+                               int64_t m, int64_t ld, int64_t steps, double *grad_bands,
+                               void *workspace, size_t workspace_bytes, void *stream)
+{
+    bb_status st = check_batch(fh, g, lam, m, ld);
+    if (st != BB_OK) return st;
+    if (m > 0 && !traj) return fail(BB_ERR_ARG, "traj is NULL");
+    if (!grad_bands) return fail(BB_ERR_ARG, "grad_bands is NULL");
+    if (steps < 1) return fail(BB_ERR_ARG, "steps < 1");
+    bb::Factor &f = fh->f;
+    const int64_t stride = f.n * ld;
+    if (steps > (int64_t(1) << 62) / stride) return fail(BB_ERR_ARG, "steps * n * ld overflows");
+    if (m == 0) { g_last_error.clear(); return BB_OK; }
+    const AdjGradPlan a = adjoint_grad_plan(f, m, ld);
+    if (workspace_bytes < a.bytes || !workspace)
+        return fail(BB_ERR_ARG, "workspace smaller than bb_adjoint_band_grad_workspace_bytes()");
+    const int nb = 2 * f.K + 1;
+    const hipStream_t s = (hipStream_t)stream;
+    if (a.fused) {
+        int dev;
+        if ((st = current_device(&dev)) != BB_OK) return st;
+        StepPlan pl;
+        bb::DeviceTable tab;
+        bb::SweepGeom geo;
+        if ((st = stepper_setup(f, dev, m, ld, &pl, &tab, &geo, true)) != BB_OK) return st;
+        double *part = (double *)workspace;
+        hipError_t e = bb::launch_adjoint_grad(f.K, f.cyclic, (const double *)tab.ptr, tab.elems,
+                                               f.adjoint.cor.q, geo, pl.scalar, steps, g, traj,
+                                               stride, lam, part, s);
+        if (e != hipSuccess) return hip_fail(e, "fused adjoint and band-gradient launch");
+        e = bb::launch_grad_fold((int64_t)nb * f.n, geo.groups, part, grad_bands, s);
+        if (e != hipSuccess) return hip_fail(e, "band-gradient fold");
+        g_last_error.clear();
+        return BB_OK;
+    }
+    // step by step: the adjoints alternate between the workspace and lam (the
+    // first step writes the workspace, so lam may be g), each followed by
+    // its band gradients against the state it pairs with
+    double *w = (double *)workspace;
+    void *bws = (char *)workspace + (size_t)stride * sizeof(double);
+    double id[5] = {0, 0, 0, 0, 0};
+    id[f.K] = 1.0;   // the identity stencil: plain transposed solves
+    const double *src = g;
+    for (int64_t t = 1; t <= steps; ++t) {
+        double *dst = (t % 2 == 1) ? w : lam;
+        if ((st = cn_steps(fh, id, src, dst, m, ld, 1, false, stream, true)) != BB_OK) return st;
+        const double *u = traj + (steps - t) * stride;
+        hipError_t e = bb::launch_band_grad(nb, f.cyclic, (int)f.n, m, ld, dst, u, grad_bands, bws, s);
+        if (e != hipSuccess) return hip_fail(e, "band-gradient launch");
+        src = dst;
+    }
+    if (src != lam) {
+        hipError_t e = hipMemcpy2DAsync(lam, ld * sizeof(double), src, ld * sizeof(double),
+                                        m * sizeof(double), f.n, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "copy of the last adjoint");
+    }
+    g_last_error.clear();
+    return BB_OK;
 }
 
 bb_status bb_copy_rows(const double *src, double *dst, int64_t n, int64_t m, int64_t ld,

@@ -5,6 +5,7 @@
 //     sweep), kept as the measured baseline design
 #include <mutex>
 
+#include "adjoint_grad.h"
 #include "internal.h"
 
 namespace bb {
@@ -389,6 +390,15 @@ hipError_t launch_band_grad_scratch(int nb, bool cyclic, int n, int64_t m, int64
     hipError_t e = band_grad_scratch_ptr(&part);
     if (e != hipSuccess) return e;
     return band_grad_launch(nb, cyclic, n, m, ld, lam, x, grad, part, kpw, s);
+}
+
+hipError_t launch_grad_fold(int64_t total, int64_t groups, const double *part, double *grad,
+                            hipStream_t s)
+{
+    if (total <= 0 || groups <= 0) return hipSuccess;
+    hipLaunchKernelGGL(band_grad_fold, dim3((unsigned)((total + kWave - 1) / kWave)),
+                       dim3(kFoldSubs * kWave), 0, s, total, groups, part, grad);
+    return hipGetLastError();
 }
 
 size_t mse_workspace(int64_t n, int64_t m)

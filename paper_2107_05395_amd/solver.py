@@ -346,6 +346,41 @@ class Factor:
                                               _stream_ptr(g)))
         return traj
 
+    def adjoint_band_grad(self, g: torch.Tensor, traj: torch.Tensor,
+                          grad: torch.Tensor | None = None):
+        """Backward over a stretch of the rollout u_t = A^{-1} u_{t-1}, t = 1..T,
+        from g = dL/du_T and the forward states traj[t-1] = u_t (a (T, n, m)
+        tensor as cn_trajectory returns it): returns (dL/du_0, grad) with
+        grad[band, i] += -sum_t sum_k d_{t-1}[i,k] u_t[i+band-nb/2, k],
+        d_t = dL/du_t (bb_adjoint_band_grad)."""
+        m, ld = _batch_view(g, self.n, torch.float64, "g")
+        if traj.dim() != 3 or traj.shape[1:] != (self.n, m) or traj.dtype != torch.float64 \
+                or traj.device != g.device or traj.stride() != (self.n * ld, ld, 1):
+            raise ValueError("traj must be a (T, n, m) float64 tensor with g's row stride, "
+                             "states n * ld apart")
+        steps = traj.shape[0]
+        if steps < 1:
+            raise ValueError("traj holds no state")
+        if grad is None:
+            grad = torch.zeros(self.nbands, self.n, dtype=torch.float64, device=g.device)
+        if grad.shape != (self.nbands, self.n) or grad.dtype != torch.float64 or not grad.is_contiguous():
+            raise ValueError("grad must be a contiguous (nbands, n) float64 tensor")
+        lam = torch.empty((self.n, ld), dtype=torch.float64, device=g.device)[:, :m]
+        nbytes = lib().bb_adjoint_band_grad_workspace_bytes(self._handle, m, ld)
+        ws = torch.empty(max(nbytes, 8), dtype=torch.uint8, device=g.device)
+        with torch.cuda.device(g.device):
+            check(lib().bb_adjoint_band_grad(self._handle, ctypes.c_void_p(g.data_ptr()),
+                                             ctypes.c_void_p(traj.data_ptr()),
+                                             ctypes.c_void_p(lam.data_ptr()), m, ld, int(steps),
+                                             ctypes.c_void_p(grad.data_ptr()),
+                                             ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                             _stream_ptr(g)))
+        return lam, grad
+
+    def adjoint_band_grad_fused(self, m: int) -> bool:
+        """Whether adjoint_band_grad with m systems runs the fused kernel."""
+        return bool(lib().bb_adjoint_band_grad_fused(self._handle, int(m)))
+
 
 TUNING_NAMES = ("max_chunk", "waves_per_system", "waves_per_block", "lockstep", "ch_uniform",
                 "grid_linear", "long_spread")

@@ -124,6 +124,17 @@ int main()
             auto wrong = K == 1 ? bb_solve_batch_penta : bb_solve_batch_tri;
             CHECK(wrong(f, fake, other, 4, 4, BB_F64, nullptr) == BB_ERR_ARG);
             CHECK(bb_band_grad(f, dfake, dfake, 4, 4, nullptr, nullptr, 0, nullptr) == BB_ERR_ARG);
+            for (int64_t m : {int64_t(1), int64_t(100), int64_t(5000), int64_t(1) << 16}) {
+                const size_t ws = bb_adjoint_band_grad_workspace_bytes(f, m, m);
+                CHECK(ws >= (size_t)(2 * K + 1) * n * sizeof(double));
+                CHECK(bb_adjoint_band_grad_fused(f, m) == 0 || bb_adjoint_band_grad_fused(f, m) == 1);
+                CHECK(bb_adjoint_band_grad(f, dfake, dother, dfake, m, m, 2, dother, fake, ws - 1,
+                                           nullptr) == BB_ERR_ARG);       // workspace too small
+            }
+            CHECK(bb_adjoint_band_grad(f, dfake, dother, dfake, 4, 4, 0, dother, fake, 1 << 30,
+                                       nullptr) == BB_ERR_ARG);           // steps < 1
+            CHECK(bb_adjoint_band_grad(f, nullptr, nullptr, nullptr, 0, 1, 1, dother, nullptr, 0,
+                                       nullptr) == BB_OK);                // m = 0
             const bool long_sys = n > (K == 1 ? 2048 : 1024);
             if (long_sys) {
                 CHECK(solve(f, fake, other, 4, 4, BB_F32_REFINE, nullptr) == BB_ERR_UNSUPPORTED);

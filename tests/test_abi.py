@@ -189,6 +189,16 @@ def test_solve_argument_checks_need_no_gpu(L):
     assert L.bb_band_grad_noalloc(None, fake, fake, 4, 4, fake, None) == -1
     assert L.bb_band_grad_noalloc(h, None, None, 0, 1, fake, None) == 0     # m = 0
     assert L.bb_solve_batch_tri_thread_per_system(hp, fake, fake, 4, 4, None) == -1
+    A = L.bb_adjoint_band_grad
+    big = 1 << 30
+    assert A(None, fake, fake, fake, 4, 4, 1, fake, fake, big, None) == -1     # no factor
+    assert A(h, fake, None, fake, 4, 4, 1, fake, fake, big, None) == -1       # no states
+    assert A(h, fake, fake, fake, 4, 4, 1, None, fake, big, None) == -1       # no gradient
+    assert A(h, fake, fake, fake, 4, 4, 0, fake, fake, big, None) == -1       # steps < 1
+    assert A(h, fake, fake, fake, 8, 4, 1, fake, fake, big, None) == -1       # ld < m
+    assert A(h, fake, fake, fake, 4, 4, 1, fake, fake, 0, None) == -1         # workspace too small
+    assert A(h, fake, fake, fake, 4, 4, 1, fake, None, big, None) == -1       # no workspace
+    assert A(h, None, None, None, 0, 1, 1, fake, None, 0, None) == 0          # m = 0
     L.bb_factor_destroy(h)
     L.bb_factor_destroy(hp)
 
@@ -206,6 +216,31 @@ def test_workspace_sizes(L):
     assert L.bb_band_grad_workspace_bytes(h, 1000) >= 3 * n * 8
     assert L.bb_mse_workspace_bytes(n, 1000) >= 8
     assert L.bb_band_grad_scratch_bytes() == 4 << 20
+    L.bb_factor_destroy(h)
+
+
+@pytest.mark.parametrize("kind,cyclic,n,m,fused", [
+    ("tri", False, 1024, 65536, True), ("tri", True, 2048, 2500, True),
+    ("penta", True, 1024, 20000, True), ("penta", False, 256, 5000, True),
+    ("tri", False, 64, 33, False), ("penta", True, 1024, 2000, False),
+    ("tri", False, 4096, 1000, False)])
+def test_adjoint_band_grad_plan_and_workspace(L, kind, cyclic, n, m, fused):
+    """Which path bb_adjoint_band_grad takes (host only) and its workspace:
+    the groups' partial sums when fused, else one adjoint state plus the band
+    gradient's partial sums."""
+    bands = inputs.random_dominant_tri(n, 1) if kind == "tri" else inputs.random_dominant_penta(n, 1)
+    name = kind + ("_cyclic" if cyclic else "")
+    _, h = _factor(L, name, bands, n)
+    nb = 3 if kind == "tri" else 5
+    assert L.bb_adjoint_band_grad_fused(h, m) == int(fused)
+    assert L.bb_adjoint_band_grad_fused(h, 0) == 0
+    assert L.bb_adjoint_band_grad_workspace_bytes(h, 0, 1) == 0
+    assert L.bb_adjoint_band_grad_workspace_bytes(h, m, m - 1) == 0       # ld < m
+    ws = L.bb_adjoint_band_grad_workspace_bytes(h, m, m + 8)
+    if fused:
+        assert ws % (nb * n * 8) == 0 and nb * n * 8 * (m // 64) <= ws <= nb * n * 8 * m
+    else:
+        assert ws >= n * (m + 8) * 8 + L.bb_band_grad_workspace_bytes(h, m)
     L.bb_factor_destroy(h)
 
 

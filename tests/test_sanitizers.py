@@ -17,7 +17,7 @@ CSRC = os.path.join(ROOT, "paper_2107_05395_amd", "csrc")
 KOBJ = os.path.join(ROOT, "_build")
 OUT = os.path.join(ROOT, "_build", "san")
 DEVICE_UNITS = ["sweep", "sweep_f32", "refine", "refine_f32rhs", "ch", "ch_forced", "cn_tri",
-                "cn_penta", "aux", "long_sweep"]
+                "cn_penta", "aux", "long_sweep", "adjoint_grad_tri", "adjoint_grad_penta"]
 SAN = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
        "-fno-sanitize-recover=undefined"]
 HIP = ["-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include")]
