@@ -34,6 +34,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ("sweep_core.h", "sweep_kernel.h", "sweep.hip", "sweep_f32.hip", "refine_kernel.h",
                   "refine.hip", "refine_f32rhs.hip", "stepper.h", "ch.hip", "ch_forced.hip",
                   "cn_stencil.h", "cn_tri.hip", "cn_penta.hip", "long_core.h", "long_sweep.hip",
+                  "adjoint_grad_kernel.h", "adjoint_grad_tri.hip", "adjoint_grad_penta.hip",
                   "internal.h")
 # the device sources behind each kernel whose HBM traffic is recorded
 KERNEL_FAMILIES = {
@@ -43,6 +44,7 @@ KERNEL_FAMILIES = {
     "stepper_ch": ("sweep_core.h", "stepper.h", "ch.hip", "internal.h"),
     "stepper_forced": ("sweep_core.h", "stepper.h", "ch_forced.hip", "internal.h"),
     "long": ("sweep_core.h", "long_core.h", "long_sweep.hip", "internal.h"),
+    "adjoint_grad": ("sweep_core.h", "adjoint_grad_kernel.h", "adjoint_grad_tri.hip", "internal.h"),
 }
 
 

@@ -176,15 +176,13 @@ void adjoint_grad_kernel(const double *__restrict__ table, int64_t table_elems, 
         for (int b = 0; b < NBLK; ++b) acc[b] = 0.0;
 
         for (int64_t step = 0; step < steps; ++step) {
-            chunk_solve<double, K, C, CYC, true, Src>(c, tab, lg, n, 1, cq, xch);
-            __builtin_amdgcn_sched_barrier(0);
-
-            // the forward state paired with this adjoint: rows row0 - K ..
-            // row0 + C + K - 1 of system k (outside the matrix: 0, or mod n
-            // when periodic; padding systems: 0)
-            // (the loads of a block take their address from an opaque value
-            // read after the previous block's staging, so the compiler cannot
-            // hoist every row's load above the reduction and hold them all)
+            // the forward state paired with this step's adjoint: rows row0 - K
+            // .. row0 + C + K - 1 of system k (outside the matrix: 0, or mod
+            // n when periodic; padding systems: 0).  The first block's rows
+            // are loaded before the transposed solve, so they arrive during
+            // it; every later block's loads take their address from an opaque
+            // value read after the previous block's staging, so the compiler
+            // cannot hoist all rows above the reduction and hold them at once.
             const int64_t ld = opaque_s(g.ld);
             const double *ucol = traj + (steps - 1 - step) * traj_stride + kk;
             auto urow = [&](int t) -> double {   // row row0 + t, t in [-K, C + K)
@@ -201,6 +199,9 @@ void adjoint_grad_kernel(const double *__restrict__ table, int64_t table_elems, 
             double win[RB + 2 * K];
 #pragma unroll
             for (int t = 0; t < RB + 2 * K; ++t) win[t] = urow(t - K);
+            __builtin_amdgcn_sched_barrier(0);
+            chunk_solve<double, K, C, CYC, true, Src>(c, tab, lg, n, 1, cq, xch);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int b = 0; b < NBLK; ++b) {
                 if (b > 0) {

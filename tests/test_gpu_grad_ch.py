@@ -96,8 +96,11 @@ def test_rollout_gradients_match_oracle(precision, tol):
 
 def test_checkpointing_is_bitwise_neutral():
     """Recomputing the states between checkpoints reproduces them exactly, so
-    the gradients of every band and of u0 do not depend on the checkpoint
-    interval.  The bands are the leaves here: a parameter feeding several
+    the adjoints, and with them the gradient of u0, do not depend on the
+    checkpoint interval, bitwise.  The band gradients are sums over the steps
+    and the batch whose grouping follows the segments (the fused backward
+    sums a segment's steps on chip before the fold), so they agree to
+    rounding.  The bands are the leaves here: a parameter feeding several
     bands (D in A(D)) has its contributions summed by torch's autograd engine,
     whose order across the CPU and GPU worker threads is not fixed."""
     from paper_2107_05395_amd import banded_rollout, mse_loss
@@ -114,7 +117,9 @@ def test_checkpointing_is_bitwise_neutral():
     for every, g in zip((7, 30), grads[1:]):
         say("checkpoint every", every, "max diffs", [float(np.max(np.abs(a - b))) for a, b in zip(g, grads[0])])
     for g in grads[1:]:
-        assert all(np.array_equal(a, b) for a, b in zip(g, grads[0]))
+        assert np.array_equal(g[-1], grads[0][-1])
+        for a, b in zip(g[:-1], grads[0][:-1]):
+            assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b))
 
 
 # ---------------------------------------------------------------- Cahn-Hilliard
