@@ -796,8 +796,9 @@ def probe(torch):
     workload, the FP64 and FP32+refine pentadiagonal sweeps on the
     hyperdiffusion workload, the three launches of a long tridiagonal solve
     (n = 8192, m = 2^16), one launch
-    of 10 fused Cahn-Hilliard steps on the n=256, m=2^20 ensemble, and one
-    Crank-Nicolson diffusion step (n=1024, m=2^16, periodic)."""
+    of 10 fused Cahn-Hilliard steps on the n=256, m=2^20 ensemble, one
+    Crank-Nicolson diffusion step (n=1024, m=2^16, periodic), and one fused
+    adjoint + band-gradient launch of 10 steps (n=1024, m=2^16)."""
     from paper_2107_05395_amd import Factor, inputs
     n, m = 512, 1 << 20
     rhs = torch.rand(n, m, dtype=torch.float64, device="cuda")
@@ -843,6 +844,13 @@ def probe(torch):
     cn = Factor.tri(*bands, cyclic=True)
     c = torch.rand(n, m, dtype=torch.float64, device="cuda")
     cn.cn_step(c, w, steps=1, out=torch.empty_like(c))
+    torch.cuda.synchronize()
+    # one segment of the differentiated rollout's backward: 10 transposed
+    # steps with the band gradients reduced as they go (tri n=1024, m=2^16)
+    D = inputs.rng(5).uniform(0.5, 1.5, n)
+    fa = Factor.tri(-0.5 * D, 1 + D, -0.5 * D)
+    traj = torch.rand(10, n, m, dtype=torch.float64, device="cuda")
+    fa.adjoint_band_grad(c, traj)
     torch.cuda.synchronize()
     print(json.dumps({"probe": "done"}), flush=True)
 
