@@ -166,6 +166,10 @@ def bench_tri(args, torch):
     cols32 = np.unique(np.r_[np.linspace(0, m - 1, 254).astype(np.int64), 0, m - 1])
     ref32 = oracle.tri_solve(*bands, rhs_host[:, cols32].astype(np.float32).astype(np.float64))
     err32 = rel_err_cols(x[:, torch.from_numpy(cols32).cuda()].cpu().numpy(), ref32)
+    # the same FP32 data solved with the FP64 sweeps (no refinement needed)
+    t32d, _ = time_launches(lambda: f.solve(rhs32, out=x, precision="f32rhs_f64"), args.steps,
+                            args.warmup, torch)
+    err32d = rel_err_cols(x[:, torch.from_numpy(cols32).cuda()].cpu().numpy(), ref32)
     del rhs32
     # torch's device-to-device copy of the same array, one read + one write
     # stream (context for the roofline; not the fastest copy on this part)
@@ -231,6 +235,11 @@ def bench_tri(args, torch):
                    "rel_err_vs_oracle": err32, "hbm_gbs_algorithmic": 12.0 * n * m * k / t32 / 1e9,
                    "note": "FP32 right-hand sides (the same draws rounded), double solution; "
                            "oracle on the rounded values"},
+        "f32rhs_f64": {"value": m * k / t32d, "unit": "systems/s", "ms_per_step": 1e3 * t32d / k,
+                       "rel_err_vs_oracle": err32d,
+                       "hbm_gbs_algorithmic": 12.0 * n * m * k / t32d / 1e9,
+                       "note": "the same FP32 right-hand sides solved with the FP64 sweeps and "
+                               "factor (promoted exactly on load), double solution"},
         "copy_gbs": copy_gbs, "tile_copy_gbs": tile_gbs,
         "hip_graph": graph,
         "thread_per_system_design": {"ms_per_step": 1e3 * pt, "value": m / pt,
@@ -278,6 +287,9 @@ def bench_penta(args, torch):
                          torch)
     ref32 = oracle.penta_solve(*bands, rhs_host[:, cols].astype(np.float32).astype(np.float64))
     out["f32rhs"] = (t, rel_err_cols(x[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref32))
+    t, _ = time_launches(lambda: f.solve(rhs32, out=x, precision="f32rhs_f64"), args.steps,
+                         args.warmup, torch)
+    out["f32rhs_f64"] = (t, rel_err_cols(x[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref32))
     del rhs32
     # the same batch in arrays with a leading dimension of m + 32 (rows no
     # longer a power of two apart; the library takes any ld >= m)
@@ -307,6 +319,9 @@ def bench_penta(args, torch):
         "f32rhs": {"value": m * k / out["f32rhs"][0], "rel_err_vs_oracle": out["f32rhs"][1],
                    "ms_per_step": 1e3 * out["f32rhs"][0] / k,
                    "hbm_gbs_algorithmic": 12.0 * n * m * k / out["f32rhs"][0] / 1e9},
+        "f32rhs_f64": {"value": m * k / out["f32rhs_f64"][0], "rel_err_vs_oracle": out["f32rhs_f64"][1],
+                       "ms_per_step": 1e3 * out["f32rhs_f64"][0] / k,
+                       "hbm_gbs_algorithmic": 12.0 * n * m * k / out["f32rhs_f64"][0] / 1e9},
         "padded_ld": {"ld": m + pad, "ms_per_step": 1e3 * tpad / k, "value": m * k / tpad,
                       "hbm_gbs_algorithmic": algo_bytes * k / tpad / 1e9,
                       "rel_err_vs_oracle": err_pad},
@@ -792,6 +807,7 @@ def probe(torch):
     """One dispatch of each kernel of interest, for rocprofv3 counter runs:
     a plain copy of known size (4 GiB read + 4 GiB written), the library's
     16 KB-tile copy of the same array, the FP64 and FP32+refine sweeps, the
+    FP64 sweep of FP32 right-hand sides, the
     thread-per-system design and the sweep-pattern copy on the bench
     workload, the FP64 and FP32+refine pentadiagonal sweeps on the
     hyperdiffusion workload, the three launches of a long tridiagonal solve
@@ -812,6 +828,10 @@ def probe(torch):
     for prec in ("f64", "f32r"):
         f.solve(rhs, out=x, precision=prec)
         torch.cuda.synchronize()
+    rhs32 = rhs.float()
+    f.solve(rhs32, out=x, precision="f32rhs_f64")
+    torch.cuda.synchronize()
+    del rhs32
     f.solve_thread_per_system(rhs, out=x)
     torch.cuda.synchronize()
     from paper_2107_05395_amd.solver import copy_rows

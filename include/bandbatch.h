@@ -58,9 +58,13 @@ typedef enum {
                           residual r = b - A x0 in double with the original bands and a float correction
                           sweep: x = x0 + A^{-1} r.  Relative error ~ (kappa eps32)^2 + kappa eps64. */
     BB_F32 = 2,        /* float rhs and x, float sweeps; no refinement */
-    BB_F32_RHS_REFINE = 3 /* float rhs (FP32 data, 4 B per entry read), double x: the BB_F32_REFINE
+    BB_F32_RHS_REFINE = 3, /* float rhs (FP32 data, 4 B per entry read), double x: the BB_F32_REFINE
                           sweeps and refinement, the residual taken with the rhs promoted exactly to
                           double.  rhs and x must not overlap. */
+    BB_F32_RHS_F64 = 4 /* float rhs (FP32 data, 4 B per entry read), double x: the rhs promoted
+                          exactly and solved with the FP64 sweeps and factor of BB_F64 (same
+                          decomposition), so x is the FP64 solution of the FP32 data.  rhs and x
+                          must not overlap. */
 } bb_precision;
 
 typedef struct bb_factor_s *bb_factor;
@@ -135,7 +139,8 @@ bb_status bb_plan(bb_factor f, int64_t m, int32_t what, bb_precision p, int32_t 
  * x[:,k] = A^{-1} rhs[:,k] for 0 <= k < m (Appendix A/B batched sweeps, with
  * the periodic correction of Section 3.3 when the factor is cyclic).
  * rhs, x: device, interleaved [i*ld + k]; double for BB_F64 and BB_F32_REFINE,
- * float for BB_F32; float rhs and double x for BB_F32_RHS_REFINE (same ld).
+ * float for BB_F32; float rhs and double x for BB_F32_RHS_REFINE and
+ * BB_F32_RHS_F64 (same ld).
  * m >= 0 (m == 0 enqueues nothing), ld >= max(m, 1).
  * The tri entry point requires a tri factor (cyclic or not), the penta one a
  * penta factor; the _cyclic names additionally require a cyclic factor.
@@ -143,7 +148,7 @@ bb_status bb_plan(bb_factor f, int64_t m, int32_t what, bb_precision p, int32_t 
  * as scratch before it receives the solution, so x must not overlap rhs;
  * BB_F64 only.
  * Errors: BB_ERR_ARG (wrong factor kind, null pointer, m or ld out of range,
- * unknown precision, rhs == x with BB_F32_RHS_REFINE), BB_ERR_UNSUPPORTED
+ * unknown precision, rhs == x with BB_F32_RHS_REFINE or BB_F32_RHS_F64), BB_ERR_UNSUPPORTED
  * (long system: another precision, or rhs == x), BB_ERR_HIP, BB_ERR_OOM
  * (first upload). */
 bb_status bb_solve_batch_tri(bb_factor f, const void *rhs, void *x, int64_t m, int64_t ld,

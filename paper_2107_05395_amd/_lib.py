@@ -15,7 +15,7 @@ STATUS = {
     0: "BB_OK", -1: "BB_ERR_ARG", -2: "BB_ERR_ZERO_PIVOT", -3: "BB_ERR_SINGULAR_CAPACITANCE",
     -4: "BB_ERR_HIP", -5: "BB_ERR_OOM", -6: "BB_ERR_UNSUPPORTED",
 }
-PRECISION = {"f64": 0, "f32r": 1, "f32": 2, "f32rhs": 3}
+PRECISION = {"f64": 0, "f32r": 1, "f32": 2, "f32rhs": 3, "f32rhs_f64": 4}
 
 # every function the header declares, with its ctypes signature
 _P = ctypes.c_void_p

@@ -14,6 +14,7 @@
 #include "../../include/bandbatch.h"
 #include "adjoint_grad.h"
 #include "factor.h"
+#include "precision.h"
 
 struct bb_factor_s {
     bb::Factor f;
@@ -393,10 +394,12 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
     bb::Factor &f = fh->f;
     if (f.K != want_k) return fail(BB_ERR_ARG, want_k == 1 ? "not a tridiagonal factor" : "not a pentadiagonal factor");
     if (want_cyclic == 1 && !f.cyclic) return fail(BB_ERR_ARG, "not a cyclic factor");
-    if (p != BB_F64 && p != BB_F32_REFINE && p != BB_F32 && p != BB_F32_RHS_REFINE)
+    if (p != BB_F64 && p != BB_F32_REFINE && p != BB_F32 && p != BB_F32_RHS_REFINE &&
+        p != BB_F32_RHS_F64)
         return fail(BB_ERR_ARG, "unknown precision");
-    if (p == BB_F32_RHS_REFINE && m > 0 && in == out)
-        return fail(BB_ERR_ARG, "BB_F32_RHS_REFINE reads float and writes double: rhs and x must not overlap");
+    if ((p == BB_F32_RHS_REFINE || p == BB_F32_RHS_F64) && m > 0 && in == out)
+        return fail(BB_ERR_ARG, "BB_F32_RHS_REFINE and BB_F32_RHS_F64 read float and write double: "
+                                "rhs and x must not overlap");
     if (is_long(f) && p != BB_F64)
         return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(f.n) +
                                              " (long system): only BB_F64 is built for it");
@@ -425,7 +428,7 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
     const int P = bb::lanes_for(f.n, C);
     int log2P = 0;
     while ((1 << log2P) < P) ++log2P;
-    const bool f32 = (p != BB_F64);
+    const bool f32 = (p != BB_F64 && p != BB_F32_RHS_F64);   // float table
     const bb::Direction &dir = adjoint ? f.adjoint : f.primal;
     bb::DeviceTable tab, band;
     st = device_table(f, f.dev, std::make_tuple(dev, (int)adjoint, (int)f32, C, 0), f32,
@@ -483,9 +486,12 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
     g.groups = (m + S - 1) / S;
     g.lockstep = lockstep_for(g.log2Q > 0 && op == bb::Op::Solve);
     g.linear = grid_linear() > 0;
-    hipError_t e = bb::launch_sweep(f.K, f.cyclic, op, f32 && p == BB_F32, tab.ptr, tab.elems,
-                                    (const double *)band.ptr, band.elems, dir.cor.q, corners, g,
-                                    in, out, (hipStream_t)stream);
+    hipError_t e = p == BB_F32_RHS_F64
+        ? bb::launch_sweep_f32in(f.K, f.cyclic, tab.ptr, tab.elems, dir.cor.q, g, (const float *)in,
+                                 (double *)out, (hipStream_t)stream)
+        : bb::launch_sweep(f.K, f.cyclic, op, f32 && p == BB_F32, tab.ptr, tab.elems,
+                           (const double *)band.ptr, band.elems, dir.cor.q, corners, g, in, out,
+                           (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "sweep launch");
     g_last_error.clear();
     return BB_OK;
@@ -587,7 +593,8 @@ bb_status bb_plan(bb_factor fh, int64_t m, int32_t what, bb_precision p, int32_t
     if (!fh) return fail(BB_ERR_ARG, "factor is NULL");
     if (m < 1) return fail(BB_ERR_ARG, "m < 1");
     if (what != 0 && what != 1) return fail(BB_ERR_ARG, "what must be 0 (solve) or 1 (fused steps)");
-    if (p != BB_F64 && p != BB_F32_REFINE && p != BB_F32 && p != BB_F32_RHS_REFINE)
+    if (p != BB_F64 && p != BB_F32_REFINE && p != BB_F32 && p != BB_F32_RHS_REFINE &&
+        p != BB_F32_RHS_F64)
         return fail(BB_ERR_ARG, "unknown precision");
     const bb::Factor &f = fh->f;
     int C, P, log2Q, sc = 0;

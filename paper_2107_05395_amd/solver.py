@@ -114,7 +114,7 @@ class Factor:
     def _run(self, fname: str, rhs: torch.Tensor, out, precision: str):
         if precision not in _lib.PRECISION:
             raise ValueError("precision must be one of %s" % list(_lib.PRECISION))
-        in_dtype = torch.float32 if precision in ("f32", "f32rhs") else torch.float64
+        in_dtype = torch.float32 if precision in ("f32", "f32rhs", "f32rhs_f64") else torch.float64
         out_dtype = torch.float32 if precision == "f32" else torch.float64
         m, ld = _batch_view(rhs, self.n, in_dtype, "rhs")
         if out is None:
@@ -134,8 +134,10 @@ class Factor:
 
         precision: "f64" (double rhs and x), "f32r" (double rhs and x, float
         sweeps + one double residual refinement), "f32" (float rhs and x, no
-        refinement), "f32rhs" (float rhs data, double x, refined like "f32r").
-        out may be rhs (in place) except with "f32rhs"."""
+        refinement), "f32rhs" (float rhs data, double x, refined like "f32r"),
+        "f32rhs_f64" (float rhs data promoted exactly and solved with the FP64
+        sweeps, double x).  out may be rhs (in place) except with "f32rhs" and
+        "f32rhs_f64"."""
         return self._run("bb_solve_batch_" + self.kind.replace("_cyclic", ""), rhs, out, precision)
 
     def adjoint(self, g: torch.Tensor, out: torch.Tensor | None = None,

@@ -118,7 +118,7 @@ def test_long_systems_host_checks(L):
     assert L.bb_plan(hp, 100000, 0, 0, ctypes.byref(chunk), ctypes.byref(lanes), ctypes.byref(waves),
                      ctypes.byref(scalar)) == 0
     assert chunk.value == 64 and lanes.value == 17 and waves.value == 1 and scalar.value == 1
-    for prec in (1, 2, 3):   # refinement and float precisions: not built for long systems
+    for prec in (1, 2, 3, 4):   # refinement and float precisions: not built for long systems
         assert L.bb_solve_batch_penta(hp, fake, other, 4, 4, prec, None) == -6
     assert L.bb_solve_batch_penta(hp, fake, fake, 4, 4, 0, None) == -6      # in place
     assert L.bb_solve_batch_penta_adjoint(hp, fake, fake, 4, 4, 0, None) == -6
@@ -155,6 +155,10 @@ def test_solve_argument_checks_need_no_gpu(L):
     assert L.bb_solve_batch_tri(h, None, fake, 4, 4, 0, None) == -1
     assert L.bb_solve_batch_tri(h, fake, fake, 4, 4, 7, None) == -1        # bad precision
     assert L.bb_solve_batch_tri(h, fake, fake, 4, 4, 3, None) == -1        # float rhs aliasing double x
+    assert L.bb_solve_batch_tri(h, fake, fake, 4, 4, 4, None) == -1        # the same, FP64 sweeps
+    for prec in range(5):
+        assert L.bb_plan(h, 1000, 0, prec, None, None, None, None) == 0
+    assert L.bb_plan(h, 1000, 0, 5, None, None, None, None) == -1
     assert L.bb_solve_batch_penta(h, fake, fake, 4, 4, 0, None) == -1      # wrong kind
     assert L.bb_solve_batch_tri(hp, fake, fake, 4, 4, 0, None) == -1
     assert L.bb_solve_batch_tri_cyclic(h, fake, fake, 4, 4, 0, None) == -1  # not cyclic

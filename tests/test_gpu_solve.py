@@ -122,6 +122,28 @@ def test_refine_f32_rhs(kind, cyclic, n):
 
 @pytest.mark.parametrize("kind", ["tri", "penta"])
 @pytest.mark.parametrize("cyclic", [False, True])
+@pytest.mark.parametrize("n,m", [(5, 70), (64, 333), (300, 1000), (1024, 70000), (2048, 3000)])
+def test_f32_rhs_f64_sweeps(kind, cyclic, n, m):
+    """FP32 right-hand-side data solved with the FP64 sweeps: the FP64 solve
+    of the promoted values, to the FP64 bar (1e-12 against the oracle on the
+    same promoted values), and bitwise the FP64 solve of the promoted array
+    (same decomposition and arithmetic); the adjoint likewise."""
+    if kind == "penta" and n > 1024:
+        pytest.skip("long pentadiagonal systems take the FP64 three-launch path only")
+    say("f32rhs_f64", kind, cyclic, n, m)
+    f, bands = make(kind, n, seed=13 * n, cyclic=cyclic, dominant=False)
+    rhs32 = inputs.uniform_batch(n, m, seed=4700 + n).astype(np.float32)
+    t = dev(rhs32, torch.float32)
+    x = f.solve(t, precision="f32rhs_f64")
+    assert x.dtype == torch.float64
+    assert rel_err(host(x), oracle_solve(kind, bands, rhs32.astype(np.float64), cyclic)) < 1e-12
+    assert torch.equal(x, f.solve(t.double(), precision="f64"))
+    lam = f.adjoint(t, precision="f32rhs_f64")
+    assert torch.equal(lam, f.adjoint(t.double(), precision="f64"))
+
+
+@pytest.mark.parametrize("kind", ["tri", "penta"])
+@pytest.mark.parametrize("cyclic", [False, True])
 def test_plain_f32(kind, cyclic):
     n = 512
     f, bands = make(kind, n, seed=11, cyclic=cyclic, dominant=False)

@@ -11,13 +11,15 @@ import subprocess
 
 import pytest
 
+from paper_2107_05395_amd import build as _build
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(ROOT, "paper_2107_05395_amd", "csrc")
 KOBJ = os.path.join(ROOT, "_build")
 OUT = os.path.join(ROOT, "_build", "san")
-DEVICE_UNITS = ["sweep", "sweep_f32", "refine", "refine_f32rhs", "ch", "ch_forced", "cn_tri",
-                "cn_penta", "aux", "long_sweep", "adjoint_grad_tri", "adjoint_grad_penta"]
+# every device unit of the library, as the build lists them
+DEVICE_UNITS = [s[:-len(".hip")] for s in _build.SOURCES if s.endswith(".hip")]
 SAN = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
        "-fno-sanitize-recover=undefined"]
 HIP = ["-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include")]
@@ -32,8 +34,7 @@ def _run(cmd):
 @pytest.fixture(scope="module")
 def san_binary():
     if not all(os.path.exists(os.path.join(KOBJ, u + ".o")) for u in DEVICE_UNITS):
-        from paper_2107_05395_amd import build
-        build.build(verbose=False)
+        _build.build(verbose=False)
     os.makedirs(OUT, exist_ok=True)
     units = [("g++", os.path.join(CSRC, "api.cpp"), ["-std=c++17"] + HIP),
              ("g++", os.path.join(CSRC, "factor.cpp"), ["-std=c++17"] + HIP),
