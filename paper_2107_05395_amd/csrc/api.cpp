@@ -150,7 +150,7 @@ int lockstep_for(bool split)
 // one wave.
 // Tuning waves_per_system = 1, 2, 4 or 8 forces the group size where it is
 // valid; otherwise the automatic choice stands.
-int split_log2(int log2P, int C, int n, bb::Op op)
+int split_log2(int log2P, int C, int n, bb::Op op, bool f32_in = false)
 {
     const bool refine = op != bb::Op::Solve;
     if (C < 32 || (refine && ((int64_t)C << log2P) != n)) return 0;
@@ -162,6 +162,14 @@ int split_log2(int log2P, int C, int n, bb::Op op)
         l = log2P > 2 ? log2P - 2 : 0;
     else if (C > 64)
         l = log2P >= 3 ? 2 : 0;
+    else if (C == 64 && f32_in)
+        // FP32 right-hand sides into the FP64 sweep: one chunk of 64 systems
+        // per wave from 4 to 8 chunks, so each row is a 256-byte float
+        // segment.  Measured, ms (groups of 64 systems against the FP64
+        // rule's): tri n = 512, m = 2^20 1.32 vs 1.50; n = 256, m = 2^21
+        // 1.33 vs 1.48; penta n = 256, m = 2^20 0.67 vs 0.76; n = 512,
+        // m = 2^19 0.71 vs 0.78; not at 2 chunks (tri n = 128: 1.35 vs 1.31)
+        l = log2P >= 4 ? 3 : log2P >= 2 ? log2P : 0;
     else if (C == 64)
         l = log2P >= 4 ? 3 : log2P == 3 ? 2 : 0;
     if (l > lmax) l = lmax;
@@ -481,7 +489,7 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
     g.exact = (f.n % C) == 0;
     g.m = m;
     g.ld = ld;
-    g.log2Q = split_log2(log2P, C, (int)f.n, op);
+    g.log2Q = split_log2(log2P, C, (int)f.n, op, p == BB_F32_RHS_F64);
     const int S = (bb::kWave << g.log2Q) / P;
     g.groups = (m + S - 1) / S;
     g.lockstep = lockstep_for(g.log2Q > 0 && op == bb::Op::Solve);
@@ -612,7 +620,7 @@ bb_status bb_plan(bb_factor fh, int64_t m, int32_t what, bb_precision p, int32_t
         while ((1 << log2P) < P) ++log2P;
         const bb::Op op = p == BB_F32_REFINE ? bb::Op::Refine
                         : p == BB_F32_RHS_REFINE ? bb::Op::RefineF32Rhs : bb::Op::Solve;
-        log2Q = split_log2(log2P, C, (int)f.n, op);
+        log2Q = split_log2(log2P, C, (int)f.n, op, p == BB_F32_RHS_F64);
     } else {
         const StepPlan pl = step_plan(f.n, m);
         C = pl.C;
