@@ -180,9 +180,12 @@ void adjoint_grad_kernel(const double *__restrict__ table, int64_t table_elems, 
             // .. row0 + C + K - 1 of system k (outside the matrix: 0, or mod
             // n when periodic; padding systems: 0).  The first block's rows
             // are loaded before the transposed solve, so they arrive during
-            // it; every later block's loads take their address from an opaque
-            // value read after the previous block's staging, so the compiler
-            // cannot hoist all rows above the reduction and hold them at once.
+            // it; each later block's rows are loaded while the block before
+            // it is reduced (one block in flight ahead: measured 1.65 against
+            // 1.74 ms for 10 steps at n = 1024, m = 2^16), their addresses
+            // taken from an opaque value read after the staging two blocks
+            // back, so the compiler cannot hoist every row's load above the
+            // reduction and hold them all at once.
             const int64_t ld = opaque_s(g.ld);
             const double *ucol = traj + (steps - 1 - step) * traj_stride + kk;
             auto urow = [&](int t) -> double {   // row row0 + t, t in [-K, C + K)
@@ -202,13 +205,18 @@ void adjoint_grad_kernel(const double *__restrict__ table, int64_t table_elems, 
             __builtin_amdgcn_sched_barrier(0);
             chunk_solve<double, K, C, CYC, true, Src>(c, tab, lg, n, 1, cq, xch);
             __builtin_amdgcn_sched_barrier(0);
+            double nxt[RB];
 #pragma unroll
             for (int b = 0; b < NBLK; ++b) {
                 if (b > 0) {
 #pragma unroll
                     for (int t = 0; t < 2 * K; ++t) win[t] = win[t + RB];
 #pragma unroll
-                    for (int t = 2 * K; t < RB + 2 * K; ++t) win[t] = urow(b * RB + t - K);
+                    for (int t = 2 * K; t < RB + 2 * K; ++t) win[t] = nxt[t - 2 * K];
+                }
+                if (b + 1 < NBLK) {
+#pragma unroll
+                    for (int t = 0; t < RB; ++t) nxt[t] = urow((b + 1) * RB + K + t);
                 }
                 double p[V];
 #pragma unroll
