@@ -113,15 +113,14 @@ def _advance(f: Factor, u, k: int, precision: str):
 
 
 class BandedRollout(torch.autograd.Function):
-    """u_T after `steps` solves u_t = A(bands)^{-1} u_{t-1}, checkpointed."""
+    """u_T after `steps` solves u_t = A(bands)^{-1} u_{t-1}, checkpointed;
+    A periodic (corner entries from the bands, Section 3.3) when cyclic."""
 
     @staticmethod
-    def forward(ctx, u0, steps, checkpoint_every, precision, *bands):
+    def forward(ctx, u0, steps, checkpoint_every, precision, cyclic, *bands):
         if steps < 1 or checkpoint_every < 1:
             raise ValueError("steps and checkpoint_every must be >= 1")
-        _kind(len(bands))
-        host = _host_bands(bands)
-        f = Factor.tri(*host) if len(host) == 3 else Factor.penta(*host)
+        f = _factor_from(bands, _kind(len(bands)), bool(cyclic))
         u = u0.detach().contiguous()
         checkpoints = [u]
         t = 0
@@ -201,11 +200,13 @@ class BandedRollout(torch.autograd.Function):
             del states
         main.wait_stream(side)
         ctx.checkpoints = None
-        return (g, None, None, None, *[gb[q].to(d) for q, d in enumerate(ctx.band_devices)])
+        return (g, None, None, None, None,
+                *[gb[q].to(d) for q, d in enumerate(ctx.band_devices)])
 
 
-def banded_rollout(u0, bands, steps: int, checkpoint_every: int = 10, precision: str = "f64"):
-    return BandedRollout.apply(u0, steps, checkpoint_every, precision, *bands)
+def banded_rollout(u0, bands, steps: int, checkpoint_every: int = 10, precision: str = "f64",
+                   cyclic: bool = False):
+    return BandedRollout.apply(u0, steps, checkpoint_every, precision, cyclic, *bands)
 
 
 class MSELoss(torch.autograd.Function):

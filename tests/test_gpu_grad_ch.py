@@ -94,6 +94,49 @@ def test_rollout_gradients_match_oracle(precision, tol):
     assert rel_err(host(tu0.grad), du0_ref) < tol
 
 
+def test_rollout_gradients_on_the_fused_backward():
+    """The FP64 rollout where its backward runs the fused adjoint and
+    band-gradient kernel (checked: bb_adjoint_band_grad_fused): the
+    diffusion workload's gradients against the oracle, and a periodic
+    pentadiagonal rollout's band gradients against the oracle's transposed
+    solves and batch reductions composed step by step."""
+    from paper_2107_05395_amd import Factor, banded_rollout, mse_loss
+    n, m, steps, r = 256, 8192, 12, 0.5
+    D0 = inputs.rng(18).uniform(0.5, 1.5, n)
+    assert Factor.tri(-r * D0, 1 + 2 * r * D0, -r * D0).adjoint_band_grad_fused(m)
+    u0 = inputs.uniform_batch(n, m, seed=19)
+    y = inputs.uniform_batch(n, m, seed=20)
+    loss_ref, dD_ref, du0_ref = oracle.diffusion_loss_and_grads(D0, r, u0, y, steps)
+    D = torch.tensor(D0, requires_grad=True)
+    tu0 = dev(u0).requires_grad_(True)
+    uT = banded_rollout(tu0, (-r * D, 1 + 2 * r * D, -r * D), steps=steps, checkpoint_every=5)
+    mse_loss(uT, dev(y)).backward()
+    assert np.max(np.abs(D.grad.numpy() - dD_ref)) < 1e-12 * np.max(np.abs(dD_ref))
+    assert rel_err(host(tu0.grad), du0_ref) < 1e-12
+
+    n, m, steps = 256, 5000, 7
+    bands = inputs.random_dominant_penta(n, seed=21)
+    f = Factor.penta(*bands, cyclic=True)
+    assert f.adjoint_band_grad_fused(m)
+    u0 = inputs.uniform_batch(n, m, seed=22)
+    y = inputs.uniform_batch(n, m, seed=23)
+    us = [u0]
+    for _ in range(steps):
+        us.append(oracle.penta_solve(*bands, us[-1], cyclic=True))
+    d = 2.0 * (us[-1] - y) / (n * m)
+    gb_ref = np.zeros((5, n))
+    for t in range(steps, 0, -1):
+        d = oracle.penta_adjoint(*bands, d, cyclic=True)
+        gb_ref += oracle.band_grad(d, us[t], 5, cyclic=True)
+    tb = [torch.tensor(v, requires_grad=True) for v in bands]
+    tu0 = dev(u0).requires_grad_(True)
+    uT = banded_rollout(tu0, tb, steps, checkpoint_every=3, cyclic=True)
+    mse_loss(uT, dev(y)).backward()
+    for q in range(5):
+        assert np.max(np.abs(tb[q].grad.numpy() - gb_ref[q])) < 1e-12 * np.max(np.abs(gb_ref))
+    assert rel_err(host(tu0.grad), d) < 1e-12
+
+
 def test_checkpointing_is_bitwise_neutral():
     """Recomputing the states between checkpoints reproduces them exactly, so
     the adjoints, and with them the gradient of u0, do not depend on the
