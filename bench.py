@@ -34,6 +34,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ("sweep_core.h", "sweep_kernel.h", "sweep.hip", "sweep_f32.hip", "refine_kernel.h",
                   "refine.hip", "refine_f32rhs.hip", "stepper.h", "ch.hip", "ch_forced.hip",
                   "cn_stencil.h", "cn_tri.hip", "cn_penta.hip", "long_core.h", "long_sweep.hip",
+                  "long_f32in.hip", "sweep_f32in.hip",
                   "adjoint_grad_kernel.h", "adjoint_grad_tri.hip", "adjoint_grad_penta.hip",
                   "internal.h")
 # the device sources behind each kernel whose HBM traffic is recorded
@@ -1018,13 +1019,20 @@ def bench_long(args, torch):
                 ref = solve(*bands, rhs_host[:, cols], cyclic=cyclic)
                 cpu_s = (time.perf_counter() - t0) / len(cols) * m
                 got = x[:, torch.from_numpy(cols).cuda()].cpu().numpy()
+                err = rel_err_cols(got, ref)
+                # the same draws as FP32 data, solved in FP64 (12 B per row)
+                r32 = rhs.float()
+                t32, _ = time_launches(lambda: f.solve(r32, out=x, precision="f32rhs_f64"), reps,
+                                       args.warmup, torch)
+                del r32
                 pl = f.plan(m)
                 points.append({"kind": kind + ("_cyclic" if cyclic else ""), "n": n, "m": m,
                                "chunk": pl["chunk"], "chunks": pl["lanes"],
                                "ms_per_solve": 1e3 * t / reps, "graph_ms_per_solve": graph_ms,
                                "hbm_gbs_algorithmic": 16.0 * n * m * reps / t / 1e9,
+                               "f32rhs_f64_ms_per_solve": 1e3 * t32 / reps,
                                "oracle_ms_per_solve": 1e3 * cpu_s,
-                               "rel_err_vs_oracle": rel_err_cols(got, ref)})
+                               "rel_err_vs_oracle": err})
                 del rhs, x
     # the largest tridiagonal point (the one whose counters are recorded)
     big = max(points, key=lambda p: (p["n"] * p["m"], p["kind"] == "tri"))

@@ -146,7 +146,7 @@ bb_status bb_plan(bb_factor f, int64_t m, int32_t what, bb_precision p, int32_t 
  * penta factor; the _cyclic names additionally require a cyclic factor.
  * Long systems (n above 2048 tri / 1024 penta): three launches, x is written
  * as scratch before it receives the solution, so x must not overlap rhs;
- * BB_F64 only.
+ * BB_F64 and BB_F32_RHS_F64 only.
  * Errors: BB_ERR_ARG (wrong factor kind, null pointer, m or ld out of range,
  * unknown precision, rhs == x with BB_F32_RHS_REFINE or BB_F32_RHS_F64), BB_ERR_UNSUPPORTED
  * (long system: another precision, or rhs == x), BB_ERR_HIP, BB_ERR_OOM

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbandbatch.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["api.cpp", "factor.cpp", "sweep.hip", "sweep_f32.hip", "refine.hip", "refine_f32rhs.hip", "ch.hip", "ch_forced.hip", "cn_tri.hip", "cn_penta.hip", "aux.hip", "long_sweep.hip", "adjoint_grad_tri.hip", "adjoint_grad_penta.hip", "sweep_f32in.hip"]
+SOURCES = ["api.cpp", "factor.cpp", "sweep.hip", "sweep_f32.hip", "refine.hip", "refine_f32rhs.hip", "ch.hip", "ch_forced.hip", "cn_tri.hip", "cn_penta.hip", "aux.hip", "long_sweep.hip", "adjoint_grad_tri.hip", "adjoint_grad_penta.hip", "sweep_f32in.hip", "long_f32in.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -408,9 +408,10 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
     if ((p == BB_F32_RHS_REFINE || p == BB_F32_RHS_F64) && m > 0 && in == out)
         return fail(BB_ERR_ARG, "BB_F32_RHS_REFINE and BB_F32_RHS_F64 read float and write double: "
                                 "rhs and x must not overlap");
-    if (is_long(f) && p != BB_F64)
+    if (is_long(f) && p != BB_F64 && p != BB_F32_RHS_F64)
         return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(f.n) +
-                                             " (long system): only BB_F64 is built for it");
+                                             " (long system): only BB_F64 and BB_F32_RHS_F64 are "
+                                             "built for it");
     if (is_long(f) && m > 0 && in == out)
         return fail(BB_ERR_UNSUPPORTED, "n = " + std::to_string(f.n) +
                                              " (long system): x serves as scratch and must not "
@@ -424,9 +425,12 @@ bb_status solve(bb_factor fh, const void *in, void *out, int64_t m, int64_t ld, 
         bb::DeviceTable tab;
         if ((st = long_table(f, dev, adjoint, C, &tab)) != BB_OK) return st;
         const bb::Direction &dir = adjoint ? f.adjoint : f.primal;
-        hipError_t e = bb::launch_long_solve(f.K, f.cyclic, (const double *)tab.ptr, dir.cor.q,
-                                             long_geom(f, m, ld, C), (const double *)in,
-                                             (double *)out, (hipStream_t)stream);
+        const bb::LongGeom lg = long_geom(f, m, ld, C);
+        hipError_t e = p == BB_F32_RHS_F64
+            ? bb::launch_long_solve_f32in(f.K, f.cyclic, (const double *)tab.ptr, dir.cor.q, lg,
+                                          (const float *)in, (double *)out, (hipStream_t)stream)
+            : bb::launch_long_solve(f.K, f.cyclic, (const double *)tab.ptr, dir.cor.q, lg,
+                                    (const double *)in, (double *)out, (hipStream_t)stream);
         if (e != hipSuccess) return hip_fail(e, "long-system launch");
         g_last_error.clear();
         return BB_OK;

@@ -118,8 +118,10 @@ def test_long_systems_host_checks(L):
     assert L.bb_plan(hp, 100000, 0, 0, ctypes.byref(chunk), ctypes.byref(lanes), ctypes.byref(waves),
                      ctypes.byref(scalar)) == 0
     assert chunk.value == 64 and lanes.value == 17 and waves.value == 1 and scalar.value == 1
-    for prec in (1, 2, 3, 4):   # refinement and float precisions: not built for long systems
+    for prec in (1, 2, 3):   # refinement and float precisions: not built for long systems
         assert L.bb_solve_batch_penta(hp, fake, other, 4, 4, prec, None) == -6
+    assert L.bb_solve_batch_penta(hp, fake, fake, 4, 4, 4, None) == -1     # float rhs aliasing x
+    assert L.bb_solve_batch_penta(hp, None, None, 0, 1, 4, None) == 0      # FP32 data: built
     assert L.bb_solve_batch_penta(hp, fake, fake, 4, 4, 0, None) == -6      # in place
     assert L.bb_solve_batch_penta_adjoint(hp, fake, fake, 4, 4, 0, None) == -6
     L.bb_factor_destroy(hp)

@@ -124,6 +124,22 @@ def test_long_strided_and_untouched_columns():
     assert np.array_equal(host(wide_in[:, :m]), rhs)
 
 
+@pytest.mark.parametrize("kind,n,m,cyclic", [("tri", 4096, 70, False), ("tri", 8192, 5000, True),
+                                             ("penta", 2048, 65, True), ("penta", 8192, 9000, False)])
+def test_long_f32_rhs_f64(kind, n, m, cyclic):
+    """FP32 right-hand-side data on long systems, solved in FP64: against the
+    oracle on the promoted values at 1e-12, and bitwise the FP64 solve of
+    the promoted array (same three launches and arithmetic); adjoint too."""
+    say("long f32rhs_f64", kind, n, m, cyclic)
+    f, bands = _make(kind, n, seed=n + 7, cyclic=cyclic)
+    r32 = inputs.uniform_batch(n, m, seed=5 * n + m).astype(np.float32)
+    t = dev(r32, torch.float32)
+    x = f.solve(t, precision="f32rhs_f64")
+    assert rel_err(host(x), _oracle(kind, bands, r32.astype(np.float64), cyclic, False)) < 1e-12
+    assert torch.equal(x, f.solve(t.double()))
+    assert torch.equal(f.adjoint(t, precision="f32rhs_f64"), f.adjoint(t.double()))
+
+
 def test_long_rejects_in_place_and_other_precisions():
     n = 4096
     f, _ = _make("tri", n, seed=1, cyclic=False)
