@@ -57,6 +57,9 @@ CASES = [
     ("penta", False, 512, 20000, 2, {}, True),       # scalar, 64-row chunks
     ("penta", True, 256, 5000, 3, {}, True),         # scalar, 32-row chunks
     ("penta", False, 128, 20000, 2, {}, True),
+    ("tri", True, 64, 140000, 2, {}, True),          # one chunk per system, one wave per group
+    ("penta", False, 64, 140000, 2, {}, True),
+    ("tri", False, 32, 140000, 3, {}, True),         # one 32-row chunk per system
     ("tri", False, 256, 8192, 2, {"ch_uniform": 0}, True),     # LDS table, 4-wave groups
     ("penta", True, 512, 20000, 2, {"ch_uniform": 0}, True),   # LDS table, 4-wave groups
     ("tri", False, 256, 8192, 3, {"ch_uniform": 0, "waves_per_system": 1}, False),
@@ -145,3 +148,27 @@ def test_adjoint_band_grad_in_place_and_odd_steps(tuning):
                                               ctypes.c_void_p(ws.data_ptr()), nbytes, None))
         torch.cuda.synchronize()
         assert torch.equal(buf, want_lam) and torch.equal(grad, want_grad), tune
+
+
+@pytest.mark.parametrize("kind,cyclic,n,m,pad", [("tri", False, 1024, 20000, 40), ("penta", True, 256, 5000, 3),
+                                               ("tri", True, 64, 33, 7)])
+def test_adjoint_band_grad_strided(kind, cyclic, n, m, pad):
+    """Batches with a leading dimension above m (g, lam and every state of
+    traj n * ld apart): the same results as the contiguous batch, bitwise,
+    and the columns past m untouched."""
+    say("adjoint + band grad strided", kind, cyclic, n, m, pad)
+    f, _ = _factor(kind, cyclic, n)
+    steps = 3
+    ld = m + pad
+    g = inputs.uniform_batch(n, m, seed=60)
+    us = [inputs.uniform_batch(n, m, seed=61 + t) for t in range(steps)]
+    lam_c, grad_c = f.adjoint_band_grad(dev(g), torch.stack([dev(u) for u in us]))
+    gs = torch.full((n, ld), 7.0, dtype=torch.float64, device="cuda")
+    gs[:, :m] = dev(g)
+    ts = torch.full((steps, n, ld), 7.0, dtype=torch.float64, device="cuda")
+    for t in range(steps):
+        ts[t, :, :m] = dev(us[t])
+    lam_s, grad_s = f.adjoint_band_grad(gs[:, :m], ts[:, :, :m])
+    assert lam_s.stride(0) == ld
+    assert torch.equal(lam_s, lam_c) and torch.equal(grad_s, grad_c)
+    assert torch.all(gs[:, m:] == 7.0) and torch.all(ts[:, :, m:] == 7.0)
