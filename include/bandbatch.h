@@ -357,8 +357,8 @@ bb_status bb_adjoint_trajectory(bb_factor f, const double *g, double *traj, int6
  * between the two paths, so they agree with bb_band_grad's to rounding.
  * workspace: device scratch of at least
  * bb_adjoint_band_grad_workspace_bytes(f, m, ld) bytes, caller-owned.
- * Errors: BB_ERR_ARG (null pointer, sizes, steps < 1, workspace too small),
- * BB_ERR_HIP, BB_ERR_OOM (first table upload). */
+ * Errors: BB_ERR_ARG (null pointer, sizes, steps < 1, workspace too small,
+ * lam overlapping traj), BB_ERR_HIP, BB_ERR_OOM (first table upload). */
 bb_status bb_adjoint_band_grad(bb_factor f, const double *g, const double *traj, double *lam,
                                int64_t m, int64_t ld, int64_t steps, double *grad_bands,
                                void *workspace, size_t workspace_bytes, void *stream);

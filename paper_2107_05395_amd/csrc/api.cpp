@@ -1077,6 +1077,12 @@ bb_status bb_adjoint_band_grad(bb_factor fh, const double *g, const double *traj
     const int64_t stride = f.n * ld;
     if (steps > (int64_t(1) << 62) / stride) return fail(BB_ERR_ARG, "steps * n * ld overflows");
     if (m == 0) { g_last_error.clear(); return BB_OK; }
+    {
+        // lam is written while other groups still read traj: no overlap
+        const uintptr_t l0 = (uintptr_t)lam, l1 = l0 + (uintptr_t)stride * sizeof(double);
+        const uintptr_t t0 = (uintptr_t)traj, t1 = t0 + (uintptr_t)(steps * stride) * sizeof(double);
+        if (l0 < t1 && t0 < l1) return fail(BB_ERR_ARG, "lam must not overlap traj");
+    }
     const AdjGradPlan a = adjoint_grad_plan(f, m, ld);
     if (workspace_bytes < a.bytes || !workspace)
         return fail(BB_ERR_ARG, "workspace smaller than bb_adjoint_band_grad_workspace_bytes()");

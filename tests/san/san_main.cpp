@@ -90,6 +90,7 @@ int main()
     // or has m = 0
     void *fake = (void *)0x1000, *other = (void *)0x2000;
     double *dfake = (double *)fake, *dother = (double *)other;
+    double *dfar = (double *)(uintptr_t(1) << 44);   // beyond every range the checks form
     // factors of every kind and size, their plans and info, argument errors
     for (int kind = 0; kind < 4; ++kind) {
         const int K = kind < 2 ? 1 : 2;
@@ -128,10 +129,12 @@ int main()
                 const size_t ws = bb_adjoint_band_grad_workspace_bytes(f, m, m);
                 CHECK(ws >= (size_t)(2 * K + 1) * n * sizeof(double));
                 CHECK(bb_adjoint_band_grad_fused(f, m) == 0 || bb_adjoint_band_grad_fused(f, m) == 1);
-                CHECK(bb_adjoint_band_grad(f, dfake, dother, dfake, m, m, 2, dother, fake, ws - 1,
+                CHECK(bb_adjoint_band_grad(f, dfake, dother, dfar, m, m, 2, dother, fake, ws - 1,
                                            nullptr) == BB_ERR_ARG);       // workspace too small
+                CHECK(bb_adjoint_band_grad(f, dfake, dother, dother, m, m, 2, dother, fake, ws,
+                                           nullptr) == BB_ERR_ARG);       // lam overlaps traj
             }
-            CHECK(bb_adjoint_band_grad(f, dfake, dother, dfake, 4, 4, 0, dother, fake, 1 << 30,
+            CHECK(bb_adjoint_band_grad(f, dfake, dother, dfar, 4, 4, 0, dother, fake, 1 << 30,
                                        nullptr) == BB_ERR_ARG);           // steps < 1
             CHECK(bb_adjoint_band_grad(f, nullptr, nullptr, nullptr, 0, 1, 1, dother, nullptr, 0,
                                        nullptr) == BB_OK);                // m = 0

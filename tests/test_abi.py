@@ -197,14 +197,17 @@ def test_solve_argument_checks_need_no_gpu(L):
     assert L.bb_solve_batch_tri_thread_per_system(hp, fake, fake, 4, 4, None) == -1
     A = L.bb_adjoint_band_grad
     big = 1 << 30
-    assert A(None, fake, fake, fake, 4, 4, 1, fake, fake, big, None) == -1     # no factor
-    assert A(h, fake, None, fake, 4, 4, 1, fake, fake, big, None) == -1       # no states
-    assert A(h, fake, fake, fake, 4, 4, 1, None, fake, big, None) == -1       # no gradient
-    assert A(h, fake, fake, fake, 4, 4, 0, fake, fake, big, None) == -1       # steps < 1
-    assert A(h, fake, fake, fake, 8, 4, 1, fake, fake, big, None) == -1       # ld < m
-    assert A(h, fake, fake, fake, 4, 4, 1, fake, fake, 0, None) == -1         # workspace too small
-    assert A(h, fake, fake, fake, 4, 4, 1, fake, None, big, None) == -1       # no workspace
+    lam = ctypes.c_void_p(0x100000)   # never dereferenced, far from fake's ranges
+    assert A(None, fake, fake, lam, 4, 4, 1, fake, fake, big, None) == -1      # no factor
+    assert A(h, fake, None, lam, 4, 4, 1, fake, fake, big, None) == -1        # no states
+    assert A(h, fake, fake, lam, 4, 4, 1, None, fake, big, None) == -1        # no gradient
+    assert A(h, fake, fake, lam, 4, 4, 0, fake, fake, big, None) == -1        # steps < 1
+    assert A(h, fake, fake, lam, 8, 4, 1, fake, fake, big, None) == -1        # ld < m
+    assert A(h, fake, fake, lam, 4, 4, 1, fake, fake, 0, None) == -1          # workspace too small
+    assert A(h, fake, fake, lam, 4, 4, 1, fake, None, big, None) == -1        # no workspace
     assert A(h, None, None, None, 0, 1, 1, fake, None, 0, None) == 0          # m = 0
+    inside = ctypes.c_void_p(0x1000 + 8 * 16 * 4)                             # traj's second state
+    assert A(h, fake, fake, inside, 4, 4, 2, fake, fake, big, None) == -1     # lam inside traj
     L.bb_factor_destroy(h)
     L.bb_factor_destroy(hp)
 
