@@ -182,10 +182,10 @@ void adjoint_grad_kernel(const double *__restrict__ table, int64_t table_elems, 
             // are loaded before the transposed solve, so they arrive during
             // it; each later block's rows are loaded while the block before
             // it is reduced (one block in flight ahead: measured 1.65 against
-            // 1.74 ms for 10 steps at n = 1024, m = 2^16), their addresses
-            // taken from an opaque value read after the staging two blocks
-            // back, so the compiler cannot hoist every row's load above the
-            // reduction and hold them all at once.
+            // 1.74 ms for 10 steps at n = 1024, m = 2^16), their row index
+            // passed through an opaque value so that the compiler cannot
+            // hoist every row's load to the top of the step and hold them all
+            // at once.
             const int64_t ld = opaque_s(g.ld);
             const double *ucol = traj + (steps - 1 - step) * traj_stride + kk;
             auto urow = [&](int t) -> double {   // row row0 + t, t in [-K, C + K)
